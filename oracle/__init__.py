@@ -1,0 +1,201 @@
+"""MPS oracle -- TEST INFRASTRUCTURE ONLY.
+
+ctypes wrapper around the plain FP64 C++ reference in ``mps_oracle.cpp``.
+Only the test-suite, the smoke check and the CPU-baseline leg of the
+benchmark may import this package; the HIP library never does.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmps_oracle.so")
+SOURCES = ["mps_oracle.cpp"]
+
+
+def build(verbose: bool = False) -> str:
+    """Compile the oracle with g++ (FP64, OpenMP, no FMA contraction so the
+    squared-distance expression rounds term by term)."""
+    cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-ffp-contract=off", "-fPIC",
+           "-shared", "-o", LIB_PATH + ".tmp"] + [os.path.join(HERE, s) for s in SOURCES]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    os.replace(LIB_PATH + ".tmp", LIB_PATH)
+    return LIB_PATH
+
+
+class OrcParams(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int32), ("pmode", C.c_int32), ("kernel", C.c_int32),
+        ("grad", C.c_int32), ("clamp", C.c_int32), ("max_neigh", C.c_int32),
+        ("cg_maxit", C.c_int32), ("grid_n", C.c_int32 * 3),
+        ("l0", C.c_double), ("re_n", C.c_double), ("re_lap", C.c_double),
+        ("rho", C.c_double), ("nu", C.c_double), ("g", C.c_double * 3),
+        ("dt", C.c_double), ("beta", C.c_double), ("c0", C.c_double),
+        ("gamma", C.c_double), ("alpha", C.c_double), ("cg_tol", C.c_double),
+        ("grid_lo", C.c_double * 3), ("cell_size", C.c_double),
+        ("smag_cs", C.c_double),
+    ]
+
+
+class OrcStepOut(C.Structure):
+    _fields_ = [
+        ("cell", C.c_void_p), ("count", C.c_void_p), ("list", C.c_void_p),
+        ("us", C.c_void_p), ("rs", C.c_void_p), ("nstar", C.c_void_p),
+        ("flags", C.c_void_p), ("diag", C.c_void_p), ("b", C.c_void_p),
+        ("aval", C.c_void_p), ("p", C.c_void_p), ("phat", C.c_void_p),
+        ("gradp", C.c_void_p), ("pos", C.c_void_p), ("vel", C.c_void_p),
+        ("type", C.c_void_p), ("cg_iters", C.c_int32), ("cg_relres", C.c_double),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = C.CDLL(LIB_PATH)
+        L.orc_weight.restype = C.c_double
+        L.orc_weight.argtypes = [C.c_int, C.c_double, C.c_double]
+        L.orc_lattice_constants.argtypes = [C.c_int, C.c_double, C.c_double, C.c_int,
+                                            C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                            C.POINTER(C.c_int32)]
+        for f in (L.orc_neighbors_brute,):
+            f.argtypes = [C.POINTER(OrcParams), C.c_int64, C.c_void_p, C.c_void_p,
+                          C.c_void_p, C.c_void_p]
+        L.orc_neighbors_cells.argtypes = [C.POINTER(OrcParams), C.c_int64, C.c_void_p,
+                                          C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_step.argtypes = [C.POINTER(OrcParams), C.c_int64, C.c_void_p, C.c_void_p,
+                               C.c_void_p, C.c_void_p, C.POINTER(OrcStepOut)]
+        L.orc_run.argtypes = [C.POINTER(OrcParams), C.c_int64, C.c_void_p, C.c_void_p,
+                              C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
+        _lib = L
+    return _lib
+
+
+def make_params(p: dict) -> OrcParams:
+    o = OrcParams()
+    for k in ("dim", "pmode", "kernel", "grad", "clamp", "max_neigh", "cg_maxit"):
+        setattr(o, k, int(p[k]))
+    for k in ("l0", "re_n", "re_lap", "rho", "nu", "dt", "beta", "c0", "gamma",
+              "alpha", "cg_tol", "cell_size", "smag_cs"):
+        setattr(o, k, float(p[k]))
+    for a in range(3):
+        o.g[a] = float(p["g"][a])
+        o.grid_lo[a] = float(p["grid_lo"][a])
+        o.grid_n[a] = int(p["grid_n"][a])
+    return o
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+def weight(kernel: int, r: float, re: float) -> float:
+    return lib().orc_weight(kernel, r, re)
+
+
+def lattice_constants(dim: int, l0: float, re: float, kernel: int):
+    """(n0, lambda, neighbour count) of an interior lattice particle."""
+    n0, lam, cnt = C.c_double(), C.c_double(), C.c_int32()
+    lib().orc_lattice_constants(dim, l0, re, kernel, C.byref(n0), C.byref(lam), C.byref(cnt))
+    return n0.value, lam.value, cnt.value
+
+
+def _prep(params, pos, ptype):
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    ptype = np.ascontiguousarray(ptype, dtype=np.int8)
+    return make_params(params), pos, ptype
+
+
+def neighbors_brute(params, pos, ptype):
+    """(status, count[n], list[n][max_neigh]) by all-pairs search."""
+    P, pos, ptype = _prep(params, pos, ptype)
+    n = pos.shape[0]
+    cnt = np.zeros(n, np.int32)
+    lst = np.zeros((n, P.max_neigh), np.int32)
+    st = lib().orc_neighbors_brute(C.byref(P), n, _ptr(pos), _ptr(ptype), _ptr(cnt), _ptr(lst))
+    return st, cnt, lst
+
+
+def neighbors_cells(params, pos, ptype):
+    """(status, cell[n], count[n], list[n][max_neigh]) by the cell-linked list."""
+    P, pos, ptype = _prep(params, pos, ptype)
+    n = pos.shape[0]
+    cell = np.zeros(n, np.int32)
+    cnt = np.zeros(n, np.int32)
+    lst = np.zeros((n, P.max_neigh), np.int32)
+    st = lib().orc_neighbors_cells(C.byref(P), n, _ptr(pos), _ptr(ptype), _ptr(cell),
+                                   _ptr(cnt), _ptr(lst))
+    return st, cell, cnt, lst
+
+
+def step(params, pos, vel, ptype, flags_override=None, *, want_lists=True,
+         want_matrix=False):
+    """One time step.  Returns (status, dict of fields)."""
+    P, pos, ptype = _prep(params, pos, ptype)
+    vel = np.ascontiguousarray(vel, dtype=np.float64)
+    n, dim = pos.shape
+    K = P.max_neigh
+    out = {
+        "cell": np.zeros(n, np.int32),
+        "count": np.zeros(n, np.int32),
+        "us": np.zeros((n, dim)), "rs": np.zeros((n, dim)),
+        "nstar": np.zeros(n), "flags": np.zeros(n, np.int8),
+        "diag": np.zeros(n), "b": np.zeros(n),
+        "p": np.zeros(n), "phat": np.zeros(n), "gradp": np.zeros((n, dim)),
+        "pos": np.zeros((n, dim)), "vel": np.zeros((n, dim)),
+        "type": np.zeros(n, np.int8),
+    }
+    if want_lists:
+        out["list"] = np.zeros((n, K), np.int32)
+    if want_matrix:
+        out["aval"] = np.zeros((n, K))
+    so = OrcStepOut()
+    for k, v in out.items():
+        setattr(so, k, v.ctypes.data)
+    fo = None
+    if flags_override is not None:
+        fo = np.ascontiguousarray(flags_override, dtype=np.int8)
+    st = lib().orc_step(C.byref(P), n, _ptr(pos), _ptr(vel), _ptr(ptype), _ptr(fo),
+                        C.byref(so))
+    out["cg_iters"] = so.cg_iters
+    out["cg_relres"] = so.cg_relres
+    return st, out
+
+
+def run(params, pos, vel, ptype, nsteps):
+    """nsteps time steps; returns (status, pos, vel, type, p, flags)."""
+    P, pos, ptype = _prep(params, pos, ptype)
+    pos = pos.copy()
+    ptype = ptype.copy()
+    vel = np.ascontiguousarray(vel, dtype=np.float64).copy()
+    n = pos.shape[0]
+    p = np.zeros(n)
+    fl = np.zeros(n, np.int8)
+    st = lib().orc_run(C.byref(P), n, _ptr(pos), _ptr(vel), _ptr(ptype), int(nsteps),
+                       _ptr(p), _ptr(fl))
+    return st, pos, vel, ptype, p, fl
+
+
+def pressure_gradient(params, rs, ptype, p):
+    """(status, phat[n], gradp[n][dim]) of a given pressure field at rs."""
+    P, rs, ptype = _prep(params, rs, ptype)
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    n, dim = rs.shape
+    phat = np.zeros(n)
+    gp = np.zeros((n, dim))
+    L = lib()
+    L.orc_pressure_gradient.argtypes = [C.POINTER(OrcParams), C.c_int64, C.c_void_p,
+                                        C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+    st = L.orc_pressure_gradient(C.byref(P), n, _ptr(rs), _ptr(ptype), _ptr(p),
+                                 _ptr(phat), _ptr(gp))
+    return st, phat, gp

@@ -1,0 +1,716 @@
+/*
+ * MPS oracle -- TEST INFRASTRUCTURE ONLY (see mps_oracle.h).
+ *
+ * Plain FP64 C++ written from the equations of arXiv 2105.01677, Section
+ * "The Moving Particle Semi-implicit Method":
+ *   kernel weight        Eq. 4 (Koshizuka) and the cubic kernel (WC model)
+ *   number density       Eq. 5, free surface Eq. 15
+ *   Laplacian model      Eq. 7 (also the PPE coefficients)
+ *   PPE                  Eq. 13 -> A x = b, assembled row-wise as in the
+ *                        listing "PPE assemble GPU code" (dummy neighbours
+ *                        give no coupling; alpha/dt^2 on the diagonal)
+ *   equation of state    Eq. 16
+ *   pressure gradient    standard MPS form, or Eq. 18 (CMPS)
+ *   time integration     semi-implicit predictor-corrector, first-order Euler
+ * Readings where the paper is silent are listed in the design doc.
+ *
+ * The step is a template on the scalar type so that the same code runs in
+ * double and with forward-mode dual numbers (the reference gradient).
+ * Discrete decisions (neighbour lists, flags, p-hat argmin, clamps) are taken
+ * on the value part, which freezes them exactly as the adjoint does.
+ */
+#include "mps_oracle.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+namespace {
+
+enum { FLUID = 0, WALL = 1, DUMMY = 2, GHOST = 3 };
+enum { FL_GHOST = -2, FL_DUMMY = -1, FL_INNER = 0, FL_SURFACE = 1 };
+
+/* ---------------------------------------------------------------- duals */
+template <int K>
+struct Dual {
+  double v;
+  double d[K];
+  Dual() : v(0) { for (int k = 0; k < K; ++k) d[k] = 0; }
+  Dual(double x) : v(x) { for (int k = 0; k < K; ++k) d[k] = 0; }
+};
+template <int K> Dual<K> operator+(const Dual<K>& a, const Dual<K>& b) {
+  Dual<K> r(a.v + b.v); for (int k = 0; k < K; ++k) r.d[k] = a.d[k] + b.d[k]; return r; }
+template <int K> Dual<K> operator-(const Dual<K>& a, const Dual<K>& b) {
+  Dual<K> r(a.v - b.v); for (int k = 0; k < K; ++k) r.d[k] = a.d[k] - b.d[k]; return r; }
+template <int K> Dual<K> operator-(const Dual<K>& a) {
+  Dual<K> r(-a.v); for (int k = 0; k < K; ++k) r.d[k] = -a.d[k]; return r; }
+template <int K> Dual<K> operator*(const Dual<K>& a, const Dual<K>& b) {
+  Dual<K> r(a.v * b.v); for (int k = 0; k < K; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k]; return r; }
+template <int K> Dual<K> operator/(const Dual<K>& a, const Dual<K>& b) {
+  Dual<K> r(a.v / b.v);
+  for (int k = 0; k < K; ++k) r.d[k] = (a.d[k] * b.v - a.v * b.d[k]) / (b.v * b.v);
+  return r; }
+template <int K> Dual<K> operator+(const Dual<K>& a, double b) { return a + Dual<K>(b); }
+template <int K> Dual<K> operator+(double a, const Dual<K>& b) { return Dual<K>(a) + b; }
+template <int K> Dual<K> operator-(const Dual<K>& a, double b) { return a - Dual<K>(b); }
+template <int K> Dual<K> operator-(double a, const Dual<K>& b) { return Dual<K>(a) - b; }
+template <int K> Dual<K> operator*(const Dual<K>& a, double b) { return a * Dual<K>(b); }
+template <int K> Dual<K> operator*(double a, const Dual<K>& b) { return Dual<K>(a) * b; }
+template <int K> Dual<K> operator/(const Dual<K>& a, double b) { return a / Dual<K>(b); }
+template <int K> Dual<K> operator/(double a, const Dual<K>& b) { return Dual<K>(a) / b; }
+template <int K> Dual<K>& operator+=(Dual<K>& a, const Dual<K>& b) { a = a + b; return a; }
+template <int K> Dual<K>& operator-=(Dual<K>& a, const Dual<K>& b) { a = a - b; return a; }
+template <int K> Dual<K> sqrt(const Dual<K>& a) {
+  double s = std::sqrt(a.v); Dual<K> r(s);
+  for (int k = 0; k < K; ++k) r.d[k] = a.d[k] / (2.0 * s);
+  return r; }
+
+inline double val(double x) { return x; }
+template <int K> double val(const Dual<K>& x) { return x.v; }
+using std::sqrt;
+
+/* ---------------------------------------------------------- parameters */
+struct Consts {
+  double n0_n, n0_lap, lam_lap;
+};
+
+/* Kernel weights: Eq. 4 (r_e/r - 1) and the cubic kernel (1 - r/r_e)^3,
+ * both zero for r >= r_e.  r is a distance, r_e the radius of interaction. */
+template <class T>
+T weight(int kernel, const T& r, double re) {
+  if (!(val(r) < re)) return T(0.0);
+  if (kernel == 0) return re / r - 1.0;
+  T q = 1.0 - r / re;
+  return q * q * q;
+}
+
+/* Squared distance between two points, each product and sum rounded in
+ * turn: (dx*dx + dy*dy) + dz*dz with dx = x_j - x_i.  The neighbour
+ * criterion d^2 < r_e^2 uses this expression on both sides of the parity
+ * check, so the lists agree bit for bit. */
+inline double dist2(const double* xi, const double* xj, int dim) {
+  double dx = xj[0] - xi[0];
+  double dy = xj[1] - xi[1];
+  double s = dx * dx + dy * dy;
+  if (dim == 3) {
+    double dz = xj[2] - xi[2];
+    s = s + dz * dz;
+  }
+  return s;
+}
+
+Consts constants(const orc_params* P) {
+  Consts c;
+  int cnt;
+  double lam_n;
+  orc_lattice_constants(P->dim, P->l0, P->re_n, P->kernel, &c.n0_n, &lam_n, &cnt);
+  orc_lattice_constants(P->dim, P->l0, P->re_lap, P->kernel, &c.n0_lap, &c.lam_lap, &cnt);
+  return c;
+}
+
+/* Whether particle position x lies in the fixed background grid, and its
+ * linear cell id (x fastest).  A particle that leaves the grid becomes a
+ * ghost and takes no further part. */
+bool grid_cell(const orc_params* P, const double* x, int* cell) {
+  double inv = 1.0 / P->cell_size;
+  int c[3] = {0, 0, 0};
+  for (int a = 0; a < P->dim; ++a) {
+    double f = std::floor((x[a] - P->grid_lo[a]) * inv);
+    if (!(f >= 0.0 && f < (double)P->grid_n[a])) return false;
+    c[a] = (int)f;
+  }
+  *cell = c[0] + P->grid_n[0] * (c[1] + P->grid_n[1] * c[2]);
+  return true;
+}
+
+/* ------------------------------------------------------ neighbour lists */
+struct Lists {
+  std::vector<int> start;  // CSR row starts, size n+1
+  std::vector<int> idx;    // ascending neighbour ids per row
+};
+
+int lists_from_rows(std::vector<std::vector<int>>& rows, int max_neigh, Lists& L) {
+  int status = 0;
+  size_t n = rows.size();
+  L.start.assign(n + 1, 0);
+  for (size_t i = 0; i < n; ++i) {
+    std::sort(rows[i].begin(), rows[i].end());
+    if ((int)rows[i].size() > max_neigh) status = -3;
+    L.start[i + 1] = L.start[i] + (int)rows[i].size();
+  }
+  L.idx.resize(L.start[n]);
+  for (size_t i = 0; i < n; ++i)
+    std::copy(rows[i].begin(), rows[i].end(), L.idx.begin() + L.start[i]);
+  return status;
+}
+
+/* The cell-linked list: particles binned into cells of side cell_size >=
+ * re_lap; the neighbours of i are searched in its own and the adjacent
+ * cells only (Section "Neighbouring search algorithms"). */
+int build_lists_cells(const orc_params* P, int n, const double* pos,
+                      const int8_t* type, Lists& L, std::vector<int>& cell) {
+  const int dim = P->dim;
+  const int nx = P->grid_n[0], ny = P->grid_n[1], nz = dim == 3 ? P->grid_n[2] : 1;
+  std::vector<std::vector<int>> bins((size_t)nx * ny * nz);
+  cell.assign(n, -1);
+  for (int i = 0; i < n; ++i) {
+    if (type[i] == GHOST) continue;
+    int c;
+    if (grid_cell(P, pos + (size_t)i * dim, &c)) {
+      cell[i] = c;
+      bins[c].push_back(i);
+    }
+  }
+  const double re2 = P->re_lap * P->re_lap;
+  std::vector<std::vector<int>> rows(n);
+  int coincident = 0;
+#pragma omp parallel for schedule(guided) reduction(| : coincident)
+  for (int i = 0; i < n; ++i) {
+    if (cell[i] < 0) continue;
+    int ci = cell[i];
+    int cx = ci % nx, cy = (ci / nx) % ny, cz = ci / (nx * ny);
+    for (int dz = -1; dz <= 1; ++dz) {
+      if (dim == 2 && dz != 0) continue;
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          int x = cx + dx, y = cy + dy, z = cz + dz;
+          if (x < 0 || y < 0 || z < 0 || x >= nx || y >= ny || z >= nz) continue;
+          for (int j : bins[x + nx * (y + ny * z)]) {
+            if (j == i) continue;
+            double d2 = dist2(pos + (size_t)i * dim, pos + (size_t)j * dim, dim);
+            if (d2 < re2) {
+              rows[i].push_back(j);
+              if (d2 == 0.0) coincident = 1;
+            }
+          }
+        }
+    }
+  }
+  int st = lists_from_rows(rows, P->max_neigh, L);
+  if (coincident) return -6;
+  return st;
+}
+
+/* The definition: every pair (i, j), j != i, both in the grid. */
+int build_lists_brute(const orc_params* P, int n, const double* pos,
+                      const int8_t* type, Lists& L) {
+  const int dim = P->dim;
+  std::vector<char> active(n, 0);
+  for (int i = 0; i < n; ++i) {
+    int c;
+    active[i] = type[i] != GHOST && grid_cell(P, pos + (size_t)i * dim, &c);
+  }
+  const double re2 = P->re_lap * P->re_lap;
+  std::vector<std::vector<int>> rows(n);
+  int coincident = 0;
+#pragma omp parallel for schedule(guided) reduction(| : coincident)
+  for (int i = 0; i < n; ++i) {
+    if (!active[i]) continue;
+    for (int j = 0; j < n; ++j) {
+      if (j == i || !active[j]) continue;
+      double d2 = dist2(pos + (size_t)i * dim, pos + (size_t)j * dim, dim);
+      if (d2 < re2) {
+        rows[i].push_back(j);
+        if (d2 == 0.0) coincident = 1;
+      }
+    }
+  }
+  int st = lists_from_rows(rows, P->max_neigh, L);
+  if (coincident) return -6;
+  return st;
+}
+
+void export_lists(const Lists& L, int n, int max_neigh, int32_t* count, int32_t* list) {
+  for (int i = 0; i < n; ++i) {
+    int c = L.start[i + 1] - L.start[i];
+    if (count) count[i] = c;
+    if (list) {
+      for (int l = 0; l < max_neigh; ++l)
+        list[(size_t)i * max_neigh + l] = l < c ? L.idx[L.start[i] + l] : -1;
+    }
+  }
+}
+
+/* ------------------------------------------------------------ PPE solve */
+/* Sparse symmetric system: diagonal plus off-diagonal entries per row. */
+struct Sparse {
+  std::vector<int> start, col;
+  std::vector<double> off;   // values
+  std::vector<double> diag;
+};
+
+void spmv(const Sparse& A, const std::vector<double>& x, std::vector<double>& y) {
+  int n = (int)A.diag.size();
+#pragma omp parallel for schedule(static)
+  for (int i = 0; i < n; ++i) {
+    double s = A.diag[i] * x[i];
+    for (int k = A.start[i]; k < A.start[i + 1]; ++k) s += A.off[k] * x[A.col[k]];
+    y[i] = s;
+  }
+}
+
+double dot(const std::vector<double>& a, const std::vector<double>& b) {
+  double s = 0.0;
+  for (size_t i = 0; i < a.size(); ++i) s += a[i] * b[i];
+  return s;
+}
+
+/* Conjugate gradients with diagonal (Jacobi) preconditioning, from x = 0,
+ * to ||b - A x|| <= tol ||b||.  The method's own solver (ICCG) only reaches
+ * the same unique solution faster; the oracle needs the solution. */
+int cg_solve(const Sparse& A, const std::vector<double>& b, std::vector<double>& x,
+             double tol, int maxit, int* iters, double* relres) {
+  int n = (int)b.size();
+  x.assign(n, 0.0);
+  double bn = std::sqrt(dot(b, b));
+  *iters = 0;
+  *relres = 0.0;
+  if (bn == 0.0) return 0;
+  std::vector<double> r = b, z(n), p(n), q(n);
+  for (int i = 0; i < n; ++i) z[i] = r[i] / A.diag[i];
+  p = z;
+  double rz = dot(r, z);
+  for (int it = 1; it <= maxit; ++it) {
+    spmv(A, p, q);
+    double alpha = rz / dot(p, q);
+    for (int i = 0; i < n; ++i) { x[i] += alpha * p[i]; r[i] -= alpha * q[i]; }
+    double rn = std::sqrt(dot(r, r));
+    *iters = it;
+    *relres = rn / bn;
+    if (rn <= tol * bn) return 0;
+    for (int i = 0; i < n; ++i) z[i] = r[i] / A.diag[i];
+    double rz2 = dot(r, z);
+    double beta = rz2 / rz;
+    rz = rz2;
+    for (int i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
+  }
+  return -4;
+}
+
+/* Solve A(T) p = b(T).  For double this is one CG solve; for duals the
+ * value system is solved first, then each tangent system
+ * A p' = b' - A' p with the same matrix (forward-mode differentiation of
+ * the exact solution). */
+template <class T>
+struct PPESolve;
+
+template <>
+struct PPESolve<double> {
+  static int run(const std::vector<int>& start, const std::vector<int>& col,
+                 const std::vector<double>& off, const std::vector<double>& diag,
+                 const std::vector<double>& b, std::vector<double>& p, double tol,
+                 int maxit, int* iters, double* relres) {
+    Sparse A{start, col, off, diag};
+    return cg_solve(A, b, p, tol, maxit, iters, relres);
+  }
+};
+
+template <int K>
+struct PPESolve<Dual<K>> {
+  using T = Dual<K>;
+  static int run(const std::vector<int>& start, const std::vector<int>& col,
+                 const std::vector<T>& off, const std::vector<T>& diag,
+                 const std::vector<T>& b, std::vector<T>& p, double tol, int maxit,
+                 int* iters, double* relres) {
+    int n = (int)diag.size();
+    Sparse A;
+    A.start = start;
+    A.col = col;
+    A.off.resize(off.size());
+    A.diag.resize(n);
+    for (size_t k = 0; k < off.size(); ++k) A.off[k] = off[k].v;
+    for (int i = 0; i < n; ++i) A.diag[i] = diag[i].v;
+    std::vector<double> bv(n), pv;
+    for (int i = 0; i < n; ++i) bv[i] = b[i].v;
+    int st = cg_solve(A, bv, pv, tol, maxit, iters, relres);
+    p.assign(n, T(0.0));
+    for (int i = 0; i < n; ++i) p[i].v = pv[i];
+    for (int k = 0; k < K; ++k) {
+      std::vector<double> rhs(n), pk;
+      for (int i = 0; i < n; ++i) {
+        double s = diag[i].d[k] * pv[i];
+        for (int e = start[i]; e < start[i + 1]; ++e) s += off[e].d[k] * pv[col[e]];
+        rhs[i] = b[i].d[k] - s;
+      }
+      int it2; double rr2;
+      cg_solve(A, rhs, pk, tol, maxit, &it2, &rr2);
+      for (int i = 0; i < n; ++i) p[i].d[k] = pk[i];
+    }
+    return st;
+  }
+};
+
+/* ------------------------------------------------------------ the step */
+template <class T>
+struct Trace {
+  std::vector<T> us, rs, nstar, p, phat, gradp, diag, b;
+  std::vector<T> aval;   // aligned with the list CSR
+  std::vector<int8_t> flags;
+  std::vector<int> cell;
+  Lists lists;
+  int cg_iters = 0;
+  double cg_relres = 0.0;
+};
+
+/* Integer power by repeated multiplication (gamma = 7 in Eq. 16). */
+template <class T>
+T ipow(const T& x, int e) {
+  T r(1.0);
+  for (int k = 0; k < e; ++k) r = r * x;
+  return r;
+}
+
+template <class T>
+void pressure_gradient(const orc_params* P, const Consts& C, int n,
+                       const std::vector<T>& rs, const std::vector<int8_t>& type,
+                       const std::vector<T>& p, const Lists& L,
+                       std::vector<T>& phat, std::vector<T>& gradp) {
+  const int dim = P->dim;
+  const std::vector<int>& Ls = L.start;
+  const std::vector<int>& Lj = L.idx;
+  auto dist = [&](int i, int j) {
+    T d2(0.0);
+    for (int a = 0; a < dim; ++a) {
+      T d = rs[(size_t)j * dim + a] - rs[(size_t)i * dim + a];
+      d2 = d2 + d * d;
+    }
+    return sqrt(d2);
+  };
+  /* 6. p-hat: the minimum pressure over i and its non-dummy neighbours
+   *    within re_n at r*.  Needed for every particle in CMPS, fluid only in
+   *    the standard gradient. */
+  phat.assign(n, T(0.0));
+  for (int i = 0; i < n; ++i) {
+    if (type[i] != FLUID && type[i] != WALL) continue;
+    T m = p[i];
+    for (int e = Ls[i]; e < Ls[i + 1]; ++e) {
+      int j = Lj[e];
+      if (type[j] == DUMMY) continue;
+      if (!(val(dist(i, j)) < P->re_n)) continue;
+      if (val(p[j]) < val(m)) m = p[j];
+    }
+    phat[i] = m;
+  }
+
+  /* 7. Pressure gradient, fluid only, over non-dummy j within re_n:
+   *    standard: grad p_i = d/n0 sum_j (p_j - phat_i)/r^2 (r_j - r_i) w
+   *    CMPS (Eq. 18): numerator (p_i + p_j) - (phat_i + phat_j). */
+  gradp.assign((size_t)n * dim, T(0.0));
+  const double cg = (double)dim / C.n0_n;
+#pragma omp parallel for schedule(guided)
+  for (int i = 0; i < n; ++i) {
+    if (type[i] != FLUID) continue;
+    T gp[3] = {T(0.0), T(0.0), T(0.0)};
+    for (int e = Ls[i]; e < Ls[i + 1]; ++e) {
+      int j = Lj[e];
+      if (type[j] == DUMMY) continue;
+      T d[3];
+      T d2(0.0);
+      for (int a = 0; a < dim; ++a) {
+        d[a] = rs[(size_t)j * dim + a] - rs[(size_t)i * dim + a];
+        d2 = d2 + d[a] * d[a];
+      }
+      T r = sqrt(d2);
+      if (!(val(r) < P->re_n)) continue;
+      T w = weight(P->kernel, r, P->re_n);
+      T num = P->grad == 0 ? p[j] - phat[i]
+                           : (p[i] + p[j]) - (phat[i] + phat[j]);
+      T f = num / d2 * w;
+      for (int a = 0; a < dim; ++a) gp[a] = gp[a] + f * d[a];
+    }
+    for (int a = 0; a < dim; ++a) gradp[(size_t)i * dim + a] = cg * gp[a];
+  }
+}
+
+template <class T>
+int step(const orc_params* P, const Consts& C, const T& nu, const T g[3], int n,
+         std::vector<T>& pos, std::vector<T>& vel, std::vector<int8_t>& type,
+         const int8_t* flags_override, Trace<T>& tr) {
+  const int dim = P->dim;
+  const double dt = P->dt;
+  const double rho = P->rho;
+  int status = 0;
+
+  /* 1. Ghosts: particles outside the grid leave the simulation. */
+  std::vector<double> x0((size_t)n * dim);
+  for (size_t k = 0; k < x0.size(); ++k) x0[k] = val(pos[k]);
+  for (int i = 0; i < n; ++i) {
+    int c;
+    if (type[i] != GHOST && !grid_cell(P, &x0[(size_t)i * dim], &c)) type[i] = GHOST;
+  }
+
+  /* 2. Neighbour lists at r^k, kept for the whole step. */
+  int st = build_lists_cells(P, n, x0.data(), type.data(), tr.lists, tr.cell);
+  if (st) return st;
+  const std::vector<int>& Ls = tr.lists.start;
+  const std::vector<int>& Lj = tr.lists.idx;
+
+  /* 3. Explicit viscous + body force prediction (Eq. 2 without pressure,
+   *    Laplacian by Eq. 7 with r_e = re_lap), fluid only:
+   *    u* = u + dt (nu lap(u) + g),  r* = r + dt u*. */
+  const double clap = 2.0 * dim / (C.lam_lap * C.n0_lap);
+  tr.us.assign((size_t)n * dim, T(0.0));
+  tr.rs.assign((size_t)n * dim, T(0.0));
+#pragma omp parallel for schedule(guided)
+  for (int i = 0; i < n; ++i) {
+    const T* ri = &pos[(size_t)i * dim];
+    const T* ui = &vel[(size_t)i * dim];
+    for (int a = 0; a < dim; ++a) {
+      tr.us[(size_t)i * dim + a] = ui[a];
+      tr.rs[(size_t)i * dim + a] = ri[a];
+    }
+    if (type[i] != FLUID) continue;
+    T lap[3] = {T(0.0), T(0.0), T(0.0)};
+    for (int e = Ls[i]; e < Ls[i + 1]; ++e) {
+      int j = Lj[e];
+      const T* rj = &pos[(size_t)j * dim];
+      const T* uj = &vel[(size_t)j * dim];
+      T d2(0.0);
+      for (int a = 0; a < dim; ++a) { T d = rj[a] - ri[a]; d2 = d2 + d * d; }
+      T w = weight(P->kernel, sqrt(d2), P->re_lap);
+      for (int a = 0; a < dim; ++a) lap[a] = lap[a] + (uj[a] - ui[a]) * w;
+    }
+    for (int a = 0; a < dim; ++a) {
+      T acc = nu * clap * lap[a] + g[a];
+      T u = ui[a] + dt * acc;
+      tr.us[(size_t)i * dim + a] = u;
+      tr.rs[(size_t)i * dim + a] = ri[a] + dt * u;
+    }
+  }
+
+  /* 4. Particle number density at r* (Eq. 5, r_e = re_n) and the
+   *    free-surface flag n* < beta n0 (Eq. 15) for fluid and wall. */
+  auto dist = [&](int i, int j) {
+    T d2(0.0);
+    for (int a = 0; a < dim; ++a) {
+      T d = tr.rs[(size_t)j * dim + a] - tr.rs[(size_t)i * dim + a];
+      d2 = d2 + d * d;
+    }
+    return sqrt(d2);
+  };
+  tr.nstar.assign(n, T(0.0));
+  tr.flags.assign(n, (int8_t)FL_INNER);
+#pragma omp parallel for schedule(guided)
+  for (int i = 0; i < n; ++i) {
+    if (type[i] == GHOST) { tr.flags[i] = FL_GHOST; continue; }
+    T s(0.0);
+    for (int e = Ls[i]; e < Ls[i + 1]; ++e) s = s + weight(P->kernel, dist(i, Lj[e]), P->re_n);
+    tr.nstar[i] = s;
+    if (type[i] == DUMMY) tr.flags[i] = FL_DUMMY;
+    else tr.flags[i] = val(s) < P->beta * C.n0_n ? FL_SURFACE : FL_INNER;
+  }
+  if (flags_override) {
+    for (int i = 0; i < n; ++i)
+      if (type[i] == FLUID || type[i] == WALL) tr.flags[i] = flags_override[i];
+  }
+
+  /* 5. Pressure. */
+  tr.p.assign(n, T(0.0));
+  tr.diag.assign(n, T(1.0));
+  tr.b.assign(n, T(0.0));
+  tr.aval.assign(Lj.size(), T(0.0));
+  if (P->pmode == 0) {
+    /* PPE (Eq. 13) with the Laplacian of Eq. 7, row-wise for inner i:
+     *   c_ij = 2d w(r*_ij) / (lambda n0 rho)  for non-dummy j with r* < re_lap
+     *   A_ii = sum_j c_ij + alpha/dt^2,  A_ij = -c_ij for inner j
+     *   b_i  = (n*_i - n0) / (n0 dt^2)
+     * A free-surface neighbour (p = 0, Dirichlet) keeps its c_ij on the
+     * diagonal only.  Rows that are not inner are the identity (p = 0). */
+    const double cpp = 2.0 * dim / (C.lam_lap * C.n0_lap * rho);
+    std::vector<int> start(n + 1, 0), col;
+    std::vector<T> off;
+    for (int i = 0; i < n; ++i) {
+      if (tr.flags[i] == FL_INNER) {
+        T dsum(0.0);
+        for (int e = Ls[i]; e < Ls[i + 1]; ++e) {
+          int j = Lj[e];
+          if (type[j] == DUMMY) continue;
+          T r = dist(i, j);
+          if (!(val(r) < P->re_lap)) continue;
+          T c = cpp * weight(P->kernel, r, P->re_lap);
+          dsum = dsum + c;
+          if (tr.flags[j] == FL_INNER) {
+            col.push_back(j);
+            off.push_back(-c);
+            tr.aval[e] = -c;
+          }
+        }
+        tr.diag[i] = dsum + P->alpha / (dt * dt);
+        tr.b[i] = (tr.nstar[i] - C.n0_n) / (C.n0_n * dt * dt);
+      }
+      start[i + 1] = (int)col.size();
+    }
+    int sst = PPESolve<T>::run(start, col, off, tr.diag, tr.b, tr.p, 1e-13,
+                               std::max(P->cg_maxit, 100000), &tr.cg_iters,
+                               &tr.cg_relres);
+    if (sst) status = sst;
+    for (int i = 0; i < n; ++i)
+      if (tr.flags[i] != FL_INNER) tr.p[i] = T(0.0);
+  } else {
+    /* Equation of state (Eq. 16): p = rho c0^2/gamma ((n* / n0)^gamma - 1)
+     * for fluid and wall particles. */
+    const double B = rho * P->c0 * P->c0 / P->gamma;
+    const int ge = (int)P->gamma;
+    for (int i = 0; i < n; ++i)
+      if (type[i] == FLUID || type[i] == WALL)
+        tr.p[i] = B * (ipow(tr.nstar[i] / C.n0_n, ge) - 1.0);
+  }
+  if (P->clamp)
+    for (int i = 0; i < n; ++i)
+      if (val(tr.p[i]) < 0.0) tr.p[i] = T(0.0);
+
+  /* 6-7. p-hat and the pressure gradient at r*. */
+  pressure_gradient<T>(P, C, n, tr.rs, type, tr.p, tr.lists, tr.phat, tr.gradp);
+
+  /* 8. First-order Euler update, fluid only:
+   *    u^{k+1} = u* - dt/rho grad p,  r^{k+1} = r* + dt (u^{k+1} - u*). */
+  for (int i = 0; i < n; ++i) {
+    for (int a = 0; a < dim; ++a) {
+      size_t k = (size_t)i * dim + a;
+      if (type[i] == FLUID) {
+        T u = tr.us[k] - dt / rho * tr.gradp[k];
+        pos[k] = tr.rs[k] + dt * (u - tr.us[k]);
+        vel[k] = u;
+      }
+    }
+  }
+  return status;
+}
+
+void to_params(const orc_params* P, double* nu, double g[3]) {
+  *nu = P->nu;
+  for (int a = 0; a < 3; ++a) g[a] = P->g[a];
+}
+
+}  // namespace
+
+/* ---------------------------------------------------------------- C API */
+extern "C" {
+
+double orc_weight(int kernel, double r, double re) { return weight(kernel, r, re); }
+
+int orc_lattice_constants(int dim, double l0, double re, int kernel, double* n0,
+                          double* lambda, int32_t* count) {
+  /* n0 = sum_{j != i} w(|r_j - r_i|) over the lattice (Eq. 5 at rest);
+   * lambda = sum r^2 w / sum w (the weighted mean of r^2 in Eq. 7). */
+  int m = (int)std::ceil(re / l0) + 1;
+  double sw = 0.0, sr2w = 0.0;
+  int cnt = 0;
+  double o[3] = {0.0, 0.0, 0.0};
+  for (int a = -m; a <= m; ++a)
+    for (int b = -m; b <= m; ++b)
+      for (int c = (dim == 3 ? -m : 0); c <= (dim == 3 ? m : 0); ++c) {
+        if (a == 0 && b == 0 && c == 0) continue;
+        double x[3] = {a * l0, b * l0, c * l0};
+        double d2 = dist2(o, x, dim);
+        if (!(d2 < re * re)) continue;
+        double w = weight(kernel, std::sqrt(d2), re);
+        sw += w;
+        sr2w += d2 * w;
+        ++cnt;
+      }
+  *n0 = sw;
+  *lambda = sr2w / sw;
+  if (count) *count = cnt;
+  return 0;
+}
+
+int orc_neighbors_brute(const orc_params* P, int64_t n, const double* pos,
+                        const int8_t* type, int32_t* count, int32_t* list) {
+  Lists L;
+  int st = build_lists_brute(P, (int)n, pos, type, L);
+  export_lists(L, (int)n, P->max_neigh, count, list);
+  return st;
+}
+
+int orc_neighbors_cells(const orc_params* P, int64_t n, const double* pos,
+                        const int8_t* type, int32_t* cell, int32_t* count,
+                        int32_t* list) {
+  Lists L;
+  std::vector<int> c;
+  std::vector<int8_t> t(type, type + n);
+  for (int64_t i = 0; i < n; ++i) {
+    int cc;
+    if (t[i] != GHOST && !grid_cell(P, pos + i * P->dim, &cc)) t[i] = GHOST;
+  }
+  int st = build_lists_cells(P, (int)n, pos, t.data(), L, c);
+  export_lists(L, (int)n, P->max_neigh, count, list);
+  if (cell) for (int64_t i = 0; i < n; ++i) cell[i] = c[i];
+  return st;
+}
+
+int orc_step(const orc_params* P, int64_t n, const double* pos, const double* vel,
+             const int8_t* type, const int8_t* flags_override, orc_step_out* out) {
+  Consts C = constants(P);
+  const int dim = P->dim;
+  std::vector<double> x(pos, pos + n * dim), u(vel, vel + n * dim);
+  std::vector<int8_t> t(type, type + n);
+  double nu, g[3];
+  to_params(P, &nu, g);
+  Trace<double> tr;
+  int st = step<double>(P, C, nu, g, (int)n, x, u, t, flags_override, tr);
+  if (st == -3 || st == -6) return st;
+  auto cp = [&](double* dst, const std::vector<double>& src) {
+    if (dst && !src.empty()) std::memcpy(dst, src.data(), src.size() * sizeof(double));
+  };
+  if (out->cell) for (int64_t i = 0; i < n; ++i) out->cell[i] = tr.cell[i];
+  export_lists(tr.lists, (int)n, P->max_neigh, out->count, out->list);
+  cp(out->us, tr.us); cp(out->rs, tr.rs); cp(out->nstar, tr.nstar);
+  if (out->flags) std::memcpy(out->flags, tr.flags.data(), n);
+  cp(out->diag, tr.diag); cp(out->b, tr.b);
+  if (out->aval) {
+    for (int64_t i = 0; i < n; ++i) {
+      int s = tr.lists.start[i], c = tr.lists.start[i + 1] - s;
+      for (int l = 0; l < P->max_neigh; ++l)
+        out->aval[i * P->max_neigh + l] = l < c ? tr.aval[s + l] : 0.0;
+    }
+  }
+  cp(out->p, tr.p); cp(out->phat, tr.phat); cp(out->gradp, tr.gradp);
+  cp(out->pos, x); cp(out->vel, u);
+  if (out->type) std::memcpy(out->type, t.data(), n);
+  out->cg_iters = tr.cg_iters;
+  out->cg_relres = tr.cg_relres;
+  return st;
+}
+
+int orc_pressure_gradient(const orc_params* P, int64_t n, const double* rs,
+                          const int8_t* type, const double* p, double* phat,
+                          double* gradp) {
+  /* Lists are taken at the given positions (here r*), as the step does. */
+  Consts C = constants(P);
+  Lists L;
+  std::vector<int> cell;
+  std::vector<int8_t> t(type, type + n);
+  int st = build_lists_cells(P, (int)n, rs, t.data(), L, cell);
+  if (st) return st;
+  std::vector<double> r(rs, rs + n * P->dim), pp(p, p + n), ph, gp;
+  pressure_gradient<double>(P, C, (int)n, r, t, pp, L, ph, gp);
+  std::memcpy(phat, ph.data(), n * sizeof(double));
+  std::memcpy(gradp, gp.data(), n * P->dim * sizeof(double));
+  return 0;
+}
+
+int orc_run(const orc_params* P, int64_t n, double* pos, double* vel, int8_t* type,
+            int32_t nsteps, double* p_out, int8_t* flags_out) {
+  Consts C = constants(P);
+  const int dim = P->dim;
+  std::vector<double> x(pos, pos + n * dim), u(vel, vel + n * dim);
+  std::vector<int8_t> t(type, type + n);
+  double nu, g[3];
+  to_params(P, &nu, g);
+  int st = 0;
+  Trace<double> tr;
+  for (int s = 0; s < nsteps; ++s) {
+    st = step<double>(P, C, nu, g, (int)n, x, u, t, nullptr, tr);
+    if (st == -3 || st == -6) break;
+  }
+  std::memcpy(pos, x.data(), x.size() * sizeof(double));
+  std::memcpy(vel, u.data(), u.size() * sizeof(double));
+  std::memcpy(type, t.data(), n);
+  if (p_out && !tr.p.empty()) std::memcpy(p_out, tr.p.data(), n * sizeof(double));
+  if (flags_out && !tr.flags.empty()) std::memcpy(flags_out, tr.flags.data(), n);
+  return st;
+}
+
+}  // extern "C"
