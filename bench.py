@@ -1,0 +1,256 @@
+#!/usr/bin/env python3
+"""Throughput of the MPS hot path on one MI355X, in particle-steps/s.
+
+Workload (headline): 2-D dam break, water column 0.2 x 0.3 m in a 0.8 x 0.6
+m tank at l0 = 1.25 mm: 38,400 fluid + 3,208 wall + 3,224 dummy = 44,832
+particles, dt = 1e-4 s, pressure by the PPE solved with CG (tolerance
+1e-9), mixed precision (FP32 neighbour sums and matrix values on
+cell-relative FP32 positions, FP64 diagonal, CG vectors, dot products and
+pressure).  One step = neighbour search + viscous prediction + number
+density/flags + PPE assembly + CG + gradient/update, everything on the GPU.
+
+Beside it, in the same run: the plain FP64 GPU path, the weakly
+compressible (equation of state) model in both precisions, the per-kernel
+time breakdown from HIP events, the roofline of the dominant kernel, and
+the FP64 CPU oracle timed on the host cores on a bounded sample.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "particle-steps/s (neighbours+PPE CG), FP32/FP64-CG vs FP64 plain; %HBM peak"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(cls: str, n: int, list_entries: int, nnz: int, dim: int,
+                      mixed: bool, wc: bool) -> float:
+    """HBM bytes one launch of a kernel class must move: each particle's own
+    state once, its list entries (4 B) and matrix row (column 4 B + value
+    4/8 B).  Gathers of neighbour data are cache hits after the cell sort
+    and are not counted."""
+    vec = 8 * (2 if dim == 2 else 4)       # stored FP64 vector
+    f4 = 16 if mixed else 0                # FP32 relative position copy
+    val = 4 if mixed else 8
+    if cls == "cg_spmv":
+        return n * (4 + 5 * 8) + nnz * (4 + val)
+    if cls == "cg_update":
+        return n * 8 * 8
+    if cls == "neighbors":
+        return n * (vec + 4 + 4) + list_entries * 4
+    if cls == "predict":
+        return n * (4 + 1 + 4 + 2 * vec + f4 + 2 * vec + f4) + list_entries * 4
+    if cls == "density":
+        return n * (4 + 1 + (f4 or vec) + 8 + 1 + (8 if wc else 0)) + list_entries * 4
+    if cls == "assemble":
+        return n * (4 + 1 + 1 + (f4 or vec) + 8 + 8 + 4 + 8 * 6) + list_entries * 4 + nnz * (4 + val)
+    if cls == "gradient":
+        return n * (4 + 1 + (f4 or vec) + 8 + 2 * vec + 2 * vec) + list_entries * 4
+    if cls == "sort":
+        return n * (2 * (2 * vec + 1 + 4 + 8) + 4 * 4 + 4 + f4)
+    raise KeyError(cls)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha1()
+    d = os.path.join(ROOT, "paper_2105_01677_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h")):
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:12]
+
+
+def read_traffic(kernel: str, workload: str):
+    """HBM traffic per launch from the committed rocprofv3 PMC summary, when
+    it was taken on the current kernel sources; None otherwise."""
+    path = os.path.join(ROOT, "profiles", "traffic.txt")
+    if not os.path.exists(path):
+        return None
+    src = kernel_source_hash()
+    for line in open(path):
+        parts = line.split()
+        if len(parts) >= 4 and not line.startswith("#") and parts[0] == kernel \
+                and parts[1] == workload and parts[2] == src:
+            return float(parts[3])
+    return None
+
+
+def run_gpu(w, steps, warmup, *, profile_all=False, profile_cls=None):
+    import torch
+
+    from paper_2105_01677_amd import mps
+    m = mps.MPS(w.params, w.pos, w.vel, w.ptype)
+    if warmup:
+        m.step(warmup)
+    if profile_all:
+        m.profile(mps.KERNEL_CLASSES)
+    elif profile_cls:
+        m.profile([profile_cls])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s = m.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = m.profile_read() if (profile_all or profile_cls) else None
+    m.close()
+    dt = t1 - t0
+    return {"seconds": dt, "ms_per_step": 1e3 * dt / steps,
+            "particle_steps_per_s": w.n * steps / dt, "stats": s, "profile": prof}
+
+
+def cpu_baseline(w, seconds):
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    os.environ.setdefault("OMP_NUM_THREADS", str(threads))
+    import numpy as np
+    pos, vel, t = w.pos.copy(), w.vel.copy(), w.ptype.copy()
+    # one step first (also loads the library), then as many as fit the budget
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        st, pos, vel, t, p, fl = oracle.run(w.params, pos, vel, t, 1)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or steps >= 400:
+            break
+    assert np.isfinite(pos).all()
+    return {"value": w.n * steps / el, "unit": "particle-steps/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"first {steps} steps of the same workload from rest "
+                      f"({el:.1f} s on {threads} host threads, FP64 C++ oracle, "
+                      f"cell-linked-list neighbours, Jacobi-CG to 1e-13)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--only-headline", action="store_true",
+                    help="time the headline configuration only (for profilers)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first copy a 64 MiB buffer once (reference kernel for HBM counters)")
+    ap.add_argument("--only", default=None,
+                    help="time one configuration only, e.g. ppe:mixed, wc:fp64 (for profilers)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        msg = ("this build runs on one GPU only: the MPS path is measured on a single "
+               "MI355X (multi-GPU domain decomposition is a design note, not built)")
+        print(msg, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2105_01677_amd import workloads as W
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(1)
+    K, Wm = args.steps, args.warmup
+    if args.calib_copy:
+        # a plain device copy of known size: reads and writes 64 MiB
+        a = torch.ones(16 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    if args.only:
+        pm, pr = args.only.split(":")
+        wo = W.config("cfg2", pmode=W.PPE_CG if pm == "ppe" else W.WC_EOS,
+                      precision=W.MIXED if pr == "mixed" else W.FP64)
+        r = run_gpu(wo, K, Wm)
+        print(json.dumps({"only": args.only, "value": r["particle_steps_per_s"],
+                          "ms_per_step": r["ms_per_step"], "steps": K}), flush=True)
+        return
+
+    w = W.config("cfg2", precision=W.MIXED, pmode=W.PPE_CG)
+    c = w.counts()
+    workload = "dam_break_2d_l0=0.00125"
+    log(f"workload {workload}: {c}")
+
+    # headline: K timed steps, no instrumentation (the step stages run as
+    # HIP graphs)
+    hd = run_gpu(w, K, Wm)
+    s = hd["stats"]
+
+    # the same K steps again with every kernel launch bracketed by HIP events
+    # on the library's stream (direct launches): per-kernel breakdown and the
+    # average duration of the dominant kernel for the roofline
+    if args.only_headline:
+        print(json.dumps({"metric": METRIC, "value": hd["particle_steps_per_s"],
+                          "ms_per_step": hd["ms_per_step"], "steps": K}), flush=True)
+        return
+    br = run_gpu(w, K, Wm, profile_all=True)
+    tot = {k: v[0] for k, v in br["profile"].items()}
+    dom = max(tot, key=tot.get)
+    log("breakdown ms:", {k: round(v, 3) for k, v in tot.items()}, "dominant:", dom)
+    ms_dom, n_dom = br["profile"][dom]
+    avg_ms = ms_dom / max(n_dom, 1)
+    nbytes = algorithmic_bytes(dom, w.n, s["list_entries"], s["ppe_nnz"], 2, True, False)
+    achieved = nbytes / (avg_ms * 1e-3) / 1e9
+    log(f"headline {hd['particle_steps_per_s']:.4g} particle-steps/s, "
+        f"{hd['ms_per_step']:.4f} ms/step, cg iters last {s['cg_iters_last']}")
+
+    extra = {}
+    if not args.only_headline:
+        for name, prec, pm in (("ppe_fp64", W.FP64, W.PPE_CG), ("wc_mixed", W.MIXED, W.WC_EOS),
+                               ("wc_fp64", W.FP64, W.WC_EOS)):
+            wx = W.config("cfg2", precision=prec, pmode=pm)
+            r = run_gpu(wx, K, Wm)
+            extra[name] = {"value": r["particle_steps_per_s"], "ms_per_step": r["ms_per_step"],
+                           "cg_iters_mean": r["stats"]["cg_iters_total"] / K}
+            log(name, extra[name])
+
+    out = {
+        "metric": METRIC,
+        "value": hd["particle_steps_per_s"],
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": Wm,
+        "ms_per_step": hd["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": workload, "n_particles": w.n, "n_fluid": c["fluid"],
+                   "pressure": "PPE-CG tol 1e-9", "precision": "mixed FP32 sums / FP64 CG",
+                   "dt": w.params["dt"], "dim": 2},
+        "fluid_particle_steps_per_s": c["fluid"] * K / hd["seconds"],
+        "cg_iters_mean": s["cg_iters_total"] / K,
+        "fp64_plain": extra.get("ppe_fp64"),
+        "wc_eos_mixed": extra.get("wc_mixed"),
+        "wc_eos_fp64": extra.get("wc_fp64"),
+        "kernel_ms_per_step": {k: v / K for k, v in tot.items()},
+        "kernel_avg_launch_us": {k: 1e3 * v[0] / max(v[1], 1) for k, v in br["profile"].items()},
+        "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": read_traffic(dom, workload),
+                     "bytes_per_launch": nbytes, "avg_launch_ms": avg_ms,
+                     "launches": n_dom},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu and not args.only_headline:
+        log("cpu baseline ...")
+        out["cpu_baseline"] = cpu_baseline(W.config("cfg2", precision=W.FP64), args.cpu_seconds)
+        log(out["cpu_baseline"])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,204 @@
+/*
+ * mps.h -- C ABI of the MI355X (gfx950) implementation of the data-parallel
+ * hot path of the Moving Particle Semi-implicit (MPS) method, arXiv
+ * 2105.01677, Section "The Moving Particle Semi-implicit Method".
+ *
+ * One time step (mps_step) is:
+ *   1. cell-linked-list neighbour search (Section "Neighbouring search
+ *      algorithms": cells with sides equal to the interaction radius, the
+ *      list constant for the whole step; neighbour cap 300, Section "CUDA");
+ *   2. explicit prediction with the viscous Laplacian (Eq. 7) and gravity;
+ *   3. particle number density (Eq. 5) and free-surface flags (Eq. 15);
+ *   4. pressure: the PPE (Eq. 13) assembled as a sparse symmetric matrix in
+ *      the row-wise manner of the listing "PPE assemble GPU code" and solved
+ *      by preconditioned conjugate gradients, or the equation of state
+ *      (Eq. 16) of the weakly-compressible model;
+ *   5. pressure gradient (standard MPS, or Eq. 18) and first-order Euler
+ *      update.
+ *
+ * Conventions for every entry point:
+ *  - Array arguments are DEVICE pointers (HIP), contiguous, in the caller's
+ *    original particle order; vectors are row-major [n][dim] FP64.  The
+ *    caller owns them; the library keeps no alias after the call returns.
+ *  - Work is enqueued on the stream given to mps_init.  Calls that return
+ *    host scalars (iteration counts, residuals, statistics) or a status
+ *    detected on the device synchronise that stream before returning.
+ *  - The library owns all its scratch memory, allocated once in mps_init;
+ *    mps_step and mps_pressure_solve never allocate.
+ *  - Every function returns an mps_status and never aborts or prints.
+ *    Argument errors leave the context untouched.  A numerical error
+ *    (NEIGH_OVERFLOW, COINCIDENT, NONFINITE) marks the context poisoned:
+ *    further steps return MPS_E_POISONED until mps_set_state.
+ *    mps_last_error gives a text description of the last error.
+ *  - One context per stream; contexts are independent of each other.
+ */
+#ifndef MPS_H
+#define MPS_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mps_ctx mps_ctx; /* opaque, owned by the library */
+
+typedef enum {
+  MPS_OK = 0,
+  MPS_E_ARG = -1,            /* invalid argument or parameter */
+  MPS_E_NOMEM = -2,          /* device allocation failed */
+  MPS_E_NEIGH_OVERFLOW = -3, /* a particle has more than max_neigh neighbours */
+  MPS_E_CG_NOCONV = -4,      /* CG reached cg_maxit; last iterate kept */
+  MPS_E_NONFINITE = -5,      /* NaN or Inf in positions or velocities */
+  MPS_E_COINCIDENT = -6,     /* two particles at distance 0 (Eq. 4 diverges) */
+  MPS_E_DEVICE = -7,         /* HIP runtime error */
+  MPS_E_POISONED = -8        /* an earlier numerical error; call mps_set_state */
+} mps_status;
+
+/* Particle types (int8 per particle).  Wall particles are pressure unknowns
+ * like fluid; dummy particles only complete the number density and the
+ * viscous sums near walls (listing "PPE assemble GPU code": bcon == -1).
+ * A particle that leaves the background grid becomes a GHOST and takes no
+ * further part; the library sets this type itself. */
+enum { MPS_FLUID = 0, MPS_WALL = 1, MPS_DUMMY = 2, MPS_GHOST = 3 };
+/* Per-particle flags of the last step (int8). */
+enum { MPS_FLAG_GHOST = -2, MPS_FLAG_DUMMY = -1, MPS_FLAG_INNER = 0, MPS_FLAG_SURFACE = 1 };
+enum { MPS_PPE_CG = 0, MPS_WC_EOS = 1 };         /* pressure model */
+enum { MPS_K_KOSHIZUKA = 0, MPS_K_CUBIC = 1 };   /* Eq. 4 / cubic kernel */
+enum { MPS_FP64 = 0, MPS_MIXED = 1 };            /* precision of the path */
+enum { MPS_GRAD_STD = 0, MPS_GRAD_CMPS = 1 };    /* standard / Eq. 18 */
+
+typedef struct {
+  int32_t dim;              /* 2 or 3 */
+  int32_t pmode;            /* MPS_PPE_CG or MPS_WC_EOS */
+  int32_t kernel;           /* MPS_K_KOSHIZUKA or MPS_K_CUBIC */
+  int32_t precision;        /* MPS_FP64, or MPS_MIXED: FP32 neighbour sums and
+                               matrix values on cell-relative FP32 positions,
+                               FP64 diagonal, right-hand side, CG vectors,
+                               dot products and pressure */
+  int32_t grad;             /* MPS_GRAD_STD or MPS_GRAD_CMPS */
+  int32_t clamp_negative_p; /* 1: p <- max(p, 0) after the pressure step */
+  int32_t max_neigh;        /* neighbour cap, 1..1024 (the paper uses 300) */
+  int32_t cg_maxit;         /* CG iteration limit */
+  int32_t grid_n[3];        /* background grid cells per axis (1 for unused) */
+  int32_t pad_;
+  double l0;                /* initial particle spacing (m) */
+  double re_n;              /* radius for number density, flags, gradient (m) */
+  double re_lap;            /* radius for the Laplacian (viscous, PPE) (m) */
+  double rho;               /* density (kg/m^3) */
+  double nu;                /* kinematic viscosity (m^2/s) */
+  double g[3];              /* body acceleration (m/s^2) */
+  double dt;                /* time step (s) */
+  double beta;              /* free-surface threshold (Eq. 15), 0.97 */
+  double c0;                /* speed of sound of the equation of state (m/s) */
+  double gamma;             /* exponent of Eq. 16, a positive integer (7) */
+  double alpha;             /* artificial compressibility on the PPE diagonal,
+                               alpha/dt^2 (1e-7) */
+  double cg_tol;            /* stop when ||b - A p|| <= cg_tol ||b|| */
+  double grid_lo[3];        /* lower corner of the background grid (m) */
+  double cell_size;         /* cell side, >= re_lap (m) */
+  double smagorinsky_cs;    /* reserved, must be 0 */
+} mps_params;
+
+typedef struct {
+  int32_t steps;           /* steps taken by the call */
+  int32_t cg_iters_last;   /* CG iterations of the last step (PPE mode) */
+  int64_t cg_iters_total;  /* CG iterations summed over the call */
+  double cg_relres_last;   /* ||b - A p|| / ||b|| of the last step */
+  int64_t n_surface;       /* free-surface particles after the last step */
+  int64_t n_ghost;         /* ghost particles */
+  int64_t list_entries;    /* neighbour-list entries of the last step */
+  int64_t ppe_nnz;         /* off-diagonal matrix entries of the last step */
+} mps_step_stats;
+
+/* Kernel classes for mps_profile: cell binning + sort + permutation (a1),
+ * neighbour lists (a2), viscous prediction (a3), number density / flags /
+ * equation of state (a4), PPE assembly (a5), the two CG kernels (a6) and
+ * the pressure gradient + update (a8). */
+enum {
+  MPS_KC_SORT = 0, MPS_KC_NEIGH, MPS_KC_PREDICT, MPS_KC_DENSITY, MPS_KC_ASSEMBLE,
+  MPS_KC_CG_SPMV, MPS_KC_CG_UPDATE, MPS_KC_GRADIENT, MPS_KC_COUNT
+};
+
+/* Create a context for n particles.  pos, vel: [n][dim] FP64; type: [n]
+ * int8 (MPS_FLUID, MPS_WALL or MPS_DUMMY).  rho_i and nu_i are reserved and
+ * must be NULL.  hip_stream is a hipStream_t (NULL = default stream).
+ * Errors: MPS_E_ARG (bad parameters: dim, radii, grid, cap, n < 1, gamma
+ * not integer), MPS_E_NOMEM, MPS_E_DEVICE. */
+mps_status mps_init(const mps_params* params, int64_t n, const double* pos,
+                    const double* vel, const int8_t* type, const double* rho_i,
+                    const double* nu_i, void* hip_stream, mps_ctx** out);
+
+/* Release every resource of the context (NULL is allowed). */
+mps_status mps_free(mps_ctx* ctx);
+
+/* Text of the last error of the context (static storage; never NULL). */
+const char* mps_last_error(const mps_ctx* ctx);
+
+/* Build the neighbour lists at the current positions (step 1) and export
+ * them in original order.  cell_id: [n] linear cell index
+ * (x fastest, -1 for ghosts) or NULL; count: [n]; list: [n][max_neigh]
+ * ascending original ids, padded with -1.  The set is exactly
+ * { j != i : d2 < re_lap^2 } with d2 = (dx*dx + dy*dy) + dz*dz rounded term
+ * by term in FP64 (dx = x_j - x_i), over particles that are not ghosts.
+ * Errors: MPS_E_NEIGH_OVERFLOW, MPS_E_COINCIDENT, MPS_E_POISONED. */
+mps_status mps_neighbors(mps_ctx* ctx, int32_t* cell_id, int32_t* count,
+                         int32_t* list);
+
+/* Advance nsteps time steps (steps 1-5 above).  stats may be NULL.
+ * Errors: MPS_E_NEIGH_OVERFLOW, MPS_E_COINCIDENT, MPS_E_NONFINITE,
+ * MPS_E_CG_NOCONV (the step still completes with the last iterate),
+ * MPS_E_POISONED. */
+mps_status mps_step(mps_ctx* ctx, int32_t nsteps, mps_step_stats* stats);
+
+/* Run steps 1-3 and the PPE assembly (Eq. 13, listing "PPE assemble GPU
+ * code") at the current state without advancing it, then solve A p = rhs
+ * by CG from p = 0.  rhs: [n] in original order, or NULL for the PPE source
+ * b_i = (n*_i - n0)/(n0 dt^2); entries of rows that are not pressure
+ * unknowns (free surface, dummy, ghost) are ignored and their p is 0.
+ * p: [n] output (device), the unclamped solution.  iters, relres: host
+ * pointers or NULL.  The state is unchanged.  Errors as mps_step. */
+mps_status mps_pressure_solve(mps_ctx* ctx, const double* rhs, double* p,
+                              int32_t* iters, double* relres);
+
+/* Export the system assembled by the last mps_step (PPE mode) or
+ * mps_pressure_solve, in original order: diag [n], b [n], nnz [n]
+ * off-diagonal entries per row, cols/vals [n][max_neigh] (original column
+ * ids and FP64 values, row order unspecified).  Any pointer may be NULL.
+ * Errors: MPS_E_ARG if no system has been assembled. */
+mps_status mps_get_ppe(mps_ctx* ctx, double* diag, double* b, int32_t* nnz,
+                       int32_t* cols, double* vals);
+
+/* Export the state in original order; any pointer may be NULL.
+ * pos, vel: [n][dim]; p: [n] pressure of the last step; n_star: [n] number
+ * density of the last step (at the predicted positions); flags: [n]
+ * (MPS_FLAG_*); type: [n]. */
+mps_status mps_get_state(mps_ctx* ctx, double* pos, double* vel, double* p,
+                         double* n_star, int8_t* flags, int8_t* type);
+
+/* Replace positions and velocities (original order, [n][dim]); types are
+ * kept unless type is non-NULL.  Clears a poisoned context. */
+mps_status mps_set_state(mps_ctx* ctx, const double* pos, const double* vel,
+                         const int8_t* type);
+
+/* The lattice constants the context uses: n0 for re_n and re_lap, lambda
+ * for re_lap (Eq. 5 and the weighted mean of r^2 of Eq. 7 at an interior
+ * particle of the initial lattice).  Host pointers, any may be NULL. */
+mps_status mps_constants(const mps_ctx* ctx, double* n0_n, double* n0_lap,
+                         double* lambda_lap);
+
+/* Per-kernel timing: when bit k of class_mask is set, every launch of
+ * kernel class k (MPS_KC_*) is bracketed by a pair of HIP events on the
+ * context's stream and its duration accumulated.  A profiling aid for
+ * roofline measurements; a mask of 0 switches it off.  Resets the totals.
+ * Errors: MPS_E_DEVICE if events cannot be created. */
+mps_status mps_profile(mps_ctx* ctx, uint32_t class_mask);
+
+/* Accumulated milliseconds and launch counts per kernel class since the
+ * last mps_profile call (host arrays of MPS_KC_COUNT entries, or NULL).
+ * Synchronises the stream. */
+mps_status mps_profile_read(mps_ctx* ctx, double* ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MPS_H */

@@ -1,0 +1,850 @@
+// C ABI (include/mps.h) and the step pipeline of the MPS library.
+//
+// The context keeps the particle state in cell-sorted order on the device
+// (double-buffered so the per-step re-sort is a gather) and all per-step
+// work arrays, allocated once.  One step enqueues, on the context's stream:
+//   bin -> scan -> scatter -> in-cell order -> permute        (a1)
+//   neighbour lists                                         (a2)
+//   viscous prediction                                      (a3)
+//   number density, flags (+ equation of state)             (a4, a7)
+//   PPE assembly + CG iterations + clamp   [PPE model]      (a5, a6)
+//   pressure gradient + Euler update                        (a8)
+// The only host synchronisations are the CG convergence polls (batches of
+// iterations, sized from the previous step's count) and one status read at
+// the end of each call.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "mps_internal.h"
+
+using namespace mps;
+
+struct mps_ctx {
+  mps_params P;
+  int64_t n = 0;
+  int dim = 2;
+  int ps = 2;          // doubles per stored vector
+  int kpad = 0;
+  int64_t slots = 0;
+  int ncell = 0;
+  hipStream_t s = nullptr;
+  double n0_n = 0, n0_lap = 0, lam_lap = 0;
+  int cur = 0;
+  // state, double-buffered
+  double* pos[2] = {nullptr, nullptr};
+  double* vel[2] = {nullptr, nullptr};
+  double* pres[2] = {nullptr, nullptr};
+  int8_t* type[2] = {nullptr, nullptr};
+  int32_t* id[2] = {nullptr, nullptr};
+  // per-step
+  int32_t* pcell = nullptr;
+  float4* posf = nullptr;
+  float4* rsf = nullptr;
+  double* us = nullptr;
+  double* rs = nullptr;
+  double* nstar = nullptr;
+  int8_t* flags = nullptr;
+  int32_t *cellid = nullptr, *slot = nullptr, *cell_count = nullptr, *cell_start = nullptr,
+          *perm = nullptr, *tile_sum = nullptr;
+  int32_t *nb_count = nullptr, *nb_list = nullptr;
+  int32_t *a_nnz = nullptr, *a_col = nullptr;
+  void* a_val = nullptr;
+  double *diag = nullptr, *b = nullptr;
+  double *r = nullptr, *z = nullptr, *pd[2] = {nullptr, nullptr}, *q = nullptr;
+  double* p_save = nullptr;
+  double* partA = nullptr;
+  double* partB = nullptr;
+  int nspmv = 0, nupd = 0;
+  CGScalars* sc = nullptr;
+  int32_t* status = nullptr;
+  int64_t* counts = nullptr;   // [4]: surface, ghost, list entries, matrix nnz
+  // pinned host mirrors
+  CGScalars* h_sc = nullptr;
+  int32_t* h_status = nullptr;
+  int64_t* h_counts = nullptr;
+  // profiling: event pairs around launches of the selected kernel classes
+  static constexpr int kPool = 2048;
+  uint32_t prof_mask = 0;
+  hipEvent_t ev_a[kPool] = {};
+  hipEvent_t ev_b[kPool] = {};
+  int ev_cls[kPool] = {};
+  int nev = 0;
+  bool ev_created = false;
+  double prof_ms[MPS_KC_COUNT] = {};
+  int64_t prof_n[MPS_KC_COUNT] = {};
+  // HIP graphs of the step stages, one per parity of the double-buffered
+  // state (pre: a1-a5 or a1-a4+a7; cg: CG_BATCH iterations; post: clamp +
+  // a8; wc2: two whole weakly-compressible steps)
+  static constexpr int CG_BATCH = 4;   // smallest CG graph; also 4x and 16x
+  bool graphs_built = false;
+  hipGraphExec_t g_pre[2] = {}, g_cg[2][3] = {}, g_post[2] = {}, g_wc2[2] = {};
+  // bookkeeping
+  bool poisoned = false;
+  bool ppe_valid = false;
+  int last_iters = 0;
+  char err[256] = {0};
+};
+
+namespace {
+
+const char* kNoCtx = "no context";
+
+mps_status fail(mps_ctx* c, mps_status st, const char* msg) {
+  if (c) std::snprintf(c->err, sizeof(c->err), "%s", msg);
+  return st;
+}
+
+mps_status hip_fail(mps_ctx* c, hipError_t e, const char* where) {
+  if (c) std::snprintf(c->err, sizeof(c->err), "%s: %s", where, hipGetErrorString(e));
+  return MPS_E_DEVICE;
+}
+
+#define HIPCHK(c, expr)                                 \
+  do {                                                  \
+    hipError_t e_ = (expr);                             \
+    if (e_ != hipSuccess) return hip_fail(c, e_, #expr); \
+  } while (0)
+
+// Lattice constants of an interior particle of the square/cubic lattice of
+// spacing l0: n0 = sum w (Eq. 5) and lambda = sum r^2 w / sum w (the weighted
+// mean of r^2 of Eq. 7).
+void lattice(int dim, double l0, double re, int kernel, double* n0, double* lam) {
+  const int m = (int)std::ceil(re / l0) + 1;
+  double sw = 0.0, s2 = 0.0;
+  const int kz = dim == 3 ? m : 0;
+  for (int k = -kz; k <= kz; ++k)
+    for (int jy = -m; jy <= m; ++jy)
+      for (int ix = -m; ix <= m; ++ix) {
+        if (ix == 0 && jy == 0 && k == 0) continue;
+        const double x = ix * l0, y = jy * l0, z = k * l0;
+        double r2 = x * x + y * y;
+        if (dim == 3) r2 = r2 + z * z;
+        if (!(r2 < re * re)) continue;
+        const double r = std::sqrt(r2);
+        const double w = kernel == MPS_K_KOSHIZUKA ? re / r - 1.0
+                                                   : (1.0 - r / re) * (1.0 - r / re) * (1.0 - r / re);
+        sw += w;
+        s2 += r2 * w;
+      }
+  *n0 = sw;
+  *lam = s2 / sw;
+}
+
+template <class T>
+hipError_t dalloc(T** p, size_t count) {
+  return hipMalloc((void**)p, count * sizeof(T) + 256);
+}
+
+View make_view(const mps_ctx* c) {
+  View v;
+  std::memset(&v, 0, sizeof(v));
+  const mps_params& P = c->P;
+  v.n = c->n;
+  v.kpad = c->kpad;
+  v.max_neigh = P.max_neigh;
+  v.nx = P.grid_n[0];
+  v.ny = P.grid_n[1];
+  v.nz = c->dim == 3 ? P.grid_n[2] : 1;
+  v.ncell = c->ncell;
+  for (int a = 0; a < 3; ++a) {
+    v.lo[a] = a < c->dim ? P.grid_lo[a] : 0.0;
+    v.g[a] = a < c->dim ? P.g[a] : 0.0;
+  }
+  v.cs = P.cell_size;
+  v.inv_cs = 1.0 / P.cell_size;
+  v.cs32 = (float)P.cell_size;
+  v.re_n = P.re_n;
+  v.re_lap = P.re_lap;
+  v.re_n2 = P.re_n * P.re_n;
+  v.re_lap2 = P.re_lap * P.re_lap;
+  v.re_n_f = (float)P.re_n;
+  v.re_lap_f = (float)P.re_lap;
+  v.n0_n = c->n0_n;
+  v.n0_lap = c->n0_lap;
+  v.lam_lap = c->lam_lap;
+  v.nu = P.nu;
+  v.rho = P.rho;
+  v.dt = P.dt;
+  v.beta = P.beta;
+  v.c0 = P.c0;
+  v.alpha = P.alpha;
+  v.cg_tol2 = P.cg_tol * P.cg_tol;
+  v.gamma_i = (int)P.gamma;
+  v.kernel = P.kernel;
+  v.grad = P.grad;
+  v.clamp = P.clamp_negative_p;
+  const int a = c->cur, o = c->cur ^ 1;
+  v.pos = c->pos[a];
+  v.pos_w = c->pos[o];
+  v.vel = c->vel[a];
+  v.vel_w = c->vel[o];
+  v.type = c->type[a];
+  v.type_w = c->type[o];
+  v.id = c->id[a];
+  v.id_w = c->id[o];
+  v.p_in = c->pres[a];
+  v.p_w = c->pres[o];
+  v.pcell = c->pcell;
+  v.posf = c->posf;
+  v.rsf = c->rsf;
+  v.us = c->us;
+  v.rs = c->rs;
+  v.nstar = c->nstar;
+  v.flags = c->flags;
+  v.cellid = c->cellid;
+  v.slot = c->slot;
+  v.cell_count = c->cell_count;
+  v.cell_start = c->cell_start;
+  v.tile_sum = c->tile_sum;
+  v.perm = c->perm;
+  v.nb_count = c->nb_count;
+  v.nb_list = c->nb_list;
+  v.a_nnz = c->a_nnz;
+  v.a_col = c->a_col;
+  v.a_val = c->a_val;
+  v.diag = c->diag;
+  v.b = c->b;
+  v.p = c->pres[a];
+  v.r = c->r;
+  v.z = c->z;
+  v.pd[0] = c->pd[0];
+  v.pd[1] = c->pd[1];
+  v.q = c->q;
+  v.partA = c->partA;
+  v.partB = c->partB;
+  v.nspmv = c->nspmv;
+  v.nupd = c->nupd;
+  v.sc = c->sc;
+  v.status = c->status;
+  return v;
+}
+
+// In-place variant: the gradient kernel writes the current buffers.
+View make_view_inplace(const mps_ctx* c) {
+  View v = make_view(c);
+  v.pos_w = c->pos[c->cur];
+  v.vel_w = c->vel[c->cur];
+  return v;
+}
+
+mps_status check_params(const mps_params* P, int64_t n) {
+  if (!P || n < 1 || n > (int64_t)INT32_MAX / 2) return MPS_E_ARG;
+  if (P->dim != 2 && P->dim != 3) return MPS_E_ARG;
+  if (!(P->l0 > 0) || !(P->re_n > 0) || !(P->re_lap > 0)) return MPS_E_ARG;
+  if (!(P->cell_size >= P->re_lap) || !(P->cell_size >= P->re_n)) return MPS_E_ARG;
+  if (!(P->dt > 0) || !(P->rho > 0) || !(P->nu >= 0)) return MPS_E_ARG;
+  if (P->max_neigh < 1 || P->max_neigh > 1024) return MPS_E_ARG;
+  if (P->pmode != MPS_PPE_CG && P->pmode != MPS_WC_EOS) return MPS_E_ARG;
+  if (P->kernel != MPS_K_KOSHIZUKA && P->kernel != MPS_K_CUBIC) return MPS_E_ARG;
+  if (P->precision != MPS_FP64 && P->precision != MPS_MIXED) return MPS_E_ARG;
+  if (P->grad != MPS_GRAD_STD && P->grad != MPS_GRAD_CMPS) return MPS_E_ARG;
+  if (P->gamma < 1 || P->gamma > 16 || P->gamma != std::floor(P->gamma)) return MPS_E_ARG;
+  if (P->cg_maxit < 1 || !(P->cg_tol > 0)) return MPS_E_ARG;
+  if (P->smagorinsky_cs != 0.0) return MPS_E_ARG;
+  int64_t nc = 1;
+  for (int a = 0; a < P->dim; ++a) {
+    if (P->grid_n[a] < 1 || P->grid_n[a] > 1023) return MPS_E_ARG;
+    nc *= P->grid_n[a];
+  }
+  if (nc > (int64_t)1 << 28) return MPS_E_ARG;
+  return MPS_OK;
+}
+
+// Element type scatter/gather for int8 state.
+__global__ void k_i8_to_orig(int64_t n, const int32_t* id, const int8_t* src, int8_t* dst) {
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k < n) dst[id[k]] = src[k];
+}
+__global__ void k_i8_from_orig(int64_t n, const int32_t* id, const int8_t* src, int8_t* dst) {
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k < n) dst[k] = src[id[k]];
+}
+__global__ void k_iota(int64_t n, int32_t* id) {
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k < n) id[k] = (int32_t)k;
+}
+// Input types are FLUID/WALL/DUMMY; anything else is rejected by a status bit.
+__global__ void k_check_types(int64_t n, const int8_t* t, int32_t* status) {
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k < n && (t[k] < MPS_FLUID || t[k] > MPS_GHOST)) atomicOr(status, 8);
+}
+__global__ __launch_bounds__(256) void k_count_flags(int64_t n, const int8_t* flags,
+                                                     const int32_t* nb_count,
+                                                     const int32_t* a_nnz, int ppe,
+                                                     int64_t* counts) {
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  unsigned long long c[4] = {0, 0, 0, 0};
+  if (k < n) {
+    const int8_t f = flags[k];
+    c[0] = f == MPS_FLAG_SURFACE;
+    c[1] = f == MPS_FLAG_GHOST;
+    c[2] = (unsigned long long)nb_count[k];
+    c[3] = ppe ? (unsigned long long)a_nnz[k] : 0ull;
+  }
+  __shared__ unsigned long long sh[4][4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    for (int o = 32; o > 0; o >>= 1) c[q] += __shfl_down(c[q], o, 64);
+    if ((threadIdx.x & 63) == 0) sh[q][threadIdx.x / 64] = c[q];
+  }
+  __syncthreads();
+  // integer atomics, one per workgroup: the totals do not depend on the order
+  if (threadIdx.x < 4) {
+    const unsigned long long t = sh[threadIdx.x][0] + sh[threadIdx.x][1] + sh[threadIdx.x][2] +
+                                 sh[threadIdx.x][3];
+    if (t) atomicAdd((unsigned long long*)&counts[threadIdx.x], t);
+  }
+}
+
+unsigned flat_blocks(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+void prof_flush(mps_ctx* c);
+
+mps_status read_status(mps_ctx* c) {
+  HIPCHK(c, hipMemcpyAsync(c->h_status, c->status, sizeof(int32_t), hipMemcpyDeviceToHost, c->s));
+  HIPCHK(c, hipStreamSynchronize(c->s));
+  prof_flush(c);
+  const int32_t st = *c->h_status;
+  if (st == 0) return MPS_OK;
+  HIPCHK(c, hipMemsetAsync(c->status, 0, sizeof(int32_t), c->s));
+  c->poisoned = true;
+  if (st & ST_OVERFLOW) return fail(c, MPS_E_NEIGH_OVERFLOW, "more than max_neigh neighbours");
+  if (st & ST_COINCIDENT) return fail(c, MPS_E_COINCIDENT, "two particles at distance 0");
+  if (st & ST_NONFINITE) return fail(c, MPS_E_NONFINITE, "non-finite position or velocity");
+  return fail(c, MPS_E_ARG, "invalid particle type");
+}
+
+// Accumulate the recorded event pairs (the stream must be synchronised).
+void prof_flush(mps_ctx* c) {
+  for (int k = 0; k < c->nev; ++k) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->ev_a[k], c->ev_b[k]) == hipSuccess) {
+      c->prof_ms[c->ev_cls[k]] += ms;
+      c->prof_n[c->ev_cls[k]] += 1;
+    }
+  }
+  c->nev = 0;
+}
+
+// Bracket a group of launches of one kernel class with events.
+struct Prof {
+  mps_ctx* c;
+  int cls;
+  bool on;
+  Prof(mps_ctx* c_, int cls_) : c(c_), cls(cls_), on((c_->prof_mask >> cls_) & 1u) {
+    if (!on) return;
+    if (c->nev == mps_ctx::kPool) {
+      (void)hipStreamSynchronize(c->s);
+      prof_flush(c);
+    }
+    (void)hipEventRecord(c->ev_a[c->nev], c->s);
+  }
+  ~Prof() {
+    if (!on) return;
+    (void)hipEventRecord(c->ev_b[c->nev], c->s);
+    c->ev_cls[c->nev] = cls;
+    c->nev += 1;
+  }
+};
+
+// a1 + a2 at the current state; leaves the context in the new sorted order.
+mps_status search(mps_ctx* c) {
+  c->ppe_valid = false;
+  View v = make_view(c);
+  {
+    Prof pr(c, MPS_KC_SORT);
+    launch_bin(v, c->dim, c->s);
+    launch_permute(v, c->dim, c->P.precision, c->s);
+  }
+  c->cur ^= 1;
+  v = make_view(c);
+  {
+    Prof pr(c, MPS_KC_NEIGH);
+    launch_neighbors(v, c->dim, c->P.precision, c->s);
+  }
+  return MPS_OK;
+}
+
+// --------------------------------------------------------------- stages
+// Stages before the pressure solve: a1-a5 (PPE) or a1-a4 + a7 (EOS).
+// Leaves the context in the new sorted order (flips cur).
+void enqueue_pre(mps_ctx* c) {
+  search(c);
+  View v = make_view(c);
+  {
+    Prof pr(c, MPS_KC_PREDICT);
+    launch_predict(v, c->dim, c->P.precision, c->s);
+  }
+  {
+    Prof pr(c, MPS_KC_DENSITY);
+    launch_density(v, c->dim, c->P.precision, c->P.pmode, c->s);
+  }
+  if (c->P.pmode == MPS_PPE_CG) {
+    Prof pr(c, MPS_KC_ASSEMBLE);
+    launch_assemble(v, c->dim, c->P.precision, nullptr, false, c->s);
+  }
+}
+
+void enqueue_cg(mps_ctx* c, int iters) {
+  View v = make_view(c);
+  for (int it = 0; it < iters; ++it) {
+    {
+      Prof pr(c, MPS_KC_CG_SPMV);
+      launch_cg_spmv(v, c->P.precision, c->s);
+    }
+    Prof pr(c, MPS_KC_CG_UPDATE);
+    launch_cg_update(v, c->s);
+  }
+}
+
+// Stages after the pressure: clamp (PPE) and a8.
+void enqueue_post(mps_ctx* c) {
+  View v = make_view(c);
+  if (c->P.pmode == MPS_PPE_CG && c->P.clamp_negative_p) launch_clamp(v, c->s);
+  Prof pr(c, MPS_KC_GRADIENT);
+  launch_gradient(make_view_inplace(c), c->dim, c->P.precision, c->s);
+}
+
+template <class F>
+mps_status capture(mps_ctx* c, hipGraphExec_t* out, F&& body) {
+  hipGraph_t g = nullptr;
+  HIPCHK(c, hipStreamBeginCapture(c->s, hipStreamCaptureModeThreadLocal));
+  body();
+  HIPCHK(c, hipStreamEndCapture(c->s, &g));
+  hipError_t e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return hip_fail(c, e, "hipGraphInstantiate");
+  return MPS_OK;
+}
+
+// Graphs are used on a non-default stream with profiling off (event timing
+// needs the direct launches).
+bool use_graphs(const mps_ctx* c) { return c->s != nullptr && c->prof_mask == 0; }
+
+mps_status build_graphs(mps_ctx* c) {
+  if (c->graphs_built) return MPS_OK;
+  const int cur0 = c->cur;
+  for (int par = 0; par < 2; ++par) {
+    c->cur = par;
+    mps_status st = capture(c, &c->g_pre[par], [&] { enqueue_pre(c); });
+    if (st != MPS_OK) return st;
+    c->cur = par;
+    st = capture(c, &c->g_post[par], [&] { enqueue_post(c); });
+    if (st != MPS_OK) return st;
+    if (c->P.pmode == MPS_PPE_CG) {
+      for (int q = 0; q < 3 && st == MPS_OK; ++q)
+        st = capture(c, &c->g_cg[par][q], [&] { enqueue_cg(c, mps_ctx::CG_BATCH << (2 * q)); });
+    } else {
+      st = capture(c, &c->g_wc2[par], [&] {
+        enqueue_pre(c);
+        enqueue_post(c);
+        enqueue_pre(c);
+        enqueue_post(c);
+      });
+    }
+    if (st != MPS_OK) return st;
+  }
+  c->cur = cur0;
+  c->graphs_built = true;
+  return MPS_OK;
+}
+
+// CG from the state left by the assembly.  Iterations are enqueued in
+// batches (graphs of CG_BATCH iterations when available) sized from the
+// previous step's count, then the device scalars are polled.
+mps_status solve(mps_ctx* c, int* iters, double* relres, bool graphs) {
+  int launched = 0;
+  const int maxit = c->P.cg_maxit;
+  const int B = mps_ctx::CG_BATCH;
+  int batch = c->last_iters > 0 ? c->last_iters + 1 : 16;
+  for (;;) {
+    int k = std::min(batch, maxit - launched);
+    if (k > 0) {
+      if (graphs) {
+        // greedy cover of k iterations by graphs of 64, 16 and 4 iterations:
+        // few host launches (hipGraphLaunch dominates the host cost)
+        int left = ((k + B - 1) / B) * B, done = 0;
+        for (int q = 2; q >= 0; --q) {
+          const int size = B << (2 * q);
+          while (left >= size) {
+            HIPCHK(c, hipGraphLaunch(c->g_cg[c->cur][q], c->s));
+            left -= size;
+            done += size;
+          }
+        }
+        k = done;
+      } else {
+        enqueue_cg(c, k);
+      }
+      launched += k;
+    }
+    HIPCHK(c, hipMemcpyAsync(c->h_sc, c->sc, sizeof(CGScalars), hipMemcpyDeviceToHost, c->s));
+    HIPCHK(c, hipStreamSynchronize(c->s));
+    prof_flush(c);
+    if (c->h_sc->converged || launched >= maxit) break;
+    batch = std::max(B, c->h_sc->iter / 8);
+  }
+  const CGScalars h = *c->h_sc;
+  *iters = h.converged ? h.iter : std::min(launched, maxit);
+  *relres = h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0;
+  if (!h.converged) return fail(c, MPS_E_CG_NOCONV, "CG reached cg_maxit");
+  return MPS_OK;
+}
+
+// nsteps steps of the weakly-compressible model: no host synchronisation.
+mps_status steps_wc(mps_ctx* c, int nsteps) {
+  const bool graphs = use_graphs(c);
+  if (graphs) {
+    mps_status st = build_graphs(c);
+    if (st != MPS_OK) return st;
+  }
+  int k = 0;
+  if (graphs) {
+    for (; k + 2 <= nsteps; k += 2) HIPCHK(c, hipGraphLaunch(c->g_wc2[c->cur], c->s));
+  }
+  for (; k < nsteps; ++k) {
+    if (graphs) {
+      HIPCHK(c, hipGraphLaunch(c->g_pre[c->cur], c->s));
+      c->cur ^= 1;
+      HIPCHK(c, hipGraphLaunch(c->g_post[c->cur], c->s));
+    } else {
+      enqueue_pre(c);
+      enqueue_post(c);
+    }
+  }
+  return MPS_OK;
+}
+
+mps_status one_step_ppe(mps_ctx* c, mps_step_stats* st) {
+  const bool graphs = use_graphs(c);
+  if (graphs) {
+    mps_status s0 = build_graphs(c);
+    if (s0 != MPS_OK) return s0;
+    HIPCHK(c, hipGraphLaunch(c->g_pre[c->cur], c->s));
+    c->cur ^= 1;
+    c->ppe_valid = true;
+  } else {
+    enqueue_pre(c);
+  }
+  c->ppe_valid = true;
+  int it = 0;
+  double rel = 0;
+  mps_status res = solve(c, &it, &rel, graphs);
+  if (res != MPS_OK && res != MPS_E_CG_NOCONV) return res;
+  c->last_iters = it;
+  if (st) {
+    st->cg_iters_last = it;
+    st->cg_iters_total += it;
+    st->cg_relres_last = rel;
+  }
+  if (graphs) HIPCHK(c, hipGraphLaunch(c->g_post[c->cur], c->s));
+  else enqueue_post(c);
+  return res;
+}
+
+}  // namespace
+
+extern "C" {
+
+mps_status mps_init(const mps_params* params, int64_t n, const double* pos, const double* vel,
+                    const int8_t* type, const double* rho_i, const double* nu_i,
+                    void* hip_stream, mps_ctx** out) {
+  if (!out) return MPS_E_ARG;
+  *out = nullptr;
+  if (check_params(params, n) != MPS_OK || !pos || !vel || !type) return MPS_E_ARG;
+  if (rho_i || nu_i) return MPS_E_ARG;
+  mps_ctx* c = new (std::nothrow) mps_ctx();
+  if (!c) return MPS_E_NOMEM;
+  c->P = *params;
+  c->n = n;
+  c->dim = params->dim;
+  c->ps = c->dim == 2 ? 2 : 4;
+  c->kpad = (params->max_neigh + TEAM - 1) / TEAM * TEAM;
+  c->slots = ((n + SLICE - 1) / SLICE) * (int64_t)c->kpad * SLICE;
+  c->ncell = params->grid_n[0] * params->grid_n[1] * (c->dim == 3 ? params->grid_n[2] : 1);
+  c->s = (hipStream_t)hip_stream;
+  double lam_n;
+  lattice(c->dim, params->l0, params->re_n, params->kernel, &c->n0_n, &lam_n);
+  lattice(c->dim, params->l0, params->re_lap, params->kernel, &c->n0_lap, &c->lam_lap);
+
+  const size_t nv = (size_t)n * c->ps;
+  hipError_t e = hipSuccess;
+  auto A = [&](hipError_t x) { if (e == hipSuccess) e = x; };
+  for (int k = 0; k < 2; ++k) {
+    A(dalloc(&c->pos[k], nv));
+    A(dalloc(&c->vel[k], nv));
+    A(dalloc(&c->pres[k], n));
+    A(dalloc(&c->type[k], n));
+    A(dalloc(&c->id[k], n));
+    A(dalloc(&c->pd[k], n));
+  }
+  A(dalloc(&c->pcell, n));
+  A(dalloc(&c->posf, n));
+  A(dalloc(&c->rsf, n));
+  A(dalloc(&c->us, nv));
+  A(dalloc(&c->rs, nv));
+  A(dalloc(&c->nstar, n));
+  A(dalloc(&c->flags, n));
+  A(dalloc(&c->cellid, n));
+  A(dalloc(&c->slot, n));
+  A(dalloc(&c->perm, n));
+  A(dalloc(&c->cell_count, c->ncell + 1));
+  A(dalloc(&c->cell_start, c->ncell + 2));
+  A(dalloc(&c->tile_sum, (c->ncell + 1 + SCAN_TILE - 1) / SCAN_TILE));
+  A(dalloc(&c->nb_count, n));
+  A(dalloc(&c->nb_list, c->slots));
+  A(dalloc(&c->a_nnz, n));
+  A(dalloc(&c->a_col, c->slots));
+  A(hipMalloc(&c->a_val, c->slots * (params->precision == MPS_MIXED ? 4 : 8) + 256));
+  A(dalloc(&c->diag, n));
+  A(dalloc(&c->b, n));
+  A(dalloc(&c->r, n));
+  A(dalloc(&c->z, n));
+  A(dalloc(&c->q, n));
+  A(dalloc(&c->p_save, n));
+  c->nspmv = cg_spmv_blocks(n);
+  c->nupd = cg_update_blocks(n);
+  A(dalloc(&c->partA, (size_t)std::max(c->nspmv, c->nupd) * 4));
+  A(dalloc(&c->partB, (size_t)c->nspmv));
+  A(dalloc(&c->sc, 1));
+  A(dalloc(&c->status, 1));
+  A(dalloc(&c->counts, 4));
+  if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_sc, sizeof(CGScalars), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_status, sizeof(int32_t), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_counts, 4 * sizeof(int64_t), hipHostMallocDefault);
+  if (e != hipSuccess) {
+    mps_free(c);
+    return e == hipErrorOutOfMemory ? MPS_E_NOMEM : MPS_E_DEVICE;
+  }
+  // initial state: identity order
+  hipStream_t s = c->s;
+  A(hipMemsetAsync(c->cell_count, 0, (c->ncell + 1) * sizeof(int32_t), s));
+  A(hipMemsetAsync(c->status, 0, sizeof(int32_t), s));
+  A(hipMemsetAsync(c->sc, 0, sizeof(CGScalars), s));
+  A(hipMemsetAsync(c->nb_count, 0, n * sizeof(int32_t), s));
+  A(hipMemsetAsync(c->a_nnz, 0, n * sizeof(int32_t), s));
+  A(hipMemsetAsync(c->nstar, 0, n * sizeof(double), s));
+  A(hipMemsetAsync(c->flags, 0, n, s));
+  A(hipMemsetAsync(c->pres[0], 0, n * sizeof(double), s));
+  k_iota<<<flat_blocks(n), 256, 0, s>>>(n, c->id[0]);
+  View v = make_view(c);
+  launch_gather_orig(v, pos, c->pos[0], c->dim, c->ps, s);
+  launch_gather_orig(v, vel, c->vel[0], c->dim, c->ps, s);
+  A(hipMemcpyAsync(c->type[0], type, n, hipMemcpyDeviceToDevice, s));
+  k_check_types<<<flat_blocks(n), 256, 0, s>>>(n, c->type[0], c->status);
+  A(hipGetLastError());
+  A(hipStreamSynchronize(s));
+  if (e != hipSuccess) {
+    mps_free(c);
+    return MPS_E_DEVICE;
+  }
+  mps_status st = read_status(c);
+  if (st != MPS_OK) {
+    mps_free(c);
+    return MPS_E_ARG;
+  }
+  *out = c;
+  return MPS_OK;
+}
+
+mps_status mps_free(mps_ctx* c) {
+  if (!c) return MPS_OK;
+  if (c->s) (void)hipStreamSynchronize(c->s);
+  void* ptrs[] = {c->pos[0], c->pos[1], c->vel[0], c->vel[1], c->pres[0], c->pres[1],
+                  c->type[0], c->type[1], c->id[0], c->id[1], c->pd[0], c->pd[1],
+                  c->pcell, c->posf, c->rsf, c->us, c->rs, c->nstar, c->flags,
+                  c->cellid, c->slot, c->perm, c->cell_count, c->cell_start, c->tile_sum,
+                  c->nb_count,
+                  c->nb_list, c->a_nnz, c->a_col, c->a_val, c->diag, c->b, c->r, c->z,
+                  c->q, c->p_save, c->partA, c->partB, c->sc, c->status, c->counts};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  for (int k = 0; k < 2; ++k) {
+    hipGraphExec_t gs[] = {c->g_pre[k], c->g_cg[k][0], c->g_cg[k][1], c->g_cg[k][2],
+                           c->g_post[k], c->g_wc2[k]};
+    for (hipGraphExec_t g : gs)
+      if (g) (void)hipGraphExecDestroy(g);
+  }
+  if (c->ev_created)
+    for (int k = 0; k < mps_ctx::kPool; ++k) {
+      (void)hipEventDestroy(c->ev_a[k]);
+      (void)hipEventDestroy(c->ev_b[k]);
+    }
+  if (c->h_sc) (void)hipHostFree(c->h_sc);
+  if (c->h_status) (void)hipHostFree(c->h_status);
+  if (c->h_counts) (void)hipHostFree(c->h_counts);
+  delete c;
+  return MPS_OK;
+}
+
+const char* mps_last_error(const mps_ctx* c) { return c ? c->err : kNoCtx; }
+
+mps_status mps_constants(const mps_ctx* c, double* n0_n, double* n0_lap, double* lambda_lap) {
+  if (!c) return MPS_E_ARG;
+  if (n0_n) *n0_n = c->n0_n;
+  if (n0_lap) *n0_lap = c->n0_lap;
+  if (lambda_lap) *lambda_lap = c->lam_lap;
+  return MPS_OK;
+}
+
+mps_status mps_neighbors(mps_ctx* c, int32_t* cell_id, int32_t* count, int32_t* list) {
+  if (!c) return MPS_E_ARG;
+  if (c->poisoned) return fail(c, MPS_E_POISONED, "context poisoned; call mps_set_state");
+  search(c);
+  View v = make_view(c);
+  launch_export_lists(v, cell_id, count, list, c->dim, c->s);
+  HIPCHK(c, hipGetLastError());
+  return read_status(c);
+}
+
+mps_status mps_step(mps_ctx* c, int32_t nsteps, mps_step_stats* stats) {
+  if (!c || nsteps < 0) return MPS_E_ARG;
+  if (c->poisoned) return fail(c, MPS_E_POISONED, "context poisoned; call mps_set_state");
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  mps_status res = MPS_OK;
+  if (c->P.pmode == MPS_WC_EOS) {
+    res = steps_wc(c, nsteps);
+    if (res != MPS_OK) return res;
+  } else {
+    for (int k = 0; k < nsteps; ++k) {
+      mps_status r1 = one_step_ppe(c, stats);
+      if (r1 == MPS_E_CG_NOCONV) res = r1;
+      else if (r1 != MPS_OK) return r1;
+    }
+  }
+  HIPCHK(c, hipGetLastError());
+  mps_status st = read_status(c);
+  if (st != MPS_OK) return st;
+  if (stats) {
+    stats->steps = nsteps;
+    HIPCHK(c, hipMemsetAsync(c->counts, 0, 4 * sizeof(int64_t), c->s));
+    k_count_flags<<<flat_blocks(c->n), 256, 0, c->s>>>(c->n, c->flags, c->nb_count, c->a_nnz,
+                                                       c->P.pmode == MPS_PPE_CG, c->counts);
+    HIPCHK(c, hipMemcpyAsync(c->h_counts, c->counts, 4 * sizeof(int64_t), hipMemcpyDeviceToHost, c->s));
+    HIPCHK(c, hipStreamSynchronize(c->s));
+    stats->n_surface = c->h_counts[0];
+    stats->n_ghost = c->h_counts[1];
+    stats->list_entries = c->h_counts[2];
+    stats->ppe_nnz = c->h_counts[3];
+  }
+  return res;
+}
+
+mps_status mps_pressure_solve(mps_ctx* c, const double* rhs, double* p, int32_t* iters,
+                              double* relres) {
+  if (!c || !p) return MPS_E_ARG;
+  if (c->poisoned) return fail(c, MPS_E_POISONED, "context poisoned; call mps_set_state");
+  search(c);
+  View v = make_view(c);
+  HIPCHK(c, hipMemcpyAsync(c->p_save, c->pres[c->cur], c->n * sizeof(double),
+                           hipMemcpyDeviceToDevice, c->s));
+  launch_predict(v, c->dim, c->P.precision, c->s);
+  launch_density(v, c->dim, c->P.precision, MPS_PPE_CG, c->s);
+  const double* rhs_sorted = nullptr;
+  if (rhs) {
+    // q is free until the CG starts
+    launch_gather_orig(v, rhs, c->q, 1, 1, c->s);
+    rhs_sorted = c->q;
+  }
+  launch_assemble(v, c->dim, c->P.precision, rhs_sorted, true, c->s);
+  c->ppe_valid = true;
+  int it = 0;
+  double rel = 0.0;
+  const int saved_last = c->last_iters;
+  c->last_iters = 0;
+  mps_status res = solve(c, &it, &rel, false);
+  c->last_iters = saved_last;
+  if (res != MPS_OK && res != MPS_E_CG_NOCONV) return res;
+  launch_scatter_orig(v, c->pres[c->cur], p, 1, 1, c->s);
+  HIPCHK(c, hipMemcpyAsync(c->pres[c->cur], c->p_save, c->n * sizeof(double),
+                           hipMemcpyDeviceToDevice, c->s));
+  if (iters) *iters = it;
+  if (relres) *relres = rel;
+  HIPCHK(c, hipGetLastError());
+  mps_status st = read_status(c);
+  return st != MPS_OK ? st : res;
+}
+
+mps_status mps_get_ppe(mps_ctx* c, double* diag, double* b, int32_t* nnz, int32_t* cols,
+                       double* vals) {
+  if (!c) return MPS_E_ARG;
+  if (!c->ppe_valid) return fail(c, MPS_E_ARG, "no assembled system");
+  View v = make_view(c);
+  launch_export_ppe(v, c->P.precision, diag, b, nnz, cols, vals, c->s);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(c->s));
+  return MPS_OK;
+}
+
+mps_status mps_get_state(mps_ctx* c, double* pos, double* vel, double* p, double* n_star,
+                         int8_t* flags, int8_t* type) {
+  if (!c) return MPS_E_ARG;
+  View v = make_view(c);
+  if (pos) launch_scatter_orig(v, c->pos[c->cur], pos, c->dim, c->ps, c->s);
+  if (vel) launch_scatter_orig(v, c->vel[c->cur], vel, c->dim, c->ps, c->s);
+  if (p) launch_scatter_orig(v, c->pres[c->cur], p, 1, 1, c->s);
+  if (n_star) launch_scatter_orig(v, c->nstar, n_star, 1, 1, c->s);
+  const unsigned nb = flat_blocks(c->n);
+  if (flags) k_i8_to_orig<<<nb, 256, 0, c->s>>>(c->n, c->id[c->cur], c->flags, flags);
+  if (type) k_i8_to_orig<<<nb, 256, 0, c->s>>>(c->n, c->id[c->cur], c->type[c->cur], type);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(c->s));
+  return MPS_OK;
+}
+
+mps_status mps_set_state(mps_ctx* c, const double* pos, const double* vel, const int8_t* type) {
+  if (!c || !pos || !vel) return MPS_E_ARG;
+  View v = make_view(c);
+  launch_gather_orig(v, pos, c->pos[c->cur], c->dim, c->ps, c->s);
+  launch_gather_orig(v, vel, c->vel[c->cur], c->dim, c->ps, c->s);
+  if (type) {
+    k_i8_from_orig<<<flat_blocks(c->n), 256, 0, c->s>>>(c->n, c->id[c->cur], type,
+                                                        c->type[c->cur]);
+    k_check_types<<<flat_blocks(c->n), 256, 0, c->s>>>(c->n, c->type[c->cur], c->status);
+  }
+  HIPCHK(c, hipMemsetAsync(c->pres[c->cur], 0, c->n * sizeof(double), c->s));
+  HIPCHK(c, hipGetLastError());
+  c->poisoned = false;
+  c->ppe_valid = false;
+  c->last_iters = 0;
+  mps_status st = read_status(c);
+  if (st != MPS_OK) {
+    c->poisoned = true;
+    return st;
+  }
+  return MPS_OK;
+}
+
+mps_status mps_profile(mps_ctx* c, uint32_t mask) {
+  if (!c) return MPS_E_ARG;
+  HIPCHK(c, hipStreamSynchronize(c->s));
+  if (mask && !c->ev_created) {
+    for (int k = 0; k < mps_ctx::kPool; ++k) {
+      HIPCHK(c, hipEventCreate(&c->ev_a[k]));
+      HIPCHK(c, hipEventCreate(&c->ev_b[k]));
+    }
+    c->ev_created = true;
+  }
+  prof_flush(c);
+  c->prof_mask = mask;
+  for (int k = 0; k < MPS_KC_COUNT; ++k) {
+    c->prof_ms[k] = 0.0;
+    c->prof_n[k] = 0;
+  }
+  return MPS_OK;
+}
+
+mps_status mps_profile_read(mps_ctx* c, double* ms, int64_t* launches) {
+  if (!c) return MPS_E_ARG;
+  HIPCHK(c, hipStreamSynchronize(c->s));
+  prof_flush(c);
+  for (int k = 0; k < MPS_KC_COUNT; ++k) {
+    if (ms) ms[k] = c->prof_ms[k];
+    if (launches) launches[k] = c->prof_n[k];
+  }
+  return MPS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,233 @@
+// Internal definitions shared by the HIP translation units of the MPS
+// library (gfx950).  Not part of the public ABI (include/mps.h).
+//
+// Execution model
+//   Every per-particle kernel assigns a TEAM of 8 lanes to one particle: a
+//   64-lane wavefront covers 8 consecutive cell-sorted particles, a 256-lane
+//   workgroup 32.  The lanes of a team split the particle's neighbour (or
+//   matrix-row) entries and combine their partial sums with cross-lane
+//   shuffles in a fixed tree, so every sum is bitwise reproducible.  Eight
+//   lanes per particle keep several wavefronts per SIMD busy already at a
+//   few ten thousand particles, where one thread per particle would leave
+//   most of the 1024 SIMDs of the chip idle.
+//
+// Sliced layout of per-neighbour arrays (lists, matrix columns and values)
+//   Rows are grouped in slices of H = 8 consecutive particles (one
+//   wavefront).  Inside a slice, entry l of row r lives at
+//     (l / TEAM) * 64 + r * TEAM + (l % TEAM)
+//   so one load instruction of a wavefront reads 64 consecutive words: a
+//   fully coalesced 256 B (int32/float) or 512 B (double) segment.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "mps.h"
+
+namespace mps {
+
+constexpr int TEAM = 8;
+constexpr int WAVE = 64;
+constexpr int SLICE = WAVE / TEAM;        // rows per wavefront
+constexpr int BLOCK = 256;
+constexpr int ROWS_PER_BLOCK = BLOCK / TEAM;
+constexpr int SCAN_TILE = 4096;  // cells per workgroup of the cell-count scan
+
+// Status bits raised by kernels (one int32 word on the device).
+enum : int32_t {
+  ST_OVERFLOW = 1,
+  ST_COINCIDENT = 2,
+  ST_NONFINITE = 4,
+};
+
+__host__ __device__ inline int64_t sl_index(int64_t row, int l, int kpad) {
+  return (row / SLICE) * ((int64_t)kpad * SLICE) + (int64_t)(l / TEAM) * WAVE +
+         (row % SLICE) * TEAM + (l % TEAM);
+}
+
+// Conjugate-gradient scalars, kept on the device so that no iteration
+// needs the host.  Each field has exactly one writer kernel and is only read
+// by later kernels (or by other workgroups of the writer that never read
+// it), so no fence or atomic is needed inside a kernel.
+struct CGScalars {
+  double rzh[2];     // (r, z) of iterate k, slot k & 1 (written by SpMV k)
+  double bb;         // (b, b) (written by SpMV 0)
+  double rr;         // (r, r) of the last iterate checked (written by SpMV k)
+  int32_t k_next;    // index of the next SpMV (written by assembly / update)
+  int32_t k_cur;     // index of the running iteration (written by SpMV)
+  int32_t converged; // 1 once ||r|| <= tol ||b|| (written by SpMV)
+  int32_t iter;      // iterations completed
+  int32_t nasm;      // number of assembly partials (written by assembly)
+  int32_t pad;
+};
+
+// Grid caps of the CG kernels: every workgroup of one kernel sums all the
+// per-workgroup partials of the previous kernel, so their number is bounded.
+constexpr int CG_SPMV_BLOCKS = 2048;
+constexpr int CG_UPD_BLOCKS = 1024;
+
+// Everything a kernel may touch, passed by value.
+struct View {
+  int64_t n;
+  int kpad;          // per-row slot capacity rounded up to TEAM
+  int max_neigh;
+  int nx, ny, nz, ncell;
+  double lo[3];
+  double cs, inv_cs;
+  float cs32;
+  double re_n, re_lap, re_n2, re_lap2;
+  float re_n_f, re_lap_f;
+  double n0_n, n0_lap, lam_lap;
+  double nu, rho, dt, beta, c0, alpha;
+  double cg_tol2;
+  double g[3];
+  int gamma_i, kernel, grad, clamp;
+  // sorted state, current buffers
+  const double* pos;  double* pos_w;
+  const double* vel;  double* vel_w;
+  const int8_t* type; int8_t* type_w;
+  const int32_t* id;  int32_t* id_w;
+  const double* p_in; double* p_w;
+  // per-step arrays (sorted order)
+  int32_t* pcell;     // packed cell coordinates
+  float4* posf;       // mixed: r^k relative to the anchor cell + packed cell
+  float4* rsf;        // mixed: r*  relative to the anchor cell + packed cell
+  double* us;         // u*
+  double* rs;         // r*
+  double* nstar;
+  int8_t* flags;
+  // binning
+  int32_t* cellid;    // old order
+  int32_t* slot;      // old order
+  int32_t* cell_count;
+  int32_t* cell_start;
+  int32_t* tile_sum;  // per-tile cell counts of the scan
+  int32_t* perm;      // unordered scatter of the particles by cell
+  // lists
+  int32_t* nb_count;
+  int32_t* nb_list;
+  // PPE
+  int32_t* a_nnz;
+  int32_t* a_col;
+  void* a_val;        // float (mixed) or double
+  double* diag;
+  double* b;
+  double* p;          // pressure (CG iterate), sorted order
+  // CG
+  double* r;
+  double* z;
+  double* pd[2];
+  double* q;
+  double* partA;      // [blocks][4]: (r,z), (r,r), (b,b) of assembly / update
+  double* partB;      // [blocks]: (p, A p) of the SpMV workgroups
+  int nspmv, nupd;    // grid sizes of the SpMV / assembly and update kernels
+  CGScalars* sc;
+  int32_t* status;
+};
+
+// Packed cell coordinates: 10 bits per axis (x lowest); GHOST_CELL marks a
+// particle outside the grid.
+constexpr int32_t GHOST_CELL = -1;
+__host__ __device__ inline int32_t pack_cell(int cx, int cy, int cz) {
+  return cx | (cy << 10) | (cz << 20);
+}
+__device__ inline int ucx(int32_t pc) { return pc & 1023; }
+__device__ inline int ucy(int32_t pc) { return (pc >> 10) & 1023; }
+__device__ inline int ucz(int32_t pc) { return (pc >> 20) & 1023; }
+
+// Position storage stride in doubles: 2-D uses double2, 3-D a padded double4.
+template <int DIM>
+struct PS { static constexpr int v = DIM == 2 ? 2 : 4; };
+
+template <int DIM>
+__device__ inline void load_vec(const double* a, int64_t i, double (&x)[DIM]) {
+  if constexpr (DIM == 2) {
+    double2 v = reinterpret_cast<const double2*>(a)[i];
+    x[0] = v.x; x[1] = v.y;
+  } else {
+    const double2* p = reinterpret_cast<const double2*>(a) + 2 * i;
+    double2 v0 = p[0], v1 = p[1];
+    x[0] = v0.x; x[1] = v0.y; x[2] = v1.x;
+  }
+}
+template <int DIM>
+__device__ inline void store_vec(double* a, int64_t i, const double (&x)[DIM]) {
+  if constexpr (DIM == 2) {
+    reinterpret_cast<double2*>(a)[i] = make_double2(x[0], x[1]);
+  } else {
+    double2* p = reinterpret_cast<double2*>(a) + 2 * i;
+    p[0] = make_double2(x[0], x[1]);
+    p[1] = make_double2(x[2], 0.0);
+  }
+}
+
+// Logical block index with consecutive particle ranges kept on one XCD:
+// hardware dispatches workgroup b to XCD b % 8, so remap such that each XCD
+// owns one contiguous chunk of the cell-sorted particles and the neighbour
+// data it gathers stays in that XCD's L2.
+__device__ inline int xcd_block() {
+  const int nb = gridDim.x, b = blockIdx.x;
+  const int xcd = b & 7, local = b >> 3;
+  const int q = nb >> 3, r = nb & 7;
+  return xcd < r ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
+}
+
+// Team helpers: lanes of one team are contiguous (lane = row * TEAM + t).
+__device__ inline int team_lane() { return threadIdx.x & (TEAM - 1); }
+
+template <class T>
+__device__ inline T team_sum(T v) {
+#pragma unroll
+  for (int o = 1; o < TEAM; o <<= 1) v += __shfl_xor(v, o, TEAM);
+  return v;
+}
+template <class T>
+__device__ inline T team_min(T v) {
+#pragma unroll
+  for (int o = 1; o < TEAM; o <<= 1) {
+    T w = __shfl_xor(v, o, TEAM);
+    v = w < v ? w : v;
+  }
+  return v;
+}
+// Bit mask of the team's lanes for which pred holds (bit t = lane t).
+__device__ inline uint32_t team_ballot(bool pred) {
+  uint64_t m = __ballot(pred);
+  int base = (threadIdx.x & (WAVE - 1)) & ~(TEAM - 1);
+  return (uint32_t)((m >> base) & ((1u << TEAM) - 1));
+}
+
+// Kernel weight (Eq. 4, or the cubic kernel), zero at and beyond re.
+template <class R>
+__device__ inline R weight(int kernel, R r, R re) {
+  if (!(r < re)) return R(0);
+  if (kernel == MPS_K_KOSHIZUKA) return re / r - R(1);
+  R q = R(1) - r / re;
+  return q * q * q;
+}
+
+// ---------------------------------------------------------------- launchers
+int launch_bin(const View& v, int dim, hipStream_t s);
+int launch_permute(const View& v, int dim, int precision, hipStream_t s);
+int launch_neighbors(const View& v, int dim, int precision, hipStream_t s);
+int launch_export_lists(const View& v, int32_t* cell_out, int32_t* count_out,
+                        int32_t* list_out, int dim, hipStream_t s);
+int launch_predict(const View& v, int dim, int precision, hipStream_t s);
+int launch_density(const View& v, int dim, int precision, int pmode, hipStream_t s);
+int launch_assemble(const View& v, int dim, int precision, const double* rhs_sorted,
+                    bool zero_x0, hipStream_t s);
+int launch_cg_spmv(const View& v, int precision, hipStream_t s);
+int launch_cg_update(const View& v, hipStream_t s);
+int launch_clamp(const View& v, hipStream_t s);
+int launch_gradient(const View& v, int dim, int precision, hipStream_t s);
+int launch_scatter_orig(const View& v, const double* src, double* dst, int comps,
+                        int stride, hipStream_t s);
+int launch_gather_orig(const View& v, const double* src, double* dst, int comps,
+                       int stride, hipStream_t s);
+int launch_export_ppe(const View& v, int precision, double* diag, double* b,
+                      int32_t* nnz, int32_t* cols, double* vals, hipStream_t s);
+int cg_spmv_blocks(int64_t n);
+int cg_update_blocks(int64_t n);
+
+}  // namespace mps

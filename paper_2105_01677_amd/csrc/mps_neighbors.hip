@@ -1,0 +1,313 @@
+// Cell-linked-list neighbour search (Section "Neighbouring search
+// algorithms" of arXiv 2105.01677): particles are binned into a fixed
+// background grid of cells with side cell_size >= re_lap, counting-sorted by
+// cell, and each particle's list is gathered from its own and the adjacent
+// cells.  The list is built once per step and kept for the whole step.
+//
+// Order of the sorted particles: by linear cell id, and inside a cell by
+// original particle id, so that the layout -- and every floating-point sum
+// over a list -- is independent of the order in which atomics resolved.
+// Sorting = cell of each particle + atomic slot (k_bin), exclusive scan of
+// the cell counts (k_scan_tiles, k_scan_apply), unordered scatter (k_scatter), rank inside the
+// cell and permutation of the state (k_rank_permute).
+#include "mps_internal.h"
+
+namespace mps {
+
+// Squared distance rounded term by term: (dx*dx + dy*dy) + dz*dz.  The
+// neighbour criterion d2 < re_lap^2 is evaluated on exactly this expression,
+// so the lists are reproducible bit for bit on any IEEE machine.
+template <int DIM>
+__device__ inline double dist2_exact(const double (&a)[DIM], const double (&b)[DIM]) {
+#pragma clang fp contract(off)
+  double dx = b[0] - a[0];
+  double dy = b[1] - a[1];
+  double s = dx * dx + dy * dy;
+  if constexpr (DIM == 3) {
+    double dz = b[2] - a[2];
+    s = s + dz * dz;
+  }
+  return s;
+}
+
+// a1: cell of every particle (current sorted order), rank inside its cell.
+// A particle outside the grid becomes a ghost and goes to cell ncell.
+template <int DIM>
+__global__ __launch_bounds__(BLOCK) void k_bin(View v, int8_t* type_cur) {
+  const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= v.n) return;
+  int c = v.ncell;
+  int8_t t = type_cur[i];
+  if (t != MPS_GHOST) {
+    double x[DIM];
+    load_vec<DIM>(v.pos, i, x);
+    const int nn[3] = {v.nx, v.ny, v.nz};
+    int ci[3] = {0, 0, 0};
+    bool in = true, finite = true;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+      finite = finite && isfinite(x[a]);
+      double f = floor((x[a] - v.lo[a]) * v.inv_cs);
+      if (!(f >= 0.0 && f < (double)nn[a])) in = false;
+      else ci[a] = (int)f;
+    }
+    if (!finite) atomicOr(v.status, ST_NONFINITE);
+    if (in) c = ci[0] + v.nx * (ci[1] + v.ny * ci[2]);
+    else type_cur[i] = MPS_GHOST;
+  }
+  v.cellid[i] = c;
+  // the ghost cell may collect many particles: one atomic per wavefront
+  const bool ghost = c == v.ncell;
+  const uint64_t gm = __ballot(ghost);
+  if (ghost) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int leader = __ffsll((unsigned long long)gm) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&v.cell_count[c], __popcll(gm));
+    base = __shfl(base, leader, WAVE);
+    v.slot[i] = base + __popcll(gm & ((1ull << lane) - 1ull));
+  } else {
+    v.slot[i] = atomicAdd(&v.cell_count[c], 1);
+  }
+}
+
+// Exclusive scan of the ncell+1 cell counts in tiles of SCAN_TILE cells:
+// k_scan_tiles sums each tile, k_scan_apply adds the sums of the preceding
+// tiles (at most a few ten) and scans its own tile.  Resets the counts for
+// the next step.
+__global__ __launch_bounds__(BLOCK) void k_scan_tiles(View v) {
+  const int m = v.ncell + 1;
+  const int base = blockIdx.x * SCAN_TILE;
+  int32_t s = 0;
+  for (int k = base + threadIdx.x; k < base + SCAN_TILE && k < m; k += BLOCK) s += v.cell_count[k];
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) s += __shfl_down(s, o, WAVE);
+  __shared__ int32_t sh[BLOCK / WAVE];
+  if ((threadIdx.x & (WAVE - 1)) == 0) sh[threadIdx.x / WAVE] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t t = 0;
+    for (int w = 0; w < BLOCK / WAVE; ++w) t += sh[w];
+    v.tile_sum[blockIdx.x] = t;
+  }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_scan_apply(View v) {
+  constexpr int PER = SCAN_TILE / BLOCK;
+  const int m = v.ncell + 1;
+  const int base = blockIdx.x * SCAN_TILE + threadIdx.x * PER;
+  __shared__ int32_t off_sh;
+  __shared__ int32_t wsum[BLOCK / WAVE];
+  if (threadIdx.x == 0) {
+    int32_t o = 0;
+    for (unsigned t = 0; t < blockIdx.x; ++t) o += v.tile_sum[t];
+    off_sh = o;
+  }
+  int32_t loc[PER];
+  int32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    loc[k] = base + k < m ? v.cell_count[base + k] : 0;
+    s += loc[k];
+  }
+  // inclusive scan of the thread sums: wave shuffles, then across waves
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  int32_t inc = s;
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    const int32_t y = __shfl_up(inc, o, WAVE);
+    if (lane >= o) inc += y;
+  }
+  if (lane == WAVE - 1) wsum[w] = inc;
+  __syncthreads();
+  int32_t run = off_sh + inc - s;
+  for (int q = 0; q < w; ++q) run += wsum[q];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    if (base + k < m) {
+      v.cell_start[base + k] = run;
+      v.cell_count[base + k] = 0;
+    }
+    run += loc[k];
+  }
+  if (base + PER >= m && base < m) v.cell_start[m] = run;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_scatter(View v) {
+  const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= v.n) return;
+  v.perm[v.cell_start[v.cellid[i]] + v.slot[i]] = (int32_t)i;
+}
+
+// Final position of every particle and the permutation of the state in one
+// pass: inside its cell a particle's rank is the number of cell members with
+// a smaller original id (cells hold a few tens of particles, read from the
+// unordered scatter in perm), so the order does not depend on how the
+// counting atomics resolved.  Ghosts keep their atomic slot: they take part
+// in no sum.  Packed cell coordinates and, on the mixed path, FP32
+// positions relative to the cell's lower corner are written alongside.
+template <int DIM, bool MIXED>
+__global__ __launch_bounds__(BLOCK) void k_rank_permute(View v) {
+  const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= v.n) return;
+  const int c = v.cellid[i];
+  const int b = v.cell_start[c];
+  const int32_t key = v.id[i];
+  int64_t k;
+  if (c == v.ncell) {
+    k = b + v.slot[i];
+  } else {
+    const int e = v.cell_start[c + 1];
+    int rank = 0;
+    for (int m = b; m < e; ++m) rank += v.id[v.perm[m]] < key ? 1 : 0;
+    k = b + rank;
+  }
+  double x[DIM], u[DIM];
+  load_vec<DIM>(v.pos, i, x);
+  load_vec<DIM>(v.vel, i, u);
+  store_vec<DIM>(v.pos_w, k, x);
+  store_vec<DIM>(v.vel_w, k, u);
+  v.type_w[k] = v.type[i];
+  v.id_w[k] = key;
+  v.p_w[k] = v.p_in[i];
+  int32_t pc = GHOST_CELL;
+  int ci[3] = {0, 0, 0};
+  if (c < v.ncell) {
+    ci[0] = c % v.nx;
+    ci[1] = (c / v.nx) % v.ny;
+    ci[2] = c / (v.nx * v.ny);
+    pc = pack_cell(ci[0], ci[1], ci[2]);
+  }
+  v.pcell[k] = pc;
+  if constexpr (MIXED) {
+    float r[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) r[a] = (float)(x[a] - (v.lo[a] + ci[a] * v.cs));
+    float4 f;
+    if constexpr (DIM == 2) f = make_float4(r[0], r[1], __int_as_float(pc), 0.f);
+    else f = make_float4(r[0], r[1], r[2], __int_as_float(pc));
+    v.posf[k] = f;
+  }
+}
+
+// a2: neighbour list of each particle, one team of TEAM lanes per
+// particle.  The candidate cells of one grid row (x-1 .. x+1) are contiguous
+// in the sorted order, so each of the 3 (2-D) or 9 (3-D) rows is one
+// contiguous index range; the team scans it TEAM candidates at a time and
+// appends hits in candidate order with a ballot, so the list order is fixed.
+template <int DIM>
+__global__ __launch_bounds__(BLOCK) void k_neighbors(View v) {
+  const int64_t row = (int64_t)xcd_block() * ROWS_PER_BLOCK + threadIdx.x / TEAM;
+  const int t = team_lane();
+  if (row >= v.n) return;
+  const int32_t pc = v.pcell[row];
+  int count = 0;
+  if (pc != GHOST_CELL) {
+    double xi[DIM];
+    load_vec<DIM>(v.pos, row, xi);
+    const int cx = ucx(pc), cy = ucy(pc), cz = ucz(pc);
+    const int x0 = max(cx - 1, 0), x1 = min(cx + 1, v.nx - 1);
+    const int zlo = DIM == 3 ? max(cz - 1, 0) : 0;
+    const int zhi = DIM == 3 ? min(cz + 1, v.nz - 1) : 0;
+    bool coinc = false;
+    for (int z = zlo; z <= zhi; ++z) {
+      for (int y = max(cy - 1, 0); y <= min(cy + 1, v.ny - 1); ++y) {
+        const int base = v.nx * (y + v.ny * z);
+        const int jb = v.cell_start[base + x0], je = v.cell_start[base + x1 + 1];
+        for (int jj = jb; jj < je; jj += TEAM) {
+          const int j = jj + t;
+          bool hit = false;
+          if (j < je && j != row) {
+            double xj[DIM];
+            load_vec<DIM>(v.pos, j, xj);
+            const double d2 = dist2_exact<DIM>(xi, xj);
+            hit = d2 < v.re_lap2;
+            coinc = coinc || (hit && d2 == 0.0);
+          }
+          const uint32_t m = team_ballot(hit);
+          if (hit) {
+            const int l = count + __popc(m & ((1u << t) - 1u));
+            if (l < v.max_neigh) v.nb_list[sl_index(row, l, v.kpad)] = j;
+          }
+          count += __popc(m);
+        }
+      }
+    }
+    if (coinc) atomicOr(v.status, ST_COINCIDENT);
+    if (count > v.max_neigh) {
+      if (t == 0) atomicOr(v.status, ST_OVERFLOW);
+      count = v.max_neigh;
+    }
+  }
+  if (t == 0) v.nb_count[row] = count;
+}
+
+// Export: lists in original order with original ids, ascending.
+__global__ __launch_bounds__(BLOCK) void k_export_lists(View v, int32_t* cell_out,
+                                                        int32_t* count_out,
+                                                        int32_t* list_out) {
+  const int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (k >= v.n) return;
+  const int64_t o = v.id[k];
+  const int c = v.nb_count[k];
+  if (count_out) count_out[o] = c;
+  if (cell_out) {
+    const int32_t pc = v.pcell[k];
+    cell_out[o] = pc == GHOST_CELL ? -1 : ucx(pc) + v.nx * (ucy(pc) + v.ny * ucz(pc));
+  }
+  if (!list_out) return;
+  int32_t* row = list_out + o * v.max_neigh;
+  for (int l = 0; l < c; ++l) {
+    const int32_t key = v.id[v.nb_list[sl_index(k, l, v.kpad)]];
+    int m = l - 1;
+    while (m >= 0 && row[m] > key) {
+      row[m + 1] = row[m];
+      --m;
+    }
+    row[m + 1] = key;
+  }
+  for (int l = c; l < v.max_neigh; ++l) row[l] = -1;
+}
+
+static inline unsigned nblk(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+int launch_bin(const View& v, int dim, hipStream_t s) {
+  // type is binned in the current buffer (ghosts are marked in place)
+  int8_t* type_cur = const_cast<int8_t*>(v.type);
+  if (dim == 2) k_bin<2><<<nblk(v.n, BLOCK), BLOCK, 0, s>>>(v, type_cur);
+  else k_bin<3><<<nblk(v.n, BLOCK), BLOCK, 0, s>>>(v, type_cur);
+  const unsigned ntiles = (unsigned)((v.ncell + 1 + SCAN_TILE - 1) / SCAN_TILE);
+  k_scan_tiles<<<ntiles, BLOCK, 0, s>>>(v);
+  k_scan_apply<<<ntiles, BLOCK, 0, s>>>(v);
+  k_scatter<<<nblk(v.n, BLOCK), BLOCK, 0, s>>>(v);
+  return 0;
+}
+
+int launch_permute(const View& v, int dim, int precision, hipStream_t s) {
+  const unsigned nb = nblk(v.n, BLOCK);
+  if (dim == 2) {
+    if (precision == MPS_MIXED) k_rank_permute<2, true><<<nb, BLOCK, 0, s>>>(v);
+    else k_rank_permute<2, false><<<nb, BLOCK, 0, s>>>(v);
+  } else {
+    if (precision == MPS_MIXED) k_rank_permute<3, true><<<nb, BLOCK, 0, s>>>(v);
+    else k_rank_permute<3, false><<<nb, BLOCK, 0, s>>>(v);
+  }
+  return 0;
+}
+
+int launch_neighbors(const View& v, int dim, int precision, hipStream_t s) {
+  (void)precision;
+  const unsigned nb = nblk(v.n, ROWS_PER_BLOCK);
+  if (dim == 2) k_neighbors<2><<<nb, BLOCK, 0, s>>>(v);
+  else k_neighbors<3><<<nb, BLOCK, 0, s>>>(v);
+  return 0;
+}
+
+int launch_export_lists(const View& v, int32_t* cell_out, int32_t* count_out,
+                        int32_t* list_out, int dim, hipStream_t s) {
+  (void)dim;
+  k_export_lists<<<nblk(v.n, BLOCK), BLOCK, 0, s>>>(v, cell_out, count_out, list_out);
+  return 0;
+}
+
+}  // namespace mps

@@ -1,0 +1,430 @@
+// Pressure Poisson equation of the fully incompressible model (arXiv
+// 2105.01677, Eq. 13 with the Laplacian model of Eq. 7): assembly (a5) and
+// Jacobi-preconditioned conjugate gradients (a6).
+//
+// Matrix.  Row-wise as in the listing "PPE assemble GPU code": for a
+// pressure unknown i (fluid or wall, not on the free surface) and every
+// listed non-dummy neighbour j with |r*_j - r*_i| < re_lap,
+//     c_ij = 2d w(r*_ij) / (lambda n0 rho),
+//     A_ii += c_ij,  A_ij = -c_ij if j is an unknown too,
+// and A_ii += alpha/dt^2 (the listing's 1e-7/dt^2 term).  A free-surface
+// neighbour (Dirichlet p = 0) keeps its c_ij on the diagonal only, so A is
+// exactly symmetric and strictly diagonally dominant, hence SPD.
+// Right-hand side b_i = (n*_i - n0)/(n0 dt^2).  Rows that are not unknowns
+// are identity rows with b = 0.
+//
+// Storage.  Off-diagonal entries compacted per row in the sliced layout
+// (mps_internal.h): FP32 values on the mixed path, FP64 otherwise; the
+// diagonal is FP64 and, on the mixed path, the FP64 sum of the rounded FP32
+// couplings, so each row of the stored matrix sums exactly like the FP64
+// matrix built from the same FP32 couplings.
+//
+// Solver.  Two kernels per iteration, all scalars on the device:
+//   k_cg_spmv    p = z + beta p_old (fused, computed on the fly for the
+//                neighbours too), q = A p, (p, q); alpha = rz/(p, q)
+//   k_cg_update  x += alpha p, r -= alpha q, z = r/diag, (r, z), (r, r);
+//                beta, convergence flag
+// FP64 dot products: wave64 shuffles, LDS across the workgroup, and the
+// last workgroup to finish sums the per-workgroup partials in index order,
+// so every reduction is deterministic.  Once converged, further launches
+// return immediately, which lets the host enqueue iterations in batches and
+// poll rarely.
+#include "mps_internal.h"
+
+namespace mps {
+
+template <int DIM, bool MIXED>
+struct PosRefP;
+
+template <int DIM>
+struct PosRefP<DIM, false> {
+  using R = double;
+  double x[DIM];
+  __device__ static PosRefP load(const View& v, int64_t i) {
+    PosRefP p;
+    load_vec<DIM>(v.rs, i, p.x);
+    return p;
+  }
+  __device__ void diff(const PosRefP& o, float, R (&d)[DIM]) const {
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) d[a] = o.x[a] - x[a];
+  }
+};
+
+template <int DIM>
+struct PosRefP<DIM, true> {
+  using R = float;
+  float4 f;
+  __device__ static PosRefP load(const View& v, int64_t i) {
+    PosRefP p;
+    p.f = v.rsf[i];
+    return p;
+  }
+  __device__ int32_t pc() const { return __float_as_int(DIM == 2 ? f.z : f.w); }
+  __device__ void diff(const PosRefP& o, float cs, R (&d)[DIM]) const {
+    const int32_t a = pc(), b = o.pc();
+    d[0] = (o.f.x - f.x) + (float)(ucx(b) - ucx(a)) * cs;
+    d[1] = (o.f.y - f.y) + (float)(ucy(b) - ucy(a)) * cs;
+    if constexpr (DIM == 3) d[2] = (o.f.z - f.z) + (float)(ucz(b) - ucz(a)) * cs;
+  }
+};
+
+// Sum over the workgroup in a fixed tree; result valid in thread 0.
+template <int NV>
+__device__ inline void block_sum(double (&x)[NV]) {
+  __shared__ double sh[NV][BLOCK / WAVE];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) x[k] += __shfl_down(x[k], o, WAVE);
+  }
+  const int w = threadIdx.x / WAVE;
+  if ((threadIdx.x & (WAVE - 1)) == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) sh[k][w] = x[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double s = 0.0;
+      for (int q = 0; q < BLOCK / WAVE; ++q) s += sh[k][q];
+      x[k] = s;
+    }
+  }
+  __syncthreads();
+}
+
+// Sum of np per-workgroup partials (stride doubles apart) in a fixed order;
+// every thread gets the result.  All workgroups that call this on the same
+// data obtain the same bits.
+template <int NV>
+__device__ inline void sum_partials(const double* part, int np, int stride, double (&tot)[NV]) {
+  __shared__ double bc[NV];
+  double s[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) s[k] = 0.0;
+  for (int b = threadIdx.x; b < np; b += BLOCK) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) s[k] += part[(int64_t)b * stride + k];
+  }
+  block_sum<NV>(s);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) bc[k] = s[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) tot[k] = bc[k];
+}
+
+// Contiguous chunk of 32-row groups handled by this workgroup of a
+// grid-capped team kernel.
+struct Chunk {
+  int64_t g0, g1;
+  __device__ Chunk(int64_t n) {
+    const int64_t ng = (n + ROWS_PER_BLOCK - 1) / ROWS_PER_BLOCK;
+    const int64_t per = (ng + gridDim.x - 1) / gridDim.x;
+    g0 = (int64_t)xcd_block() * per;
+    g1 = g0 + per < ng ? g0 + per : ng;
+  }
+};
+
+// a5: assembly of row i by its team, plus the CG start:
+// x0 = warm start (previous pressure) or 0, r0 = b - A x0, z0 = r0/diag,
+// p_old = 0 so that the first SpMV forms p = z0.  Per-workgroup partials of
+// (r0, z0), (r0, r0), (b, b) go to partA.
+template <int DIM, bool MIXED>
+__global__ __launch_bounds__(BLOCK) void k_assemble(View v, const double* rhs, int zero_x0) {
+  using P = PosRefP<DIM, MIXED>;
+  using R = typename P::R;
+  using VT = R;
+  const int t = team_lane();
+  double rz = 0.0, rr = 0.0, bb = 0.0;
+  VT* aval = reinterpret_cast<VT*>(v.a_val);
+  const Chunk ch(v.n);
+  for (int64_t g = ch.g0; g < ch.g1; ++g) {
+    const int64_t row = g * ROWS_PER_BLOCK + threadIdx.x / TEAM;
+    if (row >= v.n) continue;
+    const bool inner = v.flags[row] == MPS_FLAG_INNER;
+    double dsum = 0.0, ax = 0.0;
+    int nnz = 0;
+    if (inner) {
+      const P pi = P::load(v, row);
+      const R re = (R)v.re_lap, re2 = (R)v.re_lap2;
+      const R cpp = (R)(2.0 * DIM / (v.lam_lap * v.n0_lap * v.rho));
+      const int cnt = v.nb_count[row];
+      for (int l0 = 0; l0 < cnt; l0 += TEAM) {
+        const int l = l0 + t;
+        bool keep = false;
+        int32_t j = 0;
+        R c = R(0);
+        if (l < cnt) {
+          j = v.nb_list[sl_index(row, l, v.kpad)];
+          if (v.type[j] != MPS_DUMMY) {
+            R d[DIM];
+            pi.diff(P::load(v, j), v.cs32, d);
+            R r2 = d[0] * d[0] + d[1] * d[1];
+            if constexpr (DIM == 3) r2 += d[2] * d[2];
+            if (r2 < re2) {
+              c = cpp * weight<R>(v.kernel, sqrt(r2), re);
+              dsum += (double)c;
+              keep = v.flags[j] == MPS_FLAG_INNER;
+            }
+          }
+        }
+        const uint32_t m = team_ballot(keep);
+        if (keep) {
+          const int s = nnz + __popc(m & ((1u << t) - 1u));
+          const int64_t e = sl_index(row, s, v.kpad);
+          v.a_col[e] = j;
+          aval[e] = -c;
+          if (!zero_x0) ax -= (double)c * v.p[j];
+        }
+        nnz += __popc(m);
+      }
+      dsum = team_sum(dsum);
+      ax = team_sum(ax);
+    }
+    if (t == 0) {
+      double diag = 1.0, b = 0.0, x0 = 0.0;
+      if (inner) {
+        diag = dsum + v.alpha / (v.dt * v.dt);
+        b = rhs ? rhs[row] : (v.nstar[row] - v.n0_n) / (v.n0_n * v.dt * v.dt);
+        x0 = zero_x0 ? 0.0 : v.p[row];
+      }
+      const double r0 = b - diag * x0 - ax;
+      const double z0 = r0 / diag;
+      v.a_nnz[row] = nnz;
+      v.diag[row] = diag;
+      v.b[row] = b;
+      if (!inner || zero_x0) v.p[row] = x0;
+      v.r[row] = r0;
+      v.z[row] = z0;
+      v.pd[0][row] = 0.0;
+      rz += r0 * z0;
+      rr += r0 * r0;
+      bb += b * b;
+    }
+  }
+  double x[3] = {rz, rr, bb};
+  block_sum<3>(x);
+  if (threadIdx.x == 0) {
+    const int lb = xcd_block();
+#pragma unroll
+    for (int k = 0; k < 3; ++k) v.partA[(int64_t)lb * 4 + k] = x[k];
+    if (blockIdx.x == 0) {
+      CGScalars* sc = v.sc;
+      sc->k_next = 0;
+      sc->converged = 0;
+      sc->iter = 0;
+      sc->nasm = gridDim.x;
+    }
+  }
+}
+
+// a6, part 1 (iteration k): reduce the partials of the previous kernel into
+// (r, z) and (r, r); stop if converged; beta = rz_k / rz_{k-1};
+// p = z + beta p_old (formed on the fly for the neighbours as well),
+// q = A p, per-workgroup (p, q).
+template <class VT>
+__global__ __launch_bounds__(BLOCK) void k_cg_spmv(View v) {
+  CGScalars* sc = v.sc;
+  if (sc->converged) return;
+  const int k = sc->k_next;
+  double tot[3];
+  if (k == 0) {
+    sum_partials<3>(v.partA, sc->nasm, 4, tot);
+  } else {
+    double t2[2];
+    sum_partials<2>(v.partA, v.nupd, 4, t2);
+    tot[0] = t2[0];
+    tot[1] = t2[1];
+    tot[2] = sc->bb;
+  }
+  const double rz = tot[0], rr = tot[1], bb = tot[2];
+  const bool done = bb == 0.0 || rr <= v.cg_tol2 * bb;
+  const Chunk ch(v.n);
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    sc->rr = rr;
+    sc->k_cur = k;
+    sc->rzh[k & 1] = rz;
+    if (k == 0) sc->bb = bb;
+    if (done) {
+      sc->converged = 1;
+      sc->iter = k;
+    }
+  }
+  if (done) {
+    if (bb == 0.0) {  // b = 0: the solution is p = 0
+      for (int64_t g = ch.g0; g < ch.g1; ++g) {
+        const int64_t row = g * ROWS_PER_BLOCK + threadIdx.x / TEAM;
+        if (row < v.n && team_lane() == 0) v.p[row] = 0.0;
+      }
+    }
+    return;
+  }
+  const double beta = k == 0 ? 0.0 : rz / sc->rzh[(k - 1) & 1];
+  const double* __restrict__ pold = v.pd[k & 1];
+  double* __restrict__ pnew = v.pd[(k + 1) & 1];
+  const VT* __restrict__ aval = reinterpret_cast<const VT*>(v.a_val);
+  const int t = team_lane();
+  double pq = 0.0;
+  for (int64_t g = ch.g0; g < ch.g1; ++g) {
+    const int64_t row = g * ROWS_PER_BLOCK + threadIdx.x / TEAM;
+    if (row >= v.n) continue;
+    const int nnz = v.a_nnz[row];
+    double s = 0.0;
+    for (int l = t; l < nnz; l += TEAM) {
+      const int64_t e = sl_index(row, l, v.kpad);
+      const int32_t j = v.a_col[e];
+      const double pj = v.z[j] + beta * pold[j];
+      s += (double)aval[e] * pj;
+    }
+    s = team_sum(s);
+    if (t == 0) {
+      const double pi = v.z[row] + beta * pold[row];
+      const double qi = v.diag[row] * pi + s;
+      pnew[row] = pi;
+      v.q[row] = qi;
+      pq += pi * qi;
+    }
+  }
+  double x[1] = {pq};
+  block_sum<1>(x);
+  if (threadIdx.x == 0) v.partB[xcd_block()] = x[0];
+}
+
+// a6, part 2 (iteration k): alpha = rz_k / (p, q) from the SpMV partials;
+// x += alpha p, r -= alpha q, z = r/diag, per-workgroup (r, z), (r, r).
+__global__ __launch_bounds__(BLOCK) void k_cg_update(View v) {
+  CGScalars* sc = v.sc;
+  if (sc->converged) return;
+  const int k = sc->k_cur;
+  double pq[1];
+  sum_partials<1>(v.partB, v.nspmv, 1, pq);
+  const double alpha = sc->rzh[k & 1] / pq[0];
+  const double* __restrict__ pcur = v.pd[(k + 1) & 1];
+  double rz = 0.0, rr = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < v.n;
+       i += (int64_t)gridDim.x * BLOCK) {
+    v.p[i] += alpha * pcur[i];
+    const double r = v.r[i] - alpha * v.q[i];
+    const double z = r / v.diag[i];
+    v.r[i] = r;
+    v.z[i] = z;
+    rz += r * z;
+    rr += r * r;
+  }
+  double x[2] = {rz, rr};
+  block_sum<2>(x);
+  if (threadIdx.x == 0) {
+    v.partA[(int64_t)blockIdx.x * 4 + 0] = x[0];
+    v.partA[(int64_t)blockIdx.x * 4 + 1] = x[1];
+    if (blockIdx.x == 0) {
+      sc->k_next = k + 1;
+      sc->iter = k + 1;
+    }
+  }
+}
+
+// Export of the assembled system in original order.
+template <class VT>
+__global__ __launch_bounds__(BLOCK) void k_export_ppe(View v, double* diag, double* b,
+                                                      int32_t* nnz, int32_t* cols,
+                                                      double* vals) {
+  const int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (k >= v.n) return;
+  const int64_t o = v.id[k];
+  const int m = v.a_nnz[k];
+  if (diag) diag[o] = v.diag[k];
+  if (b) b[o] = v.b[k];
+  if (nnz) nnz[o] = m;
+  const VT* aval = reinterpret_cast<const VT*>(v.a_val);
+  for (int l = 0; l < v.max_neigh; ++l) {
+    const bool in = l < m;
+    const int64_t e = in ? sl_index(k, l, v.kpad) : 0;
+    if (cols) cols[o * v.max_neigh + l] = in ? v.id[v.a_col[e]] : -1;
+    if (vals) vals[o * v.max_neigh + l] = in ? (double)aval[e] : 0.0;
+  }
+}
+
+// Reorder between the caller's original order and the sorted order.
+__global__ __launch_bounds__(BLOCK) void k_to_orig(View v, const double* src, double* dst,
+                                                   int comps, int stride) {
+  const int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (k >= v.n) return;
+  const int64_t o = v.id[k];
+  for (int a = 0; a < comps; ++a) dst[o * comps + a] = src[k * stride + a];
+}
+__global__ __launch_bounds__(BLOCK) void k_from_orig(View v, const double* src, double* dst,
+                                                     int comps, int stride) {
+  const int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (k >= v.n) return;
+  const int64_t o = v.id[k];
+  for (int a = 0; a < comps; ++a) dst[k * stride + a] = src[o * comps + a];
+  for (int a = comps; a < stride; ++a) dst[k * stride + a] = 0.0;
+}
+
+static inline unsigned nb_team(int64_t n) {
+  return (unsigned)((n + ROWS_PER_BLOCK - 1) / ROWS_PER_BLOCK);
+}
+static inline unsigned nb_flat(int64_t n) { return (unsigned)((n + BLOCK - 1) / BLOCK); }
+
+int cg_spmv_blocks(int64_t n) {
+  const int64_t a = nb_team(n);
+  return (int)(a < CG_SPMV_BLOCKS ? a : CG_SPMV_BLOCKS);
+}
+int cg_update_blocks(int64_t n) {
+  const int64_t a = nb_flat(n);
+  return (int)(a < CG_UPD_BLOCKS ? a : CG_UPD_BLOCKS);
+}
+
+int launch_assemble(const View& v, int dim, int precision, const double* rhs, bool zero_x0,
+                    hipStream_t s) {
+  const unsigned nb = (unsigned)v.nspmv;
+  const int zx = zero_x0 ? 1 : 0;
+  const bool mx = precision == MPS_MIXED;
+  if (dim == 2) {
+    if (mx) k_assemble<2, true><<<nb, BLOCK, 0, s>>>(v, rhs, zx);
+    else k_assemble<2, false><<<nb, BLOCK, 0, s>>>(v, rhs, zx);
+  } else {
+    if (mx) k_assemble<3, true><<<nb, BLOCK, 0, s>>>(v, rhs, zx);
+    else k_assemble<3, false><<<nb, BLOCK, 0, s>>>(v, rhs, zx);
+  }
+  return 0;
+}
+
+int launch_cg_spmv(const View& v, int precision, hipStream_t s) {
+  const unsigned nt = (unsigned)v.nspmv;
+  if (precision == MPS_MIXED) k_cg_spmv<float><<<nt, BLOCK, 0, s>>>(v);
+  else k_cg_spmv<double><<<nt, BLOCK, 0, s>>>(v);
+  return 0;
+}
+
+int launch_cg_update(const View& v, hipStream_t s) {
+  k_cg_update<<<(unsigned)v.nupd, BLOCK, 0, s>>>(v);
+  return 0;
+}
+
+int launch_export_ppe(const View& v, int precision, double* diag, double* b, int32_t* nnz,
+                      int32_t* cols, double* vals, hipStream_t s) {
+  if (precision == MPS_MIXED)
+    k_export_ppe<float><<<nb_flat(v.n), BLOCK, 0, s>>>(v, diag, b, nnz, cols, vals);
+  else
+    k_export_ppe<double><<<nb_flat(v.n), BLOCK, 0, s>>>(v, diag, b, nnz, cols, vals);
+  return 0;
+}
+
+int launch_scatter_orig(const View& v, const double* src, double* dst, int comps, int stride,
+                        hipStream_t s) {
+  k_to_orig<<<nb_flat(v.n), BLOCK, 0, s>>>(v, src, dst, comps, stride);
+  return 0;
+}
+int launch_gather_orig(const View& v, const double* src, double* dst, int comps, int stride,
+                       hipStream_t s) {
+  k_from_orig<<<nb_flat(v.n), BLOCK, 0, s>>>(v, src, dst, comps, stride);
+  return 0;
+}
+
+}  // namespace mps

@@ -1,0 +1,342 @@
+// Kernel-weighted neighbour sums of one MPS step (arXiv 2105.01677,
+// Section "The Moving Particle Semi-implicit Method"):
+//   k_predict   viscous Laplacian (Eq. 7, radius re_lap) + body force, the
+//               explicit prediction u* = u + dt a, r* = r + dt u* (fluid)
+//   k_density   number density n* at r* (Eq. 5, radius re_n), free-surface
+//               flag n* < beta n0 (Eq. 15); in the weakly-compressible model
+//               also the equation of state (Eq. 16)
+//   k_gradient  p-hat, pressure gradient (standard MPS form or Eq. 18) and
+//               the first-order Euler update
+// Each particle is handled by a team of TEAM lanes that split its neighbour
+// list (see mps_internal.h).  The precision template: FP64 throughout, or
+// MIXED = FP32 distances and sums on positions stored relative to the lower
+// corner of the particle's cell (so the FP32 values are at most one cell
+// side and keep ~1e-7 relative accuracy in the separations), with FP64
+// master state.
+#include "mps_internal.h"
+
+namespace mps {
+
+// Position of a particle as seen by the sums: FP64 absolute, or FP32
+// relative to its anchor cell with the packed cell coordinates.
+template <int DIM, bool MIXED>
+struct PosRef;
+
+template <int DIM>
+struct PosRef<DIM, false> {
+  using R = double;
+  double x[DIM];
+  __device__ static PosRef load(const double* a, const float4*, int64_t i) {
+    PosRef p;
+    load_vec<DIM>(a, i, p.x);
+    return p;
+  }
+  __device__ void diff(const PosRef& o, float, R (&d)[DIM]) const {
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) d[a] = o.x[a] - x[a];
+  }
+};
+
+template <int DIM>
+struct PosRef<DIM, true> {
+  using R = float;
+  float4 f;
+  __device__ static PosRef load(const double*, const float4* a, int64_t i) {
+    PosRef p;
+    p.f = a[i];
+    return p;
+  }
+  __device__ int32_t pc() const { return __float_as_int(DIM == 2 ? f.z : f.w); }
+  __device__ void diff(const PosRef& o, float cs, R (&d)[DIM]) const {
+    const int32_t a = pc(), b = o.pc();
+    d[0] = (o.f.x - f.x) + (float)(ucx(b) - ucx(a)) * cs;
+    d[1] = (o.f.y - f.y) + (float)(ucy(b) - ucy(a)) * cs;
+    if constexpr (DIM == 3) d[2] = (o.f.z - f.z) + (float)(ucz(b) - ucz(a)) * cs;
+  }
+};
+
+template <int DIM, class R>
+__device__ inline R norm2(const R (&d)[DIM]) {
+  R s = d[0] * d[0] + d[1] * d[1];
+  if constexpr (DIM == 3) s += d[2] * d[2];
+  return s;
+}
+
+// FP32 copy of an FP64 position relative to the lower corner of the
+// particle's anchor cell (the cell it was binned in this step).
+template <int DIM>
+__device__ inline float4 to_rel(const View& v, const double (&x)[DIM], int32_t pc) {
+  const int ci[3] = {ucx(pc), ucy(pc), ucz(pc)};
+  float r[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) r[a] = (float)(x[a] - (v.lo[a] + ci[a] * v.cs));
+  return DIM == 2 ? make_float4(r[0], r[1], __int_as_float(pc), 0.f)
+                  : make_float4(r[0], r[1], r[2], __int_as_float(pc));
+}
+
+__device__ inline int64_t team_row() {
+  return (int64_t)xcd_block() * ROWS_PER_BLOCK + threadIdx.x / TEAM;
+}
+
+// a3: u* = u + dt (nu 2d/(lambda n0) sum_j (u_j - u_i) w(r_ij) + g),
+//     r* = r + dt u*  for fluid; other particles keep r and u.
+template <int DIM, bool MIXED>
+__global__ __launch_bounds__(BLOCK) void k_predict(View v) {
+  using P = PosRef<DIM, MIXED>;
+  using R = typename P::R;
+  const int64_t row = team_row();
+  const int t = team_lane();
+  if (row >= v.n) return;
+  double ui[DIM], xi[DIM];
+  load_vec<DIM>(v.vel, row, ui);
+  load_vec<DIM>(v.pos, row, xi);
+  double us[DIM], rs[DIM];
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) { us[a] = ui[a]; rs[a] = xi[a]; }
+  if (v.type[row] == MPS_FLUID) {
+    const P pi = P::load(v.pos, v.posf, row);
+    const R re = (R)v.re_lap;
+    R acc[DIM];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) acc[a] = R(0);
+    const int cnt = v.nb_count[row];
+    for (int l = t; l < cnt; l += TEAM) {
+      const int32_t j = v.nb_list[sl_index(row, l, v.kpad)];
+      R d[DIM];
+      pi.diff(P::load(v.pos, v.posf, j), v.cs32, d);
+      const R w = weight<R>(v.kernel, sqrt(norm2<DIM, R>(d)), re);
+      double uj[DIM];
+      load_vec<DIM>(v.vel, j, uj);
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) acc[a] += (R)(uj[a] - ui[a]) * w;
+    }
+    const double clap = 2.0 * DIM / (v.lam_lap * v.n0_lap);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+      const double lap = (double)team_sum(acc[a]);
+      us[a] = ui[a] + v.dt * (v.nu * clap * lap + v.g[a]);
+      rs[a] = xi[a] + v.dt * us[a];
+    }
+  }
+  if (t == 0) {
+    store_vec<DIM>(v.us, row, us);
+    store_vec<DIM>(v.rs, row, rs);
+    if constexpr (MIXED) v.rsf[row] = to_rel<DIM>(v, rs, v.pcell[row]);
+  }
+}
+
+// Integer power by multiplication (Eq. 16 uses gamma = 7).
+__device__ inline double ipow(double x, int e) {
+  double r = 1.0;
+  for (int k = 0; k < e; ++k) r *= x;
+  return r;
+}
+
+// a4 (+a7): n*_i = sum_j w(|r*_j - r*_i|) over the list within re_n; flags;
+// equation of state p = rho c0^2/gamma ((n*/n0)^gamma - 1) for fluid and
+// wall in the weakly-compressible model.
+// Always FP64, also on the mixed path: the pressure source (n* - n0)/n0 of
+// Eq. 13 and the EOS (Eq. 16) amplify the rounding of n*, and from rest
+// n* - n0 is of the order of the FP32 rounding of n* itself.  In 2-D the
+// FP64 position (double2) is as wide as the FP32 copy (float4), so this
+// costs no extra bytes.
+template <int DIM>
+__global__ __launch_bounds__(BLOCK) void k_density(View v, int wc) {
+  using P = PosRef<DIM, false>;
+  using R = typename P::R;
+  const int64_t row = team_row();
+  const int t = team_lane();
+  if (row >= v.n) return;
+  const int8_t ty = v.type[row];
+  R s = R(0);
+  if (ty != MPS_GHOST) {
+    const P pi = P::load(v.rs, v.rsf, row);
+    const R re = (R)v.re_n, re2 = (R)v.re_n2;
+    const int cnt = v.nb_count[row];
+    for (int l = t; l < cnt; l += TEAM) {
+      const int32_t j = v.nb_list[sl_index(row, l, v.kpad)];
+      R d[DIM];
+      pi.diff(P::load(v.rs, v.rsf, j), v.cs32, d);
+      const R r2 = norm2<DIM, R>(d);
+      if (r2 < re2) s += weight<R>(v.kernel, sqrt(r2), re);
+    }
+    s = team_sum(s);
+  }
+  if (t != 0) return;
+  const double ns = (double)s;
+  int8_t fl;
+  if (ty == MPS_GHOST) fl = MPS_FLAG_GHOST;
+  else if (ty == MPS_DUMMY) fl = MPS_FLAG_DUMMY;
+  else fl = ns < v.beta * v.n0_n ? MPS_FLAG_SURFACE : MPS_FLAG_INNER;
+  v.nstar[row] = ns;
+  v.flags[row] = fl;
+  if (wc) {
+    double p = 0.0;
+    if (ty == MPS_FLUID || ty == MPS_WALL) {
+      const double B = v.rho * v.c0 * v.c0 / (double)v.gamma_i;
+      p = B * (ipow(ns / v.n0_n, v.gamma_i) - 1.0);
+      if (v.clamp && p < 0.0) p = 0.0;
+    }
+    v.p[row] = p;
+  }
+}
+
+// p <- max(p, 0) after the PPE solve.
+__global__ __launch_bounds__(BLOCK) void k_clamp(View v) {
+  const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= v.n) return;
+  const double p = v.p[i];
+  if (p < 0.0) v.p[i] = 0.0;
+}
+
+// p-hat of every fluid and wall particle (needed by Eq. 18 for both ends of
+// a pair): minimum of p over i and its non-dummy neighbours within re_n.
+template <int DIM, bool MIXED>
+__global__ __launch_bounds__(BLOCK) void k_phat(View v, double* phat) {
+  using P = PosRef<DIM, MIXED>;
+  using R = typename P::R;
+  const int64_t row = team_row();
+  const int t = team_lane();
+  if (row >= v.n) return;
+  const int8_t ty = v.type[row];
+  double m = v.p[row];
+  if (ty == MPS_FLUID || ty == MPS_WALL) {
+    const P pi = P::load(v.rs, v.rsf, row);
+    const R re2 = (R)v.re_n2;
+    const int cnt = v.nb_count[row];
+    for (int l = t; l < cnt; l += TEAM) {
+      const int32_t j = v.nb_list[sl_index(row, l, v.kpad)];
+      if (v.type[j] == MPS_DUMMY) continue;
+      R d[DIM];
+      pi.diff(P::load(v.rs, v.rsf, j), v.cs32, d);
+      if (norm2<DIM, R>(d) < re2) m = fmin(m, v.p[j]);
+    }
+    m = team_min(m);
+  }
+  if (t == 0) phat[row] = m;
+}
+
+// a8: grad p_i = d/n0 sum_j num_ij / r^2 (r*_j - r*_i) w(r) over non-dummy j
+// within re_n, num = p_j - phat_i (standard) or (p_i + p_j) - (phat_i +
+// phat_j) (Eq. 18); u = u* - dt/rho grad p, r = r* + dt (u - u*).
+template <int DIM, bool MIXED, bool CMPS>
+__global__ __launch_bounds__(BLOCK) void k_gradient(View v, const double* phat) {
+  using P = PosRef<DIM, MIXED>;
+  using R = typename P::R;
+  const int64_t row = team_row();
+  const int t = team_lane();
+  if (row >= v.n) return;
+  if (v.type[row] != MPS_FLUID) return;
+  const P pi = P::load(v.rs, v.rsf, row);
+  const R re = (R)v.re_n, re2 = (R)v.re_n2;
+  const int cnt = v.nb_count[row];
+  const double p_i = v.p[row];
+  double ph_i;
+  if constexpr (CMPS) {
+    ph_i = phat[row];
+  } else {
+    double m = p_i;
+    for (int l = t; l < cnt; l += TEAM) {
+      const int32_t j = v.nb_list[sl_index(row, l, v.kpad)];
+      if (v.type[j] == MPS_DUMMY) continue;
+      R d[DIM];
+      pi.diff(P::load(v.rs, v.rsf, j), v.cs32, d);
+      if (norm2<DIM, R>(d) < re2) m = fmin(m, v.p[j]);
+    }
+    ph_i = team_min(m);
+  }
+  R gs[DIM];
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) gs[a] = R(0);
+  for (int l = t; l < cnt; l += TEAM) {
+    const int32_t j = v.nb_list[sl_index(row, l, v.kpad)];
+    if (v.type[j] == MPS_DUMMY) continue;
+    R d[DIM];
+    pi.diff(P::load(v.rs, v.rsf, j), v.cs32, d);
+    const R r2 = norm2<DIM, R>(d);
+    if (!(r2 < re2)) continue;
+    const R w = weight<R>(v.kernel, sqrt(r2), re);
+    double num;
+    if constexpr (CMPS) num = (p_i + v.p[j]) - (ph_i + phat[j]);
+    else num = v.p[j] - ph_i;
+    const R f = (R)num / r2 * w;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) gs[a] += f * d[a];
+  }
+  double us[DIM], rs[DIM], un[DIM], xn[DIM];
+  load_vec<DIM>(v.us, row, us);
+  load_vec<DIM>(v.rs, row, rs);
+  const double cg = (double)DIM / v.n0_n;
+  bool finite = true;
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    const double gp = cg * (double)team_sum(gs[a]);
+    un[a] = us[a] - v.dt / v.rho * gp;
+    xn[a] = rs[a] + v.dt * (un[a] - us[a]);
+    finite = finite && isfinite(un[a]) && isfinite(xn[a]);
+  }
+  if (t == 0) {
+    store_vec<DIM>(v.vel_w, row, un);
+    store_vec<DIM>(v.pos_w, row, xn);
+    if (!finite) atomicOr(v.status, ST_NONFINITE);
+  }
+}
+
+static inline unsigned team_blocks(int64_t n) {
+  return (unsigned)((n + ROWS_PER_BLOCK - 1) / ROWS_PER_BLOCK);
+}
+
+int launch_predict(const View& v, int dim, int precision, hipStream_t s) {
+  const unsigned nb = team_blocks(v.n);
+  const bool mx = precision == MPS_MIXED;
+  if (dim == 2) {
+    if (mx) k_predict<2, true><<<nb, BLOCK, 0, s>>>(v);
+    else k_predict<2, false><<<nb, BLOCK, 0, s>>>(v);
+  } else {
+    if (mx) k_predict<3, true><<<nb, BLOCK, 0, s>>>(v);
+    else k_predict<3, false><<<nb, BLOCK, 0, s>>>(v);
+  }
+  return 0;
+}
+
+int launch_density(const View& v, int dim, int precision, int pmode, hipStream_t s) {
+  const unsigned nb = team_blocks(v.n);
+  const bool mx = precision == MPS_MIXED;
+  const int wc = pmode == MPS_WC_EOS;
+  (void)mx;
+  if (dim == 2) k_density<2><<<nb, BLOCK, 0, s>>>(v, wc);
+  else k_density<3><<<nb, BLOCK, 0, s>>>(v, wc);
+  return 0;
+}
+
+int launch_clamp(const View& v, hipStream_t s) {
+  k_clamp<<<(unsigned)((v.n + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(v);
+  return 0;
+}
+
+template <int DIM, bool MIXED>
+static void gradient_dim(const View& v, hipStream_t s) {
+  const unsigned nb = team_blocks(v.n);
+  if (v.grad == MPS_GRAD_CMPS) {
+    // the CG residual buffer is free at this point of the step
+    double* phat = v.r;
+    k_phat<DIM, MIXED><<<nb, BLOCK, 0, s>>>(v, phat);
+    k_gradient<DIM, MIXED, true><<<nb, BLOCK, 0, s>>>(v, phat);
+  } else {
+    k_gradient<DIM, MIXED, false><<<nb, BLOCK, 0, s>>>(v, nullptr);
+  }
+}
+
+int launch_gradient(const View& v, int dim, int precision, hipStream_t s) {
+  const bool mx = precision == MPS_MIXED;
+  if (dim == 2) {
+    if (mx) gradient_dim<2, true>(v, s);
+    else gradient_dim<2, false>(v, s);
+  } else {
+    if (mx) gradient_dim<3, true>(v, s);
+    else gradient_dim<3, false>(v, s);
+  }
+  return 0;
+}
+
+}  // namespace mps
