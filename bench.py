@@ -93,7 +93,7 @@ def run_gpu(w, steps, warmup, *, profile_all=False, profile_cls=None):
     import torch
 
     from paper_2105_01677_amd import mps
-    m = mps.MPS(w.params, w.pos, w.vel, w.ptype)
+    m = mps.MPS(w.params, w.pos, w.vel, w.ptype, rho_i=w.rho_i, nu_i=w.nu_i)
     if warmup:
         m.step(warmup)
     if profile_all:
@@ -110,6 +110,37 @@ def run_gpu(w, steps, warmup, *, profile_all=False, profile_cls=None):
     dt = t1 - t0
     return {"seconds": dt, "ms_per_step": 1e3 * dt / steps,
             "particle_steps_per_s": w.n * steps / dt, "stats": s, "profile": prof}
+
+
+def kernel_bandwidth(w, r, mixed, wc):
+    """Per kernel class: ms per step and algorithmic GB/s (HIP events)."""
+    s = r["stats"]
+    out = {}
+    for k, (ms, nl) in r["profile"].items():
+        if nl == 0:
+            continue
+        avg = ms / nl
+        b = algorithmic_bytes(k, w.n, s["list_entries"], s["ppe_nnz"], w.params["dim"], mixed, wc)
+        out[k] = {"avg_launch_us": 1e3 * avg, "launches": nl, "algorithmic_GBps": b / (avg * 1e-3) / 1e9,
+                  "hbm_frac": b / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    return out
+
+
+def run_3d(name, w, steps, warmup):
+    """A 3-D configuration: timed steps (graphs) and an event-timed pass."""
+    c = w.counts()
+    log(f"{name}: {c}")
+    r = run_gpu(w, steps, warmup)
+    br = run_gpu(w, steps, warmup, profile_all=True)
+    mixed = w.params["precision"] == 1
+    res = {"n_particles": w.n, "n_fluid": c["fluid"], "steps": steps,
+           "value": r["particle_steps_per_s"], "ms_per_step": r["ms_per_step"],
+           "cg_iters_mean": r["stats"]["cg_iters_total"] / steps,
+           "kernels": kernel_bandwidth(w, br, mixed, w.params["pmode"] == 1)}
+    log(name, {k: v for k, v in res.items() if k != "kernels"})
+    for k, v in res["kernels"].items():
+        log(f"   {k:10s} {v['avg_launch_us']:9.2f} us  {v['algorithmic_GBps']:8.1f} GB/s")
+    return res
 
 
 def cpu_baseline(w, seconds):
@@ -141,10 +172,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 3-D configurations")
+    ap.add_argument("--steps-3d", type=int, default=20)
     ap.add_argument("--only-headline", action="store_true",
                     help="time the headline configuration only (for profilers)")
     ap.add_argument("--calib-copy", action="store_true",
-                    help="first copy a 64 MiB buffer once (reference kernel for HBM counters)")
+                    help="first copy a cold 1 GiB buffer once (reference kernel for HBM counters)")
     ap.add_argument("--only", default=None,
                     help="time one configuration only, e.g. ppe:mixed, wc:fp64 (for profilers)")
     args = ap.parse_args()
@@ -162,12 +195,15 @@ def main():
         sys.exit(1)
     K, Wm = args.steps, args.warmup
     if args.calib_copy:
-        # a plain device copy of known size: reads and writes 64 MiB
-        a = torch.ones(16 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        # a plain device copy of known size, 1 GiB read + 1 GiB written, from
+        # a source evicted from L2 and the Infinity Cache by another 1 GiB fill
+        a = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        flush = torch.zeros_like(a)
         b = torch.empty_like(a)
+        torch.cuda.synchronize()
         b.copy_(a)
         torch.cuda.synchronize()
-        del a, b
+        del a, b, flush
     if args.only:
         pm, pr = args.only.split(":")
         wo = W.config("cfg2", pmode=W.PPE_CG if pm == "ppe" else W.WC_EOS,
@@ -207,13 +243,26 @@ def main():
 
     extra = {}
     if not args.only_headline:
-        for name, prec, pm in (("ppe_fp64", W.FP64, W.PPE_CG), ("wc_mixed", W.MIXED, W.WC_EOS),
-                               ("wc_fp64", W.FP64, W.WC_EOS)):
+        for name, prec, pm, pl in (("ppe_fp64", W.FP64, W.PPE_CG, 0),
+                                   ("ppe_mixed_pipelined", W.MIXED, W.PPE_CG, 1),
+                                   ("ppe_fp64_pipelined", W.FP64, W.PPE_CG, 1),
+                                   ("wc_mixed", W.MIXED, W.WC_EOS, 0),
+                                   ("wc_fp64", W.FP64, W.WC_EOS, 0)):
             wx = W.config("cfg2", precision=prec, pmode=pm)
+            wx.params["cg_pipelined"] = pl
             r = run_gpu(wx, K, Wm)
             extra[name] = {"value": r["particle_steps_per_s"], "ms_per_step": r["ms_per_step"],
                            "cg_iters_mean": r["stats"]["cg_iters_total"] / K}
             log(name, extra[name])
+
+    cfg3d = {}
+    if not args.only_headline and not args.no_3d:
+        w3 = W.config("cfg3", precision=W.MIXED)
+        w3.params["cg_pipelined"] = 1
+        cfg3d["dam_break_3d_l0=0.007"] = run_3d("dam_break_3d", w3, args.steps_3d, 2)
+        w5 = W.config("cfg5", precision=W.MIXED)
+        w5.params["cg_pipelined"] = 1
+        cfg3d["two_phase_3d_l0=0.005"] = run_3d("two_phase_3d", w5, max(args.steps_3d // 2, 2), 1)
 
     out = {
         "metric": METRIC,
@@ -234,6 +283,8 @@ def main():
         "fluid_particle_steps_per_s": c["fluid"] * K / hd["seconds"],
         "cg_iters_mean": s["cg_iters_total"] / K,
         "fp64_plain": extra.get("ppe_fp64"),
+        "mixed_pipelined_cg": extra.get("ppe_mixed_pipelined"),
+        "fp64_pipelined_cg": extra.get("ppe_fp64_pipelined"),
         "wc_eos_mixed": extra.get("wc_mixed"),
         "wc_eos_fp64": extra.get("wc_fp64"),
         "kernel_ms_per_step": {k: v / K for k, v in tot.items()},
@@ -244,6 +295,7 @@ def main():
                      "bytes_per_launch": nbytes, "avg_launch_ms": avg_ms,
                      "launches": n_dom},
         "cpu_baseline": None,
+        "configs_3d": cfg3d,
     }
     if not args.no_cpu and not args.only_headline:
         log("cpu baseline ...")

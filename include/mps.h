@@ -80,7 +80,9 @@ typedef struct {
   int32_t max_neigh;        /* neighbour cap, 1..1024 (the paper uses 300) */
   int32_t cg_maxit;         /* CG iteration limit */
   int32_t grid_n[3];        /* background grid cells per axis (1 for unused) */
-  int32_t pad_;
+  int32_t cg_pipelined;     /* 0: CG with two kernels (two reductions) per
+                               iteration; 1: pipelined CG, one kernel and one
+                               reduction per iteration (same solution) */
   double l0;                /* initial particle spacing (m) */
   double re_n;              /* radius for number density, flags, gradient (m) */
   double re_lap;            /* radius for the Laplacian (viscous, PPE) (m) */
@@ -96,7 +98,8 @@ typedef struct {
   double cg_tol;            /* stop when ||b - A p|| <= cg_tol ||b|| */
   double grid_lo[3];        /* lower corner of the background grid (m) */
   double cell_size;         /* cell side, >= re_lap (m) */
-  double smagorinsky_cs;    /* reserved, must be 0 */
+  double smagorinsky_cs;    /* Smagorinsky constant Cs of the sub-particle-scale
+                               eddy viscosity (0 = off; 0.12 typical) */
 } mps_params;
 
 typedef struct {
@@ -120,8 +123,18 @@ enum {
 };
 
 /* Create a context for n particles.  pos, vel: [n][dim] FP64; type: [n]
- * int8 (MPS_FLUID, MPS_WALL or MPS_DUMMY).  rho_i and nu_i are reserved and
- * must be NULL.  hip_stream is a hipStream_t (NULL = default stream).
+ * int8 (MPS_FLUID, MPS_WALL or MPS_DUMMY).  rho_i, nu_i: [n] per-particle
+ * density and laminar kinematic viscosity, or NULL for params->rho / nu.
+ * Any of them, or smagorinsky_cs > 0, selects the two-phase / turbulence
+ * model (Section "Fluid flow models"): each particle carries a smoothed
+ * density <rho>_i = sum_j rho_j w / sum_j w over non-dummy neighbours
+ * (re_n), computed here once; the viscous term uses the harmonic mean of
+ * the dynamic viscosities mu = <rho>(nu_i + nu_t) with the Smagorinsky
+ * eddy viscosity nu_t = (Cs l0)^2 sqrt(2 S:S) (Eq. for tau/rho with the
+ * k term absorbed into the pressure); the PPE coupling uses
+ * 2/(<rho>_i + <rho>_j) and the update 1/<rho>_i.
+ * hip_stream is a hipStream_t (NULL = default stream; step stages are then
+ * launched one by one instead of as HIP graphs).
  * Errors: MPS_E_ARG (bad parameters: dim, radii, grid, cap, n < 1, gamma
  * not integer), MPS_E_NOMEM, MPS_E_DEVICE. */
 mps_status mps_init(const mps_params* params, int64_t n, const double* pos,
@@ -180,11 +193,51 @@ mps_status mps_get_state(mps_ctx* ctx, double* pos, double* vel, double* p,
 mps_status mps_set_state(mps_ctx* ctx, const double* pos, const double* vel,
                          const int8_t* type);
 
+/* Two-phase model: smoothed density <rho> and Smagorinsky eddy viscosity
+ * nu_t of the last step, [n] each in original order (device; either may be
+ * NULL).  Errors: MPS_E_ARG for a single-phase context. */
+mps_status mps_get_phase(mps_ctx* ctx, double* rho_s, double* nu_t);
+
 /* The lattice constants the context uses: n0 for re_n and re_lap, lambda
  * for re_lap (Eq. 5 and the weighted mean of r^2 of Eq. 7 at an interior
  * particle of the initial lattice).  Host pointers, any may be NULL. */
 mps_status mps_constants(const mps_ctx* ctx, double* n0_n, double* n0_lap,
                          double* lambda_lap);
+
+/* ------------------------------------------------------------ adjoint
+ * Reverse-mode derivative of the step (hand-written adjoint kernels), for
+ * gradients of a loss on a final state with respect to the viscosity nu,
+ * the body acceleration g and the initial velocities.  Lists, free-surface
+ * flags, the p-hat argmin and the clamp masks of each step are frozen.  In
+ * the PPE model the adjoint of the pressure solve is the transposed solve
+ * A lambda = x-bar, run with the same CG kernels (A is symmetric).  The
+ * standard pressure gradient is supported (grad = MPS_GRAD_STD).
+ * Typical use (checkpointing every K steps): save a slot every K steps in
+ * the forward run; for each segment in reverse, load its checkpoint,
+ * re-run the K steps saving each step's input state, then walk back with
+ * mps_tape_load + mps_step_adjoint. */
+
+/* Allocate nslots state slots (positions, velocities, pressure, types of
+ * the context's particle storage) and the adjoint work arrays.  Frees any
+ * previous tape.  Errors: MPS_E_ARG, MPS_E_NOMEM. */
+mps_status mps_tape_alloc(mps_ctx* ctx, int32_t nslots);
+
+/* Copy the current state into / from a slot (stream-ordered, no sync).
+ * Errors: MPS_E_ARG (bad slot, or loading a slot never saved). */
+mps_status mps_tape_save(mps_ctx* ctx, int32_t slot);
+mps_status mps_tape_load(mps_ctx* ctx, int32_t slot);
+
+/* Adjoint of one step taken from the CURRENT state (r^k, u^k): given the
+ * cotangents pos_bar, vel_bar of the step's output (r^{k+1}, u^{k+1}),
+ * returns those of its input in pos_bar_prev, vel_bar_prev (device,
+ * original order, [n][dim] FP64; may not alias the inputs) and this step's
+ * contributions to dL/dnu (*nu_bar, host) and dL/dg (g_bar[dim], host);
+ * either may be NULL.  Recomputes the step's forward stages first; the
+ * state is not advanced.  Errors: MPS_E_ARG (no tape, CMPS gradient),
+ * the errors of mps_step. */
+mps_status mps_step_adjoint(mps_ctx* ctx, const double* pos_bar, const double* vel_bar,
+                            double* pos_bar_prev, double* vel_bar_prev, double* nu_bar,
+                            double* g_bar);
 
 /* Per-kernel timing: when bit k of class_mask is set, every launch of
  * kernel class k (MPS_KC_*) is bracketed by a pair of HIP events on the

@@ -49,7 +49,7 @@ class OrcStepOut(C.Structure):
         ("us", C.c_void_p), ("rs", C.c_void_p), ("nstar", C.c_void_p),
         ("flags", C.c_void_p), ("diag", C.c_void_p), ("b", C.c_void_p),
         ("aval", C.c_void_p), ("p", C.c_void_p), ("phat", C.c_void_p),
-        ("gradp", C.c_void_p), ("pos", C.c_void_p), ("vel", C.c_void_p),
+        ("gradp", C.c_void_p), ("nut", C.c_void_p), ("pos", C.c_void_p), ("vel", C.c_void_p),
         ("type", C.c_void_p), ("cg_iters", C.c_int32), ("cg_relres", C.c_double),
     ]
 
@@ -74,9 +74,13 @@ def lib():
         L.orc_neighbors_cells.argtypes = [C.POINTER(OrcParams), C.c_int64, C.c_void_p,
                                           C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.orc_step.argtypes = [C.POINTER(OrcParams), C.c_int64, C.c_void_p, C.c_void_p,
-                               C.c_void_p, C.c_void_p, C.POINTER(OrcStepOut)]
+                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                               C.POINTER(OrcStepOut)]
         L.orc_run.argtypes = [C.POINTER(OrcParams), C.c_int64, C.c_void_p, C.c_void_p,
-                              C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
+                              C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                              C.c_void_p]
+        L.orc_smoothed_density.argtypes = [C.POINTER(OrcParams), C.c_int64, C.c_void_p,
+                                           C.c_void_p, C.c_void_p, C.c_void_p]
         _lib = L
     return _lib
 
@@ -138,8 +142,12 @@ def neighbors_cells(params, pos, ptype):
     return st, cell, cnt, lst
 
 
+def _opt(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
 def step(params, pos, vel, ptype, flags_override=None, *, want_lists=True,
-         want_matrix=False):
+         want_matrix=False, rho_s=None, nu_i=None):
     """One time step.  Returns (status, dict of fields)."""
     P, pos, ptype = _prep(params, pos, ptype)
     vel = np.ascontiguousarray(vel, dtype=np.float64)
@@ -152,6 +160,7 @@ def step(params, pos, vel, ptype, flags_override=None, *, want_lists=True,
         "nstar": np.zeros(n), "flags": np.zeros(n, np.int8),
         "diag": np.zeros(n), "b": np.zeros(n),
         "p": np.zeros(n), "phat": np.zeros(n), "gradp": np.zeros((n, dim)),
+        "nut": np.zeros(n),
         "pos": np.zeros((n, dim)), "vel": np.zeros((n, dim)),
         "type": np.zeros(n, np.int8),
     }
@@ -165,14 +174,15 @@ def step(params, pos, vel, ptype, flags_override=None, *, want_lists=True,
     fo = None
     if flags_override is not None:
         fo = np.ascontiguousarray(flags_override, dtype=np.int8)
+    rs_, nu_ = _opt(rho_s), _opt(nu_i)
     st = lib().orc_step(C.byref(P), n, _ptr(pos), _ptr(vel), _ptr(ptype), _ptr(fo),
-                        C.byref(so))
+                        _ptr(rs_), _ptr(nu_), C.byref(so))
     out["cg_iters"] = so.cg_iters
     out["cg_relres"] = so.cg_relres
     return st, out
 
 
-def run(params, pos, vel, ptype, nsteps):
+def run(params, pos, vel, ptype, nsteps, *, rho_s=None, nu_i=None):
     """nsteps time steps; returns (status, pos, vel, type, p, flags)."""
     P, pos, ptype = _prep(params, pos, ptype)
     pos = pos.copy()
@@ -181,8 +191,9 @@ def run(params, pos, vel, ptype, nsteps):
     n = pos.shape[0]
     p = np.zeros(n)
     fl = np.zeros(n, np.int8)
+    rs_, nu_ = _opt(rho_s), _opt(nu_i)
     st = lib().orc_run(C.byref(P), n, _ptr(pos), _ptr(vel), _ptr(ptype), int(nsteps),
-                       _ptr(p), _ptr(fl))
+                       _ptr(rs_), _ptr(nu_), _ptr(p), _ptr(fl))
     return st, pos, vel, ptype, p, fl
 
 
@@ -199,3 +210,40 @@ def pressure_gradient(params, rs, ptype, p):
     st = L.orc_pressure_gradient(C.byref(P), n, _ptr(rs), _ptr(ptype), _ptr(p),
                                  _ptr(phat), _ptr(gp))
     return st, phat, gp
+
+
+def rollout_grad(params, pos, vel, ptype, nsteps, direction, w_ke=1.0, w_var=9.81):
+    """(status, L, dL/dnu, dL/dgx, <dL/du0, direction>) by dual numbers."""
+    P, pos, ptype = _prep(params, pos, ptype)
+    vel = np.ascontiguousarray(vel, dtype=np.float64)
+    d = np.ascontiguousarray(direction, dtype=np.float64)
+    out = np.zeros(4)
+    L = lib()
+    L.orc_rollout_grad.argtypes = [C.POINTER(OrcParams), C.c_int64, C.c_void_p, C.c_void_p,
+                                   C.c_void_p, C.c_int32, C.c_void_p, C.c_double, C.c_double,
+                                   C.c_void_p]
+    st = L.orc_rollout_grad(C.byref(P), pos.shape[0], _ptr(pos), _ptr(vel), _ptr(ptype),
+                            int(nsteps), _ptr(d), float(w_ke), float(w_var), _ptr(out))
+    return st, out[0], out[1], out[2], out[3]
+
+
+def loss(params, pos, vel, ptype, flags, w_ke=1.0, w_var=9.81):
+    P, pos, ptype = _prep(params, pos, ptype)
+    vel = np.ascontiguousarray(vel, dtype=np.float64)
+    fl = np.ascontiguousarray(flags, dtype=np.int8)
+    L = lib()
+    L.orc_loss.argtypes = [C.POINTER(OrcParams), C.c_int64, C.c_void_p, C.c_void_p,
+                           C.c_void_p, C.c_void_p, C.c_double, C.c_double]
+    L.orc_loss.restype = C.c_double
+    return L.orc_loss(C.byref(P), pos.shape[0], _ptr(pos), _ptr(vel), _ptr(ptype), _ptr(fl),
+                      float(w_ke), float(w_var))
+
+
+def smoothed_density(params, pos, ptype, rho_i):
+    """(status, <rho>[n]) of the two-phase model."""
+    P, pos, ptype = _prep(params, pos, ptype)
+    r = np.ascontiguousarray(rho_i, dtype=np.float64)
+    out = np.zeros(pos.shape[0])
+    st = lib().orc_smoothed_density(C.byref(P), pos.shape[0], _ptr(pos), _ptr(ptype), _ptr(r),
+                                    _ptr(out))
+    return st, out

@@ -344,7 +344,7 @@ struct PPESolve<Dual<K>> {
 /* ------------------------------------------------------------ the step */
 template <class T>
 struct Trace {
-  std::vector<T> us, rs, nstar, p, phat, gradp, diag, b;
+  std::vector<T> us, rs, nstar, p, phat, gradp, diag, b, nut;
   std::vector<T> aval;   // aligned with the list CSR
   std::vector<int8_t> flags;
   std::vector<int> cell;
@@ -426,11 +426,17 @@ void pressure_gradient(const orc_params* P, const Consts& C, int n,
 template <class T>
 int step(const orc_params* P, const Consts& C, const T& nu, const T g[3], int n,
          std::vector<T>& pos, std::vector<T>& vel, std::vector<int8_t>& type,
-         const int8_t* flags_override, Trace<T>& tr) {
+         const int8_t* flags_override, Trace<T>& tr, const double* rho_s = nullptr,
+         const double* nu_i = nullptr) {
   const int dim = P->dim;
   const double dt = P->dt;
   const double rho = P->rho;
   int status = 0;
+  /* Two-phase / turbulence extension (Section "Fluid flow models"): per
+   * particle smoothed density <rho>_i (fixed before the run) and laminar
+   * viscosity nu_i, Smagorinsky eddy viscosity when smag_cs > 0. */
+  const bool multi = rho_s || nu_i || P->smag_cs > 0.0;
+  auto rho_of = [&](int i) { return rho_s ? rho_s[i] : rho; };
 
   /* 1. Ghosts: particles outside the grid leave the simulation. */
   std::vector<double> x0((size_t)n * dim);
@@ -452,6 +458,50 @@ int step(const orc_params* P, const Consts& C, const T& nu, const T g[3], int n,
   const double clap = 2.0 * dim / (C.lam_lap * C.n0_lap);
   tr.us.assign((size_t)n * dim, T(0.0));
   tr.rs.assign((size_t)n * dim, T(0.0));
+  /* 3a. Smagorinsky eddy viscosity nu_t = (Cs l0)^2 sqrt(2 S:S) of fluid
+   *     particles, S the symmetric part of the MPS velocity gradient
+   *     grad u_i = d/n0 sum_j (u_j - u_i) (r_j - r_i)^T w(r)/r^2 (re_n, r^k);
+   *     mu_i = <rho>_i (nu_i + nu_t,i). */
+  std::vector<T> mu;
+  tr.nut.assign(n, T(0.0));
+  if (multi) {
+    mu.assign(n, T(0.0));
+    const double cs2 = (P->smag_cs * P->l0) * (P->smag_cs * P->l0);
+#pragma omp parallel for schedule(guided)
+    for (int i = 0; i < n; ++i) {
+      if (type[i] == GHOST) continue;
+      T nut(0.0);
+      if (P->smag_cs > 0.0 && type[i] == FLUID) {
+        T G[3][3];
+        for (int a = 0; a < 3; ++a)
+          for (int b = 0; b < 3; ++b) G[a][b] = T(0.0);
+        const T* ri = &pos[(size_t)i * dim];
+        const T* ui = &vel[(size_t)i * dim];
+        for (int e = Ls[i]; e < Ls[i + 1]; ++e) {
+          int j = Lj[e];
+          const T* rj = &pos[(size_t)j * dim];
+          const T* uj = &vel[(size_t)j * dim];
+          T d[3], d2(0.0);
+          for (int a = 0; a < dim; ++a) { d[a] = rj[a] - ri[a]; d2 = d2 + d[a] * d[a]; }
+          T r = sqrt(d2);
+          if (!(val(r) < P->re_n)) continue;
+          T f = weight(P->kernel, r, P->re_n) / d2;
+          for (int a = 0; a < dim; ++a)
+            for (int b = 0; b < dim; ++b) G[a][b] = G[a][b] + (uj[a] - ui[a]) * d[b] * f;
+        }
+        T ss(0.0);
+        for (int a = 0; a < dim; ++a)
+          for (int b = 0; b < dim; ++b) {
+            T sab = 0.5 * (G[a][b] + G[b][a]) * ((double)dim / C.n0_n);
+            ss = ss + sab * sab;
+          }
+        if (val(ss) > 0.0) nut = cs2 * sqrt(2.0 * ss);
+      }
+      tr.nut[i] = nut;
+      T nui = nu_i ? T(nu_i[i]) : nu;
+      mu[i] = rho_of(i) * (nui + nut);
+    }
+  }
 #pragma omp parallel for schedule(guided)
   for (int i = 0; i < n; ++i) {
     const T* ri = &pos[(size_t)i * dim];
@@ -469,10 +519,16 @@ int step(const orc_params* P, const Consts& C, const T& nu, const T g[3], int n,
       T d2(0.0);
       for (int a = 0; a < dim; ++a) { T d = rj[a] - ri[a]; d2 = d2 + d * d; }
       T w = weight(P->kernel, sqrt(d2), P->re_lap);
+      if (multi) {
+        /* harmonic mean of the dynamic viscosities of the pair */
+        T ms = mu[i] + mu[j];
+        T muij = val(ms) > 0.0 ? 2.0 * mu[i] * mu[j] / ms : T(0.0);
+        w = w * muij;
+      }
       for (int a = 0; a < dim; ++a) lap[a] = lap[a] + (uj[a] - ui[a]) * w;
     }
     for (int a = 0; a < dim; ++a) {
-      T acc = nu * clap * lap[a] + g[a];
+      T acc = multi ? clap * lap[a] / rho_of(i) + g[a] : nu * clap * lap[a] + g[a];
       T u = ui[a] + dt * acc;
       tr.us[(size_t)i * dim + a] = u;
       tr.rs[(size_t)i * dim + a] = ri[a] + dt * u;
@@ -529,6 +585,7 @@ int step(const orc_params* P, const Consts& C, const T& nu, const T g[3], int n,
           T r = dist(i, j);
           if (!(val(r) < P->re_lap)) continue;
           T c = cpp * weight(P->kernel, r, P->re_lap);
+          if (multi) c = c * (rho * 2.0 / (rho_of(i) + rho_of(j)));
           dsum = dsum + c;
           if (tr.flags[j] == FL_INNER) {
             col.push_back(j);
@@ -550,11 +607,12 @@ int step(const orc_params* P, const Consts& C, const T& nu, const T g[3], int n,
   } else {
     /* Equation of state (Eq. 16): p = rho c0^2/gamma ((n* / n0)^gamma - 1)
      * for fluid and wall particles. */
-    const double B = rho * P->c0 * P->c0 / P->gamma;
     const int ge = (int)P->gamma;
     for (int i = 0; i < n; ++i)
-      if (type[i] == FLUID || type[i] == WALL)
+      if (type[i] == FLUID || type[i] == WALL) {
+        const double B = rho_of(i) * P->c0 * P->c0 / P->gamma;
         tr.p[i] = B * (ipow(tr.nstar[i] / C.n0_n, ge) - 1.0);
+      }
   }
   if (P->clamp)
     for (int i = 0; i < n; ++i)
@@ -569,13 +627,50 @@ int step(const orc_params* P, const Consts& C, const T& nu, const T g[3], int n,
     for (int a = 0; a < dim; ++a) {
       size_t k = (size_t)i * dim + a;
       if (type[i] == FLUID) {
-        T u = tr.us[k] - dt / rho * tr.gradp[k];
+        T u = tr.us[k] - dt / rho_of(i) * tr.gradp[k];
         pos[k] = tr.rs[k] + dt * (u - tr.us[k]);
         vel[k] = u;
       }
     }
   }
   return status;
+}
+
+/* Loss of a final state: w_ke * mean over active fluid of |u|^2/2 plus
+ * w_var * the variance of the vertical coordinate over the fluid particles
+ * flagged free surface in the last step (that set is frozen). */
+template <class T>
+T final_loss(int n, int dim, const std::vector<T>& pos, const std::vector<T>& vel,
+             const std::vector<int8_t>& type, const std::vector<int8_t>& flags, double w_ke,
+             double w_var) {
+  T ke(0.0);
+  int nf = 0;
+  for (int i = 0; i < n; ++i) {
+    if (type[i] != FLUID) continue;
+    T s(0.0);
+    for (int a = 0; a < dim; ++a) s = s + vel[(size_t)i * dim + a] * vel[(size_t)i * dim + a];
+    ke = ke + 0.5 * s;
+    ++nf;
+  }
+  ke = ke / (double)(nf > 0 ? nf : 1);
+  T mean(0.0);
+  int ns = 0;
+  for (int i = 0; i < n; ++i)
+    if (type[i] == FLUID && flags[i] == FL_SURFACE) {
+      mean = mean + pos[(size_t)i * dim + dim - 1];
+      ++ns;
+    }
+  T var(0.0);
+  if (ns > 0) {
+    mean = mean / (double)ns;
+    for (int i = 0; i < n; ++i)
+      if (type[i] == FLUID && flags[i] == FL_SURFACE) {
+        T d = pos[(size_t)i * dim + dim - 1] - mean;
+        var = var + d * d;
+      }
+    var = var / (double)ns;
+  }
+  return w_ke * ke + w_var * var;
 }
 
 void to_params(const orc_params* P, double* nu, double g[3]) {
@@ -641,7 +736,8 @@ int orc_neighbors_cells(const orc_params* P, int64_t n, const double* pos,
 }
 
 int orc_step(const orc_params* P, int64_t n, const double* pos, const double* vel,
-             const int8_t* type, const int8_t* flags_override, orc_step_out* out) {
+             const int8_t* type, const int8_t* flags_override, const double* rho_s,
+             const double* nu_i, orc_step_out* out) {
   Consts C = constants(P);
   const int dim = P->dim;
   std::vector<double> x(pos, pos + n * dim), u(vel, vel + n * dim);
@@ -649,7 +745,7 @@ int orc_step(const orc_params* P, int64_t n, const double* pos, const double* ve
   double nu, g[3];
   to_params(P, &nu, g);
   Trace<double> tr;
-  int st = step<double>(P, C, nu, g, (int)n, x, u, t, flags_override, tr);
+  int st = step<double>(P, C, nu, g, (int)n, x, u, t, flags_override, tr, rho_s, nu_i);
   if (st == -3 || st == -6) return st;
   auto cp = [&](double* dst, const std::vector<double>& src) {
     if (dst && !src.empty()) std::memcpy(dst, src.data(), src.size() * sizeof(double));
@@ -667,11 +763,80 @@ int orc_step(const orc_params* P, int64_t n, const double* pos, const double* ve
     }
   }
   cp(out->p, tr.p); cp(out->phat, tr.phat); cp(out->gradp, tr.gradp);
+  cp(out->nut, tr.nut);
   cp(out->pos, x); cp(out->vel, u);
   if (out->type) std::memcpy(out->type, t.data(), n);
   out->cg_iters = tr.cg_iters;
   out->cg_relres = tr.cg_relres;
   return st;
+}
+
+int orc_rollout_grad(const orc_params* P, int64_t n, const double* pos, const double* vel,
+                     const int8_t* type, int32_t nsteps, const double* dir, double w_ke,
+                     double w_var, double* out) {
+  /* Forward-mode derivative of the loss after nsteps steps along three
+   * directions: d/dnu, d/dg_x and <d/du0, dir> (dual numbers through the
+   * whole rollout, the PPE solves differentiated exactly). */
+  using D = Dual<3>;
+  Consts C = constants(P);
+  const int dim = P->dim;
+  std::vector<D> x(n * dim), u(n * dim);
+  for (int64_t k = 0; k < n * dim; ++k) {
+    x[k] = D(pos[k]);
+    u[k] = D(vel[k]);
+    if (dir && type[k / dim] == FLUID) u[k].d[2] = dir[k];
+  }
+  std::vector<int8_t> t(type, type + n);
+  D nu(P->nu);
+  nu.d[0] = 1.0;
+  D g[3] = {D(P->g[0]), D(P->g[1]), D(P->g[2])};
+  g[0].d[1] = 1.0;
+  Trace<D> tr;
+  int st = 0;
+  for (int s = 0; s < nsteps; ++s) {
+    st = step<D>(P, C, nu, g, (int)n, x, u, t, nullptr, tr);
+    if (st == -3 || st == -6) return st;
+  }
+  D L = final_loss<D>((int)n, dim, x, u, t, tr.flags, w_ke, w_var);
+  out[0] = L.v;
+  out[1] = L.d[0];
+  out[2] = L.d[1];
+  out[3] = L.d[2];
+  return st;
+}
+
+int orc_smoothed_density(const orc_params* P, int64_t n, const double* pos,
+                         const int8_t* type, const double* rho_i, double* rho_s) {
+  /* <rho>_i = sum_j rho_j w(r_ij) / sum_j w(r_ij) over non-dummy neighbours
+   * within re_n, for fluid particles; wall and dummy keep their own rho. */
+  Lists L;
+  std::vector<int> cell;
+  std::vector<int8_t> t(type, type + n);
+  int st = build_lists_cells(P, (int)n, pos, t.data(), L, cell);
+  if (st) return st;
+  const int dim = P->dim;
+  for (int64_t i = 0; i < n; ++i) {
+    rho_s[i] = rho_i[i];
+    if (t[i] != FLUID) continue;
+    double sw = 0.0, srw = 0.0;
+    for (int e = L.start[i]; e < L.start[i + 1]; ++e) {
+      int j = L.idx[e];
+      if (t[j] == DUMMY) continue;
+      double d2 = dist2(pos + i * dim, pos + (int64_t)j * dim, dim);
+      double w = weight(P->kernel, std::sqrt(d2), P->re_n);
+      sw += w;
+      srw += rho_i[j] * w;
+    }
+    if (sw > 0.0) rho_s[i] = srw / sw;
+  }
+  return 0;
+}
+
+double orc_loss(const orc_params* P, int64_t n, const double* pos, const double* vel,
+                const int8_t* type, const int8_t* flags, double w_ke, double w_var) {
+  std::vector<double> x(pos, pos + n * P->dim), u(vel, vel + n * P->dim);
+  std::vector<int8_t> t(type, type + n), f(flags, flags + n);
+  return final_loss<double>((int)n, P->dim, x, u, t, f, w_ke, w_var);
 }
 
 int orc_pressure_gradient(const orc_params* P, int64_t n, const double* rs,
@@ -692,7 +857,8 @@ int orc_pressure_gradient(const orc_params* P, int64_t n, const double* rs,
 }
 
 int orc_run(const orc_params* P, int64_t n, double* pos, double* vel, int8_t* type,
-            int32_t nsteps, double* p_out, int8_t* flags_out) {
+            int32_t nsteps, const double* rho_s, const double* nu_i, double* p_out,
+            int8_t* flags_out) {
   Consts C = constants(P);
   const int dim = P->dim;
   std::vector<double> x(pos, pos + n * dim), u(vel, vel + n * dim);
@@ -702,7 +868,7 @@ int orc_run(const orc_params* P, int64_t n, double* pos, double* vel, int8_t* ty
   int st = 0;
   Trace<double> tr;
   for (int s = 0; s < nsteps; ++s) {
-    st = step<double>(P, C, nu, g, (int)n, x, u, t, nullptr, tr);
+    st = step<double>(P, C, nu, g, (int)n, x, u, t, nullptr, tr, rho_s, nu_i);
     if (st == -3 || st == -6) break;
   }
   std::memcpy(pos, x.data(), x.size() * sizeof(double));

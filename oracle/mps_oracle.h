@@ -35,6 +35,7 @@ typedef struct {
   int8_t *flags;
   double *diag, *b, *aval;
   double *p, *phat, *gradp;
+  double *nut;
   double *pos, *vel;
   int8_t *type;
   int32_t cg_iters;
@@ -64,17 +65,35 @@ int orc_neighbors_cells(const orc_params* P, int64_t n, const double* pos,
  * decision (used when a flag sits on the n* = beta n0 tie). */
 int orc_step(const orc_params* P, int64_t n, const double* pos,
              const double* vel, const int8_t* type, const int8_t* flags_override,
-             orc_step_out* out);
+             const double* rho_s, const double* nu_i, orc_step_out* out);
 
-/* nsteps time steps; state arrays are updated in place. */
+/* nsteps time steps; state arrays are updated in place.  rho_s (smoothed
+ * density) and nu_i (laminar viscosity) per particle select the two-phase
+ * model (NULL: single phase with P->rho, P->nu). */
 int orc_run(const orc_params* P, int64_t n, double* pos, double* vel,
-            int8_t* type, int32_t nsteps, double* p_out, int8_t* flags_out);
+            int8_t* type, int32_t nsteps, const double* rho_s, const double* nu_i,
+            double* p_out, int8_t* flags_out);
+
+/* Smoothed density of the two-phase model, fixed before the run. */
+int orc_smoothed_density(const orc_params* P, int64_t n, const double* pos,
+                         const int8_t* type, const double* rho_i, double* rho_s);
 
 /* p-hat and the pressure gradient (standard or Eq. 18) of a given pressure
  * field p at positions rs, lists taken at rs. */
 int orc_pressure_gradient(const orc_params* P, int64_t n, const double* rs,
                           const int8_t* type, const double* p, double* phat,
                           double* gradp);
+
+/* Loss after nsteps (w_ke * mean fluid kinetic energy + w_var * variance of
+ * the free-surface height) and its forward-mode derivatives along d/dnu,
+ * d/dg_x and <d/du0, dir>: out[4] = {L, dL/dnu, dL/dgx, <dL/du0, dir>}. */
+int orc_rollout_grad(const orc_params* P, int64_t n, const double* pos,
+                     const double* vel, const int8_t* type, int32_t nsteps,
+                     const double* dir, double w_ke, double w_var, double* out);
+/* The same loss of a given final state and last-step flags. */
+double orc_loss(const orc_params* P, int64_t n, const double* pos,
+                const double* vel, const int8_t* type, const int8_t* flags,
+                double w_ke, double w_var);
 
 #ifdef __cplusplus
 }

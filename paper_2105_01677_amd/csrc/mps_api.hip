@@ -54,8 +54,16 @@ struct mps_ctx {
   double *diag = nullptr, *b = nullptr;
   double *r = nullptr, *z = nullptr, *pd[2] = {nullptr, nullptr}, *q = nullptr;
   double* p_save = nullptr;
+  // two-phase / turbulence
+  bool multi = false;
+  double* rho_s[2] = {nullptr, nullptr};
+  double* nu_l[2] = {nullptr, nullptr};
+  double* nut = nullptr;
+  double* mu = nullptr;
   double* partA = nullptr;
   double* partB = nullptr;
+  double *pl_u = nullptr, *pl_z = nullptr, *pl_s = nullptr, *pl_w[2] = {nullptr, nullptr},
+         *pl_part[2] = {nullptr, nullptr};
   int nspmv = 0, nupd = 0;
   CGScalars* sc = nullptr;
   int32_t* status = nullptr;
@@ -80,6 +88,18 @@ struct mps_ctx {
   static constexpr int CG_BATCH = 4;   // smallest CG graph; also 4x and 16x
   bool graphs_built = false;
   hipGraphExec_t g_pre[2] = {}, g_cg[2][3] = {}, g_post[2] = {}, g_wc2[2] = {};
+  // checkpoint tape: per slot the sorted state (pos, vel, p, type, id)
+  struct Slot {
+    double *pos = nullptr, *vel = nullptr, *p = nullptr;
+    int8_t* type = nullptr;
+    int32_t* id = nullptr;
+    bool valid = false;
+  };
+  Slot* tape = nullptr;
+  int ntape = 0;
+  // adjoint work arrays (allocated with the tape)
+  AdjView adj = {};
+  double* h_part = nullptr;
   // bookkeeping
   bool poisoned = false;
   bool ppe_valid = false;
@@ -214,10 +234,26 @@ View make_view(const mps_ctx* c) {
   v.q = c->q;
   v.partA = c->partA;
   v.partB = c->partB;
+  v.pl_u = c->pl_u;
+  v.pl_z = c->pl_z;
+  v.pl_s = c->pl_s;
+  v.pl_w[0] = c->pl_w[0];
+  v.pl_w[1] = c->pl_w[1];
+  v.pl_part[0] = c->pl_part[0];
+  v.pl_part[1] = c->pl_part[1];
   v.nspmv = c->nspmv;
   v.nupd = c->nupd;
   v.sc = c->sc;
   v.status = c->status;
+  if (c->multi) {
+    v.rho_s = c->rho_s[a];
+    v.rho_s_w = c->rho_s[o];
+    v.nu_l = c->nu_l[a];
+    v.nu_l_w = c->nu_l[o];
+    v.nut = c->nut;
+    v.mu = c->mu;
+    v.smag_c2 = (P.smagorinsky_cs * P.l0) * (P.smagorinsky_cs * P.l0);
+  }
   return v;
 }
 
@@ -242,7 +278,8 @@ mps_status check_params(const mps_params* P, int64_t n) {
   if (P->grad != MPS_GRAD_STD && P->grad != MPS_GRAD_CMPS) return MPS_E_ARG;
   if (P->gamma < 1 || P->gamma > 16 || P->gamma != std::floor(P->gamma)) return MPS_E_ARG;
   if (P->cg_maxit < 1 || !(P->cg_tol > 0)) return MPS_E_ARG;
-  if (P->smagorinsky_cs != 0.0) return MPS_E_ARG;
+  if (P->cg_pipelined != 0 && P->cg_pipelined != 1) return MPS_E_ARG;
+  if (!(P->smagorinsky_cs >= 0.0) || P->smagorinsky_cs > 1.0) return MPS_E_ARG;
   int64_t nc = 1;
   for (int a = 0; a < P->dim; ++a) {
     if (P->grid_n[a] < 1 || P->grid_n[a] > 1023) return MPS_E_ARG;
@@ -260,6 +297,10 @@ __global__ void k_i8_to_orig(int64_t n, const int32_t* id, const int8_t* src, in
 __global__ void k_i8_from_orig(int64_t n, const int32_t* id, const int8_t* src, int8_t* dst) {
   const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (k < n) dst[k] = src[id[k]];
+}
+__global__ void k_fill(int64_t n, double* a, double x) {
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k < n) a[k] = x;
 }
 __global__ void k_iota(int64_t n, int32_t* id) {
   const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -368,11 +409,27 @@ mps_status search(mps_ctx* c) {
 }
 
 // --------------------------------------------------------------- stages
+// PPE assembly and the start of the CG (pipelined: its setup SpMV).
+void enqueue_assemble(mps_ctx* c, const View& v, const double* rhs, bool zero_x0) {
+  {
+    Prof pr(c, MPS_KC_ASSEMBLE);
+    launch_assemble(v, c->dim, c->P.precision, rhs, zero_x0, c->s);
+  }
+  if (c->P.cg_pipelined) {
+    Prof pr(c, MPS_KC_CG_SPMV);
+    launch_pcg_setup(v, c->P.precision, c->s);
+  }
+}
+
 // Stages before the pressure solve: a1-a5 (PPE) or a1-a4 + a7 (EOS).
 // Leaves the context in the new sorted order (flips cur).
 void enqueue_pre(mps_ctx* c) {
   search(c);
   View v = make_view(c);
+  if (c->multi) {
+    Prof pr(c, MPS_KC_PREDICT);
+    launch_viscosity(v, c->dim, c->P.precision, c->s);
+  }
   {
     Prof pr(c, MPS_KC_PREDICT);
     launch_predict(v, c->dim, c->P.precision, c->s);
@@ -381,14 +438,20 @@ void enqueue_pre(mps_ctx* c) {
     Prof pr(c, MPS_KC_DENSITY);
     launch_density(v, c->dim, c->P.precision, c->P.pmode, c->s);
   }
-  if (c->P.pmode == MPS_PPE_CG) {
-    Prof pr(c, MPS_KC_ASSEMBLE);
-    launch_assemble(v, c->dim, c->P.precision, nullptr, false, c->s);
-  }
+  if (c->P.pmode == MPS_PPE_CG) enqueue_assemble(c, v, nullptr, false);
 }
 
+// CG iterations; the pipelined variant alternates buffer parities, and
+// every batch has an even length so each starts at parity 0.
 void enqueue_cg(mps_ctx* c, int iters) {
   View v = make_view(c);
+  if (c->P.cg_pipelined) {
+    for (int it = 0; it < iters; ++it) {
+      Prof pr(c, MPS_KC_CG_SPMV);
+      launch_pcg_iter(v, c->P.precision, it & 1, c->s);
+    }
+    return;
+  }
   for (int it = 0; it < iters; ++it) {
     {
       Prof pr(c, MPS_KC_CG_SPMV);
@@ -476,6 +539,7 @@ mps_status solve(mps_ctx* c, int* iters, double* relres, bool graphs) {
         }
         k = done;
       } else {
+        k += k & 1;
         enqueue_cg(c, k);
       }
       launched += k;
@@ -544,6 +608,26 @@ mps_status one_step_ppe(mps_ctx* c, mps_step_stats* st) {
   return res;
 }
 
+void free_tape(mps_ctx* c) {
+  for (int k = 0; k < c->ntape; ++k) {
+    mps_ctx::Slot& t = c->tape[k];
+    void* ps[] = {t.pos, t.vel, t.p, t.type, t.id};
+    for (void* q : ps)
+      if (q) (void)hipFree(q);
+  }
+  delete[] c->tape;
+  c->tape = nullptr;
+  c->ntape = 0;
+  AdjView& a = c->adj;
+  void* as[] = {(void*)a.pos_bar, (void*)a.vel_bar, a.gbar, a.phat_bar, a.pbar, a.nbar,
+                a.rs_bar, a.ut, a.sbar, a.pos_bar_in, a.vel_bar_in, a.arg, a.lam, a.part};
+  for (void* q : as)
+    if (q) (void)hipFree(q);
+  c->adj = AdjView{};
+  if (c->h_part) (void)hipHostFree(c->h_part);
+  c->h_part = nullptr;
+}
+
 }  // namespace
 
 extern "C" {
@@ -554,7 +638,6 @@ mps_status mps_init(const mps_params* params, int64_t n, const double* pos, cons
   if (!out) return MPS_E_ARG;
   *out = nullptr;
   if (check_params(params, n) != MPS_OK || !pos || !vel || !type) return MPS_E_ARG;
-  if (rho_i || nu_i) return MPS_E_ARG;
   mps_ctx* c = new (std::nothrow) mps_ctx();
   if (!c) return MPS_E_NOMEM;
   c->P = *params;
@@ -565,6 +648,7 @@ mps_status mps_init(const mps_params* params, int64_t n, const double* pos, cons
   c->slots = ((n + SLICE - 1) / SLICE) * (int64_t)c->kpad * SLICE;
   c->ncell = params->grid_n[0] * params->grid_n[1] * (c->dim == 3 ? params->grid_n[2] : 1);
   c->s = (hipStream_t)hip_stream;
+  c->multi = rho_i || nu_i || params->smagorinsky_cs > 0.0;
   double lam_n;
   lattice(c->dim, params->l0, params->re_n, params->kernel, &c->n0_n, &lam_n);
   lattice(c->dim, params->l0, params->re_lap, params->kernel, &c->n0_lap, &c->lam_lap);
@@ -604,10 +688,27 @@ mps_status mps_init(const mps_params* params, int64_t n, const double* pos, cons
   A(dalloc(&c->z, n));
   A(dalloc(&c->q, n));
   A(dalloc(&c->p_save, n));
+  if (c->multi) {
+    for (int k = 0; k < 2; ++k) {
+      A(dalloc(&c->rho_s[k], n));
+      A(dalloc(&c->nu_l[k], n));
+    }
+    A(dalloc(&c->nut, n));
+    A(dalloc(&c->mu, n));
+  }
   c->nspmv = cg_spmv_blocks(n);
   c->nupd = cg_update_blocks(n);
   A(dalloc(&c->partA, (size_t)std::max(c->nspmv, c->nupd) * 4));
   A(dalloc(&c->partB, (size_t)c->nspmv));
+  if (params->cg_pipelined) {
+    A(dalloc(&c->pl_u, n));
+    A(dalloc(&c->pl_z, n));
+    A(dalloc(&c->pl_s, n));
+    for (int k = 0; k < 2; ++k) {
+      A(dalloc(&c->pl_w[k], n));
+      A(dalloc(&c->pl_part[k], (size_t)c->nspmv * 4));
+    }
+  }
   A(dalloc(&c->sc, 1));
   A(dalloc(&c->status, 1));
   A(dalloc(&c->counts, 4));
@@ -634,6 +735,19 @@ mps_status mps_init(const mps_params* params, int64_t n, const double* pos, cons
   launch_gather_orig(v, vel, c->vel[0], c->dim, c->ps, s);
   A(hipMemcpyAsync(c->type[0], type, n, hipMemcpyDeviceToDevice, s));
   k_check_types<<<flat_blocks(n), 256, 0, s>>>(n, c->type[0], c->status);
+  if (c->multi) {
+    if (rho_i) launch_gather_orig(v, rho_i, c->rho_s[0], 1, 1, s);
+    else k_fill<<<flat_blocks(n), 256, 0, s>>>(n, c->rho_s[0], params->rho);
+    if (nu_i) launch_gather_orig(v, nu_i, c->nu_l[0], 1, 1, s);
+    else k_fill<<<flat_blocks(n), 256, 0, s>>>(n, c->nu_l[0], params->nu);
+    A(hipMemsetAsync(c->nut, 0, n * sizeof(double), s));
+    // the smoothed density is fixed before the run, from the initial lists
+    search(c);
+    View w = make_view(c);
+    launch_smooth_density(w, c->rho_s[c->cur], c->rho_s[c->cur ^ 1], c->dim, s);
+    A(hipMemcpyAsync(c->rho_s[c->cur], c->rho_s[c->cur ^ 1], n * sizeof(double),
+                     hipMemcpyDeviceToDevice, s));
+  }
   A(hipGetLastError());
   A(hipStreamSynchronize(s));
   if (e != hipSuccess) {
@@ -649,6 +763,10 @@ mps_status mps_init(const mps_params* params, int64_t n, const double* pos, cons
   return MPS_OK;
 }
 
+namespace {
+void free_tape(mps_ctx* c);
+}
+
 mps_status mps_free(mps_ctx* c) {
   if (!c) return MPS_OK;
   if (c->s) (void)hipStreamSynchronize(c->s);
@@ -658,7 +776,10 @@ mps_status mps_free(mps_ctx* c) {
                   c->cellid, c->slot, c->perm, c->cell_count, c->cell_start, c->tile_sum,
                   c->nb_count,
                   c->nb_list, c->a_nnz, c->a_col, c->a_val, c->diag, c->b, c->r, c->z,
-                  c->q, c->p_save, c->partA, c->partB, c->sc, c->status, c->counts};
+                  c->q, c->p_save, c->partA, c->partB, c->sc, c->status, c->counts,
+                  c->rho_s[0], c->rho_s[1], c->nu_l[0], c->nu_l[1], c->nut, c->mu,
+                  c->pl_u, c->pl_z, c->pl_s, c->pl_w[0], c->pl_w[1], c->pl_part[0],
+                  c->pl_part[1]};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (int k = 0; k < 2; ++k) {
@@ -672,6 +793,7 @@ mps_status mps_free(mps_ctx* c) {
       (void)hipEventDestroy(c->ev_a[k]);
       (void)hipEventDestroy(c->ev_b[k]);
     }
+  free_tape(c);
   if (c->h_sc) (void)hipHostFree(c->h_sc);
   if (c->h_status) (void)hipHostFree(c->h_status);
   if (c->h_counts) (void)hipHostFree(c->h_counts);
@@ -748,7 +870,7 @@ mps_status mps_pressure_solve(mps_ctx* c, const double* rhs, double* p, int32_t*
     launch_gather_orig(v, rhs, c->q, 1, 1, c->s);
     rhs_sorted = c->q;
   }
-  launch_assemble(v, c->dim, c->P.precision, rhs_sorted, true, c->s);
+  enqueue_assemble(c, v, rhs_sorted, true);
   c->ppe_valid = true;
   int it = 0;
   double rel = 0.0;
@@ -845,6 +967,155 @@ mps_status mps_profile_read(mps_ctx* c, double* ms, int64_t* launches) {
     if (launches) launches[k] = c->prof_n[k];
   }
   return MPS_OK;
+}
+
+mps_status mps_get_phase(mps_ctx* c, double* rho_s, double* nu_t) {
+  if (!c) return MPS_E_ARG;
+  if (!c->multi) return fail(c, MPS_E_ARG, "single-phase context");
+  View v = make_view(c);
+  if (rho_s) launch_scatter_orig(v, c->rho_s[c->cur], rho_s, 1, 1, c->s);
+  if (nu_t) launch_scatter_orig(v, c->nut, nu_t, 1, 1, c->s);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(c->s));
+  return MPS_OK;
+}
+
+mps_status mps_tape_alloc(mps_ctx* c, int32_t nslots) {
+  if (!c || nslots < 1) return MPS_E_ARG;
+  HIPCHK(c, hipStreamSynchronize(c->s));
+  free_tape(c);
+  const int64_t n = c->n;
+  const size_t nv = (size_t)n * c->ps;
+  c->tape = new (std::nothrow) mps_ctx::Slot[nslots];
+  if (!c->tape) return fail(c, MPS_E_NOMEM, "tape");
+  c->ntape = nslots;
+  hipError_t e = hipSuccess;
+  auto A = [&](hipError_t x) { if (e == hipSuccess) e = x; };
+  for (int k = 0; k < nslots; ++k) {
+    mps_ctx::Slot& t = c->tape[k];
+    A(dalloc(&t.pos, nv));
+    A(dalloc(&t.vel, nv));
+    A(dalloc(&t.p, n));
+    A(dalloc(&t.type, n));
+    A(dalloc(&t.id, n));
+  }
+  AdjView& a = c->adj;
+  double *pb = nullptr, *vb = nullptr;
+  A(dalloc(&pb, nv));
+  A(dalloc(&vb, nv));
+  a.pos_bar = pb;
+  a.vel_bar = vb;
+  A(dalloc(&a.gbar, nv));
+  A(dalloc(&a.phat_bar, n));
+  A(dalloc(&a.pbar, n));
+  A(dalloc(&a.nbar, n));
+  A(dalloc(&a.rs_bar, nv));
+  A(dalloc(&a.ut, nv));
+  A(dalloc(&a.sbar, nv));
+  A(dalloc(&a.pos_bar_in, nv));
+  A(dalloc(&a.vel_bar_in, nv));
+  A(dalloc(&a.arg, n));
+  A(dalloc(&a.lam, n));
+  const int nb = adj_partial_blocks(n);
+  A(dalloc(&a.part, (size_t)nb * 4));
+  if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_part, (size_t)nb * 4 * sizeof(double), hipHostMallocDefault);
+  if (e != hipSuccess) {
+    free_tape(c);
+    return e == hipErrorOutOfMemory ? fail(c, MPS_E_NOMEM, "tape allocation")
+                                    : hip_fail(c, e, "tape allocation");
+  }
+  return MPS_OK;
+}
+
+mps_status mps_tape_save(mps_ctx* c, int32_t slot) {
+  if (!c || slot < 0 || slot >= c->ntape) return MPS_E_ARG;
+  mps_ctx::Slot& t = c->tape[slot];
+  const int64_t n = c->n;
+  const size_t nv = (size_t)n * c->ps * sizeof(double);
+  const int a = c->cur;
+  HIPCHK(c, hipMemcpyAsync(t.pos, c->pos[a], nv, hipMemcpyDeviceToDevice, c->s));
+  HIPCHK(c, hipMemcpyAsync(t.vel, c->vel[a], nv, hipMemcpyDeviceToDevice, c->s));
+  HIPCHK(c, hipMemcpyAsync(t.p, c->pres[a], n * sizeof(double), hipMemcpyDeviceToDevice, c->s));
+  HIPCHK(c, hipMemcpyAsync(t.type, c->type[a], n, hipMemcpyDeviceToDevice, c->s));
+  HIPCHK(c, hipMemcpyAsync(t.id, c->id[a], n * sizeof(int32_t), hipMemcpyDeviceToDevice, c->s));
+  t.valid = true;
+  return MPS_OK;
+}
+
+mps_status mps_tape_load(mps_ctx* c, int32_t slot) {
+  if (!c || slot < 0 || slot >= c->ntape || !c->tape[slot].valid) return MPS_E_ARG;
+  mps_ctx::Slot& t = c->tape[slot];
+  const int64_t n = c->n;
+  const size_t nv = (size_t)n * c->ps * sizeof(double);
+  const int a = c->cur;
+  HIPCHK(c, hipMemcpyAsync(c->pos[a], t.pos, nv, hipMemcpyDeviceToDevice, c->s));
+  HIPCHK(c, hipMemcpyAsync(c->vel[a], t.vel, nv, hipMemcpyDeviceToDevice, c->s));
+  HIPCHK(c, hipMemcpyAsync(c->pres[a], t.p, n * sizeof(double), hipMemcpyDeviceToDevice, c->s));
+  HIPCHK(c, hipMemcpyAsync(c->type[a], t.type, n, hipMemcpyDeviceToDevice, c->s));
+  HIPCHK(c, hipMemcpyAsync(c->id[a], t.id, n * sizeof(int32_t), hipMemcpyDeviceToDevice, c->s));
+  c->ppe_valid = false;
+  return MPS_OK;
+}
+
+mps_status mps_step_adjoint(mps_ctx* c, const double* pos_bar, const double* vel_bar,
+                            double* pos_bar_prev, double* vel_bar_prev, double* nu_bar,
+                            double* g_bar) {
+  if (!c || !pos_bar || !vel_bar || !pos_bar_prev || !vel_bar_prev) return MPS_E_ARG;
+  if (!c->tape) return fail(c, MPS_E_ARG, "call mps_tape_alloc first");
+  if (c->P.grad != MPS_GRAD_STD) return fail(c, MPS_E_ARG, "adjoint needs the standard gradient");
+  if (c->multi) return fail(c, MPS_E_ARG, "adjoint of the two-phase / turbulence model not built");
+  if (c->poisoned) return fail(c, MPS_E_POISONED, "context poisoned; call mps_set_state");
+  const bool wc = c->P.pmode == MPS_WC_EOS;
+  // forward recompute of the step's stages from the current (taped) state
+  enqueue_pre(c);
+  mps_status res = MPS_OK;
+  if (!wc) {
+    int it = 0;
+    double rel = 0.0;
+    res = solve(c, &it, &rel, false);
+    if (res != MPS_OK && res != MPS_E_CG_NOCONV) return res;
+    c->last_iters = it;
+  }
+  View v = make_view(c);
+  AdjView a = c->adj;
+  launch_gather_orig(v, pos_bar, const_cast<double*>(a.pos_bar), c->dim, c->ps, c->s);
+  launch_gather_orig(v, vel_bar, const_cast<double*>(a.vel_bar), c->dim, c->ps, c->s);
+  launch_adjoint_head(v, a, c->dim, c->P.precision, wc ? 1 : 0, c->s);
+  if (!wc) {
+    // transposed solve A lambda = x-bar (A is symmetric): same matrix, same
+    // CG kernels, from lambda = 0; the forward pressure is kept aside
+    HIPCHK(c, hipMemcpyAsync(c->p_save, c->pres[c->cur], c->n * sizeof(double),
+                             hipMemcpyDeviceToDevice, c->s));
+    enqueue_assemble(c, v, a.pbar, true);
+    int it = 0;
+    double rel = 0.0;
+    const int saved = c->last_iters;
+    mps_status r2 = solve(c, &it, &rel, false);
+    c->last_iters = saved;
+    if (r2 != MPS_OK && r2 != MPS_E_CG_NOCONV) return r2;
+    if (r2 == MPS_E_CG_NOCONV) res = r2;
+    HIPCHK(c, hipMemcpyAsync(a.lam, c->pres[c->cur], c->n * sizeof(double),
+                             hipMemcpyDeviceToDevice, c->s));
+    HIPCHK(c, hipMemcpyAsync(c->pres[c->cur], c->p_save, c->n * sizeof(double),
+                             hipMemcpyDeviceToDevice, c->s));
+    launch_adjoint_ppe(v, a, c->dim, c->s);
+  }
+  launch_adjoint_tail(v, a, c->dim, c->s);
+  launch_scatter_orig(v, a.pos_bar_in, pos_bar_prev, c->dim, c->ps, c->s);
+  launch_scatter_orig(v, a.vel_bar_in, vel_bar_prev, c->dim, c->ps, c->s);
+  const int nb = adj_partial_blocks(c->n);
+  HIPCHK(c, hipMemcpyAsync(c->h_part, a.part, (size_t)nb * 4 * sizeof(double),
+                           hipMemcpyDeviceToHost, c->s));
+  HIPCHK(c, hipGetLastError());
+  mps_status st = read_status(c);
+  if (st != MPS_OK) return st;
+  double s4[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int b = 0; b < nb; ++b)
+    for (int q = 0; q < 4; ++q) s4[q] += c->h_part[(size_t)b * 4 + q];
+  if (nu_bar) *nu_bar = s4[0];
+  if (g_bar)
+    for (int q = 0; q < c->dim; ++q) g_bar[q] = s4[1 + q];
+  return res;
 }
 
 }  // extern "C"

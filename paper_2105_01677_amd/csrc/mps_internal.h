@@ -60,6 +60,10 @@ struct CGScalars {
   int32_t iter;      // iterations completed
   int32_t nasm;      // number of assembly partials (written by assembly)
   int32_t pad;
+  // pipelined variant: (r,u) and alpha of iteration k in slot k & 1, written
+  // by workgroup 0 of iteration k and read by iteration k + 1 only
+  double gam[2];
+  double alp[2];
 };
 
 // Grid caps of the CG kernels: every workgroup of one kernel sums all the
@@ -123,7 +127,40 @@ struct View {
   double* partB;      // [blocks]: (p, A p) of the SpMV workgroups
   int nspmv, nupd;    // grid sizes of the SpMV / assembly and update kernels
   CGScalars* sc;
+  // pipelined CG (one kernel per iteration): u = M^-1 r, w = A u (double
+  // buffered), z, s; q and the direction p reuse q and pd[0]
+  double* pl_u;
+  double* pl_z;
+  double* pl_s;
+  double* pl_w[2];
+  double* pl_part[2]; // per-workgroup (r,u), (w,u), (r,r), double buffered
   int32_t* status;
+  // two-phase / turbulence (null when single phase)
+  const double* rho_s;   // smoothed density <rho>_i, sorted
+  double* rho_s_w;       // permutation target
+  const double* nu_l;    // laminar viscosity per particle, sorted
+  double* nu_l_w;
+  double* nut;           // Smagorinsky eddy viscosity
+  double* mu;            // dynamic viscosity <rho> (nu + nu_t)
+  double smag_c2;        // (Cs l0)^2
+};
+
+// Adjoint work arrays (sorted order).
+struct AdjView {
+  const double* pos_bar;   // r-bar of the step output
+  const double* vel_bar;   // u-bar of the step output
+  double* gbar;            // G-bar   [n][ps]
+  double* phat_bar;        // phat-bar [n]
+  double* pbar;            // p-bar (then n*-bar)  [n]
+  double* nbar;            // n*-bar [n]
+  double* rs_bar;          // r*-bar [n][ps]
+  double* ut;              // u-tilde = u*-bar + dt r*-bar  [n][ps]
+  double* sbar;            // S-bar [n][ps]
+  double* pos_bar_in;      // r-bar of the step input  [n][ps]
+  double* vel_bar_in;      // u-bar of the step input  [n][ps]
+  int32_t* arg;            // p-hat argmin (sorted index)
+  double* lam;             // PPE adjoint solution (lambda)
+  double* part;            // [blocks][4]: nu-bar, g-bar
 };
 
 // Packed cell coordinates: 10 bits per axis (x lowest); GHOST_CELL marks a
@@ -215,10 +252,15 @@ int launch_export_lists(const View& v, int32_t* cell_out, int32_t* count_out,
                         int32_t* list_out, int dim, hipStream_t s);
 int launch_predict(const View& v, int dim, int precision, hipStream_t s);
 int launch_density(const View& v, int dim, int precision, int pmode, hipStream_t s);
+int launch_viscosity(const View& v, int dim, int precision, hipStream_t s);
+int launch_smooth_density(const View& v, const double* rho_raw, double* rho_out, int dim,
+                          hipStream_t s);
 int launch_assemble(const View& v, int dim, int precision, const double* rhs_sorted,
                     bool zero_x0, hipStream_t s);
 int launch_cg_spmv(const View& v, int precision, hipStream_t s);
 int launch_cg_update(const View& v, hipStream_t s);
+int launch_pcg_setup(const View& v, int precision, hipStream_t s);
+int launch_pcg_iter(const View& v, int precision, int parity, hipStream_t s);
 int launch_clamp(const View& v, hipStream_t s);
 int launch_gradient(const View& v, int dim, int precision, hipStream_t s);
 int launch_scatter_orig(const View& v, const double* src, double* dst, int comps,
@@ -228,6 +270,11 @@ int launch_gather_orig(const View& v, const double* src, double* dst, int comps,
 int launch_export_ppe(const View& v, int precision, double* diag, double* b,
                       int32_t* nnz, int32_t* cols, double* vals, hipStream_t s);
 int cg_spmv_blocks(int64_t n);
+int adj_partial_blocks(int64_t n);
+int launch_adjoint_head(const View& v, const AdjView& a, int dim, int precision, int wc,
+                        hipStream_t s);
+int launch_adjoint_ppe(const View& v, const AdjView& a, int dim, hipStream_t s);
+int launch_adjoint_tail(const View& v, const AdjView& a, int dim, hipStream_t s);
 int cg_update_blocks(int64_t n);
 
 }  // namespace mps

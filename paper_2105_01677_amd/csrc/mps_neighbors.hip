@@ -170,6 +170,10 @@ __global__ __launch_bounds__(BLOCK) void k_rank_permute(View v) {
   v.type_w[k] = v.type[i];
   v.id_w[k] = key;
   v.p_w[k] = v.p_in[i];
+  if (v.rho_s) {
+    v.rho_s_w[k] = v.rho_s[i];
+    v.nu_l_w[k] = v.nu_l[i];
+  }
   int32_t pc = GHOST_CELL;
   int ci[3] = {0, 0, 0};
   if (c < v.ncell) {

@@ -168,6 +168,8 @@ __global__ __launch_bounds__(BLOCK) void k_assemble(View v, const double* rhs, i
             if constexpr (DIM == 3) r2 += d[2] * d[2];
             if (r2 < re2) {
               c = cpp * weight<R>(v.kernel, sqrt(r2), re);
+              // two-phase: 1/rho -> 2/(<rho>_i + <rho>_j), symmetric
+              if (v.rho_s) c *= (R)(v.rho * 2.0 / (v.rho_s[row] + v.rho_s[j]));
               dsum += (double)c;
               keep = v.flags[j] == MPS_FLAG_INNER;
             }
@@ -328,6 +330,151 @@ __global__ __launch_bounds__(BLOCK) void k_cg_update(View v) {
   }
 }
 
+// ------------------------------------------------------- pipelined variant
+// Preconditioned CG with one global reduction per iteration (Ghysels and
+// Vanroose's pipelined CG), Jacobi M = diag(A):
+//   gamma = (r, u), delta = (w, u), m = M^-1 w, n = A m,
+//   beta = gamma/gamma_old, alpha = gamma/(delta - beta gamma/alpha_old),
+//   z = n + beta z, q = m + beta q, s = w + beta s, p = u + beta p,
+//   x += alpha p, r -= alpha s, u -= alpha q, w -= alpha z.
+// The dot products of iteration k+1 are formed by the workgroups of
+// iteration k and reduced (redundantly, fixed order) at the start of k+1,
+// so each iteration is one kernel.  w is double-buffered because the SpMV
+// reads the neighbours' w of this iteration while the new w is written.
+// Setup: w0 = A u0 with u0 = r0/diag from the assembly; gamma_old = inf
+// and alpha_old = 1 make the first iteration beta = 0, alpha = gamma/delta.
+template <class VT>
+__global__ __launch_bounds__(BLOCK) void k_pcg_setup(View v) {
+  CGScalars* sc = v.sc;
+  double tot[3];
+  sum_partials<3>(v.partA, sc->nasm, 4, tot);
+  const double rr = tot[1], bb = tot[2];
+  const bool done = bb == 0.0 || rr <= v.cg_tol2 * bb;
+  const Chunk ch(v.n);
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    sc->bb = bb;
+    sc->rr = rr;
+    sc->iter = 0;
+    sc->converged = done ? 1 : 0;
+    sc->gam[1] = __builtin_inf();
+    sc->alp[1] = 1.0;
+  }
+  const int t = team_lane();
+  if (done) {
+    if (bb == 0.0) {
+      for (int64_t g = ch.g0; g < ch.g1; ++g) {
+        const int64_t row = g * ROWS_PER_BLOCK + threadIdx.x / TEAM;
+        if (row < v.n && t == 0) v.p[row] = 0.0;
+      }
+    }
+    return;
+  }
+  const VT* __restrict__ aval = reinterpret_cast<const VT*>(v.a_val);
+  double gam = 0.0, del = 0.0, rr2 = 0.0;
+  for (int64_t g = ch.g0; g < ch.g1; ++g) {
+    const int64_t row = g * ROWS_PER_BLOCK + threadIdx.x / TEAM;
+    if (row >= v.n) continue;
+    const int nnz = v.a_nnz[row];
+    double s = 0.0;
+    for (int l = t; l < nnz; l += TEAM) {
+      const int64_t e = sl_index(row, l, v.kpad);
+      s += (double)aval[e] * v.z[v.a_col[e]];
+    }
+    s = team_sum(s);
+    if (t == 0) {
+      const double u = v.z[row], r = v.r[row];
+      const double w = v.diag[row] * u + s;
+      v.pl_u[row] = u;
+      v.pl_w[0][row] = w;
+      v.pl_z[row] = 0.0;
+      v.pl_s[row] = 0.0;
+      v.q[row] = 0.0;
+      v.pd[0][row] = 0.0;
+      gam += r * u;
+      del += w * u;
+      rr2 += r * r;
+    }
+  }
+  double x[3] = {gam, del, rr2};
+  block_sum<3>(x);
+  if (threadIdx.x == 0) {
+    const int lb = xcd_block();
+#pragma unroll
+    for (int k = 0; k < 3; ++k) v.pl_part[0][(int64_t)lb * 4 + k] = x[k];
+  }
+}
+
+template <class VT, int PAR>
+__global__ __launch_bounds__(BLOCK) void k_pcg_iter(View v) {
+  CGScalars* sc = v.sc;
+  if (sc->converged) return;
+  double tot[3];
+  sum_partials<3>(v.pl_part[PAR], v.nspmv, 4, tot);
+  const double gam = tot[0], del = tot[1], rr = tot[2];
+  const bool done = rr <= v.cg_tol2 * sc->bb;
+  const double beta = gam / sc->gam[PAR ^ 1];
+  const double alpha = gam / (del - beta * gam / sc->alp[PAR ^ 1]);
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    sc->rr = rr;
+    if (done) {
+      sc->converged = 1;
+    } else {
+      sc->gam[PAR] = gam;
+      sc->alp[PAR] = alpha;
+      sc->iter += 1;
+    }
+  }
+  if (done) return;
+  const double* __restrict__ W = v.pl_w[PAR];
+  double* __restrict__ Wn = v.pl_w[PAR ^ 1];
+  const VT* __restrict__ aval = reinterpret_cast<const VT*>(v.a_val);
+  const int t = team_lane();
+  const Chunk ch(v.n);
+  double g2 = 0.0, d2 = 0.0, r2 = 0.0;
+  for (int64_t g = ch.g0; g < ch.g1; ++g) {
+    const int64_t row = g * ROWS_PER_BLOCK + threadIdx.x / TEAM;
+    if (row >= v.n) continue;
+    const int nnz = v.a_nnz[row];
+    double s = 0.0;
+    for (int l = t; l < nnz; l += TEAM) {
+      const int64_t e = sl_index(row, l, v.kpad);
+      const int32_t j = v.a_col[e];
+      s += (double)aval[e] * (W[j] / v.diag[j]);
+    }
+    s = team_sum(s);
+    if (t == 0) {
+      const double dg = v.diag[row], w = W[row];
+      const double m = w / dg;
+      const double nn = dg * m + s;
+      const double z = nn + beta * v.pl_z[row];
+      const double q = m + beta * v.q[row];
+      const double sv = w + beta * v.pl_s[row];
+      const double pv = v.pl_u[row] + beta * v.pd[0][row];
+      const double r = v.r[row] - alpha * sv;
+      const double u = v.pl_u[row] - alpha * q;
+      const double wn = w - alpha * z;
+      v.p[row] += alpha * pv;
+      v.pl_z[row] = z;
+      v.q[row] = q;
+      v.pl_s[row] = sv;
+      v.pd[0][row] = pv;
+      v.r[row] = r;
+      v.pl_u[row] = u;
+      Wn[row] = wn;
+      g2 += r * u;
+      d2 += wn * u;
+      r2 += r * r;
+    }
+  }
+  double x[3] = {g2, d2, r2};
+  block_sum<3>(x);
+  if (threadIdx.x == 0) {
+    const int lb = xcd_block();
+#pragma unroll
+    for (int k = 0; k < 3; ++k) v.pl_part[PAR ^ 1][(int64_t)lb * 4 + k] = x[k];
+  }
+}
+
 // Export of the assembled system in original order.
 template <class VT>
 __global__ __launch_bounds__(BLOCK) void k_export_ppe(View v, double* diag, double* b,
@@ -399,6 +546,24 @@ int launch_cg_spmv(const View& v, int precision, hipStream_t s) {
   const unsigned nt = (unsigned)v.nspmv;
   if (precision == MPS_MIXED) k_cg_spmv<float><<<nt, BLOCK, 0, s>>>(v);
   else k_cg_spmv<double><<<nt, BLOCK, 0, s>>>(v);
+  return 0;
+}
+
+int launch_pcg_setup(const View& v, int precision, hipStream_t s) {
+  if (precision == MPS_MIXED) k_pcg_setup<float><<<(unsigned)v.nspmv, BLOCK, 0, s>>>(v);
+  else k_pcg_setup<double><<<(unsigned)v.nspmv, BLOCK, 0, s>>>(v);
+  return 0;
+}
+
+int launch_pcg_iter(const View& v, int precision, int parity, hipStream_t s) {
+  const unsigned nb = (unsigned)v.nspmv;
+  if (precision == MPS_MIXED) {
+    if (parity) k_pcg_iter<float, 1><<<nb, BLOCK, 0, s>>>(v);
+    else k_pcg_iter<float, 0><<<nb, BLOCK, 0, s>>>(v);
+  } else {
+    if (parity) k_pcg_iter<double, 1><<<nb, BLOCK, 0, s>>>(v);
+    else k_pcg_iter<double, 0><<<nb, BLOCK, 0, s>>>(v);
+  }
   return 0;
 }
 

@@ -104,17 +104,23 @@ __global__ __launch_bounds__(BLOCK) void k_predict(View v) {
       const int32_t j = v.nb_list[sl_index(row, l, v.kpad)];
       R d[DIM];
       pi.diff(P::load(v.pos, v.posf, j), v.cs32, d);
-      const R w = weight<R>(v.kernel, sqrt(norm2<DIM, R>(d)), re);
+      R w = weight<R>(v.kernel, sqrt(norm2<DIM, R>(d)), re);
+      if (v.rho_s) {
+        // two-phase: harmonic mean of the pair's dynamic viscosities
+        const double mi = v.mu[row], mj = v.mu[j], ms = mi + mj;
+        w *= (R)(ms > 0.0 ? 2.0 * mi * mj / ms : 0.0);
+      }
       double uj[DIM];
       load_vec<DIM>(v.vel, j, uj);
 #pragma unroll
       for (int a = 0; a < DIM; ++a) acc[a] += (R)(uj[a] - ui[a]) * w;
     }
     const double clap = 2.0 * DIM / (v.lam_lap * v.n0_lap);
+    const double visc = v.rho_s ? clap / v.rho_s[row] : v.nu * clap;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
       const double lap = (double)team_sum(acc[a]);
-      us[a] = ui[a] + v.dt * (v.nu * clap * lap + v.g[a]);
+      us[a] = ui[a] + v.dt * (visc * lap + v.g[a]);
       rs[a] = xi[a] + v.dt * us[a];
     }
   }
@@ -173,12 +179,103 @@ __global__ __launch_bounds__(BLOCK) void k_density(View v, int wc) {
   if (wc) {
     double p = 0.0;
     if (ty == MPS_FLUID || ty == MPS_WALL) {
-      const double B = v.rho * v.c0 * v.c0 / (double)v.gamma_i;
+      const double B = (v.rho_s ? v.rho_s[row] : v.rho) * v.c0 * v.c0 / (double)v.gamma_i;
       p = B * (ipow(ns / v.n0_n, v.gamma_i) - 1.0);
       if (v.clamp && p < 0.0) p = 0.0;
     }
     v.p[row] = p;
   }
+}
+
+// Two-phase / turbulence: Smagorinsky eddy viscosity of fluid particles,
+// nu_t = (Cs l0)^2 sqrt(2 S:S), S the symmetric part of the MPS velocity
+// gradient d/n0 sum_j (u_j - u_i) (r_j - r_i)^T w(r)/r^2 (re_n, at r^k), and
+// the dynamic viscosity mu_i = <rho>_i (nu_i + nu_t,i) of every particle.
+template <int DIM, bool MIXED>
+__global__ __launch_bounds__(BLOCK) void k_viscosity(View v) {
+  using P = PosRef<DIM, MIXED>;
+  using R = typename P::R;
+  const int64_t row = team_row();
+  const int t = team_lane();
+  if (row >= v.n) return;
+  const int8_t ty = v.type[row];
+  double nut = 0.0;
+  if (ty == MPS_FLUID && v.smag_c2 > 0.0) {
+    const P pi = P::load(v.pos, v.posf, row);
+    double ui[DIM];
+    load_vec<DIM>(v.vel, row, ui);
+    R G[DIM][DIM];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+#pragma unroll
+      for (int b = 0; b < DIM; ++b) G[a][b] = R(0);
+    const R re = (R)v.re_n, re2 = (R)v.re_n2;
+    const int cnt = v.nb_count[row];
+    for (int l = t; l < cnt; l += TEAM) {
+      const int32_t j = v.nb_list[sl_index(row, l, v.kpad)];
+      R d[DIM];
+      pi.diff(P::load(v.pos, v.posf, j), v.cs32, d);
+      const R r2 = norm2<DIM, R>(d);
+      if (!(r2 < re2)) continue;
+      const R f = weight<R>(v.kernel, sqrt(r2), re) / r2;
+      double uj[DIM];
+      load_vec<DIM>(v.vel, j, uj);
+#pragma unroll
+      for (int a = 0; a < DIM; ++a)
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) G[a][b] += (R)(uj[a] - ui[a]) * d[b] * f;
+    }
+    double ss = 0.0;
+    const double cg = (double)DIM / v.n0_n;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+#pragma unroll
+      for (int b = 0; b < DIM; ++b) G[a][b] = team_sum(G[a][b]);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+#pragma unroll
+      for (int b = 0; b < DIM; ++b) {
+        const double sab = 0.5 * ((double)G[a][b] + (double)G[b][a]) * cg;
+        ss += sab * sab;
+      }
+    nut = ss > 0.0 ? v.smag_c2 * sqrt(2.0 * ss) : 0.0;
+  }
+  if (t == 0) {
+    v.nut[row] = nut;
+    v.mu[row] = ty == MPS_GHOST ? 0.0 : v.rho_s[row] * (v.nu_l[row] + nut);
+  }
+}
+
+// Smoothed density of the two-phase model, once before the run:
+// <rho>_i = sum_j rho_j w / sum_j w over non-dummy neighbours within re_n
+// (fluid); wall and dummy keep their own density.
+template <int DIM>
+__global__ __launch_bounds__(BLOCK) void k_smooth_density(View v, const double* rho,
+                                                          double* out) {
+  const int64_t row = team_row();
+  const int t = team_lane();
+  if (row >= v.n) return;
+  double sw = 0.0, srw = 0.0;
+  if (v.type[row] == MPS_FLUID) {
+    double xi[DIM];
+    load_vec<DIM>(v.pos, row, xi);
+    const int cnt = v.nb_count[row];
+    for (int l = t; l < cnt; l += TEAM) {
+      const int32_t j = v.nb_list[sl_index(row, l, v.kpad)];
+      if (v.type[j] == MPS_DUMMY) continue;
+      double xj[DIM];
+      load_vec<DIM>(v.pos, j, xj);
+      double r2 = 0.0;
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) r2 += (xj[a] - xi[a]) * (xj[a] - xi[a]);
+      const double w = weight<double>(v.kernel, sqrt(r2), v.re_n);
+      sw += w;
+      srw += rho[j] * w;
+    }
+    sw = team_sum(sw);
+    srw = team_sum(srw);
+  }
+  if (t == 0) out[row] = sw > 0.0 ? srw / sw : rho[row];
 }
 
 // p <- max(p, 0) after the PPE solve.
@@ -271,7 +368,7 @@ __global__ __launch_bounds__(BLOCK) void k_gradient(View v, const double* phat) 
 #pragma unroll
   for (int a = 0; a < DIM; ++a) {
     const double gp = cg * (double)team_sum(gs[a]);
-    un[a] = us[a] - v.dt / v.rho * gp;
+    un[a] = us[a] - v.dt / (v.rho_s ? v.rho_s[row] : v.rho) * gp;
     xn[a] = rs[a] + v.dt * (un[a] - us[a]);
     finite = finite && isfinite(un[a]) && isfinite(xn[a]);
   }
@@ -306,6 +403,27 @@ int launch_density(const View& v, int dim, int precision, int pmode, hipStream_t
   (void)mx;
   if (dim == 2) k_density<2><<<nb, BLOCK, 0, s>>>(v, wc);
   else k_density<3><<<nb, BLOCK, 0, s>>>(v, wc);
+  return 0;
+}
+
+int launch_viscosity(const View& v, int dim, int precision, hipStream_t s) {
+  const unsigned nb = team_blocks(v.n);
+  const bool mx = precision == MPS_MIXED;
+  if (dim == 2) {
+    if (mx) k_viscosity<2, true><<<nb, BLOCK, 0, s>>>(v);
+    else k_viscosity<2, false><<<nb, BLOCK, 0, s>>>(v);
+  } else {
+    if (mx) k_viscosity<3, true><<<nb, BLOCK, 0, s>>>(v);
+    else k_viscosity<3, false><<<nb, BLOCK, 0, s>>>(v);
+  }
+  return 0;
+}
+
+int launch_smooth_density(const View& v, const double* rho_raw, double* rho_out, int dim,
+                          hipStream_t s) {
+  const unsigned nb = team_blocks(v.n);
+  if (dim == 2) k_smooth_density<2><<<nb, BLOCK, 0, s>>>(v, rho_raw, rho_out);
+  else k_smooth_density<3><<<nb, BLOCK, 0, s>>>(v, rho_raw, rho_out);
   return 0;
 }
 

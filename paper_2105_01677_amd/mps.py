@@ -32,7 +32,7 @@ class Params(C.Structure):
         ("dim", C.c_int32), ("pmode", C.c_int32), ("kernel", C.c_int32),
         ("precision", C.c_int32), ("grad", C.c_int32), ("clamp_negative_p", C.c_int32),
         ("max_neigh", C.c_int32), ("cg_maxit", C.c_int32), ("grid_n", C.c_int32 * 3),
-        ("pad_", C.c_int32),
+        ("cg_pipelined", C.c_int32),
         ("l0", C.c_double), ("re_n", C.c_double), ("re_lap", C.c_double),
         ("rho", C.c_double), ("nu", C.c_double), ("g", C.c_double * 3),
         ("dt", C.c_double), ("beta", C.c_double), ("c0", C.c_double),
@@ -72,13 +72,19 @@ def lib() -> C.CDLL:
         L.mps_get_ppe.argtypes = [_VP, _VP, _VP, _VP, _VP, _VP]
         L.mps_get_state.argtypes = [_VP, _VP, _VP, _VP, _VP, _VP, _VP]
         L.mps_set_state.argtypes = [_VP, _VP, _VP, _VP]
+        L.mps_get_phase.argtypes = [_VP, _VP, _VP]
+        L.mps_tape_alloc.argtypes = [_VP, C.c_int32]
+        L.mps_tape_save.argtypes = [_VP, C.c_int32]
+        L.mps_tape_load.argtypes = [_VP, C.c_int32]
+        L.mps_step_adjoint.argtypes = [_VP, _VP, _VP, _VP, _VP, C.POINTER(C.c_double), _VP]
         L.mps_profile.argtypes = [_VP, C.c_uint32]
         L.mps_profile_read.argtypes = [_VP, _VP, _VP]
         L.mps_constants.argtypes = [_VP, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                     C.POINTER(C.c_double)]
         for f in ("mps_init", "mps_free", "mps_neighbors", "mps_step", "mps_pressure_solve",
                   "mps_get_ppe", "mps_get_state", "mps_set_state", "mps_constants",
-                  "mps_profile", "mps_profile_read"):
+                  "mps_profile", "mps_profile_read", "mps_tape_alloc", "mps_tape_save",
+                  "mps_tape_load", "mps_step_adjoint", "mps_get_phase"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -86,7 +92,8 @@ def lib() -> C.CDLL:
 
 EXPORTED = ["mps_init", "mps_free", "mps_last_error", "mps_neighbors", "mps_step",
             "mps_pressure_solve", "mps_get_ppe", "mps_get_state", "mps_set_state",
-            "mps_constants", "mps_profile", "mps_profile_read"]
+            "mps_constants", "mps_profile", "mps_profile_read", "mps_tape_alloc",
+            "mps_tape_save", "mps_tape_load", "mps_step_adjoint", "mps_get_phase"]
 
 KERNEL_CLASSES = ["sort", "neighbors", "predict", "density", "assemble", "cg_spmv",
                   "cg_update", "gradient"]
@@ -98,6 +105,7 @@ def make_params(p: dict) -> Params:
     o.precision, o.grad = int(p["precision"]), int(p["grad"])
     o.clamp_negative_p = int(p["clamp"])
     o.max_neigh, o.cg_maxit = int(p["max_neigh"]), int(p["cg_maxit"])
+    o.cg_pipelined = int(p.get("cg_pipelined", 0))
     for k in ("l0", "re_n", "re_lap", "rho", "nu", "dt", "beta", "c0", "gamma", "alpha",
               "cg_tol", "cell_size"):
         setattr(o, k, float(p[k]))
@@ -113,19 +121,28 @@ def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
 
 
+def _dev(x, dtype):
+    """A contiguous device tensor of the given dtype from numpy or torch."""
+    import torch
+    if x is None:
+        return None
+    if isinstance(x, torch.Tensor):
+        return x.detach().to(device="cuda", dtype=dtype).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype).to("cuda")
+
+
 class MPS:
     """One simulation context on the current CUDA (HIP) device and stream."""
 
-    def __init__(self, params: dict, pos, vel, ptype):
+    def __init__(self, params: dict, pos, vel, ptype, rho_i=None, nu_i=None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("the MPS library needs a HIP device")
         self.torch = torch
         self.params = dict(params)
-        dev = torch.device("cuda")
-        self.pos0 = torch.as_tensor(np.ascontiguousarray(pos), dtype=torch.float64).to(dev)
-        vel0 = torch.as_tensor(np.ascontiguousarray(vel), dtype=torch.float64).to(dev)
-        t0 = torch.as_tensor(np.ascontiguousarray(ptype), dtype=torch.int8).to(dev)
+        self.pos0 = _dev(pos, torch.float64)
+        vel0 = _dev(vel, torch.float64)
+        t0 = _dev(ptype, torch.int8)
         if self.pos0.ndim != 2 or vel0.shape != self.pos0.shape or t0.shape != (self.pos0.shape[0],):
             raise MPSError(E_ARG, "pos/vel must be [n][dim] and type [n]")
         self.n, self.dim = self.pos0.shape
@@ -137,8 +154,11 @@ class MPS:
         self.stream.wait_stream(torch.cuda.current_stream())
         self._P = make_params(params)
         h = C.c_void_p()
+        r_i = _dev(rho_i, torch.float64)
+        n_i = _dev(nu_i, torch.float64)
+        self.stream.wait_stream(torch.cuda.current_stream())
         st = lib().mps_init(C.byref(self._P), self.n, _ptr(self.pos0), _ptr(vel0), _ptr(t0),
-                            None, None, C.c_void_p(self.stream.cuda_stream), C.byref(h))
+                            _ptr(r_i), _ptr(n_i), C.c_void_p(self.stream.cuda_stream), C.byref(h))
         if st != OK:
             raise MPSError(st, "mps_init failed")
         self.h = h
@@ -189,6 +209,38 @@ class MPS:
         self._check(lib().mps_profile_read(self.h, ms, n), "mps_profile_read")
         return {k: (ms[i], n[i]) for i, k in enumerate(KERNEL_CLASSES)}
 
+    def phase(self):
+        """(smoothed density, eddy viscosity) of a two-phase context."""
+        torch = self.torch
+        r = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        nt = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        self._check(lib().mps_get_phase(self.h, _ptr(r), _ptr(nt)), "mps_get_phase")
+        return r, nt
+
+    def tape_alloc(self, nslots: int):
+        self._check(lib().mps_tape_alloc(self.h, int(nslots)), "mps_tape_alloc")
+
+    def tape_save(self, slot: int):
+        self._check(lib().mps_tape_save(self.h, int(slot)), "mps_tape_save")
+
+    def tape_load(self, slot: int):
+        self._check(lib().mps_tape_load(self.h, int(slot)), "mps_tape_load")
+
+    def step_adjoint(self, pos_bar, vel_bar):
+        """Cotangents of the current step's input from those of its output:
+        returns (pos_bar_prev, vel_bar_prev, nu_bar, g_bar[dim])."""
+        torch = self.torch
+        pb = _dev(pos_bar, torch.float64)
+        vb = _dev(vel_bar, torch.float64)
+        pp = torch.empty_like(pb)
+        vp = torch.empty_like(vb)
+        nub = C.c_double()
+        gb = (C.c_double * 3)()
+        self.stream.wait_stream(torch.cuda.current_stream())
+        self._check(lib().mps_step_adjoint(self.h, _ptr(pb), _ptr(vb), _ptr(pp), _ptr(vp),
+                                           C.byref(nub), gb), "mps_step_adjoint")
+        return pp, vp, nub.value, [gb[a] for a in range(self.dim)]
+
     def step_raw(self, nsteps: int) -> int:
         """mps_step without statistics; returns the status."""
         return lib().mps_step(self.h, int(nsteps), None)
@@ -205,8 +257,7 @@ class MPS:
     def pressure_solve(self, rhs=None):
         torch = self.torch
         p = torch.empty(self.n, dtype=torch.float64, device="cuda")
-        if rhs is not None:
-            rhs = torch.as_tensor(rhs, dtype=torch.float64).to("cuda").contiguous()
+        rhs = _dev(rhs, torch.float64)
         self.stream.wait_stream(torch.cuda.current_stream())
         it, rr = C.c_int32(), C.c_double()
         st = lib().mps_pressure_solve(self.h, _ptr(rhs), _ptr(p), C.byref(it), C.byref(rr))
@@ -241,8 +292,8 @@ class MPS:
 
     def set_state(self, pos, vel, ptype=None):
         torch = self.torch
-        pos = torch.as_tensor(pos, dtype=torch.float64).to("cuda").contiguous()
-        vel = torch.as_tensor(vel, dtype=torch.float64).to("cuda").contiguous()
-        t = None if ptype is None else torch.as_tensor(ptype, dtype=torch.int8).to("cuda").contiguous()
+        pos = _dev(pos, torch.float64)
+        vel = _dev(vel, torch.float64)
+        t = _dev(ptype, torch.int8)
         self.stream.wait_stream(torch.cuda.current_stream())
         self._check(lib().mps_set_state(self.h, _ptr(pos), _ptr(vel), _ptr(t)), "mps_set_state")

@@ -321,3 +321,65 @@ def test_constants(gpu, orc):
     assert n0n == pytest.approx(a[0], rel=1e-14)
     assert n0l == pytest.approx(b[0], rel=1e-14)
     assert lam == pytest.approx(b[1], rel=1e-14)
+
+
+def _two_phase_cases():
+    w2 = W.jitter(W.lattice_block(2, 18, walls_below=True, dt=1e-4))
+    heavy = w2.pos[:, 1] > 0.09
+    rho2 = np.where(heavy, 1500.0, 1000.0)
+    nu2 = np.where(heavy, 1e-3, 1e-4)
+    w3 = W.jitter(W.two_phase_3d(0.04, dt=2e-4))
+    return [(w2, rho2, nu2), (w3, w3.rho_i, w3.nu_i)]
+
+
+@pytest.mark.parametrize("case", [0, 1])
+@pytest.mark.parametrize("precision,cg_tol,tol", PRECISIONS)
+def test_two_phase_smagorinsky_one_step(gpu, orc, case, precision, cg_tol, tol):
+    """Smoothed density, eddy viscosity and one step of the two-phase +
+    Smagorinsky model (PPE) against the oracle."""
+    w, rho_i, nu_i = _two_phase_cases()[case]
+    prm = dict(w.params, precision=precision, cg_tol=cg_tol, smag_cs=0.12, nu=1e-6)
+    st, rs = orc.smoothed_density(prm, w.pos, w.ptype, rho_i)
+    assert st == 0
+    m = gpu.MPS(prm, w.pos, w.vel, w.ptype, rho_i=rho_i, nu_i=nu_i)
+    r0, _ = m.phase()
+    assert rel_err(_np(r0), rs) < 1e-14
+    m.step(1)
+    g = {k: _np(v) for k, v in m.state().items()}
+    _, nut = m.phase()
+    m.close()
+    st, o = orc.step(prm, w.pos, w.vel, w.ptype, want_lists=False, rho_s=rs, nu_i=nu_i)
+    assert st == 0
+    np.testing.assert_array_equal(g["flags"], o["flags"])
+    errs = {"disp": rel_err(g["pos"] - w.pos, o["pos"] - w.pos), "vel": rel_err(g["vel"], o["vel"]),
+            "p": rel_err(g["p"], o["p"]), "nut": rel_err(_np(nut), o["nut"])}
+    print(w.name, "two-phase errors", errs, flush=True)
+    assert np.abs(o["nut"]).max() > 0
+    for k, e in errs.items():
+        assert e < tol, (k, e)
+
+
+@pytest.mark.parametrize("precision,cg_tol,tol", [(W.FP64, 1e-11, 1e-7), (W.MIXED, 1e-9, 1e-4)])
+def test_pipelined_cg_one_step(gpu, orc, precision, cg_tol, tol):
+    """The single-reduction (pipelined) CG reaches the same pressure: one
+    step at bench size, jittered and from rest, against the oracle."""
+    for w in (W.jitter(W.config("cfg2", precision=precision)),
+              W.config("cfg2", precision=precision)):
+        w.params.update(cg_tol=cg_tol, cg_pipelined=1)
+        _compare_step(gpu, orc, w, tol)
+
+
+def test_pipelined_cg_pressure_solve(gpu):
+    """mps_pressure_solve with both CG variants on the same system: the same
+    solution to the solver tolerance; 3-D as well."""
+    for w in (W.jitter(W.config("cfg1", precision=W.MIXED)),
+              W.jitter(W.lattice_block(3, [14, 12, 10], walls_below=True, dt=2e-4))):
+        out = []
+        for pl in (0, 1):
+            prm = dict(w.params, cg_pipelined=pl, cg_tol=1e-11)
+            m = gpu.MPS(prm, w.pos, w.vel, w.ptype)
+            p, it, rr = m.pressure_solve()
+            m.close()
+            assert rr < 1e-11
+            out.append(_np(p))
+        assert rel_err(out[1], out[0]) < 1e-8

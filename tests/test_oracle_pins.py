@@ -355,3 +355,78 @@ def test_ghosts_and_particle_count(orc):
         assert (t1 == t).sum() == (w.ptype == t).sum()
     st, p2, v2, t2, _, _ = orc.run(w.params, p1, v1, t1, 1)
     np.testing.assert_array_equal(p2[f[:5]], p1[f[:5]])
+
+
+# ------------------------------------------------------- two-phase, turbulence
+
+def _two_phase_block(m=16, pmode=W.PPE_CG):
+    w = W.jitter(W.lattice_block(2, m, pmode=pmode, dt=1e-4))
+    heavy = w.pos[:, 1] > w.pos[:, 1].mean()
+    rho_i = np.where(heavy, 1500.0, 1000.0)
+    nu_i = np.where(heavy, 1e-3, 1e-4)
+    return w, rho_i, nu_i
+
+
+def test_smoothed_density(orc):
+    """<rho>_i = sum_j rho_j w / sum_j w over non-dummy neighbours (numpy);
+    uniform density gives rho exactly, deep particles keep their phase's."""
+    w, rho_i, _ = _two_phase_block()
+    st, rs = orc.smoothed_density(w.params, w.pos, w.ptype, rho_i)
+    assert st == 0
+    re = w.params["re_n"]
+    for i in range(0, w.n, 5):
+        d = np.sqrt(((w.pos - w.pos[i]) ** 2).sum(1))
+        m = (d < re) & (np.arange(w.n) != i)
+        wt = re / d[m] - 1.0
+        assert rs[i] == pytest.approx((rho_i[m] * wt).sum() / wt.sum(), rel=1e-12)
+    st, rs1 = orc.smoothed_density(w.params, w.pos, w.ptype, np.full(w.n, 1000.0))
+    np.testing.assert_allclose(rs1, 1000.0, rtol=1e-14)
+    y = w.pos[:, 1]
+    deep = np.abs(y - y.mean()) > 3 * w.params["l0"]
+    np.testing.assert_allclose(rs[deep], rho_i[deep], rtol=1e-14)
+
+
+def test_smagorinsky_linear_shear(orc):
+    """Linear shear u = (s y, 0): the MPS velocity gradient is exact on a
+    perfect lattice, S:S = s^2/2, so nu_t = (Cs l0)^2 s."""
+    w = W.lattice_block(2, 14)
+    prm = dict(w.params, smag_cs=0.12)
+    s = 3.0
+    vel = np.zeros_like(w.pos)
+    vel[:, 0] = s * (w.pos[:, 1] - w.pos[:, 1].mean())
+    st, o = orc.step(prm, w.pos, vel, w.ptype)
+    inner = _interior(w.pos, w.pos.min(0), w.pos.max(0), prm["re_n"] + 1e-9)
+    np.testing.assert_allclose(o["nut"][inner], (0.12 * prm["l0"]) ** 2 * s, rtol=1e-10)
+
+
+def test_two_phase_reduces_to_single_phase(orc):
+    w = W.jitter(W.config("cfg1"))
+    st, a = orc.step(w.params, w.pos, w.vel, w.ptype)
+    st, b = orc.step(w.params, w.pos, w.vel, w.ptype,
+                     rho_s=np.full(w.n, w.params["rho"]), nu_i=np.full(w.n, w.params["nu"]))
+    for k in ("pos", "vel", "p", "nstar"):
+        np.testing.assert_allclose(b[k], a[k], rtol=1e-9, atol=1e-12 * np.abs(a[k]).max())
+
+
+def test_two_phase_matrix_symmetric_and_momentum(orc):
+    """2/(<rho>_i + <rho>_j) keeps the PPE symmetric; with g = 0 and the
+    CMPS gradient, the harmonic-mean viscous pair terms and the pressure pair
+    terms conserve the mass-weighted momentum sum_i <rho>_i u_i."""
+    w, rho_i, nu_i = _two_phase_block()
+    st, rs = orc.smoothed_density(w.params, w.pos, w.ptype, rho_i)
+    prm = dict(w.params, grad=W.GRAD_CMPS, smag_cs=0.12)
+    st, o = orc.step(prm, w.pos, w.vel, w.ptype, want_matrix=True, rho_s=rs, nu_i=nu_i)
+    assert st == 0
+    n = w.n
+    inner = np.nonzero(o["flags"] == 0)[0]
+    A = np.zeros((n, n))
+    for i in inner:
+        c = o["count"][i]
+        A[i, o["list"][i, :c]] = o["aval"][i, :c]
+    Ai = A[np.ix_(inner, inner)]
+    np.testing.assert_array_equal(Ai, Ai.T)
+    m0 = (rs[:, None] * w.vel).sum(0)
+    m1 = (rs[:, None] * o["vel"]).sum(0)
+    scale = (rs[:, None] * np.abs(w.vel)).sum(0).max()
+    np.testing.assert_allclose(m1, m0, rtol=0, atol=1e-12 * scale)
+    assert np.abs(o["nut"]).max() > 0
