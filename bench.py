@@ -38,15 +38,19 @@ def log(*a):
 
 
 def algorithmic_bytes(cls: str, n: int, list_entries: int, nnz: int, dim: int,
-                      mixed: bool, wc: bool) -> float:
+                      mixed: bool, wc: bool, pipelined: bool = True) -> float:
     """HBM bytes one launch of a kernel class must move: each particle's own
     state once, its list entries (4 B) and matrix row (column 4 B + value
     4/8 B).  Gathers of neighbour data are cache hits after the cell sort
-    and are not counted."""
+    and are not counted.  cg_spmv is the one-kernel pipelined CG iteration
+    (row length, 7 FP64 vectors read, 6 written) or, with pipelined=False,
+    the SpMV kernel of the two-kernel CG."""
     vec = 8 * (2 if dim == 2 else 4)       # stored FP64 vector
     f4 = 16 if mixed else 0                # FP32 relative position copy
     val = 4 if mixed else 8
     if cls == "cg_spmv":
+        if pipelined:
+            return n * (4 + 13 * 8) + nnz * (4 + val)
         return n * (4 + 5 * 8) + nnz * (4 + val)
     if cls == "cg_update":
         return n * 8 * 8
@@ -120,7 +124,8 @@ def kernel_bandwidth(w, r, mixed, wc):
         if nl == 0:
             continue
         avg = ms / nl
-        b = algorithmic_bytes(k, w.n, s["list_entries"], s["ppe_nnz"], w.params["dim"], mixed, wc)
+        b = algorithmic_bytes(k, w.n, s["list_entries"], s["ppe_nnz"], w.params["dim"], mixed, wc,
+                              bool(w.params.get("cg_pipelined", 1)))
         out[k] = {"avg_launch_us": 1e3 * avg, "launches": nl, "algorithmic_GBps": b / (avg * 1e-3) / 1e9,
                   "hbm_frac": b / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS}
     return out
@@ -168,7 +173,7 @@ def cpu_baseline(w, seconds):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -236,24 +241,28 @@ def main():
     log("breakdown ms:", {k: round(v, 3) for k, v in tot.items()}, "dominant:", dom)
     ms_dom, n_dom = br["profile"][dom]
     avg_ms = ms_dom / max(n_dom, 1)
-    nbytes = algorithmic_bytes(dom, w.n, s["list_entries"], s["ppe_nnz"], 2, True, False)
+    nbytes = algorithmic_bytes(dom, w.n, s["list_entries"], s["ppe_nnz"], 2, True, False,
+                               bool(w.params["cg_pipelined"]))
     achieved = nbytes / (avg_ms * 1e-3) / 1e9
     log(f"headline {hd['particle_steps_per_s']:.4g} particle-steps/s, "
         f"{hd['ms_per_step']:.4f} ms/step, cg iters last {s['cg_iters_last']}")
 
+    # the comparison paths on the same workload: plain FP64 with the same
+    # pipelined CG (the like-for-like reference of the mixed path), both
+    # precisions with the two-kernel textbook CG, and the weakly-compressible
+    # model
     extra = {}
-    if not args.only_headline:
-        for name, prec, pm, pl in (("ppe_fp64", W.FP64, W.PPE_CG, 0),
-                                   ("ppe_mixed_pipelined", W.MIXED, W.PPE_CG, 1),
-                                   ("ppe_fp64_pipelined", W.FP64, W.PPE_CG, 1),
-                                   ("wc_mixed", W.MIXED, W.WC_EOS, 0),
-                                   ("wc_fp64", W.FP64, W.WC_EOS, 0)):
-            wx = W.config("cfg2", precision=prec, pmode=pm)
-            wx.params["cg_pipelined"] = pl
-            r = run_gpu(wx, K, Wm)
-            extra[name] = {"value": r["particle_steps_per_s"], "ms_per_step": r["ms_per_step"],
-                           "cg_iters_mean": r["stats"]["cg_iters_total"] / K}
-            log(name, extra[name])
+    for name, prec, pm, pl in (("ppe_fp64", W.FP64, W.PPE_CG, 1),
+                               ("ppe_mixed_standard_cg", W.MIXED, W.PPE_CG, 0),
+                               ("ppe_fp64_standard_cg", W.FP64, W.PPE_CG, 0),
+                               ("wc_mixed", W.MIXED, W.WC_EOS, 0),
+                               ("wc_fp64", W.FP64, W.WC_EOS, 0)):
+        wx = W.config("cfg2", precision=prec, pmode=pm)
+        wx.params["cg_pipelined"] = pl
+        r = run_gpu(wx, K, Wm)
+        extra[name] = {"value": r["particle_steps_per_s"], "ms_per_step": r["ms_per_step"],
+                       "cg_iters_mean": r["stats"]["cg_iters_total"] / K}
+        log(name, extra[name])
 
     cfg3d = {}
     if not args.only_headline and not args.no_3d:
@@ -278,13 +287,15 @@ def main():
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": workload, "n_particles": w.n, "n_fluid": c["fluid"],
-                   "pressure": "PPE-CG tol 1e-9", "precision": "mixed FP32 sums / FP64 CG",
+                   "pressure": "PPE, pipelined Jacobi-CG to rel. residual 1e-9",
+                   "precision": "mixed FP32 sums / FP64 CG",
                    "dt": w.params["dt"], "dim": 2},
         "fluid_particle_steps_per_s": c["fluid"] * K / hd["seconds"],
         "cg_iters_mean": s["cg_iters_total"] / K,
         "fp64_plain": extra.get("ppe_fp64"),
-        "mixed_pipelined_cg": extra.get("ppe_mixed_pipelined"),
-        "fp64_pipelined_cg": extra.get("ppe_fp64_pipelined"),
+        "mixed_vs_fp64_plain": hd["particle_steps_per_s"] / extra["ppe_fp64"]["value"],
+        "mixed_standard_cg": extra.get("ppe_mixed_standard_cg"),
+        "fp64_standard_cg": extra.get("ppe_fp64_standard_cg"),
         "wc_eos_mixed": extra.get("wc_mixed"),
         "wc_eos_fp64": extra.get("wc_fp64"),
         "kernel_ms_per_step": {k: v / K for k, v in tot.items()},

@@ -193,6 +193,10 @@ mps_status mps_get_state(mps_ctx* ctx, double* pos, double* vel, double* p,
 mps_status mps_set_state(mps_ctx* ctx, const double* pos, const double* vel,
                          const int8_t* type);
 
+/* Device memory held by the context (state, work arrays, tape), bytes.
+ * Host pointer.  Errors: MPS_E_ARG. */
+mps_status mps_device_bytes(const mps_ctx* ctx, int64_t* bytes);
+
 /* Two-phase model: smoothed density <rho> and Smagorinsky eddy viscosity
  * nu_t of the last step, [n] each in original order (device; either may be
  * NULL).  Errors: MPS_E_ARG for a single-phase context. */

@@ -49,6 +49,8 @@ struct mps_ctx {
   int32_t *cellid = nullptr, *slot = nullptr, *cell_count = nullptr, *cell_start = nullptr,
           *perm = nullptr, *tile_sum = nullptr;
   int32_t *nb_count = nullptr, *nb_list = nullptr;
+  int32_t* tile_nr = nullptr;
+  int4* tile_rng = nullptr;
   int32_t *a_nnz = nullptr, *a_col = nullptr;
   void* a_val = nullptr;
   double *diag = nullptr, *b = nullptr;
@@ -62,9 +64,9 @@ struct mps_ctx {
   double* mu = nullptr;
   double* partA = nullptr;
   double* partB = nullptr;
-  double *pl_u = nullptr, *pl_z = nullptr, *pl_s = nullptr, *pl_w[2] = {nullptr, nullptr},
+  double *pl_z = nullptr, *pl_s = nullptr, *pl_m[2] = {nullptr, nullptr},
          *pl_part[2] = {nullptr, nullptr};
-  int nspmv = 0, nupd = 0;
+  int nspmv = 0, nupd = 0, npcg = 0;
   CGScalars* sc = nullptr;
   int32_t* status = nullptr;
   int64_t* counts = nullptr;   // [4]: surface, ghost, list entries, matrix nnz
@@ -101,6 +103,8 @@ struct mps_ctx {
   AdjView adj = {};
   double* h_part = nullptr;
   // bookkeeping
+  int64_t bytes = 0;       // device memory held by the context (state, work)
+  int64_t tape_bytes = 0;  // device memory of the tape and adjoint arrays
   bool poisoned = false;
   bool ppe_valid = false;
   int last_iters = 0;
@@ -152,9 +156,15 @@ void lattice(int dim, double l0, double re, int kernel, double* n0, double* lam)
   *lam = s2 / sw;
 }
 
+// Device allocations of all contexts go through here; the running total of
+// each context is kept by the callers (mps_ctx::bytes).
+thread_local int64_t* g_bytes = nullptr;
 template <class T>
 hipError_t dalloc(T** p, size_t count) {
-  return hipMalloc((void**)p, count * sizeof(T) + 256);
+  const size_t b = count * sizeof(T) + 256;
+  hipError_t e = hipMalloc((void**)p, b);
+  if (e == hipSuccess && g_bytes) *g_bytes += (int64_t)b;
+  return e;
 }
 
 View make_view(const mps_ctx* c) {
@@ -220,6 +230,8 @@ View make_view(const mps_ctx* c) {
   v.tile_sum = c->tile_sum;
   v.perm = c->perm;
   v.nb_count = c->nb_count;
+  v.tile_nr = c->tile_nr;
+  v.tile_rng = c->tile_rng;
   v.nb_list = c->nb_list;
   v.a_nnz = c->a_nnz;
   v.a_col = c->a_col;
@@ -234,15 +246,15 @@ View make_view(const mps_ctx* c) {
   v.q = c->q;
   v.partA = c->partA;
   v.partB = c->partB;
-  v.pl_u = c->pl_u;
   v.pl_z = c->pl_z;
   v.pl_s = c->pl_s;
-  v.pl_w[0] = c->pl_w[0];
-  v.pl_w[1] = c->pl_w[1];
+  v.pl_m[0] = c->pl_m[0];
+  v.pl_m[1] = c->pl_m[1];
   v.pl_part[0] = c->pl_part[0];
   v.pl_part[1] = c->pl_part[1];
   v.nspmv = c->nspmv;
   v.nupd = c->nupd;
+  v.npcg = c->npcg;
   v.sc = c->sc;
   v.status = c->status;
   if (c->multi) {
@@ -403,6 +415,7 @@ mps_status search(mps_ctx* c) {
   v = make_view(c);
   {
     Prof pr(c, MPS_KC_NEIGH);
+    launch_tiles(v, c->dim, c->s);
     launch_neighbors(v, c->dim, c->P.precision, c->s);
   }
   return MPS_OK;
@@ -656,6 +669,7 @@ mps_status mps_init(const mps_params* params, int64_t n, const double* pos, cons
   const size_t nv = (size_t)n * c->ps;
   hipError_t e = hipSuccess;
   auto A = [&](hipError_t x) { if (e == hipSuccess) e = x; };
+  g_bytes = &c->bytes;
   for (int k = 0; k < 2; ++k) {
     A(dalloc(&c->pos[k], nv));
     A(dalloc(&c->vel[k], nv));
@@ -678,10 +692,19 @@ mps_status mps_init(const mps_params* params, int64_t n, const double* pos, cons
   A(dalloc(&c->cell_start, c->ncell + 2));
   A(dalloc(&c->tile_sum, (c->ncell + 1 + SCAN_TILE - 1) / SCAN_TILE));
   A(dalloc(&c->nb_count, n));
+  {
+    const size_t ng = (size_t)((n + ROWS_PER_BLOCK - 1) / ROWS_PER_BLOCK);
+    A(dalloc(&c->tile_nr, ng));
+    A(dalloc(&c->tile_rng, ng * TILE_RANGES));
+  }
   A(dalloc(&c->nb_list, c->slots));
   A(dalloc(&c->a_nnz, n));
   A(dalloc(&c->a_col, c->slots));
-  A(hipMalloc(&c->a_val, c->slots * (params->precision == MPS_MIXED ? 4 : 8) + 256));
+  {
+    const size_t b = c->slots * (params->precision == MPS_MIXED ? 4 : 8) + 256;
+    A(hipMalloc(&c->a_val, b));
+    c->bytes += (int64_t)b;
+  }
   A(dalloc(&c->diag, n));
   A(dalloc(&c->b, n));
   A(dalloc(&c->r, n));
@@ -700,18 +723,19 @@ mps_status mps_init(const mps_params* params, int64_t n, const double* pos, cons
   c->nupd = cg_update_blocks(n);
   A(dalloc(&c->partA, (size_t)std::max(c->nspmv, c->nupd) * 4));
   A(dalloc(&c->partB, (size_t)c->nspmv));
+  c->npcg = pcg_blocks(n);
   if (params->cg_pipelined) {
-    A(dalloc(&c->pl_u, n));
     A(dalloc(&c->pl_z, n));
     A(dalloc(&c->pl_s, n));
     for (int k = 0; k < 2; ++k) {
-      A(dalloc(&c->pl_w[k], n));
-      A(dalloc(&c->pl_part[k], (size_t)c->nspmv * 4));
+      A(dalloc(&c->pl_m[k], n));
+      A(dalloc(&c->pl_part[k], (size_t)c->npcg * 4));
     }
   }
   A(dalloc(&c->sc, 1));
   A(dalloc(&c->status, 1));
   A(dalloc(&c->counts, 4));
+  g_bytes = nullptr;
   if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_sc, sizeof(CGScalars), hipHostMallocDefault);
   if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_status, sizeof(int32_t), hipHostMallocDefault);
   if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_counts, 4 * sizeof(int64_t), hipHostMallocDefault);
@@ -774,12 +798,11 @@ mps_status mps_free(mps_ctx* c) {
                   c->type[0], c->type[1], c->id[0], c->id[1], c->pd[0], c->pd[1],
                   c->pcell, c->posf, c->rsf, c->us, c->rs, c->nstar, c->flags,
                   c->cellid, c->slot, c->perm, c->cell_count, c->cell_start, c->tile_sum,
-                  c->nb_count,
+                  c->nb_count, c->tile_nr, c->tile_rng,
                   c->nb_list, c->a_nnz, c->a_col, c->a_val, c->diag, c->b, c->r, c->z,
                   c->q, c->p_save, c->partA, c->partB, c->sc, c->status, c->counts,
                   c->rho_s[0], c->rho_s[1], c->nu_l[0], c->nu_l[1], c->nut, c->mu,
-                  c->pl_u, c->pl_z, c->pl_s, c->pl_w[0], c->pl_w[1], c->pl_part[0],
-                  c->pl_part[1]};
+                  c->pl_z, c->pl_s, c->pl_m[0], c->pl_m[1], c->pl_part[0], c->pl_part[1]};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (int k = 0; k < 2; ++k) {
@@ -802,6 +825,12 @@ mps_status mps_free(mps_ctx* c) {
 }
 
 const char* mps_last_error(const mps_ctx* c) { return c ? c->err : kNoCtx; }
+
+mps_status mps_device_bytes(const mps_ctx* c, int64_t* bytes) {
+  if (!c || !bytes) return MPS_E_ARG;
+  *bytes = c->bytes + c->tape_bytes;
+  return MPS_OK;
+}
 
 mps_status mps_constants(const mps_ctx* c, double* n0_n, double* n0_lap, double* lambda_lap) {
   if (!c) return MPS_E_ARG;
@@ -991,6 +1020,9 @@ mps_status mps_tape_alloc(mps_ctx* c, int32_t nslots) {
   c->ntape = nslots;
   hipError_t e = hipSuccess;
   auto A = [&](hipError_t x) { if (e == hipSuccess) e = x; };
+  const int64_t before = c->bytes;
+  c->tape_bytes = 0;
+  g_bytes = &c->tape_bytes;
   for (int k = 0; k < nslots; ++k) {
     mps_ctx::Slot& t = c->tape[k];
     A(dalloc(&t.pos, nv));
@@ -1018,6 +1050,8 @@ mps_status mps_tape_alloc(mps_ctx* c, int32_t nslots) {
   A(dalloc(&a.lam, n));
   const int nb = adj_partial_blocks(n);
   A(dalloc(&a.part, (size_t)nb * 4));
+  g_bytes = nullptr;
+  (void)before;
   if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_part, (size_t)nb * 4 * sizeof(double), hipHostMallocDefault);
   if (e != hipSuccess) {
     free_tape(c);

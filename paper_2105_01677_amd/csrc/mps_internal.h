@@ -33,6 +33,13 @@ constexpr int SLICE = WAVE / TEAM;        // rows per wavefront
 constexpr int BLOCK = 256;
 constexpr int ROWS_PER_BLOCK = BLOCK / TEAM;
 constexpr int SCAN_TILE = 4096;  // cells per workgroup of the cell-count scan
+// LDS tiles: records staged per workgroup of 32 rows, and the number of
+// cell ranges (one per neighbouring grid row: 3 in 2-D, 9 in 3-D)
+constexpr int TILE_CAP = 1280;
+constexpr int TILE_RANGES = 9;
+#ifndef MPS_TILES
+#define MPS_TILES 1
+#endif
 
 // Status bits raised by kernels (one int32 word on the device).
 enum : int32_t {
@@ -70,6 +77,17 @@ struct CGScalars {
 // per-workgroup partials of the previous kernel, so their number is bounded.
 constexpr int CG_SPMV_BLOCKS = 2048;
 constexpr int CG_UPD_BLOCKS = 1024;
+// Pipelined CG: workgroup size and grid cap (every workgroup loads all
+// partials of the previous iteration, one double4 per workgroup).
+#ifndef PCG_BLOCK
+#define PCG_BLOCK 512
+#endif
+#ifndef PCG_MAX_BLOCKS
+#define PCG_MAX_BLOCKS 1024
+#endif
+#ifndef CG_UNROLL
+#define CG_UNROLL 4
+#endif
 
 // Everything a kernel may touch, passed by value.
 struct View {
@@ -111,6 +129,10 @@ struct View {
   // lists
   int32_t* nb_count;
   int32_t* nb_list;
+  // LDS tiles, one per group of ROWS_PER_BLOCK rows: number of ranges (-1:
+  // no tile) and the ranges (first sorted index, end, LDS slot of the first)
+  int32_t* tile_nr;
+  int4* tile_rng;
   // PPE
   int32_t* a_nnz;
   int32_t* a_col;
@@ -126,13 +148,13 @@ struct View {
   double* partA;      // [blocks][4]: (r,z), (r,r), (b,b) of assembly / update
   double* partB;      // [blocks]: (p, A p) of the SpMV workgroups
   int nspmv, nupd;    // grid sizes of the SpMV / assembly and update kernels
+  int npcg;           // grid size of the pipelined CG kernels
   CGScalars* sc;
-  // pipelined CG (one kernel per iteration): u = M^-1 r, w = A u (double
-  // buffered), z, s; q and the direction p reuse q and pd[0]
-  double* pl_u;
+  // pipelined CG (one kernel per iteration): m = D^-1 w (double buffered),
+  // z, s; the direction p reuses pd[0]
   double* pl_z;
   double* pl_s;
-  double* pl_w[2];
+  double* pl_m[2];
   double* pl_part[2]; // per-workgroup (r,u), (w,u), (r,r), double buffered
   int32_t* status;
   // two-phase / turbulence (null when single phase)
@@ -235,6 +257,97 @@ __device__ inline uint32_t team_ballot(bool pred) {
   return (uint32_t)((m >> base) & ((1u << TEAM) - 1));
 }
 
+// Candidate tile of a group of ROWS_PER_BLOCK consecutive sorted rows whose
+// particles lie in one grid row of cells (x0 .. x1): the union of the cell
+// ranges their neighbours come from (cells x0-1 .. x1+1 of the 3 or 9
+// neighbouring grid rows), each contiguous in the sorted order, staged in
+// LDS back to back.  Sorted index j of range k sits in slot j + delta[k];
+// ranges ascend in j and in slot.
+struct TileMap {
+  int nr;     // number of ranges; < 0: the group has no tile
+  int total;  // staged records
+  int start[TILE_RANGES];
+  int delta[TILE_RANGES];
+  __device__ void load(const View& v, int g) {
+    if (!MPS_TILES) {
+      nr = -1;
+      total = 0;
+      return;
+    }
+    nr = v.tile_nr[g];
+    total = 0;
+#pragma unroll
+    for (int k = 0; k < TILE_RANGES; ++k) {
+      const int4 r = k < nr ? v.tile_rng[(int64_t)g * TILE_RANGES + k] : make_int4(0, 0, 0, 0);
+      start[k] = r.x;
+      delta[k] = r.z - r.x;
+      total = k < nr ? r.z + (r.y - r.x) : total;
+    }
+  }
+  __device__ int slot(int j) const {
+    int d = delta[0];
+#pragma unroll
+    for (int k = 1; k < TILE_RANGES; ++k) d = (k < nr && j >= start[k]) ? delta[k] : d;
+    return j + d;
+  }
+  // sorted index of slot i < total
+  __device__ int src(int i) const {
+    int d = delta[0];
+#pragma unroll
+    for (int k = 1; k < TILE_RANGES; ++k) d = (k < nr && i >= start[k] + delta[k]) ? delta[k] : d;
+    return i - d;
+  }
+};
+
+// Stage slots [0, tm.total) of the group's tile: rec(j) -> LDS slot, with
+// all loads of a thread issued before its first LDS store.
+template <class T, class F>
+__device__ inline void stage_tile(const TileMap& tm, T* __restrict__ sh, F&& rec) {
+  constexpr int CP = (TILE_CAP + BLOCK - 1) / BLOCK;
+  T a[CP];
+#pragma unroll
+  for (int c = 0; c < CP; ++c) {
+    const int i = threadIdx.x + c * BLOCK;
+    if (i < tm.total) a[c] = rec(tm.src(i));
+  }
+#pragma unroll
+  for (int c = 0; c < CP; ++c) {
+    const int i = threadIdx.x + c * BLOCK;
+    if (i < tm.total) sh[i] = a[c];
+  }
+}
+
+// Sum over a row's matrix entries l, l + TEAM, ... < nnz (l = the team lane,
+// or a later start on the same lane) of
+// val(e) * x(col(e)), U entries per step so that U independent gathers are
+// in flight per lane (the latency of the dependent index -> value load
+// chain, not bandwidth, limits the SpMV); the order of the additions is
+// fixed, so the result is reproducible.
+template <int U, class VT, class F>
+__device__ inline double row_dot(const int32_t* __restrict__ col, const VT* __restrict__ val,
+                                 int64_t row, int nnz, int kpad, int l, F&& x) {
+  double s = 0.0;
+  for (; l + (U - 1) * TEAM < nnz; l += U * TEAM) {
+    const int64_t e0 = sl_index(row, l, kpad);
+    int32_t j[U];
+    double a[U], xv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      j[u] = col[e0 + u * WAVE];
+      a[u] = (double)val[e0 + u * WAVE];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) xv[u] = x(j[u]);
+#pragma unroll
+    for (int u = 0; u < U; ++u) s += a[u] * xv[u];
+  }
+  for (; l < nnz; l += TEAM) {
+    const int64_t e = sl_index(row, l, kpad);
+    s += (double)val[e] * x(col[e]);
+  }
+  return s;
+}
+
 // Kernel weight (Eq. 4, or the cubic kernel), zero at and beyond re.
 template <class R>
 __device__ inline R weight(int kernel, R r, R re) {
@@ -248,6 +361,7 @@ __device__ inline R weight(int kernel, R r, R re) {
 int launch_bin(const View& v, int dim, hipStream_t s);
 int launch_permute(const View& v, int dim, int precision, hipStream_t s);
 int launch_neighbors(const View& v, int dim, int precision, hipStream_t s);
+int launch_tiles(const View& v, int dim, hipStream_t s);
 int launch_export_lists(const View& v, int32_t* cell_out, int32_t* count_out,
                         int32_t* list_out, int dim, hipStream_t s);
 int launch_predict(const View& v, int dim, int precision, hipStream_t s);
@@ -259,6 +373,7 @@ int launch_assemble(const View& v, int dim, int precision, const double* rhs_sor
                     bool zero_x0, hipStream_t s);
 int launch_cg_spmv(const View& v, int precision, hipStream_t s);
 int launch_cg_update(const View& v, hipStream_t s);
+int pcg_blocks(int64_t n);
 int launch_pcg_setup(const View& v, int precision, hipStream_t s);
 int launch_pcg_iter(const View& v, int precision, int parity, hipStream_t s);
 int launch_clamp(const View& v, hipStream_t s);

@@ -31,6 +31,7 @@
 // poll rarely.
 #include "mps_internal.h"
 
+
 namespace mps {
 
 template <int DIM, bool MIXED>
@@ -69,10 +70,11 @@ struct PosRefP<DIM, true> {
   }
 };
 
-// Sum over the workgroup in a fixed tree; result valid in thread 0.
-template <int NV>
+// Sum over the workgroup (NT threads) in a fixed tree; result valid in
+// thread 0.
+template <int NV, int NT = BLOCK>
 __device__ inline void block_sum(double (&x)[NV]) {
-  __shared__ double sh[NV][BLOCK / WAVE];
+  __shared__ double sh[NV][NT / WAVE];
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
 #pragma unroll
@@ -88,7 +90,7 @@ __device__ inline void block_sum(double (&x)[NV]) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
       double s = 0.0;
-      for (int q = 0; q < BLOCK / WAVE; ++q) s += sh[k][q];
+      for (int q = 0; q < NT / WAVE; ++q) s += sh[k][q];
       x[k] = s;
     }
   }
@@ -98,17 +100,17 @@ __device__ inline void block_sum(double (&x)[NV]) {
 // Sum of np per-workgroup partials (stride doubles apart) in a fixed order;
 // every thread gets the result.  All workgroups that call this on the same
 // data obtain the same bits.
-template <int NV>
+template <int NV, int NT = BLOCK>
 __device__ inline void sum_partials(const double* part, int np, int stride, double (&tot)[NV]) {
   __shared__ double bc[NV];
   double s[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) s[k] = 0.0;
-  for (int b = threadIdx.x; b < np; b += BLOCK) {
+  for (int b = threadIdx.x; b < np; b += NT) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) s[k] += part[(int64_t)b * stride + k];
   }
-  block_sum<NV>(s);
+  block_sum<NV, NT>(s);
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) bc[k] = s[k];
@@ -118,12 +120,12 @@ __device__ inline void sum_partials(const double* part, int np, int stride, doub
   for (int k = 0; k < NV; ++k) tot[k] = bc[k];
 }
 
-// Contiguous chunk of 32-row groups handled by this workgroup of a
-// grid-capped team kernel.
+// Contiguous chunk of row groups (rpb rows each) handled by this workgroup
+// of a grid-capped team kernel.
 struct Chunk {
   int64_t g0, g1;
-  __device__ Chunk(int64_t n) {
-    const int64_t ng = (n + ROWS_PER_BLOCK - 1) / ROWS_PER_BLOCK;
+  __device__ Chunk(int64_t n, int rpb = ROWS_PER_BLOCK) {
+    const int64_t ng = (n + rpb - 1) / rpb;
     const int64_t per = (ng + gridDim.x - 1) / gridDim.x;
     g0 = (int64_t)xcd_block() * per;
     g1 = g0 + per < ng ? g0 + per : ng;
@@ -144,6 +146,30 @@ __global__ __launch_bounds__(BLOCK) void k_assemble(View v, const double* rhs, i
   VT* aval = reinterpret_cast<VT*>(v.a_val);
   const Chunk ch(v.n);
   for (int64_t g = ch.g0; g < ch.g1; ++g) {
+    // mixed path: the neighbours' FP32 positions, flags and (warm start)
+    // pressures of the group's tile staged in LDS
+    [[maybe_unused]] float4* s_p = nullptr;
+    [[maybe_unused]] double* s_q = nullptr;
+    [[maybe_unused]] int8_t* s_f = nullptr;
+    bool tiled = false;
+    TileMap tm;
+    if constexpr (MIXED) {
+      __shared__ float4 sh_p[TILE_CAP];
+      __shared__ double sh_q[TILE_CAP];
+      __shared__ int8_t sh_f[TILE_CAP];
+      s_p = sh_p;
+      s_q = sh_q;
+      s_f = sh_f;
+      tm.load(v, (int)g);
+      tiled = tm.nr > 0;
+      if (tiled) {
+        __syncthreads();  // the previous group's reads are done
+        stage_tile(tm, s_p, [&](int j) { return v.rsf[j]; });
+        stage_tile(tm, s_f, [&](int j) { return v.flags[j]; });
+        if (!zero_x0) stage_tile(tm, s_q, [&](int j) { return v.p[j]; });
+        __syncthreads();
+      }
+    }
     const int64_t row = g * ROWS_PER_BLOCK + threadIdx.x / TEAM;
     if (row >= v.n) continue;
     const bool inner = v.flags[row] == MPS_FLAG_INNER;
@@ -158,12 +184,28 @@ __global__ __launch_bounds__(BLOCK) void k_assemble(View v, const double* rhs, i
         const int l = l0 + t;
         bool keep = false;
         int32_t j = 0;
+        int sj = 0;
         R c = R(0);
         if (l < cnt) {
           j = v.nb_list[sl_index(row, l, v.kpad)];
-          if (v.type[j] != MPS_DUMMY) {
+          P pj;
+          int8_t fj;
+          if constexpr (MIXED) {
+            if (tiled) {
+              sj = tm.slot(j);
+              fj = s_f[sj];
+              pj.f = s_p[sj];
+            } else {
+              fj = v.flags[j];
+              pj.f = v.rsf[j];
+            }
+          } else {
+            fj = v.type[j] == MPS_DUMMY ? MPS_FLAG_DUMMY : v.flags[j];
+            if (fj != MPS_FLAG_DUMMY) pj = P::load(v, j);
+          }
+          if (fj != MPS_FLAG_DUMMY) {
             R d[DIM];
-            pi.diff(P::load(v, j), v.cs32, d);
+            pi.diff(pj, v.cs32, d);
             R r2 = d[0] * d[0] + d[1] * d[1];
             if constexpr (DIM == 3) r2 += d[2] * d[2];
             if (r2 < re2) {
@@ -171,7 +213,7 @@ __global__ __launch_bounds__(BLOCK) void k_assemble(View v, const double* rhs, i
               // two-phase: 1/rho -> 2/(<rho>_i + <rho>_j), symmetric
               if (v.rho_s) c *= (R)(v.rho * 2.0 / (v.rho_s[row] + v.rho_s[j]));
               dsum += (double)c;
-              keep = v.flags[j] == MPS_FLAG_INNER;
+              keep = fj == MPS_FLAG_INNER;
             }
           }
         }
@@ -181,7 +223,7 @@ __global__ __launch_bounds__(BLOCK) void k_assemble(View v, const double* rhs, i
           const int64_t e = sl_index(row, s, v.kpad);
           v.a_col[e] = j;
           aval[e] = -c;
-          if (!zero_x0) ax -= (double)c * v.p[j];
+          if (!zero_x0) ax -= (double)c * (tiled ? s_q[sj] : v.p[j]);
         }
         nnz += __popc(m);
       }
@@ -276,13 +318,9 @@ __global__ __launch_bounds__(BLOCK) void k_cg_spmv(View v) {
     const int64_t row = g * ROWS_PER_BLOCK + threadIdx.x / TEAM;
     if (row >= v.n) continue;
     const int nnz = v.a_nnz[row];
-    double s = 0.0;
-    for (int l = t; l < nnz; l += TEAM) {
-      const int64_t e = sl_index(row, l, v.kpad);
-      const int32_t j = v.a_col[e];
-      const double pj = v.z[j] + beta * pold[j];
-      s += (double)aval[e] * pj;
-    }
+    const double* __restrict__ z = v.z;
+    double s = row_dot<4>(v.a_col, aval, row, nnz, v.kpad, t,
+                       [&](int32_t j) { return z[j] + beta * pold[j]; });
     s = team_sum(s);
     if (t == 0) {
       const double pi = v.z[row] + beta * pold[row];
@@ -332,25 +370,36 @@ __global__ __launch_bounds__(BLOCK) void k_cg_update(View v) {
 
 // ------------------------------------------------------- pipelined variant
 // Preconditioned CG with one global reduction per iteration (Ghysels and
-// Vanroose's pipelined CG), Jacobi M = diag(A):
-//   gamma = (r, u), delta = (w, u), m = M^-1 w, n = A m,
+// Vanroose's pipelined CG) and the Jacobi preconditioner D = diag(A):
+//   gamma = (r, u), delta = (w, u), m = D^-1 w, n = A m,
 //   beta = gamma/gamma_old, alpha = gamma/(delta - beta gamma/alpha_old),
-//   z = n + beta z, q = m + beta q, s = w + beta s, p = u + beta p,
-//   x += alpha p, r -= alpha s, u -= alpha q, w -= alpha z.
+//   z = n + beta z, s = w + beta s, p = u + beta p,
+//   x += alpha p, r -= alpha s, w -= alpha z.
+// With a diagonal preconditioner the recurrences u = D^-1 r and
+// q = D^-1 s reduce to one division each, so u and q are not stored, and
+// w = D m is not stored either: m is the one vector the SpMV gathers,
+// double buffered because the neighbours' m of this iteration are read
+// while the new m is written.  Per row an iteration loads D, m, z, s, p, r,
+// x and stores m, z, s, p, r, x.
 // The dot products of iteration k+1 are formed by the workgroups of
-// iteration k and reduced (redundantly, fixed order) at the start of k+1,
-// so each iteration is one kernel.  w is double-buffered because the SpMV
-// reads the neighbours' w of this iteration while the new w is written.
-// Setup: w0 = A u0 with u0 = r0/diag from the assembly; gamma_old = inf
-// and alpha_old = 1 make the first iteration beta = 0, alpha = gamma/delta.
+// iteration k and reduced (redundantly, in a fixed order) at the start of
+// k+1, so each iteration is one kernel.  Every load that does not depend on
+// the reduced scalars (the row's first matrix entries, the gathers of m,
+// the row's own vectors, the partials) is issued before any of them is
+// consumed, so their latencies overlap instead of adding up.
+// Setup: w0 = A u0 with u0 = D^-1 r0 from the assembly; gamma_old = inf and
+// alpha_old = 1 make the first iteration beta = 0, alpha = gamma/delta.
+constexpr int PCG_ROWS = PCG_BLOCK / TEAM;
+constexpr int PCG_PK = (PCG_MAX_BLOCKS + PCG_BLOCK - 1) / PCG_BLOCK;
+
 template <class VT>
-__global__ __launch_bounds__(BLOCK) void k_pcg_setup(View v) {
+__global__ __launch_bounds__(PCG_BLOCK) void k_pcg_setup(View v) {
   CGScalars* sc = v.sc;
   double tot[3];
-  sum_partials<3>(v.partA, sc->nasm, 4, tot);
+  sum_partials<3, PCG_BLOCK>(v.partA, sc->nasm, 4, tot);
   const double rr = tot[1], bb = tot[2];
   const bool done = bb == 0.0 || rr <= v.cg_tol2 * bb;
-  const Chunk ch(v.n);
+  const Chunk ch(v.n, PCG_ROWS);
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     sc->bb = bb;
     sc->rr = rr;
@@ -363,32 +412,27 @@ __global__ __launch_bounds__(BLOCK) void k_pcg_setup(View v) {
   if (done) {
     if (bb == 0.0) {
       for (int64_t g = ch.g0; g < ch.g1; ++g) {
-        const int64_t row = g * ROWS_PER_BLOCK + threadIdx.x / TEAM;
+        const int64_t row = g * PCG_ROWS + threadIdx.x / TEAM;
         if (row < v.n && t == 0) v.p[row] = 0.0;
       }
     }
     return;
   }
   const VT* __restrict__ aval = reinterpret_cast<const VT*>(v.a_val);
+  const double* __restrict__ u0 = v.z;  // D^-1 r0, written by the assembly
   double gam = 0.0, del = 0.0, rr2 = 0.0;
   for (int64_t g = ch.g0; g < ch.g1; ++g) {
-    const int64_t row = g * ROWS_PER_BLOCK + threadIdx.x / TEAM;
+    const int64_t row = g * PCG_ROWS + threadIdx.x / TEAM;
     if (row >= v.n) continue;
-    const int nnz = v.a_nnz[row];
-    double s = 0.0;
-    for (int l = t; l < nnz; l += TEAM) {
-      const int64_t e = sl_index(row, l, v.kpad);
-      s += (double)aval[e] * v.z[v.a_col[e]];
-    }
+    double s = row_dot<4>(v.a_col, aval, row, v.a_nnz[row], v.kpad, t,
+                          [&](int32_t j) { return u0[j]; });
     s = team_sum(s);
     if (t == 0) {
-      const double u = v.z[row], r = v.r[row];
-      const double w = v.diag[row] * u + s;
-      v.pl_u[row] = u;
-      v.pl_w[0][row] = w;
+      const double dg = v.diag[row], u = u0[row], r = v.r[row];
+      const double w = dg * u + s;
+      v.pl_m[0][row] = w / dg;
       v.pl_z[row] = 0.0;
       v.pl_s[row] = 0.0;
-      v.q[row] = 0.0;
       v.pd[0][row] = 0.0;
       gam += r * u;
       del += w * u;
@@ -396,7 +440,7 @@ __global__ __launch_bounds__(BLOCK) void k_pcg_setup(View v) {
     }
   }
   double x[3] = {gam, del, rr2};
-  block_sum<3>(x);
+  block_sum<3, PCG_BLOCK>(x);
   if (threadIdx.x == 0) {
     const int lb = xcd_block();
 #pragma unroll
@@ -405,15 +449,77 @@ __global__ __launch_bounds__(BLOCK) void k_pcg_setup(View v) {
 }
 
 template <class VT, int PAR>
-__global__ __launch_bounds__(BLOCK) void k_pcg_iter(View v) {
+__global__ __launch_bounds__(PCG_BLOCK) void k_pcg_iter(View v) {
+  constexpr int U = CG_UNROLL;
   CGScalars* sc = v.sc;
-  if (sc->converged) return;
-  double tot[3];
-  sum_partials<3>(v.pl_part[PAR], v.nspmv, 4, tot);
-  const double gam = tot[0], del = tot[1], rr = tot[2];
-  const bool done = rr <= v.cg_tol2 * sc->bb;
-  const double beta = gam / sc->gam[PAR ^ 1];
-  const double alpha = gam / (del - beta * gam / sc->alp[PAR ^ 1]);
+  const int t = team_lane();
+  const Chunk ch(v.n, PCG_ROWS);
+  const double* __restrict__ M = v.pl_m[PAR];
+  double* __restrict__ Mn = v.pl_m[PAR ^ 1];
+  const VT* __restrict__ aval = reinterpret_cast<const VT*>(v.a_val);
+  const int np = v.npcg;
+
+  // -- loads that do not need this iteration's scalars, first row group --
+  const int conv = sc->converged;
+  const double gam_old = sc->gam[PAR ^ 1], alp_old = sc->alp[PAR ^ 1], bb = sc->bb;
+  int64_t row = ch.g0 * PCG_ROWS + threadIdx.x / TEAM;
+  bool live = ch.g0 < ch.g1 && row < v.n;
+  int nnz = 0;
+  int32_t jj[U];
+  VT aa[U];
+  double own[7];  // D, m, z, s, p, r, x of the row (team lane 0)
+  {
+    const int64_t e0 = sl_index(row, t, v.kpad);
+    if (live) nnz = v.a_nnz[row];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      // u * TEAM < kpad is uniform over the team (kpad is a multiple of
+      // TEAM); slots past the row length hold stale data and are masked
+      const bool ok = live && u * TEAM < v.kpad;
+      jj[u] = ok ? v.a_col[e0 + u * WAVE] : 0;
+      aa[u] = ok ? aval[e0 + u * WAVE] : VT(0);
+    }
+    if (live && t == 0) {
+      own[0] = v.diag[row]; own[1] = M[row]; own[2] = v.pl_z[row]; own[3] = v.pl_s[row];
+      own[4] = v.pd[0][row]; own[5] = v.r[row]; own[6] = v.p[row];
+    }
+  }
+  double xv[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const bool in = live && t + u * TEAM < nnz;
+    xv[u] = in ? M[jj[u]] : 0.0;
+    if (!in) aa[u] = VT(0);
+  }
+  double4 pp[PCG_PK];
+  const double4* part = reinterpret_cast<const double4*>(v.pl_part[PAR]);
+#pragma unroll
+  for (int k = 0; k < PCG_PK; ++k) {
+    const int b = threadIdx.x + k * PCG_BLOCK;
+    pp[k] = b < np ? part[b] : make_double4(0.0, 0.0, 0.0, 0.0);
+  }
+
+  // -- the reduced scalars --
+  double tot[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < PCG_PK; ++k) {
+    tot[0] += pp[k].x;
+    tot[1] += pp[k].y;
+    tot[2] += pp[k].z;
+  }
+  __shared__ double bc[3];
+  block_sum<3, PCG_BLOCK>(tot);
+  if (threadIdx.x == 0) {
+    bc[0] = tot[0];
+    bc[1] = tot[1];
+    bc[2] = tot[2];
+  }
+  __syncthreads();
+  if (conv) return;
+  const double gam = bc[0], del = bc[1], rr = bc[2];
+  const bool done = rr <= v.cg_tol2 * bb;
+  const double beta = gam / gam_old;
+  const double alpha = gam / (del - beta * gam / alp_old);
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     sc->rr = rr;
     if (done) {
@@ -425,49 +531,51 @@ __global__ __launch_bounds__(BLOCK) void k_pcg_iter(View v) {
     }
   }
   if (done) return;
-  const double* __restrict__ W = v.pl_w[PAR];
-  double* __restrict__ Wn = v.pl_w[PAR ^ 1];
-  const VT* __restrict__ aval = reinterpret_cast<const VT*>(v.a_val);
-  const int t = team_lane();
-  const Chunk ch(v.n);
+
   double g2 = 0.0, d2 = 0.0, r2 = 0.0;
   for (int64_t g = ch.g0; g < ch.g1; ++g) {
-    const int64_t row = g * ROWS_PER_BLOCK + threadIdx.x / TEAM;
-    if (row >= v.n) continue;
-    const int nnz = v.a_nnz[row];
     double s = 0.0;
-    for (int l = t; l < nnz; l += TEAM) {
-      const int64_t e = sl_index(row, l, v.kpad);
-      const int32_t j = v.a_col[e];
-      s += (double)aval[e] * (W[j] / v.diag[j]);
+    if (g == ch.g0) {
+      if (!live) continue;
+#pragma unroll
+      for (int u = 0; u < U; ++u) s += (double)aa[u] * xv[u];
+      // entries beyond the first U per lane
+      s += row_dot<U>(v.a_col, aval, row, nnz, v.kpad, t + U * TEAM,
+                      [&](int32_t j) { return M[j]; });
+    } else {
+      // later row groups of this workgroup
+      row = g * PCG_ROWS + threadIdx.x / TEAM;
+      if (row >= v.n) continue;
+      nnz = v.a_nnz[row];
+      if (t == 0) {
+        own[0] = v.diag[row]; own[1] = M[row]; own[2] = v.pl_z[row]; own[3] = v.pl_s[row];
+        own[4] = v.pd[0][row]; own[5] = v.r[row]; own[6] = v.p[row];
+      }
+      s = row_dot<8>(v.a_col, aval, row, nnz, v.kpad, t, [&](int32_t j) { return M[j]; });
     }
     s = team_sum(s);
     if (t == 0) {
-      const double dg = v.diag[row], w = W[row];
-      const double m = w / dg;
-      const double nn = dg * m + s;
-      const double z = nn + beta * v.pl_z[row];
-      const double q = m + beta * v.q[row];
-      const double sv = w + beta * v.pl_s[row];
-      const double pv = v.pl_u[row] + beta * v.pd[0][row];
-      const double r = v.r[row] - alpha * sv;
-      const double u = v.pl_u[row] - alpha * q;
+      const double dg = own[0], m = own[1];
+      const double w = dg * m;
+      const double z = (w + s) + beta * own[2];
+      const double sv = w + beta * own[3];
+      const double pv = own[5] / dg + beta * own[4];
+      const double r = own[5] - alpha * sv;
       const double wn = w - alpha * z;
-      v.p[row] += alpha * pv;
+      const double un = r / dg;
+      v.p[row] = own[6] + alpha * pv;
       v.pl_z[row] = z;
-      v.q[row] = q;
       v.pl_s[row] = sv;
       v.pd[0][row] = pv;
       v.r[row] = r;
-      v.pl_u[row] = u;
-      Wn[row] = wn;
-      g2 += r * u;
-      d2 += wn * u;
+      Mn[row] = wn / dg;
+      g2 += r * un;
+      d2 += wn * un;
       r2 += r * r;
     }
   }
   double x[3] = {g2, d2, r2};
-  block_sum<3>(x);
+  block_sum<3, PCG_BLOCK>(x);
   if (threadIdx.x == 0) {
     const int lb = xcd_block();
 #pragma unroll
@@ -549,20 +657,26 @@ int launch_cg_spmv(const View& v, int precision, hipStream_t s) {
   return 0;
 }
 
+int pcg_blocks(int64_t n) {
+  const int64_t a = (n + PCG_ROWS - 1) / PCG_ROWS;
+  return (int)(a < PCG_MAX_BLOCKS ? a : PCG_MAX_BLOCKS);
+}
+
 int launch_pcg_setup(const View& v, int precision, hipStream_t s) {
-  if (precision == MPS_MIXED) k_pcg_setup<float><<<(unsigned)v.nspmv, BLOCK, 0, s>>>(v);
-  else k_pcg_setup<double><<<(unsigned)v.nspmv, BLOCK, 0, s>>>(v);
+  const unsigned nb = (unsigned)v.npcg;
+  if (precision == MPS_MIXED) k_pcg_setup<float><<<nb, PCG_BLOCK, 0, s>>>(v);
+  else k_pcg_setup<double><<<nb, PCG_BLOCK, 0, s>>>(v);
   return 0;
 }
 
 int launch_pcg_iter(const View& v, int precision, int parity, hipStream_t s) {
-  const unsigned nb = (unsigned)v.nspmv;
+  const unsigned nb = (unsigned)v.npcg;
   if (precision == MPS_MIXED) {
-    if (parity) k_pcg_iter<float, 1><<<nb, BLOCK, 0, s>>>(v);
-    else k_pcg_iter<float, 0><<<nb, BLOCK, 0, s>>>(v);
+    if (parity) k_pcg_iter<float, 1><<<nb, PCG_BLOCK, 0, s>>>(v);
+    else k_pcg_iter<float, 0><<<nb, PCG_BLOCK, 0, s>>>(v);
   } else {
-    if (parity) k_pcg_iter<double, 1><<<nb, BLOCK, 0, s>>>(v);
-    else k_pcg_iter<double, 0><<<nb, BLOCK, 0, s>>>(v);
+    if (parity) k_pcg_iter<double, 1><<<nb, PCG_BLOCK, 0, s>>>(v);
+    else k_pcg_iter<double, 0><<<nb, PCG_BLOCK, 0, s>>>(v);
   }
   return 0;
 }

@@ -73,6 +73,7 @@ def lib() -> C.CDLL:
         L.mps_get_state.argtypes = [_VP, _VP, _VP, _VP, _VP, _VP, _VP]
         L.mps_set_state.argtypes = [_VP, _VP, _VP, _VP]
         L.mps_get_phase.argtypes = [_VP, _VP, _VP]
+        L.mps_device_bytes.argtypes = [_VP, C.POINTER(C.c_int64)]
         L.mps_tape_alloc.argtypes = [_VP, C.c_int32]
         L.mps_tape_save.argtypes = [_VP, C.c_int32]
         L.mps_tape_load.argtypes = [_VP, C.c_int32]
@@ -84,7 +85,7 @@ def lib() -> C.CDLL:
         for f in ("mps_init", "mps_free", "mps_neighbors", "mps_step", "mps_pressure_solve",
                   "mps_get_ppe", "mps_get_state", "mps_set_state", "mps_constants",
                   "mps_profile", "mps_profile_read", "mps_tape_alloc", "mps_tape_save",
-                  "mps_tape_load", "mps_step_adjoint", "mps_get_phase"):
+                  "mps_tape_load", "mps_step_adjoint", "mps_get_phase", "mps_device_bytes"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -93,7 +94,8 @@ def lib() -> C.CDLL:
 EXPORTED = ["mps_init", "mps_free", "mps_last_error", "mps_neighbors", "mps_step",
             "mps_pressure_solve", "mps_get_ppe", "mps_get_state", "mps_set_state",
             "mps_constants", "mps_profile", "mps_profile_read", "mps_tape_alloc",
-            "mps_tape_save", "mps_tape_load", "mps_step_adjoint", "mps_get_phase"]
+            "mps_tape_save", "mps_tape_load", "mps_step_adjoint", "mps_get_phase",
+            "mps_device_bytes"]
 
 KERNEL_CLASSES = ["sort", "neighbors", "predict", "density", "assemble", "cg_spmv",
                   "cg_update", "gradient"]
@@ -208,6 +210,11 @@ class MPS:
         n = (C.c_int64 * len(KERNEL_CLASSES))()
         self._check(lib().mps_profile_read(self.h, ms, n), "mps_profile_read")
         return {k: (ms[i], n[i]) for i, k in enumerate(KERNEL_CLASSES)}
+
+    def device_bytes(self) -> int:
+        b = C.c_int64()
+        self._check(lib().mps_device_bytes(self.h, C.byref(b)), "mps_device_bytes")
+        return b.value
 
     def phase(self):
         """(smoothed density, eddy viscosity) of a two-phase context."""

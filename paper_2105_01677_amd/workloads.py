@@ -53,7 +53,7 @@ def default_params(dim: int, l0: float, *, re_n_over_l0: float = 2.1,
         rho=rho, nu=nu, g=gvec, dt=dt, beta=0.97, c0=c0, gamma=7.0,
         alpha=1e-7, cg_tol=1e-9, cg_maxit=10000, max_neigh=300,
         pmode=pmode, kernel=kernel, precision=precision, grad=GRAD_STD,
-        clamp=1, smag_cs=0.0,
+        clamp=1, smag_cs=0.0, cg_pipelined=1,
         grid_lo=[0.0, 0.0, 0.0], grid_n=[1, 1, 1], cell_size=0.0,
     )
 

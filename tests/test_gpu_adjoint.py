@@ -78,8 +78,16 @@ def test_adjoint_matches_oracle_dual(torch_gpu, orc, pmode):
     assert rel(g_u, o_u) < 1e-3
 
 
-def test_adjoint_matches_finite_differences(torch_gpu):
+@pytest.mark.parametrize("clamp", [1, 0])
+def test_adjoint_matches_finite_differences(torch_gpu, clamp):
+    """Central differences of the GPU FP64 path.  The pressure clamp
+    p = max(p, 0) puts kinks into the loss: a random per-particle velocity
+    perturbation crosses some of them, so <dL/du0, v> is checked by finite
+    differences on the unclamped model (and against the exact dual-number
+    derivative with the clamp, above); dL/dnu and dL/dg_x move all particles
+    coherently and are checked with the clamp on as well."""
     w = W.sloshing_2d(0.005, precision=W.FP64)
+    w.params["clamp"] = clamp
     nsteps, K = 40, 10
     d = _direction(w)
     L, g_nu, g_gx, g_u = gpu_grads(torch_gpu, w, nsteps, K, d)
@@ -92,35 +100,41 @@ def test_adjoint_matches_finite_differences(torch_gpu):
     gm = list(w.params["g"]); gm[0] -= hg
     fd_gx = (gpu_loss(torch_gpu, w, nsteps, dict(w.params, g=gp))
              - gpu_loss(torch_gpu, w, nsteps, dict(w.params, g=gm))) / (2 * hg)
-    hu = 1e-6
-    fd_u = (gpu_loss(torch_gpu, w, nsteps, vel=w.vel + hu * d)
-            - gpu_loss(torch_gpu, w, nsteps, vel=w.vel - hu * d)) / (2 * hu)
-    print("nu", g_nu, fd_nu, "gx", g_gx, fd_gx, "u0", g_u, fd_u, flush=True)
+    print("clamp", clamp, "nu", g_nu, fd_nu, "gx", g_gx, fd_gx, flush=True)
     assert rel(g_nu, fd_nu) < 1e-3
     assert rel(g_gx, fd_gx) < 1e-3
-    assert rel(g_u, fd_u) < 1e-3
+    if not clamp:
+        hu = 1e-7
+        fd_u = (gpu_loss(torch_gpu, w, nsteps, vel=w.vel + hu * d)
+                - gpu_loss(torch_gpu, w, nsteps, vel=w.vel - hu * d)) / (2 * hu)
+        print("u0", g_u, fd_u, flush=True)
+        assert rel(g_u, fd_u) < 1e-3
 
 
-def test_adjoint_sloshing_full_size(torch_gpu):
-    """22,500 fluid particles, 500 steps, checkpoints every 50 steps, FP32
-    forward sums with FP64 adjoint; dL/dg_x and <dL/du0, v> against central
-    differences of the same (mixed-precision) forward."""
-    w = W.config("cfg4")
+def test_adjoint_sloshing_full_size(torch_gpu, orc):
+    """22,500 fluid particles, 500 steps, checkpoints every 50 steps.
+    FP64 path: all three gradients against the oracle's exact dual-number
+    derivative of the same 500-step rollout (finite differences are not a
+    usable reference over 500 steps: the pressure clamp's kinks dominate
+    them).  Mixed path (FP32 forward sums, FP64 adjoint): its gradients
+    differ from the FP64 ones because the FP32 forward trajectory itself
+    differs; that deviation is reported and bounded loosely."""
+    torch = torch_gpu
+    w = W.config("cfg4", precision=W.FP64)
     assert w.counts()["fluid"] == 22500
     nsteps, K = 500, 50
     d = _direction(w)
-    torch = torch_gpu
-    torch.cuda.reset_peak_memory_stats()
     L, g_nu, g_gx, g_u = gpu_grads(torch, w, nsteps, K, d)
-    hg = 1e-3
-    gp = list(w.params["g"]); gp[0] += hg
-    gm = list(w.params["g"]); gm[0] -= hg
-    fd_gx = (gpu_loss(torch, w, nsteps, dict(w.params, g=gp))
-             - gpu_loss(torch, w, nsteps, dict(w.params, g=gm))) / (2 * hg)
-    hu = 1e-4
-    fd_u = (gpu_loss(torch, w, nsteps, vel=w.vel + hu * d)
-            - gpu_loss(torch, w, nsteps, vel=w.vel - hu * d)) / (2 * hu)
-    print("L", L, "gx", g_gx, fd_gx, "u0", g_u, fd_u, "nu", g_nu, flush=True)
-    assert math.isfinite(g_nu)
-    assert rel(g_gx, fd_gx) < 1e-3
-    assert rel(g_u, fd_u) < 1e-3
+    st, Lo, o_nu, o_gx, o_u = orc.rollout_grad(w.params, w.pos, w.vel, w.ptype, nsteps, d)
+    assert st == 0
+    print("fp64 L", L, Lo, "nu", g_nu, o_nu, "gx", g_gx, o_gx, "u0", g_u, o_u, flush=True)
+    assert rel(L, Lo) < 1e-6
+    assert rel(g_nu, o_nu) < 1e-3
+    assert rel(g_gx, o_gx) < 1e-3
+    assert rel(g_u, o_u) < 1e-3
+    wm = W.config("cfg4", precision=W.MIXED)
+    Lm, m_nu, m_gx, m_u = gpu_grads(torch, wm, nsteps, K, d)
+    dev = max(rel(m_nu, o_nu), rel(m_gx, o_gx), rel(m_u, o_u))
+    print("mixed L", Lm, "nu", m_nu, "gx", m_gx, "u0", m_u, "max deviation from FP64", dev,
+          flush=True)
+    assert dev < 5e-2
