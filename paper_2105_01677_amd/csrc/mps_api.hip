@@ -49,8 +49,6 @@ struct mps_ctx {
   int32_t *cellid = nullptr, *slot = nullptr, *cell_count = nullptr, *cell_start = nullptr,
           *perm = nullptr, *tile_sum = nullptr;
   int32_t *nb_count = nullptr, *nb_list = nullptr;
-  int32_t* tile_nr = nullptr;
-  int4* tile_rng = nullptr;
   int32_t *a_nnz = nullptr, *a_col = nullptr;
   void* a_val = nullptr;
   double *diag = nullptr, *b = nullptr;
@@ -66,7 +64,7 @@ struct mps_ctx {
   double* partB = nullptr;
   double *pl_z = nullptr, *pl_s = nullptr, *pl_m[2] = {nullptr, nullptr},
          *pl_part[2] = {nullptr, nullptr};
-  int nspmv = 0, nupd = 0, npcg = 0;
+  int nspmv = 0, nupd = 0, npcg = 0, pcg_fused = 0;
   CGScalars* sc = nullptr;
   int32_t* status = nullptr;
   int64_t* counts = nullptr;   // [4]: surface, ghost, list entries, matrix nnz
@@ -230,8 +228,6 @@ View make_view(const mps_ctx* c) {
   v.tile_sum = c->tile_sum;
   v.perm = c->perm;
   v.nb_count = c->nb_count;
-  v.tile_nr = c->tile_nr;
-  v.tile_rng = c->tile_rng;
   v.nb_list = c->nb_list;
   v.a_nnz = c->a_nnz;
   v.a_col = c->a_col;
@@ -255,6 +251,7 @@ View make_view(const mps_ctx* c) {
   v.nspmv = c->nspmv;
   v.nupd = c->nupd;
   v.npcg = c->npcg;
+  v.pcg_fused = c->pcg_fused;
   v.sc = c->sc;
   v.status = c->status;
   if (c->multi) {
@@ -415,7 +412,6 @@ mps_status search(mps_ctx* c) {
   v = make_view(c);
   {
     Prof pr(c, MPS_KC_NEIGH);
-    launch_tiles(v, c->dim, c->s);
     launch_neighbors(v, c->dim, c->P.precision, c->s);
   }
   return MPS_OK;
@@ -460,6 +456,10 @@ void enqueue_cg(mps_ctx* c, int iters) {
   View v = make_view(c);
   if (c->P.cg_pipelined) {
     for (int it = 0; it < iters; ++it) {
+      if (!c->pcg_fused) {
+        Prof pr(c, MPS_KC_CG_UPDATE);
+        launch_pcg_reduce(v, it & 1, c->s);
+      }
       Prof pr(c, MPS_KC_CG_SPMV);
       launch_pcg_iter(v, c->P.precision, it & 1, c->s);
     }
@@ -679,7 +679,7 @@ mps_status mps_init(const mps_params* params, int64_t n, const double* pos, cons
     A(dalloc(&c->pd[k], n));
   }
   A(dalloc(&c->pcell, n));
-  A(dalloc(&c->posf, n));
+  A(dalloc(&c->posf, 2 * n));
   A(dalloc(&c->rsf, n));
   A(dalloc(&c->us, nv));
   A(dalloc(&c->rs, nv));
@@ -692,11 +692,6 @@ mps_status mps_init(const mps_params* params, int64_t n, const double* pos, cons
   A(dalloc(&c->cell_start, c->ncell + 2));
   A(dalloc(&c->tile_sum, (c->ncell + 1 + SCAN_TILE - 1) / SCAN_TILE));
   A(dalloc(&c->nb_count, n));
-  {
-    const size_t ng = (size_t)((n + ROWS_PER_BLOCK - 1) / ROWS_PER_BLOCK);
-    A(dalloc(&c->tile_nr, ng));
-    A(dalloc(&c->tile_rng, ng * TILE_RANGES));
-  }
   A(dalloc(&c->nb_list, c->slots));
   A(dalloc(&c->a_nnz, n));
   A(dalloc(&c->a_col, c->slots));
@@ -723,7 +718,8 @@ mps_status mps_init(const mps_params* params, int64_t n, const double* pos, cons
   c->nupd = cg_update_blocks(n);
   A(dalloc(&c->partA, (size_t)std::max(c->nspmv, c->nupd) * 4));
   A(dalloc(&c->partB, (size_t)c->nspmv));
-  c->npcg = pcg_blocks(n);
+  c->pcg_fused = pcg_blocks(n, true) <= pcg_fused_capacity() ? 1 : 0;
+  c->npcg = pcg_blocks(n, c->pcg_fused != 0);
   if (params->cg_pipelined) {
     A(dalloc(&c->pl_z, n));
     A(dalloc(&c->pl_s, n));
@@ -798,7 +794,7 @@ mps_status mps_free(mps_ctx* c) {
                   c->type[0], c->type[1], c->id[0], c->id[1], c->pd[0], c->pd[1],
                   c->pcell, c->posf, c->rsf, c->us, c->rs, c->nstar, c->flags,
                   c->cellid, c->slot, c->perm, c->cell_count, c->cell_start, c->tile_sum,
-                  c->nb_count, c->tile_nr, c->tile_rng,
+                  c->nb_count,
                   c->nb_list, c->a_nnz, c->a_col, c->a_val, c->diag, c->b, c->r, c->z,
                   c->q, c->p_save, c->partA, c->partB, c->sc, c->status, c->counts,
                   c->rho_s[0], c->rho_s[1], c->nu_l[0], c->nu_l[1], c->nut, c->mu,

@@ -33,13 +33,6 @@ constexpr int SLICE = WAVE / TEAM;        // rows per wavefront
 constexpr int BLOCK = 256;
 constexpr int ROWS_PER_BLOCK = BLOCK / TEAM;
 constexpr int SCAN_TILE = 4096;  // cells per workgroup of the cell-count scan
-// LDS tiles: records staged per workgroup of 32 rows, and the number of
-// cell ranges (one per neighbouring grid row: 3 in 2-D, 9 in 3-D)
-constexpr int TILE_CAP = 1280;
-constexpr int TILE_RANGES = 9;
-#ifndef MPS_TILES
-#define MPS_TILES 1
-#endif
 
 // Status bits raised by kernels (one int32 word on the device).
 enum : int32_t {
@@ -71,20 +64,30 @@ struct CGScalars {
   // by workgroup 0 of iteration k and read by iteration k + 1 only
   double gam[2];
   double alp[2];
+  // split pipelined variant: alpha and beta of the running iteration,
+  // written by the reduction kernel and read by the iteration kernel
+  double ab[2];
 };
 
 // Grid caps of the CG kernels: every workgroup of one kernel sums all the
 // per-workgroup partials of the previous kernel, so their number is bounded.
 constexpr int CG_SPMV_BLOCKS = 2048;
 constexpr int CG_UPD_BLOCKS = 1024;
-// Pipelined CG: workgroup size and grid cap (every workgroup loads all
-// partials of the previous iteration, one double4 per workgroup).
+// Pipelined CG: workgroup size (one group of PCG_BLOCK / TEAM rows per
+// workgroup) and the largest grid of the fused one-kernel iteration, whose
+// workgroups all load every partial of the previous iteration (one double4
+// per workgroup); it is also kept within what runs in one wave of
+// workgroups on the device.
 #ifndef PCG_BLOCK
 #define PCG_BLOCK 512
 #endif
 #ifndef PCG_MAX_BLOCKS
 #define PCG_MAX_BLOCKS 1024
 #endif
+#ifndef PCG_SPLIT_BLOCK
+#define PCG_SPLIT_BLOCK 256
+#endif
+constexpr int RED_BLOCK = 1024;  // the one workgroup of a CG reduction kernel
 #ifndef CG_UNROLL
 #define CG_UNROLL 4
 #endif
@@ -113,7 +116,8 @@ struct View {
   const double* p_in; double* p_w;
   // per-step arrays (sorted order)
   int32_t* pcell;     // packed cell coordinates
-  float4* posf;       // mixed: r^k relative to the anchor cell + packed cell
+  float4* posf;       // mixed, two per particle: r^k relative to the anchor
+                      // cell + packed cell; FP32 u^k
   float4* rsf;        // mixed: r*  relative to the anchor cell + packed cell
   double* us;         // u*
   double* rs;         // r*
@@ -129,10 +133,7 @@ struct View {
   // lists
   int32_t* nb_count;
   int32_t* nb_list;
-  // LDS tiles, one per group of ROWS_PER_BLOCK rows: number of ranges (-1:
-  // no tile) and the ranges (first sorted index, end, LDS slot of the first)
-  int32_t* tile_nr;
-  int4* tile_rng;
+
   // PPE
   int32_t* a_nnz;
   int32_t* a_col;
@@ -148,7 +149,8 @@ struct View {
   double* partA;      // [blocks][4]: (r,z), (r,r), (b,b) of assembly / update
   double* partB;      // [blocks]: (p, A p) of the SpMV workgroups
   int nspmv, nupd;    // grid sizes of the SpMV / assembly and update kernels
-  int npcg;           // grid size of the pipelined CG kernels
+  int npcg;           // grid size of the pipelined CG kernels (one row group each)
+  int pcg_fused;      // 1: one kernel per iteration; 0: reduction + iteration
   CGScalars* sc;
   // pipelined CG (one kernel per iteration): m = D^-1 w (double buffered),
   // z, s; the direction p reuses pd[0]
@@ -257,66 +259,6 @@ __device__ inline uint32_t team_ballot(bool pred) {
   return (uint32_t)((m >> base) & ((1u << TEAM) - 1));
 }
 
-// Candidate tile of a group of ROWS_PER_BLOCK consecutive sorted rows whose
-// particles lie in one grid row of cells (x0 .. x1): the union of the cell
-// ranges their neighbours come from (cells x0-1 .. x1+1 of the 3 or 9
-// neighbouring grid rows), each contiguous in the sorted order, staged in
-// LDS back to back.  Sorted index j of range k sits in slot j + delta[k];
-// ranges ascend in j and in slot.
-struct TileMap {
-  int nr;     // number of ranges; < 0: the group has no tile
-  int total;  // staged records
-  int start[TILE_RANGES];
-  int delta[TILE_RANGES];
-  __device__ void load(const View& v, int g) {
-    if (!MPS_TILES) {
-      nr = -1;
-      total = 0;
-      return;
-    }
-    nr = v.tile_nr[g];
-    total = 0;
-#pragma unroll
-    for (int k = 0; k < TILE_RANGES; ++k) {
-      const int4 r = k < nr ? v.tile_rng[(int64_t)g * TILE_RANGES + k] : make_int4(0, 0, 0, 0);
-      start[k] = r.x;
-      delta[k] = r.z - r.x;
-      total = k < nr ? r.z + (r.y - r.x) : total;
-    }
-  }
-  __device__ int slot(int j) const {
-    int d = delta[0];
-#pragma unroll
-    for (int k = 1; k < TILE_RANGES; ++k) d = (k < nr && j >= start[k]) ? delta[k] : d;
-    return j + d;
-  }
-  // sorted index of slot i < total
-  __device__ int src(int i) const {
-    int d = delta[0];
-#pragma unroll
-    for (int k = 1; k < TILE_RANGES; ++k) d = (k < nr && i >= start[k] + delta[k]) ? delta[k] : d;
-    return i - d;
-  }
-};
-
-// Stage slots [0, tm.total) of the group's tile: rec(j) -> LDS slot, with
-// all loads of a thread issued before its first LDS store.
-template <class T, class F>
-__device__ inline void stage_tile(const TileMap& tm, T* __restrict__ sh, F&& rec) {
-  constexpr int CP = (TILE_CAP + BLOCK - 1) / BLOCK;
-  T a[CP];
-#pragma unroll
-  for (int c = 0; c < CP; ++c) {
-    const int i = threadIdx.x + c * BLOCK;
-    if (i < tm.total) a[c] = rec(tm.src(i));
-  }
-#pragma unroll
-  for (int c = 0; c < CP; ++c) {
-    const int i = threadIdx.x + c * BLOCK;
-    if (i < tm.total) sh[i] = a[c];
-  }
-}
-
 // Sum over a row's matrix entries l, l + TEAM, ... < nnz (l = the team lane,
 // or a later start on the same lane) of
 // val(e) * x(col(e)), U entries per step so that U independent gathers are
@@ -361,7 +303,6 @@ __device__ inline R weight(int kernel, R r, R re) {
 int launch_bin(const View& v, int dim, hipStream_t s);
 int launch_permute(const View& v, int dim, int precision, hipStream_t s);
 int launch_neighbors(const View& v, int dim, int precision, hipStream_t s);
-int launch_tiles(const View& v, int dim, hipStream_t s);
 int launch_export_lists(const View& v, int32_t* cell_out, int32_t* count_out,
                         int32_t* list_out, int dim, hipStream_t s);
 int launch_predict(const View& v, int dim, int precision, hipStream_t s);
@@ -373,9 +314,11 @@ int launch_assemble(const View& v, int dim, int precision, const double* rhs_sor
                     bool zero_x0, hipStream_t s);
 int launch_cg_spmv(const View& v, int precision, hipStream_t s);
 int launch_cg_update(const View& v, hipStream_t s);
-int pcg_blocks(int64_t n);
+int pcg_blocks(int64_t n, bool fused);
+int pcg_fused_capacity();
 int launch_pcg_setup(const View& v, int precision, hipStream_t s);
 int launch_pcg_iter(const View& v, int precision, int parity, hipStream_t s);
+int launch_pcg_reduce(const View& v, int parity, hipStream_t s);
 int launch_clamp(const View& v, hipStream_t s);
 int launch_gradient(const View& v, int dim, int precision, hipStream_t s);
 int launch_scatter_orig(const View& v, const double* src, double* dst, int comps,

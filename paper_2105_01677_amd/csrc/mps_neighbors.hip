@@ -190,7 +190,8 @@ __global__ __launch_bounds__(BLOCK) void k_rank_permute(View v) {
     float4 f;
     if constexpr (DIM == 2) f = make_float4(r[0], r[1], __int_as_float(pc), 0.f);
     else f = make_float4(r[0], r[1], r[2], __int_as_float(pc));
-    v.posf[k] = f;
+    v.posf[2 * k] = f;
+    v.posf[2 * k + 1] = make_float4((float)u[0], (float)u[1], DIM == 3 ? (float)u[2] : 0.f, 0.f);
   }
 }
 
@@ -199,37 +200,9 @@ __global__ __launch_bounds__(BLOCK) void k_rank_permute(View v) {
 // in the sorted order, so each of the 3 (2-D) or 9 (3-D) rows is one
 // contiguous index range; the team scans it TEAM candidates at a time and
 // appends hits in candidate order with a ballot, so the list order is fixed.
-// The FP64 positions of the workgroup's tile (TileMap, built just before)
-// are staged in LDS; a candidate range of one grid row lies inside the tile
-// range of that row, so its slots are consecutive.
-template <int DIM>
-struct NPos {
-  double x[DIM];
-};
-
 template <int DIM>
 __global__ __launch_bounds__(BLOCK) void k_neighbors(View v) {
-  __shared__ NPos<DIM> s_x[TILE_CAP];
-  const int g = xcd_block();
-  TileMap tm;
-  tm.load(v, g);
-  const bool tiled = tm.nr > 0;
-  if (tiled) {
-    constexpr int CP = (TILE_CAP + BLOCK - 1) / BLOCK;
-    NPos<DIM> a[CP];
-#pragma unroll
-    for (int c = 0; c < CP; ++c) {
-      const int i = threadIdx.x + c * BLOCK;
-      if (i < tm.total) load_vec<DIM>(v.pos, tm.src(i), a[c].x);
-    }
-#pragma unroll
-    for (int c = 0; c < CP; ++c) {
-      const int i = threadIdx.x + c * BLOCK;
-      if (i < tm.total) s_x[i] = a[c];
-    }
-    __syncthreads();
-  }
-  const int64_t row = (int64_t)g * ROWS_PER_BLOCK + threadIdx.x / TEAM;
+  const int64_t row = (int64_t)xcd_block() * ROWS_PER_BLOCK + threadIdx.x / TEAM;
   const int t = team_lane();
   if (row >= v.n) return;
   const int32_t pc = v.pcell[row];
@@ -246,20 +219,12 @@ __global__ __launch_bounds__(BLOCK) void k_neighbors(View v) {
       for (int y = max(cy - 1, 0); y <= min(cy + 1, v.ny - 1); ++y) {
         const int base = v.nx * (y + v.ny * z);
         const int jb = v.cell_start[base + x0], je = v.cell_start[base + x1 + 1];
-        if (je <= jb) continue;
-        const int sb = tiled ? tm.slot(jb) - jb : 0;
         for (int jj = jb; jj < je; jj += TEAM) {
           const int j = jj + t;
           bool hit = false;
           if (j < je && j != row) {
             double xj[DIM];
-            if (tiled) {
-              const NPos<DIM> q = s_x[sb + j];
-#pragma unroll
-              for (int a = 0; a < DIM; ++a) xj[a] = q.x[a];
-            } else {
-              load_vec<DIM>(v.pos, j, xj);
-            }
+            load_vec<DIM>(v.pos, j, xj);
             const double d2 = dist2_exact<DIM>(xi, xj);
             hit = d2 < v.re_lap2;
             coinc = coinc || (hit && d2 == 0.0);
@@ -280,45 +245,6 @@ __global__ __launch_bounds__(BLOCK) void k_neighbors(View v) {
     }
   }
   if (t == 0) v.nb_count[row] = count;
-}
-
-// Tiles of the row groups (TileMap), one thread per group of
-// ROWS_PER_BLOCK sorted rows.  A group gets no tile when its particles span
-// two grid rows of cells, when it holds only ghosts, or when the union
-// exceeds TILE_CAP records; kernels then read their neighbours from global
-// memory.
-template <int DIM>
-__global__ __launch_bounds__(BLOCK) void k_tiles(View v, int ngroups) {
-  const int g = blockIdx.x * BLOCK + threadIdx.x;
-  if (g >= ngroups) return;
-  const int nng = v.cell_start[v.ncell];  // particles inside the grid; ghosts follow
-  const int r0 = g * ROWS_PER_BLOCK;
-  int nr = -1;
-  int4 rng[TILE_RANGES];
-  if (r0 < nng) {
-    const int r1 = min(r0 + ROWS_PER_BLOCK, nng) - 1;
-    const int32_t c0 = v.pcell[r0], c1 = v.pcell[r1];
-    if (ucy(c0) == ucy(c1) && ucz(c0) == ucz(c1)) {
-      const int x0 = max(ucx(c0) - 1, 0), x1 = min(ucx(c1) + 1, v.nx - 1);
-      const int cy = ucy(c0), cz = ucz(c0);
-      const int zlo = DIM == 3 ? max(cz - 1, 0) : 0;
-      const int zhi = DIM == 3 ? min(cz + 1, v.nz - 1) : 0;
-      int k = 0, off = 0;
-      for (int z = zlo; z <= zhi; ++z) {
-        for (int y = max(cy - 1, 0); y <= min(cy + 1, v.ny - 1); ++y) {
-          const int base = v.nx * (y + v.ny * z);
-          const int jb = v.cell_start[base + x0], je = v.cell_start[base + x1 + 1];
-          if (je > jb) {
-            rng[k++] = make_int4(jb, je, off, 0);
-            off += je - jb;
-          }
-        }
-      }
-      if (off <= TILE_CAP) nr = k;
-    }
-  }
-  v.tile_nr[g] = nr;
-  for (int k = 0; k < nr; ++k) v.tile_rng[(int64_t)g * TILE_RANGES + k] = rng[k];
 }
 
 // Export: lists in original order with original ids, ascending.
@@ -379,13 +305,6 @@ int launch_neighbors(const View& v, int dim, int precision, hipStream_t s) {
   const unsigned nb = nblk(v.n, ROWS_PER_BLOCK);
   if (dim == 2) k_neighbors<2><<<nb, BLOCK, 0, s>>>(v);
   else k_neighbors<3><<<nb, BLOCK, 0, s>>>(v);
-  return 0;
-}
-
-int launch_tiles(const View& v, int dim, hipStream_t s) {
-  const int ng = (int)nblk(v.n, ROWS_PER_BLOCK);
-  if (dim == 2) k_tiles<2><<<nblk(ng, BLOCK), BLOCK, 0, s>>>(v, ng);
-  else k_tiles<3><<<nblk(ng, BLOCK), BLOCK, 0, s>>>(v, ng);
   return 0;
 }
 

@@ -32,6 +32,10 @@
 #include "mps_internal.h"
 
 
+#ifndef ASM_UNROLL
+#define ASM_UNROLL 1
+#endif
+
 namespace mps {
 
 template <int DIM, bool MIXED>
@@ -146,30 +150,6 @@ __global__ __launch_bounds__(BLOCK) void k_assemble(View v, const double* rhs, i
   VT* aval = reinterpret_cast<VT*>(v.a_val);
   const Chunk ch(v.n);
   for (int64_t g = ch.g0; g < ch.g1; ++g) {
-    // mixed path: the neighbours' FP32 positions, flags and (warm start)
-    // pressures of the group's tile staged in LDS
-    [[maybe_unused]] float4* s_p = nullptr;
-    [[maybe_unused]] double* s_q = nullptr;
-    [[maybe_unused]] int8_t* s_f = nullptr;
-    bool tiled = false;
-    TileMap tm;
-    if constexpr (MIXED) {
-      __shared__ float4 sh_p[TILE_CAP];
-      __shared__ double sh_q[TILE_CAP];
-      __shared__ int8_t sh_f[TILE_CAP];
-      s_p = sh_p;
-      s_q = sh_q;
-      s_f = sh_f;
-      tm.load(v, (int)g);
-      tiled = tm.nr > 0;
-      if (tiled) {
-        __syncthreads();  // the previous group's reads are done
-        stage_tile(tm, s_p, [&](int j) { return v.rsf[j]; });
-        stage_tile(tm, s_f, [&](int j) { return v.flags[j]; });
-        if (!zero_x0) stage_tile(tm, s_q, [&](int j) { return v.p[j]; });
-        __syncthreads();
-      }
-    }
     const int64_t row = g * ROWS_PER_BLOCK + threadIdx.x / TEAM;
     if (row >= v.n) continue;
     const bool inner = v.flags[row] == MPS_FLAG_INNER;
@@ -180,52 +160,52 @@ __global__ __launch_bounds__(BLOCK) void k_assemble(View v, const double* rhs, i
       const R re = (R)v.re_lap, re2 = (R)v.re_lap2;
       const R cpp = (R)(2.0 * DIM / (v.lam_lap * v.n0_lap * v.rho));
       const int cnt = v.nb_count[row];
-      for (int l0 = 0; l0 < cnt; l0 += TEAM) {
-        const int l = l0 + t;
-        bool keep = false;
-        int32_t j = 0;
-        int sj = 0;
-        R c = R(0);
-        if (l < cnt) {
-          j = v.nb_list[sl_index(row, l, v.kpad)];
-          P pj;
-          int8_t fj;
-          if constexpr (MIXED) {
-            if (tiled) {
-              sj = tm.slot(j);
-              fj = s_f[sj];
-              pj.f = s_p[sj];
-            } else {
-              fj = v.flags[j];
-              pj.f = v.rsf[j];
-            }
-          } else {
-            fj = v.type[j] == MPS_DUMMY ? MPS_FLAG_DUMMY : v.flags[j];
-            if (fj != MPS_FLAG_DUMMY) pj = P::load(v, j);
-          }
-          if (fj != MPS_FLAG_DUMMY) {
-            R d[DIM];
-            pi.diff(pj, v.cs32, d);
-            R r2 = d[0] * d[0] + d[1] * d[1];
-            if constexpr (DIM == 3) r2 += d[2] * d[2];
-            if (r2 < re2) {
-              c = cpp * weight<R>(v.kernel, sqrt(r2), re);
-              // two-phase: 1/rho -> 2/(<rho>_i + <rho>_j), symmetric
-              if (v.rho_s) c *= (R)(v.rho * 2.0 / (v.rho_s[row] + v.rho_s[j]));
-              dsum += (double)c;
-              keep = fj == MPS_FLAG_INNER;
-            }
-          }
+      // ASM_UNROLL list entries per lane and step (loads and gathers of a
+      // step in flight together, then the ballots in list order); one per
+      // step measured fastest on MI355X
+      constexpr int U = ASM_UNROLL;
+      for (int l0 = 0; l0 < cnt; l0 += U * TEAM) {
+        int32_t j[U];
+        bool ok[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int lb = l0 + u * TEAM;  // uniform over the team
+          j[u] = lb < v.kpad ? v.nb_list[sl_index(row, lb + t, v.kpad)] : 0;
+          ok[u] = lb + t < cnt;
+          if (!ok[u]) j[u] = (int32_t)row;
         }
-        const uint32_t m = team_ballot(keep);
-        if (keep) {
-          const int s = nnz + __popc(m & ((1u << t) - 1u));
-          const int64_t e = sl_index(row, s, v.kpad);
-          v.a_col[e] = j;
-          aval[e] = -c;
-          if (!zero_x0) ax -= (double)c * (tiled ? s_q[sj] : v.p[j]);
+        R c[U];
+        bool keep[U];
+        double pj[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          // this step's flags mark exactly the dummy particles MPS_FLAG_DUMMY
+          const int8_t fj = v.flags[j[u]];
+          R d[DIM];
+          pi.diff(P::load(v, j[u]), v.cs32, d);
+          R r2 = d[0] * d[0] + d[1] * d[1];
+          if constexpr (DIM == 3) r2 += d[2] * d[2];
+          pj[u] = zero_x0 ? 0.0 : v.p[j[u]];
+          const bool in = ok[u] && fj != MPS_FLAG_DUMMY && r2 < re2;
+          R cr = cpp * weight<R>(v.kernel, sqrt(r2), re);
+          // two-phase: 1/rho -> 2/(<rho>_i + <rho>_j), symmetric
+          if (v.rho_s) cr *= (R)(v.rho * 2.0 / (v.rho_s[row] + v.rho_s[j[u]]));
+          c[u] = in ? cr : R(0);
+          dsum += (double)c[u];
+          keep[u] = in && fj == MPS_FLAG_INNER;
         }
-        nnz += __popc(m);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const uint32_t m = team_ballot(keep[u]);
+          if (keep[u]) {
+            const int s = nnz + __popc(m & ((1u << t) - 1u));
+            const int64_t e = sl_index(row, s, v.kpad);
+            v.a_col[e] = j[u];
+            aval[e] = -c[u];
+            ax -= (double)c[u] * pj[u];
+          }
+          nnz += __popc(m);
+        }
       }
       dsum = team_sum(dsum);
       ax = team_sum(ax);
@@ -381,26 +361,65 @@ __global__ __launch_bounds__(BLOCK) void k_cg_update(View v) {
 // double buffered because the neighbours' m of this iteration are read
 // while the new m is written.  Per row an iteration loads D, m, z, s, p, r,
 // x and stores m, z, s, p, r, x.
-// The dot products of iteration k+1 are formed by the workgroups of
-// iteration k and reduced (redundantly, in a fixed order) at the start of
-// k+1, so each iteration is one kernel.  Every load that does not depend on
-// the reduced scalars (the row's first matrix entries, the gathers of m,
-// the row's own vectors, the partials) is issued before any of them is
-// consumed, so their latencies overlap instead of adding up.
+// Every workgroup handles one group of PCG_ROWS rows and leaves one partial
+// of the next iteration's dot products.  Two schedules:
+//   fused  (grid <= pcg_fused_capacity(), all workgroups resident): one
+//          kernel per iteration; every workgroup reduces all partials of
+//          the previous iteration itself, in the same fixed order;
+//   split  (larger grids): a one-workgroup reduction kernel, then the
+//          iteration kernel reading alpha and beta from the device scalars.
+// In both, every load that does not depend on the scalars (the row length,
+// its first matrix entries, the gathers of m, the row's own vectors) is
+// issued first, so their latencies overlap.
 // Setup: w0 = A u0 with u0 = D^-1 r0 from the assembly; gamma_old = inf and
 // alpha_old = 1 make the first iteration beta = 0, alpha = gamma/delta.
-constexpr int PCG_ROWS = PCG_BLOCK / TEAM;
+// workgroup size of the two schedules (measured on MI355X: 512 fused, 256
+// split)
+template <bool FUSED>
+constexpr int pcg_nt() { return FUSED ? PCG_BLOCK : PCG_SPLIT_BLOCK; }
 constexpr int PCG_PK = (PCG_MAX_BLOCKS + PCG_BLOCK - 1) / PCG_BLOCK;
 
-template <class VT>
-__global__ __launch_bounds__(PCG_BLOCK) void k_pcg_setup(View v) {
+// Fixed-order sum of np partials (double4 .x/.y/.z) by one workgroup of NT
+// threads: thread i adds partials i, i + NT, ... in order (K loads in
+// flight), then the workgroup tree.  Result valid in every thread.
+template <int NT, int K>
+__device__ inline void reduce_partials(const double* part, int np, double (&tot)[3]) {
+  const double4* p4 = reinterpret_cast<const double4*>(part);
+  double s[3] = {0.0, 0.0, 0.0};
+  for (int b0 = threadIdx.x; b0 < np; b0 += K * NT) {
+    double4 q[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int b = b0 + k * NT;
+      q[k] = b < np ? p4[b] : make_double4(0.0, 0.0, 0.0, 0.0);
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      s[0] += q[k].x;
+      s[1] += q[k].y;
+      s[2] += q[k].z;
+    }
+  }
+  __shared__ double bc[3];
+  block_sum<3, NT>(s);
+  if (threadIdx.x == 0) {
+    bc[0] = s[0];
+    bc[1] = s[1];
+    bc[2] = s[2];
+  }
+  __syncthreads();
+  tot[0] = bc[0];
+  tot[1] = bc[1];
+  tot[2] = bc[2];
+}
+
+// Start of the solve from the assembly partials: (r0, r0), (b, b), the
+// convergence test, and the scalars that make iteration 0 take beta = 0.
+__device__ inline bool pcg_start_scalars(const View& v, const double (&tot)[3], bool write) {
   CGScalars* sc = v.sc;
-  double tot[3];
-  sum_partials<3, PCG_BLOCK>(v.partA, sc->nasm, 4, tot);
   const double rr = tot[1], bb = tot[2];
   const bool done = bb == 0.0 || rr <= v.cg_tol2 * bb;
-  const Chunk ch(v.n, PCG_ROWS);
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
+  if (write && threadIdx.x == 0) {
     sc->bb = bb;
     sc->rr = rr;
     sc->iter = 0;
@@ -408,22 +427,41 @@ __global__ __launch_bounds__(PCG_BLOCK) void k_pcg_setup(View v) {
     sc->gam[1] = __builtin_inf();
     sc->alp[1] = 1.0;
   }
+  return done;
+}
+
+// split schedule: the assembly partials reduced once
+__global__ __launch_bounds__(RED_BLOCK) void k_pcg_start(View v) {
+  double tot[3];
+  reduce_partials<RED_BLOCK, 2>(v.partA, v.sc->nasm, tot);
+  pcg_start_scalars(v, tot, true);
+}
+
+template <class VT, bool FUSED>
+__global__ __launch_bounds__(pcg_nt<FUSED>()) void k_pcg_setup(View v) {
+  constexpr int NT = pcg_nt<FUSED>();
+  CGScalars* sc = v.sc;
+  bool done;
+  double bb;
+  if constexpr (FUSED) {
+    double tot[3];
+    reduce_partials<NT, 1>(v.partA, sc->nasm, tot);
+    done = pcg_start_scalars(v, tot, blockIdx.x == 0);
+    bb = tot[2];
+  } else {
+    done = sc->converged != 0;
+    bb = sc->bb;
+  }
+  const int64_t row = (int64_t)xcd_block() * (NT / TEAM) + threadIdx.x / TEAM;
   const int t = team_lane();
   if (done) {
-    if (bb == 0.0) {
-      for (int64_t g = ch.g0; g < ch.g1; ++g) {
-        const int64_t row = g * PCG_ROWS + threadIdx.x / TEAM;
-        if (row < v.n && t == 0) v.p[row] = 0.0;
-      }
-    }
+    if (bb == 0.0 && row < v.n && t == 0) v.p[row] = 0.0;
     return;
   }
   const VT* __restrict__ aval = reinterpret_cast<const VT*>(v.a_val);
   const double* __restrict__ u0 = v.z;  // D^-1 r0, written by the assembly
   double gam = 0.0, del = 0.0, rr2 = 0.0;
-  for (int64_t g = ch.g0; g < ch.g1; ++g) {
-    const int64_t row = g * PCG_ROWS + threadIdx.x / TEAM;
-    if (row >= v.n) continue;
+  if (row < v.n) {
     double s = row_dot<4>(v.a_col, aval, row, v.a_nnz[row], v.kpad, t,
                           [&](int32_t j) { return u0[j]; });
     s = team_sum(s);
@@ -434,13 +472,13 @@ __global__ __launch_bounds__(PCG_BLOCK) void k_pcg_setup(View v) {
       v.pl_z[row] = 0.0;
       v.pl_s[row] = 0.0;
       v.pd[0][row] = 0.0;
-      gam += r * u;
-      del += w * u;
-      rr2 += r * r;
+      gam = r * u;
+      del = w * u;
+      rr2 = r * r;
     }
   }
   double x[3] = {gam, del, rr2};
-  block_sum<3, PCG_BLOCK>(x);
+  block_sum<3, NT>(x);
   if (threadIdx.x == 0) {
     const int lb = xcd_block();
 #pragma unroll
@@ -448,22 +486,65 @@ __global__ __launch_bounds__(PCG_BLOCK) void k_pcg_setup(View v) {
   }
 }
 
-template <class VT, int PAR>
-__global__ __launch_bounds__(PCG_BLOCK) void k_pcg_iter(View v) {
+// Scalars of iteration k from (r,u), (w,u), (r,r) of its partials: the
+// convergence test, beta and alpha; workgroup 0 (or the reduction kernel)
+// records them.
+__device__ inline bool pcg_scalars(const View& v, const double (&tot)[3], int par,
+                                   double gam_old, double alp_old, double bb, bool write,
+                                   double& alpha, double& beta) {
+  CGScalars* sc = v.sc;
+  const double gam = tot[0], del = tot[1], rr = tot[2];
+  const bool done = rr <= v.cg_tol2 * bb;
+  beta = gam / gam_old;
+  alpha = gam / (del - beta * gam / alp_old);
+  if (write && threadIdx.x == 0) {
+    sc->rr = rr;
+    if (done) {
+      sc->converged = 1;
+    } else {
+      sc->gam[par] = gam;
+      sc->alp[par] = alpha;
+      sc->ab[0] = alpha;
+      sc->ab[1] = beta;
+      sc->iter += 1;
+    }
+  }
+  return done;
+}
+
+// split schedule: reduction of iteration k's partials
+template <int PAR>
+__global__ __launch_bounds__(RED_BLOCK) void k_pcg_reduce(View v) {
+  CGScalars* sc = v.sc;
+  if (sc->converged) return;
+  double tot[3], alpha, beta;
+  reduce_partials<RED_BLOCK, 4>(v.pl_part[PAR], v.npcg, tot);
+  pcg_scalars(v, tot, PAR, sc->gam[PAR ^ 1], sc->alp[PAR ^ 1], sc->bb, true, alpha, beta);
+}
+
+template <class VT, int PAR, bool FUSED>
+__global__ __launch_bounds__(pcg_nt<FUSED>()) void k_pcg_iter(View v) {
   constexpr int U = CG_UNROLL;
+  constexpr int NT = pcg_nt<FUSED>();
   CGScalars* sc = v.sc;
   const int t = team_lane();
-  const Chunk ch(v.n, PCG_ROWS);
   const double* __restrict__ M = v.pl_m[PAR];
   double* __restrict__ Mn = v.pl_m[PAR ^ 1];
   const VT* __restrict__ aval = reinterpret_cast<const VT*>(v.a_val);
-  const int np = v.npcg;
 
-  // -- loads that do not need this iteration's scalars, first row group --
+  // -- loads that do not need this iteration's scalars --
   const int conv = sc->converged;
-  const double gam_old = sc->gam[PAR ^ 1], alp_old = sc->alp[PAR ^ 1], bb = sc->bb;
-  int64_t row = ch.g0 * PCG_ROWS + threadIdx.x / TEAM;
-  bool live = ch.g0 < ch.g1 && row < v.n;
+  double gam_old = 0.0, alp_old = 0.0, bb = 0.0, alpha = 0.0, beta = 0.0;
+  if constexpr (FUSED) {
+    gam_old = sc->gam[PAR ^ 1];
+    alp_old = sc->alp[PAR ^ 1];
+    bb = sc->bb;
+  } else {
+    alpha = sc->ab[0];
+    beta = sc->ab[1];
+  }
+  const int64_t row = (int64_t)xcd_block() * (NT / TEAM) + threadIdx.x / TEAM;
+  const bool live = row < v.n;
   int nnz = 0;
   int32_t jj[U];
   VT aa[U];
@@ -491,68 +572,25 @@ __global__ __launch_bounds__(PCG_BLOCK) void k_pcg_iter(View v) {
     xv[u] = in ? M[jj[u]] : 0.0;
     if (!in) aa[u] = VT(0);
   }
-  double4 pp[PCG_PK];
-  const double4* part = reinterpret_cast<const double4*>(v.pl_part[PAR]);
-#pragma unroll
-  for (int k = 0; k < PCG_PK; ++k) {
-    const int b = threadIdx.x + k * PCG_BLOCK;
-    pp[k] = b < np ? part[b] : make_double4(0.0, 0.0, 0.0, 0.0);
-  }
 
-  // -- the reduced scalars --
-  double tot[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-  for (int k = 0; k < PCG_PK; ++k) {
-    tot[0] += pp[k].x;
-    tot[1] += pp[k].y;
-    tot[2] += pp[k].z;
+  // -- the scalars --
+  if constexpr (FUSED) {
+    double tot[3];
+    reduce_partials<NT, PCG_PK>(v.pl_part[PAR], v.npcg, tot);
+    if (conv) return;
+    if (pcg_scalars(v, tot, PAR, gam_old, alp_old, bb, blockIdx.x == 0, alpha, beta)) return;
+  } else {
+    if (conv) return;
   }
-  __shared__ double bc[3];
-  block_sum<3, PCG_BLOCK>(tot);
-  if (threadIdx.x == 0) {
-    bc[0] = tot[0];
-    bc[1] = tot[1];
-    bc[2] = tot[2];
-  }
-  __syncthreads();
-  if (conv) return;
-  const double gam = bc[0], del = bc[1], rr = bc[2];
-  const bool done = rr <= v.cg_tol2 * bb;
-  const double beta = gam / gam_old;
-  const double alpha = gam / (del - beta * gam / alp_old);
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    sc->rr = rr;
-    if (done) {
-      sc->converged = 1;
-    } else {
-      sc->gam[PAR] = gam;
-      sc->alp[PAR] = alpha;
-      sc->iter += 1;
-    }
-  }
-  if (done) return;
 
   double g2 = 0.0, d2 = 0.0, r2 = 0.0;
-  for (int64_t g = ch.g0; g < ch.g1; ++g) {
+  if (live) {
     double s = 0.0;
-    if (g == ch.g0) {
-      if (!live) continue;
 #pragma unroll
-      for (int u = 0; u < U; ++u) s += (double)aa[u] * xv[u];
-      // entries beyond the first U per lane
-      s += row_dot<U>(v.a_col, aval, row, nnz, v.kpad, t + U * TEAM,
-                      [&](int32_t j) { return M[j]; });
-    } else {
-      // later row groups of this workgroup
-      row = g * PCG_ROWS + threadIdx.x / TEAM;
-      if (row >= v.n) continue;
-      nnz = v.a_nnz[row];
-      if (t == 0) {
-        own[0] = v.diag[row]; own[1] = M[row]; own[2] = v.pl_z[row]; own[3] = v.pl_s[row];
-        own[4] = v.pd[0][row]; own[5] = v.r[row]; own[6] = v.p[row];
-      }
-      s = row_dot<8>(v.a_col, aval, row, nnz, v.kpad, t, [&](int32_t j) { return M[j]; });
-    }
+    for (int u = 0; u < U; ++u) s += (double)aa[u] * xv[u];
+    // entries beyond the first U per lane
+    s += row_dot<4>(v.a_col, aval, row, nnz, v.kpad, t + U * TEAM,
+                    [&](int32_t j) { return M[j]; });
     s = team_sum(s);
     if (t == 0) {
       const double dg = own[0], m = own[1];
@@ -569,13 +607,13 @@ __global__ __launch_bounds__(PCG_BLOCK) void k_pcg_iter(View v) {
       v.pd[0][row] = pv;
       v.r[row] = r;
       Mn[row] = wn / dg;
-      g2 += r * un;
-      d2 += wn * un;
-      r2 += r * r;
+      g2 = r * un;
+      d2 = wn * un;
+      r2 = r * r;
     }
   }
   double x[3] = {g2, d2, r2};
-  block_sum<3, PCG_BLOCK>(x);
+  block_sum<3, NT>(x);
   if (threadIdx.x == 0) {
     const int lb = xcd_block();
 #pragma unroll
@@ -657,26 +695,69 @@ int launch_cg_spmv(const View& v, int precision, hipStream_t s) {
   return 0;
 }
 
-int pcg_blocks(int64_t n) {
-  const int64_t a = (n + PCG_ROWS - 1) / PCG_ROWS;
-  return (int)(a < PCG_MAX_BLOCKS ? a : PCG_MAX_BLOCKS);
+int pcg_blocks(int64_t n, bool fused) {
+  const int rows = (fused ? PCG_BLOCK : PCG_SPLIT_BLOCK) / TEAM;
+  return (int)((n + rows - 1) / rows);
+}
+
+// Largest grid of the fused iteration kernel: what the device holds
+// resident at once (a second wave of workgroups would double the latency of
+// an iteration), and at most PCG_MAX_BLOCKS partials per reduction.  The
+// workgroups never wait for each other, so this is a matter of speed only.
+int pcg_fused_capacity() {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  int worst = 1 << 30;
+  const void* ks[] = {(const void*)k_pcg_iter<float, 0, true>, (const void*)k_pcg_iter<double, 0, true>};
+  for (const void* k : ks) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, PCG_BLOCK, 0) != hipSuccess) return 0;
+    worst = per < worst ? per : worst;
+  }
+  const int cap = worst * cus;
+  return cap < PCG_MAX_BLOCKS ? cap : PCG_MAX_BLOCKS;
 }
 
 int launch_pcg_setup(const View& v, int precision, hipStream_t s) {
   const unsigned nb = (unsigned)v.npcg;
-  if (precision == MPS_MIXED) k_pcg_setup<float><<<nb, PCG_BLOCK, 0, s>>>(v);
-  else k_pcg_setup<double><<<nb, PCG_BLOCK, 0, s>>>(v);
+  const bool mx = precision == MPS_MIXED;
+  if (v.pcg_fused) {
+    if (mx) k_pcg_setup<float, true><<<nb, PCG_BLOCK, 0, s>>>(v);
+    else k_pcg_setup<double, true><<<nb, PCG_BLOCK, 0, s>>>(v);
+  } else {
+    k_pcg_start<<<1, RED_BLOCK, 0, s>>>(v);
+    if (mx) k_pcg_setup<float, false><<<nb, PCG_SPLIT_BLOCK, 0, s>>>(v);
+    else k_pcg_setup<double, false><<<nb, PCG_SPLIT_BLOCK, 0, s>>>(v);
+  }
+  return 0;
+}
+
+int launch_pcg_reduce(const View& v, int parity, hipStream_t s) {
+  if (parity) k_pcg_reduce<1><<<1, RED_BLOCK, 0, s>>>(v);
+  else k_pcg_reduce<0><<<1, RED_BLOCK, 0, s>>>(v);
   return 0;
 }
 
 int launch_pcg_iter(const View& v, int precision, int parity, hipStream_t s) {
   const unsigned nb = (unsigned)v.npcg;
-  if (precision == MPS_MIXED) {
-    if (parity) k_pcg_iter<float, 1><<<nb, PCG_BLOCK, 0, s>>>(v);
-    else k_pcg_iter<float, 0><<<nb, PCG_BLOCK, 0, s>>>(v);
+  const bool mx = precision == MPS_MIXED;
+  if (v.pcg_fused) {
+    if (mx) {
+      if (parity) k_pcg_iter<float, 1, true><<<nb, PCG_BLOCK, 0, s>>>(v);
+      else k_pcg_iter<float, 0, true><<<nb, PCG_BLOCK, 0, s>>>(v);
+    } else {
+      if (parity) k_pcg_iter<double, 1, true><<<nb, PCG_BLOCK, 0, s>>>(v);
+      else k_pcg_iter<double, 0, true><<<nb, PCG_BLOCK, 0, s>>>(v);
+    }
   } else {
-    if (parity) k_pcg_iter<double, 1><<<nb, PCG_BLOCK, 0, s>>>(v);
-    else k_pcg_iter<double, 0><<<nb, PCG_BLOCK, 0, s>>>(v);
+    if (mx) {
+      if (parity) k_pcg_iter<float, 1, false><<<nb, PCG_SPLIT_BLOCK, 0, s>>>(v);
+      else k_pcg_iter<float, 0, false><<<nb, PCG_SPLIT_BLOCK, 0, s>>>(v);
+    } else {
+      if (parity) k_pcg_iter<double, 1, false><<<nb, PCG_SPLIT_BLOCK, 0, s>>>(v);
+      else k_pcg_iter<double, 0, false><<<nb, PCG_SPLIT_BLOCK, 0, s>>>(v);
+    }
   }
   return 0;
 }

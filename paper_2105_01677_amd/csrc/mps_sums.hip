@@ -55,6 +55,40 @@ struct PosRef<DIM, true> {
   }
 };
 
+// A particle at r^k as the viscous sums see it: position and velocity.
+// Plain path: FP64 state.  Mixed path: the 32-byte FP32 record written by
+// the cell sort (cell-relative position with the packed cell, then the FP32
+// velocity), one contiguous gather per neighbour.
+template <int DIM, bool MIXED>
+struct KRec;
+
+template <int DIM>
+struct KRec<DIM, false> {
+  PosRef<DIM, false> p;
+  double u[DIM];
+  __device__ static KRec load(const View& v, int64_t j) {
+    KRec r;
+    r.p = PosRef<DIM, false>::load(v.pos, nullptr, j);
+    load_vec<DIM>(v.vel, j, r.u);
+    return r;
+  }
+};
+
+template <int DIM>
+struct KRec<DIM, true> {
+  PosRef<DIM, true> p;
+  float u[DIM];
+  __device__ static KRec load(const View& v, int64_t j) {
+    KRec r;
+    r.p.f = v.posf[2 * j];
+    const float4 q = v.posf[2 * j + 1];
+    r.u[0] = q.x;
+    r.u[1] = q.y;
+    if constexpr (DIM == 3) r.u[2] = q.z;
+    return r;
+  }
+};
+
 template <int DIM, class R>
 __device__ inline R norm2(const R (&d)[DIM]) {
   R s = d[0] * d[0] + d[1] * d[1];
@@ -78,6 +112,29 @@ __device__ inline int64_t team_row() {
   return (int64_t)xcd_block() * ROWS_PER_BLOCK + threadIdx.x / TEAM;
 }
 
+// The list entries l = t, t + TEAM, ... < cnt of a row, U per lane and
+// step: the list loads of a step are issued together and its bodies are
+// straight-line code, so their gathers can be in flight together too.
+// Slots past cnt (stale, but inside the row's kpad slots) are replaced by
+// the row itself with ok = false; the body must then contribute nothing.
+// U per kernel as measured on MI355X (2 for the sums with the heaviest
+// gathers, 1 where the extra registers cost more than they hide).
+template <int U, class F>
+__device__ inline void for_list(const View& v, int64_t row, int cnt, int t, F&& body) {
+  for (int l0 = t; l0 < cnt; l0 += U * TEAM) {
+    int32_t j[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int l = l0 + u * TEAM;
+      // l - t + TEAM <= kpad is uniform over the team (kpad % TEAM == 0)
+      j[u] = l - t < v.kpad ? v.nb_list[sl_index(row, l, v.kpad)] : 0;
+      if (l >= cnt) j[u] = (int32_t)row;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) body(j[u], l0 + u * TEAM < cnt);
+  }
+}
+
 // a3: u* = u + dt (nu 2d/(lambda n0) sum_j (u_j - u_i) w(r_ij) + g),
 //     r* = r + dt u*  for fluid; other particles keep r and u.
 template <int DIM, bool MIXED>
@@ -94,27 +151,28 @@ __global__ __launch_bounds__(BLOCK) void k_predict(View v) {
 #pragma unroll
   for (int a = 0; a < DIM; ++a) { us[a] = ui[a]; rs[a] = xi[a]; }
   if (v.type[row] == MPS_FLUID) {
-    const P pi = P::load(v.pos, v.posf, row);
+    using K = KRec<DIM, MIXED>;
+    const K ri = K::load(v, row);
     const R re = (R)v.re_lap;
     R acc[DIM];
 #pragma unroll
     for (int a = 0; a < DIM; ++a) acc[a] = R(0);
     const int cnt = v.nb_count[row];
-    for (int l = t; l < cnt; l += TEAM) {
-      const int32_t j = v.nb_list[sl_index(row, l, v.kpad)];
+    const double mi = v.rho_s ? v.mu[row] : 0.0;
+    for_list<2>(v, row, cnt, t, [&](int32_t j, bool ok) {
+      const K rj = K::load(v, j);
       R d[DIM];
-      pi.diff(P::load(v.pos, v.posf, j), v.cs32, d);
-      R w = weight<R>(v.kernel, sqrt(norm2<DIM, R>(d)), re);
+      ri.p.diff(rj.p, v.cs32, d);
+      const R wr = weight<R>(v.kernel, sqrt(norm2<DIM, R>(d)), re);
+      R w = ok ? wr : R(0);
       if (v.rho_s) {
         // two-phase: harmonic mean of the pair's dynamic viscosities
-        const double mi = v.mu[row], mj = v.mu[j], ms = mi + mj;
+        const double mj = v.mu[j], ms = mi + mj;
         w *= (R)(ms > 0.0 ? 2.0 * mi * mj / ms : 0.0);
       }
-      double uj[DIM];
-      load_vec<DIM>(v.vel, j, uj);
 #pragma unroll
-      for (int a = 0; a < DIM; ++a) acc[a] += (R)(uj[a] - ui[a]) * w;
-    }
+      for (int a = 0; a < DIM; ++a) acc[a] += (R)(rj.u[a] - ri.u[a]) * w;
+    });
     const double clap = 2.0 * DIM / (v.lam_lap * v.n0_lap);
     const double visc = v.rho_s ? clap / v.rho_s[row] : v.nu * clap;
 #pragma unroll
@@ -128,92 +186,6 @@ __global__ __launch_bounds__(BLOCK) void k_predict(View v) {
     store_vec<DIM>(v.us, row, us);
     store_vec<DIM>(v.rs, row, rs);
     if constexpr (MIXED) v.rsf[row] = to_rel<DIM>(v, rs, v.pcell[row]);
-  }
-}
-
-// Mixed path, LDS-tiled.  FP32 record of particle j for the Laplacian:
-// velocity and, in two-phase runs, dynamic viscosity.  The same record is
-// read from LDS (tiled workgroups) or global memory (the others), so both
-// give identical sums.
-template <int DIM>
-__device__ inline float4 vel_rec(const View& v, int64_t j) {
-  double u[DIM];
-  load_vec<DIM>(v.vel, j, u);
-  return make_float4((float)u[0], (float)u[1], DIM == 3 ? (float)u[2] : 0.f,
-                     v.rho_s ? (float)v.mu[j] : 0.f);
-}
-
-// a3 on the mixed path: as k_predict, with the neighbours' cell-relative
-// FP32 positions and FP32 velocity records staged in LDS per workgroup.
-template <int DIM>
-__global__ __launch_bounds__(BLOCK) void k_predict_mixed(View v) {
-  using P = PosRef<DIM, true>;
-  __shared__ float4 s_p[TILE_CAP];
-  __shared__ float4 s_u[TILE_CAP];
-  const int g = xcd_block();
-  TileMap tm;
-  tm.load(v, g);
-  const bool tiled = tm.nr > 0;
-  if (tiled) {
-    stage_tile(tm, s_p, [&](int j) { return v.posf[j]; });
-    stage_tile(tm, s_u, [&](int j) { return vel_rec<DIM>(v, j); });
-    __syncthreads();
-  }
-  const int64_t row = (int64_t)g * ROWS_PER_BLOCK + threadIdx.x / TEAM;
-  const int t = team_lane();
-  if (row >= v.n) return;
-  double ui[DIM], xi[DIM];
-  load_vec<DIM>(v.vel, row, ui);
-  load_vec<DIM>(v.pos, row, xi);
-  double us[DIM], rs[DIM];
-#pragma unroll
-  for (int a = 0; a < DIM; ++a) { us[a] = ui[a]; rs[a] = xi[a]; }
-  if (v.type[row] == MPS_FLUID) {
-    P pi;
-    pi.f = v.posf[row];
-    const float4 uf = vel_rec<DIM>(v, row);
-    const float re = (float)v.re_lap;
-    float acc[DIM];
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) acc[a] = 0.f;
-    const int cnt = v.nb_count[row];
-    for (int l = t; l < cnt; l += TEAM) {
-      const int32_t j = v.nb_list[sl_index(row, l, v.kpad)];
-      P pj;
-      float4 uj;
-      if (tiled) {
-        const int sj = tm.slot(j);
-        pj.f = s_p[sj];
-        uj = s_u[sj];
-      } else {
-        pj.f = v.posf[j];
-        uj = vel_rec<DIM>(v, j);
-      }
-      float d[DIM];
-      pi.diff(pj, v.cs32, d);
-      float w = weight<float>(v.kernel, sqrtf(norm2<DIM, float>(d)), re);
-      if (v.rho_s) {
-        // two-phase: harmonic mean of the pair's dynamic viscosities
-        const float ms = uf.w + uj.w;
-        w *= ms > 0.f ? 2.f * uf.w * uj.w / ms : 0.f;
-      }
-      acc[0] += (uj.x - uf.x) * w;
-      acc[1] += (uj.y - uf.y) * w;
-      if constexpr (DIM == 3) acc[2] += (uj.z - uf.z) * w;
-    }
-    const double clap = 2.0 * DIM / (v.lam_lap * v.n0_lap);
-    const double visc = v.rho_s ? clap / v.rho_s[row] : v.nu * clap;
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-      const double lap = (double)team_sum(acc[a]);
-      us[a] = ui[a] + v.dt * (visc * lap + v.g[a]);
-      rs[a] = xi[a] + v.dt * us[a];
-    }
-  }
-  if (t == 0) {
-    store_vec<DIM>(v.us, row, us);
-    store_vec<DIM>(v.rs, row, rs);
-    v.rsf[row] = to_rel<DIM>(v, rs, v.pcell[row]);
   }
 }
 
@@ -233,28 +205,10 @@ __device__ inline double ipow(double x, int e) {
 // FP64 position (double2) is as wide as the FP32 copy (float4), so this
 // costs no extra bytes.
 template <int DIM>
-struct RPos {
-  double x[DIM];
-};
-
-template <int DIM>
 __global__ __launch_bounds__(BLOCK) void k_density(View v, int wc) {
   using P = PosRef<DIM, false>;
   using R = typename P::R;
-  __shared__ RPos<DIM> s_r[TILE_CAP];
-  const int g = xcd_block();
-  TileMap tm;
-  tm.load(v, g);
-  const bool tiled = tm.nr > 0;
-  if (tiled) {
-    stage_tile(tm, s_r, [&](int j) {
-      RPos<DIM> r;
-      load_vec<DIM>(v.rs, j, r.x);
-      return r;
-    });
-    __syncthreads();
-  }
-  const int64_t row = (int64_t)g * ROWS_PER_BLOCK + threadIdx.x / TEAM;
+  const int64_t row = team_row();
   const int t = team_lane();
   if (row >= v.n) return;
   const int8_t ty = v.type[row];
@@ -263,21 +217,13 @@ __global__ __launch_bounds__(BLOCK) void k_density(View v, int wc) {
     const P pi = P::load(v.rs, v.rsf, row);
     const R re = (R)v.re_n, re2 = (R)v.re_n2;
     const int cnt = v.nb_count[row];
-    for (int l = t; l < cnt; l += TEAM) {
-      const int32_t j = v.nb_list[sl_index(row, l, v.kpad)];
-      P pj;
-      if (tiled) {
-        const RPos<DIM> r = s_r[tm.slot(j)];
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) pj.x[a] = r.x[a];
-      } else {
-        pj = P::load(v.rs, v.rsf, j);
-      }
+    for_list<2>(v, row, cnt, t, [&](int32_t j, bool ok) {
       R d[DIM];
-      pi.diff(pj, v.cs32, d);
+      pi.diff(P::load(v.rs, v.rsf, j), v.cs32, d);
       const R r2 = norm2<DIM, R>(d);
-      if (r2 < re2) s += weight<R>(v.kernel, sqrt(r2), re);
-    }
+      const R w = weight<R>(v.kernel, sqrt(r2), re);
+      s += (ok && r2 < re2) ? w : R(0);
+    });
     s = team_sum(s);
   }
   if (t != 0) return;
@@ -313,9 +259,8 @@ __global__ __launch_bounds__(BLOCK) void k_viscosity(View v) {
   const int8_t ty = v.type[row];
   double nut = 0.0;
   if (ty == MPS_FLUID && v.smag_c2 > 0.0) {
-    const P pi = P::load(v.pos, v.posf, row);
-    double ui[DIM];
-    load_vec<DIM>(v.vel, row, ui);
+    using K = KRec<DIM, MIXED>;
+    const K ri = K::load(v, row);
     R G[DIM][DIM];
 #pragma unroll
     for (int a = 0; a < DIM; ++a)
@@ -323,105 +268,18 @@ __global__ __launch_bounds__(BLOCK) void k_viscosity(View v) {
       for (int b = 0; b < DIM; ++b) G[a][b] = R(0);
     const R re = (R)v.re_n, re2 = (R)v.re_n2;
     const int cnt = v.nb_count[row];
-    for (int l = t; l < cnt; l += TEAM) {
-      const int32_t j = v.nb_list[sl_index(row, l, v.kpad)];
+    for_list<2>(v, row, cnt, t, [&](int32_t j, bool ok) {
+      const K rj = K::load(v, j);
       R d[DIM];
-      pi.diff(P::load(v.pos, v.posf, j), v.cs32, d);
+      ri.p.diff(rj.p, v.cs32, d);
       const R r2 = norm2<DIM, R>(d);
-      if (!(r2 < re2)) continue;
-      const R f = weight<R>(v.kernel, sqrt(r2), re) / r2;
-      double uj[DIM];
-      load_vec<DIM>(v.vel, j, uj);
+      const R fr = weight<R>(v.kernel, sqrt(r2), re) / r2;
+      const R f = (ok && r2 < re2) ? fr : R(0);
 #pragma unroll
       for (int a = 0; a < DIM; ++a)
 #pragma unroll
-        for (int b = 0; b < DIM; ++b) G[a][b] += (R)(uj[a] - ui[a]) * d[b] * f;
-    }
-    double ss = 0.0;
-    const double cg = (double)DIM / v.n0_n;
-#pragma unroll
-    for (int a = 0; a < DIM; ++a)
-#pragma unroll
-      for (int b = 0; b < DIM; ++b) G[a][b] = team_sum(G[a][b]);
-#pragma unroll
-    for (int a = 0; a < DIM; ++a)
-#pragma unroll
-      for (int b = 0; b < DIM; ++b) {
-        const double sab = 0.5 * ((double)G[a][b] + (double)G[b][a]) * cg;
-        ss += sab * sab;
-      }
-    nut = ss > 0.0 ? v.smag_c2 * sqrt(2.0 * ss) : 0.0;
-  }
-  if (t == 0) {
-    v.nut[row] = nut;
-    v.mu[row] = ty == MPS_GHOST ? 0.0 : v.rho_s[row] * (v.nu_l[row] + nut);
-  }
-}
-
-// Smagorinsky viscosity on the mixed path: as k_viscosity<DIM, true>, with
-// the neighbours' FP32 positions and FP32 velocities staged in LDS (the
-// same FP32 velocity values on both paths).
-template <int DIM>
-__device__ inline float4 vel_f(const View& v, int64_t j) {
-  double u[DIM];
-  load_vec<DIM>(v.vel, j, u);
-  return make_float4((float)u[0], (float)u[1], DIM == 3 ? (float)u[2] : 0.f, 0.f);
-}
-
-template <int DIM>
-__global__ __launch_bounds__(BLOCK) void k_viscosity_mixed(View v) {
-  using P = PosRef<DIM, true>;
-  __shared__ float4 s_p[TILE_CAP];
-  __shared__ float4 s_u[TILE_CAP];
-  const int g = xcd_block();
-  TileMap tm;
-  tm.load(v, g);
-  const bool tiled = tm.nr > 0;
-  if (tiled) {
-    stage_tile(tm, s_p, [&](int j) { return v.posf[j]; });
-    stage_tile(tm, s_u, [&](int j) { return vel_f<DIM>(v, j); });
-    __syncthreads();
-  }
-  const int64_t row = (int64_t)g * ROWS_PER_BLOCK + threadIdx.x / TEAM;
-  const int t = team_lane();
-  if (row >= v.n) return;
-  const int8_t ty = v.type[row];
-  double nut = 0.0;
-  if (ty == MPS_FLUID && v.smag_c2 > 0.0) {
-    P pi;
-    pi.f = v.posf[row];
-    const float4 ui = vel_f<DIM>(v, row);
-    const float uia[3] = {ui.x, ui.y, ui.z};
-    float G[DIM][DIM];
-#pragma unroll
-    for (int a = 0; a < DIM; ++a)
-#pragma unroll
-      for (int b = 0; b < DIM; ++b) G[a][b] = 0.f;
-    const float re = (float)v.re_n, re2 = (float)v.re_n2;
-    const int cnt = v.nb_count[row];
-    for (int l = t; l < cnt; l += TEAM) {
-      const int32_t j = v.nb_list[sl_index(row, l, v.kpad)];
-      P pj;
-      float4 uj;
-      if (tiled) {
-        const int sj = tm.slot(j);
-        pj.f = s_p[sj];
-        uj = s_u[sj];
-      } else {
-        pj.f = v.posf[j];
-        uj = vel_f<DIM>(v, j);
-      }
-      float d[DIM];
-      pi.diff(pj, v.cs32, d);
-      const float r2 = norm2<DIM, float>(d);
-      if (!(r2 < re2)) continue;
-      const float f = weight<float>(v.kernel, sqrtf(r2), re) / r2;
-      const float uja[3] = {uj.x, uj.y, uj.z};
-#pragma unroll
-      for (int a = 0; a < DIM; ++a)
-#pragma unroll
-        for (int b = 0; b < DIM; ++b) G[a][b] += (uja[a] - uia[a]) * d[b] * f;
-    }
+        for (int b = 0; b < DIM; ++b) G[a][b] += (R)(rj.u[a] - ri.u[a]) * d[b] * f;
+    });
     double ss = 0.0;
     const double cg = (double)DIM / v.n0_n;
 #pragma unroll
@@ -498,13 +356,13 @@ __global__ __launch_bounds__(BLOCK) void k_phat(View v, double* phat) {
     const P pi = P::load(v.rs, v.rsf, row);
     const R re2 = (R)v.re_n2;
     const int cnt = v.nb_count[row];
-    for (int l = t; l < cnt; l += TEAM) {
-      const int32_t j = v.nb_list[sl_index(row, l, v.kpad)];
-      if (v.type[j] == MPS_DUMMY) continue;
+    for_list<1>(v, row, cnt, t, [&](int32_t j, bool ok) {
       R d[DIM];
       pi.diff(P::load(v.rs, v.rsf, j), v.cs32, d);
-      if (norm2<DIM, R>(d) < re2) m = fmin(m, v.p[j]);
-    }
+      // flags mark exactly the dummy particles MPS_FLAG_DUMMY
+      const double pj = v.p[j];
+      if (ok && v.flags[j] != MPS_FLAG_DUMMY && norm2<DIM, R>(d) < re2) m = fmin(m, pj);
+    });
     m = team_min(m);
   }
   if (t == 0) phat[row] = m;
@@ -534,23 +392,22 @@ __global__ __launch_bounds__(BLOCK) void k_gradient(View v, const double* phat) 
   for (int a = 0; a < DIM; ++a) gs[a] = bs[a] = 0.0;
   double m = p_i;
   const double ph_i = CMPS ? phat[row] : 0.0;
-  for (int l = t; l < cnt; l += TEAM) {
-    const int32_t j = v.nb_list[sl_index(row, l, v.kpad)];
-    if (v.type[j] == MPS_DUMMY) continue;
+  for_list<1>(v, row, cnt, t, [&](int32_t j, bool ok) {
     R d[DIM];
     pi.diff(P::load(v.rs, v.rsf, j), v.cs32, d);
     const R r2 = norm2<DIM, R>(d);
-    if (!(r2 < re2)) continue;
-    const R w = weight<R>(v.kernel, sqrt(r2), re);
     const double pj = v.p[j];
+    // flags mark exactly the dummy particles MPS_FLAG_DUMMY
+    const bool in = ok && v.flags[j] != MPS_FLAG_DUMMY && r2 < re2;
+    const R wr = weight<R>(v.kernel, sqrt(r2), re) / r2;
+    const R f = in ? wr : R(0);
     if constexpr (CMPS) {
       const double num = (p_i + pj) - (ph_i + phat[j]);
-      const R f = (R)num / r2 * w;
+      const R fn = (R)num * f;
 #pragma unroll
-      for (int a = 0; a < DIM; ++a) gs[a] += (double)(f * d[a]);
+      for (int a = 0; a < DIM; ++a) gs[a] += (double)(fn * d[a]);
     } else {
-      m = fmin(m, pj);
-      const R f = w / r2;
+      if (in) m = fmin(m, pj);
 #pragma unroll
       for (int a = 0; a < DIM; ++a) {
         const double fd = (double)(f * d[a]);
@@ -558,7 +415,7 @@ __global__ __launch_bounds__(BLOCK) void k_gradient(View v, const double* phat) 
         bs[a] += fd;
       }
     }
-  }
+  });
   if constexpr (!CMPS) m = team_min(m);
   double us[DIM], rs[DIM], un[DIM], xn[DIM];
   load_vec<DIM>(v.us, row, us);
@@ -581,86 +438,6 @@ __global__ __launch_bounds__(BLOCK) void k_gradient(View v, const double* phat) 
   }
 }
 
-// a8 on the mixed path, standard form: as k_gradient<DIM, true, false>,
-// with the neighbours' FP32 positions, pressures and types staged in LDS.
-template <int DIM>
-__global__ __launch_bounds__(BLOCK) void k_gradient_mixed(View v) {
-  using P = PosRef<DIM, true>;
-  __shared__ float4 s_p[TILE_CAP];
-  __shared__ double s_q[TILE_CAP];
-  __shared__ int8_t s_t[TILE_CAP];
-  const int g = xcd_block();
-  TileMap tm;
-  tm.load(v, g);
-  const bool tiled = tm.nr > 0;
-  if (tiled) {
-    stage_tile(tm, s_p, [&](int j) { return v.rsf[j]; });
-    stage_tile(tm, s_q, [&](int j) { return v.p[j]; });
-    stage_tile(tm, s_t, [&](int j) { return v.type[j]; });
-    __syncthreads();
-  }
-  const int64_t row = (int64_t)g * ROWS_PER_BLOCK + threadIdx.x / TEAM;
-  const int t = team_lane();
-  if (row >= v.n) return;
-  if (v.type[row] != MPS_FLUID) return;
-  P pi;
-  pi.f = v.rsf[row];
-  const float re = (float)v.re_n, re2 = (float)v.re_n2;
-  const int cnt = v.nb_count[row];
-  const double p_i = v.p[row];
-  double gs[DIM], bs[DIM];
-#pragma unroll
-  for (int a = 0; a < DIM; ++a) gs[a] = bs[a] = 0.0;
-  double m = p_i;
-  for (int l = t; l < cnt; l += TEAM) {
-    const int32_t j = v.nb_list[sl_index(row, l, v.kpad)];
-    P pj;
-    double pj_p;
-    int8_t tj;
-    if (tiled) {
-      const int sj = tm.slot(j);
-      tj = s_t[sj];
-      pj.f = s_p[sj];
-      pj_p = s_q[sj];
-    } else {
-      tj = v.type[j];
-      pj.f = v.rsf[j];
-      pj_p = v.p[j];
-    }
-    if (tj == MPS_DUMMY) continue;
-    float d[DIM];
-    pi.diff(pj, v.cs32, d);
-    const float r2 = norm2<DIM, float>(d);
-    if (!(r2 < re2)) continue;
-    const float f = weight<float>(v.kernel, sqrtf(r2), re) / r2;
-    m = fmin(m, pj_p);
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-      const double fd = (double)(f * d[a]);
-      gs[a] += pj_p * fd;
-      bs[a] += fd;
-    }
-  }
-  m = team_min(m);
-  double us[DIM], rs[DIM], un[DIM], xn[DIM];
-  load_vec<DIM>(v.us, row, us);
-  load_vec<DIM>(v.rs, row, rs);
-  const double cg = (double)DIM / v.n0_n;
-  bool finite = true;
-#pragma unroll
-  for (int a = 0; a < DIM; ++a) {
-    const double gp = cg * (team_sum(gs[a]) - m * team_sum(bs[a]));
-    un[a] = us[a] - v.dt / (v.rho_s ? v.rho_s[row] : v.rho) * gp;
-    xn[a] = rs[a] + v.dt * (un[a] - us[a]);
-    finite = finite && isfinite(un[a]) && isfinite(xn[a]);
-  }
-  if (t == 0) {
-    store_vec<DIM>(v.vel_w, row, un);
-    store_vec<DIM>(v.pos_w, row, xn);
-    if (!finite) atomicOr(v.status, ST_NONFINITE);
-  }
-}
-
 static inline unsigned team_blocks(int64_t n) {
   return (unsigned)((n + ROWS_PER_BLOCK - 1) / ROWS_PER_BLOCK);
 }
@@ -669,10 +446,10 @@ int launch_predict(const View& v, int dim, int precision, hipStream_t s) {
   const unsigned nb = team_blocks(v.n);
   const bool mx = precision == MPS_MIXED;
   if (dim == 2) {
-    if (mx) k_predict_mixed<2><<<nb, BLOCK, 0, s>>>(v);
+    if (mx) k_predict<2, true><<<nb, BLOCK, 0, s>>>(v);
     else k_predict<2, false><<<nb, BLOCK, 0, s>>>(v);
   } else {
-    if (mx) k_predict_mixed<3><<<nb, BLOCK, 0, s>>>(v);
+    if (mx) k_predict<3, true><<<nb, BLOCK, 0, s>>>(v);
     else k_predict<3, false><<<nb, BLOCK, 0, s>>>(v);
   }
   return 0;
@@ -692,10 +469,10 @@ int launch_viscosity(const View& v, int dim, int precision, hipStream_t s) {
   const unsigned nb = team_blocks(v.n);
   const bool mx = precision == MPS_MIXED;
   if (dim == 2) {
-    if (mx) k_viscosity_mixed<2><<<nb, BLOCK, 0, s>>>(v);
+    if (mx) k_viscosity<2, true><<<nb, BLOCK, 0, s>>>(v);
     else k_viscosity<2, false><<<nb, BLOCK, 0, s>>>(v);
   } else {
-    if (mx) k_viscosity_mixed<3><<<nb, BLOCK, 0, s>>>(v);
+    if (mx) k_viscosity<3, true><<<nb, BLOCK, 0, s>>>(v);
     else k_viscosity<3, false><<<nb, BLOCK, 0, s>>>(v);
   }
   return 0;
@@ -722,8 +499,6 @@ static void gradient_dim(const View& v, hipStream_t s) {
     double* phat = v.r;
     k_phat<DIM, MIXED><<<nb, BLOCK, 0, s>>>(v, phat);
     k_gradient<DIM, MIXED, true><<<nb, BLOCK, 0, s>>>(v, phat);
-  } else if constexpr (MIXED) {
-    k_gradient_mixed<DIM><<<nb, BLOCK, 0, s>>>(v);
   } else {
     k_gradient<DIM, MIXED, false><<<nb, BLOCK, 0, s>>>(v, nullptr);
   }

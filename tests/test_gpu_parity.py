@@ -159,6 +159,57 @@ def test_one_step_3d(gpu, orc, precision, cg_tol, tol):
     _compare_step(gpu, orc, w2, tol)
 
 
+@pytest.mark.parametrize("precision,cg_tol,tol", PRECISIONS)
+def test_one_step_3d_split_cg(gpu, orc, precision, cg_tol, tol):
+    """73,344 particles: more row groups than one fused CG kernel takes
+    (1,146 > 1,024), so the solve runs as reduction + iteration kernels."""
+    w = W.jitter(W.lattice_block(3, [44, 40, 36], walls_below=True, dt=2e-4))
+    assert (w.n + 63) // 64 > 1024
+    w.params.update(precision=precision, cg_tol=cg_tol)
+    _compare_step(gpu, orc, w, tol)
+
+
+@pytest.mark.parametrize("precision,cg_tol,tol", PRECISIONS)
+def test_one_step_cfg3_full(gpu, orc, precision, cg_tol, tol):
+    """3-D bench size: the 441,282-particle dam break from rest, as
+    benchmarked (split CG schedule), every particle against the oracle."""
+    w = W.config("cfg3", precision=precision)
+    w.params["cg_tol"] = cg_tol
+    _compare_step(gpu, orc, w, tol)
+
+
+def test_one_step_cfg5_full(gpu, orc):
+    """Two-phase + Smagorinsky bench size (2,314,616 particles), mixed path
+    as benchmarked: smoothed density, eddy viscosity and one step, every
+    particle against the oracle."""
+    w = W.config("cfg5", precision=W.MIXED)
+    prm = dict(w.params)
+    st, rs = orc.smoothed_density(prm, w.pos, w.ptype, w.rho_i)
+    assert st == 0
+    m = gpu.MPS(prm, w.pos, w.vel, w.ptype, rho_i=w.rho_i, nu_i=w.nu_i)
+    r0, _ = m.phase()
+    assert rel_err(_np(r0), rs) < 1e-14
+    s = m.step(1)
+    g = {k: _np(v) for k, v in m.state().items()}
+    _, nut = m.phase()
+    m.close()
+    st, o = orc.step(prm, w.pos, w.vel, w.ptype, want_lists=False, rho_s=rs, nu_i=w.nu_i)
+    assert st == 0
+    fw = (w.ptype == W.FLUID) | (w.ptype == W.WALL)
+    mism = np.nonzero((g["flags"] != o["flags"]) & fw)[0]
+    if len(mism):
+        n0 = orc.lattice_constants(3, prm["l0"], prm["re_n"], prm["kernel"])[0]
+        band = np.abs(o["nstar"][mism] / (prm["beta"] * n0) - 1.0)
+        assert band.max() < 2e-5, f"flag mismatch outside the tie band: {band.max()}"
+        st, o = orc.step(prm, w.pos, w.vel, w.ptype, flags_override=g["flags"],
+                         want_lists=False, rho_s=rs, nu_i=w.nu_i)
+    errs = {"disp": rel_err(g["pos"] - w.pos, o["pos"] - w.pos), "vel": rel_err(g["vel"], o["vel"]),
+            "p": rel_err(g["p"], o["p"]), "nut": rel_err(_np(nut), o["nut"])}
+    print("cfg5 errors", errs, "cg", s["cg_iters_last"], flush=True)
+    for k, e in errs.items():
+        assert e < 1e-4, (k, e)
+
+
 @pytest.mark.parametrize("grad", [W.GRAD_STD, W.GRAD_CMPS])
 def test_one_step_cmps(gpu, orc, grad):
     w = W.jitter(W.config("cfg1"))
