@@ -110,10 +110,31 @@ def run_gpu(w, steps, warmup, *, profile_all=False, profile_cls=None):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = m.profile_read() if (profile_all or profile_cls) else None
+    check = state_check(w, m.state())
     m.close()
     dt = t1 - t0
     return {"seconds": dt, "ms_per_step": 1e3 * dt / steps,
-            "particle_steps_per_s": w.n * steps / dt, "stats": s, "profile": prof}
+            "particle_steps_per_s": w.n * steps / dt, "stats": s, "profile": prof,
+            "state_check": check}
+
+
+def state_check(w, st):
+    """The timed state must still be the physical flow: no particle left the
+    grid (ghosts do no work) and every fluid speed below 10 sqrt(2 g H), H
+    the initial fluid height."""
+    import numpy as np
+    from paper_2105_01677_amd import workloads as W
+    vel = st["vel"].cpu().numpy()
+    typ = st["type"].cpu().numpy()
+    dim = w.params["dim"]
+    f0 = w.ptype == W.FLUID
+    h = float(w.pos[f0, dim - 1].max() - w.pos[f0, dim - 1].min())
+    g = float(np.linalg.norm(w.params["g"][:dim]))
+    bound = 10.0 * np.sqrt(2.0 * g * h)
+    vmax = float(np.linalg.norm(vel[typ == W.FLUID], axis=1).max())
+    ghosts = int((typ == W.GHOST).sum())
+    return {"max_fluid_speed": vmax, "speed_bound": bound, "ghosts": ghosts,
+            "ok": bool(np.isfinite(vel).all() and vmax < bound and ghosts == 0)}
 
 
 def kernel_bandwidth(w, r, mixed, wc):
@@ -141,6 +162,7 @@ def run_3d(name, w, steps, warmup):
     res = {"n_particles": w.n, "n_fluid": c["fluid"], "steps": steps,
            "value": r["particle_steps_per_s"], "ms_per_step": r["ms_per_step"],
            "cg_iters_mean": r["stats"]["cg_iters_total"] / steps,
+           "state_ok": r["state_check"]["ok"],
            "kernels": kernel_bandwidth(w, br, mixed, w.params["pmode"] == 1)}
     log(name, {k: v for k, v in res.items() if k != "kernels"})
     for k, v in res["kernels"].items():
@@ -173,7 +195,7 @@ def cpu_baseline(w, seconds):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -261,7 +283,8 @@ def main():
         wx.params["cg_pipelined"] = pl
         r = run_gpu(wx, K, Wm)
         extra[name] = {"value": r["particle_steps_per_s"], "ms_per_step": r["ms_per_step"],
-                       "cg_iters_mean": r["stats"]["cg_iters_total"] / K}
+                       "cg_iters_mean": r["stats"]["cg_iters_total"] / K,
+                       "state_ok": r["state_check"]["ok"]}
         log(name, extra[name])
 
     cfg3d = {}
@@ -269,6 +292,14 @@ def main():
         w3 = W.config("cfg3", precision=W.MIXED)
         w3.params["cg_pipelined"] = 1
         cfg3d["dam_break_3d_l0=0.007"] = run_3d("dam_break_3d", w3, args.steps_3d, 2)
+        # the same 3-D case on the plain FP64 path (same solver): the
+        # bandwidth-bound comparison of the two precisions
+        w3d = W.config("cfg3", precision=W.FP64)
+        w3d.params["cg_pipelined"] = 1
+        f64 = run_3d("dam_break_3d_fp64", w3d, args.steps_3d, 2)
+        cfg3d["dam_break_3d_l0=0.007_fp64_plain"] = f64
+        cfg3d["dam_break_3d_l0=0.007"]["mixed_vs_fp64_plain"] = (
+            cfg3d["dam_break_3d_l0=0.007"]["value"] / f64["value"])
         w5 = W.config("cfg5", precision=W.MIXED)
         w5.params["cg_pipelined"] = 1
         cfg3d["two_phase_3d_l0=0.005"] = run_3d("two_phase_3d", w5, max(args.steps_3d // 2, 2), 1)
@@ -292,6 +323,7 @@ def main():
                    "dt": w.params["dt"], "dim": 2},
         "fluid_particle_steps_per_s": c["fluid"] * K / hd["seconds"],
         "cg_iters_mean": s["cg_iters_total"] / K,
+        "state_check": hd["state_check"],
         "fp64_plain": extra.get("ppe_fp64"),
         "mixed_vs_fp64_plain": hd["particle_steps_per_s"] / extra["ppe_fp64"]["value"],
         "mixed_standard_cg": extra.get("ppe_mixed_standard_cg"),

@@ -378,22 +378,46 @@ void prof_flush(mps_ctx* c) {
   c->nev = 0;
 }
 
-// Bracket a group of launches of one kernel class with events.
+}  // namespace
+
+namespace mps {
+thread_local ExtTiming* g_ext_timing = nullptr;
+}
+
+namespace {
+
+// Bracket a group of launches of one kernel class with events.  With
+// single = true the scope holds exactly one launch made through launch_k,
+// which records the events from its own dispatch (kernel execution only).
 struct Prof {
   mps_ctx* c;
   int cls;
   bool on;
-  Prof(mps_ctx* c_, int cls_) : c(c_), cls(cls_), on((c_->prof_mask >> cls_) & 1u) {
+  bool single;
+  ExtTiming et;
+  Prof(mps_ctx* c_, int cls_, bool single_ = false)
+      : c(c_), cls(cls_), on((c_->prof_mask >> cls_) & 1u), single(single_) {
     if (!on) return;
     if (c->nev == mps_ctx::kPool) {
       (void)hipStreamSynchronize(c->s);
       prof_flush(c);
     }
-    (void)hipEventRecord(c->ev_a[c->nev], c->s);
+    if (single) {
+      et.start = c->ev_a[c->nev];
+      et.stop = c->ev_b[c->nev];
+      g_ext_timing = &et;
+    } else {
+      (void)hipEventRecord(c->ev_a[c->nev], c->s);
+    }
   }
   ~Prof() {
     if (!on) return;
-    (void)hipEventRecord(c->ev_b[c->nev], c->s);
+    if (single) {
+      g_ext_timing = nullptr;
+      if (!et.used) return;  // nothing was launched
+    } else {
+      (void)hipEventRecord(c->ev_b[c->nev], c->s);
+    }
     c->ev_cls[c->nev] = cls;
     c->nev += 1;
   }
@@ -425,7 +449,8 @@ void enqueue_assemble(mps_ctx* c, const View& v, const double* rhs, bool zero_x0
     launch_assemble(v, c->dim, c->P.precision, rhs, zero_x0, c->s);
   }
   if (c->P.cg_pipelined) {
-    Prof pr(c, MPS_KC_CG_SPMV);
+    // the CG start (w0 = A u0 and its dot products) is timed with the assembly
+    Prof pr(c, MPS_KC_ASSEMBLE);
     launch_pcg_setup(v, c->P.precision, c->s);
   }
 }
@@ -457,20 +482,20 @@ void enqueue_cg(mps_ctx* c, int iters) {
   if (c->P.cg_pipelined) {
     for (int it = 0; it < iters; ++it) {
       if (!c->pcg_fused) {
-        Prof pr(c, MPS_KC_CG_UPDATE);
+        Prof pr(c, MPS_KC_CG_UPDATE, true);
         launch_pcg_reduce(v, it & 1, c->s);
       }
-      Prof pr(c, MPS_KC_CG_SPMV);
+      Prof pr(c, MPS_KC_CG_SPMV, true);
       launch_pcg_iter(v, c->P.precision, it & 1, c->s);
     }
     return;
   }
   for (int it = 0; it < iters; ++it) {
     {
-      Prof pr(c, MPS_KC_CG_SPMV);
+      Prof pr(c, MPS_KC_CG_SPMV, true);
       launch_cg_spmv(v, c->P.precision, c->s);
     }
-    Prof pr(c, MPS_KC_CG_UPDATE);
+    Prof pr(c, MPS_KC_CG_UPDATE, true);
     launch_cg_update(v, c->s);
   }
 }

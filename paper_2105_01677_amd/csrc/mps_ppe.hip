@@ -690,8 +690,8 @@ int launch_assemble(const View& v, int dim, int precision, const double* rhs, bo
 
 int launch_cg_spmv(const View& v, int precision, hipStream_t s) {
   const unsigned nt = (unsigned)v.nspmv;
-  if (precision == MPS_MIXED) k_cg_spmv<float><<<nt, BLOCK, 0, s>>>(v);
-  else k_cg_spmv<double><<<nt, BLOCK, 0, s>>>(v);
+  if (precision == MPS_MIXED) launch_k(k_cg_spmv<float>, nt, BLOCK, s, v);
+  else launch_k(k_cg_spmv<double>, nt, BLOCK, s, v);
   return 0;
 }
 
@@ -734,8 +734,8 @@ int launch_pcg_setup(const View& v, int precision, hipStream_t s) {
 }
 
 int launch_pcg_reduce(const View& v, int parity, hipStream_t s) {
-  if (parity) k_pcg_reduce<1><<<1, RED_BLOCK, 0, s>>>(v);
-  else k_pcg_reduce<0><<<1, RED_BLOCK, 0, s>>>(v);
+  if (parity) launch_k(k_pcg_reduce<1>, 1, RED_BLOCK, s, v);
+  else launch_k(k_pcg_reduce<0>, 1, RED_BLOCK, s, v);
   return 0;
 }
 
@@ -743,27 +743,19 @@ int launch_pcg_iter(const View& v, int precision, int parity, hipStream_t s) {
   const unsigned nb = (unsigned)v.npcg;
   const bool mx = precision == MPS_MIXED;
   if (v.pcg_fused) {
-    if (mx) {
-      if (parity) k_pcg_iter<float, 1, true><<<nb, PCG_BLOCK, 0, s>>>(v);
-      else k_pcg_iter<float, 0, true><<<nb, PCG_BLOCK, 0, s>>>(v);
-    } else {
-      if (parity) k_pcg_iter<double, 1, true><<<nb, PCG_BLOCK, 0, s>>>(v);
-      else k_pcg_iter<double, 0, true><<<nb, PCG_BLOCK, 0, s>>>(v);
-    }
+    const unsigned nt = PCG_BLOCK;
+    if (mx) launch_k(parity ? k_pcg_iter<float, 1, true> : k_pcg_iter<float, 0, true>, nb, nt, s, v);
+    else launch_k(parity ? k_pcg_iter<double, 1, true> : k_pcg_iter<double, 0, true>, nb, nt, s, v);
   } else {
-    if (mx) {
-      if (parity) k_pcg_iter<float, 1, false><<<nb, PCG_SPLIT_BLOCK, 0, s>>>(v);
-      else k_pcg_iter<float, 0, false><<<nb, PCG_SPLIT_BLOCK, 0, s>>>(v);
-    } else {
-      if (parity) k_pcg_iter<double, 1, false><<<nb, PCG_SPLIT_BLOCK, 0, s>>>(v);
-      else k_pcg_iter<double, 0, false><<<nb, PCG_SPLIT_BLOCK, 0, s>>>(v);
-    }
+    const unsigned nt = PCG_SPLIT_BLOCK;
+    if (mx) launch_k(parity ? k_pcg_iter<float, 1, false> : k_pcg_iter<float, 0, false>, nb, nt, s, v);
+    else launch_k(parity ? k_pcg_iter<double, 1, false> : k_pcg_iter<double, 0, false>, nb, nt, s, v);
   }
   return 0;
 }
 
 int launch_cg_update(const View& v, hipStream_t s) {
-  k_cg_update<<<(unsigned)v.nupd, BLOCK, 0, s>>>(v);
+  launch_k(k_cg_update, (unsigned)v.nupd, BLOCK, s, v);
   return 0;
 }
 

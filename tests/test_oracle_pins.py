@@ -430,3 +430,34 @@ def test_two_phase_matrix_symmetric_and_momentum(orc):
     scale = (rs[:, None] * np.abs(w.vel)).sum(0).max()
     np.testing.assert_allclose(m1, m0, rtol=0, atol=1e-12 * scale)
     assert np.abs(o["nut"]).max() > 0
+
+
+def test_still_tank_hydrostatic_level(orc):
+    """Still water, 0.3 m wide and 0.2 m deep at l0 = 0.01 m, 400 steps of
+    dt = 5e-4 s: the pressure averaged over the second half follows
+    rho g (H - y) in the interior.  A loose check, as the plain method is
+    noisy (the pressure from rest is ~0 and builds up, and spurious
+    velocities grow to ~0.6 m/s), but a lost factor (2d, rho, lambda, n0 or
+    dt^2) or a sign error in the pressure chain fails it."""
+    l0 = 0.01
+    w = W.dam_break_2d(l0, tank=(0.3, 0.3), column=(0.3, 0.2), dt=5e-4)
+    f0 = w.ptype == W.FLUID
+    H = w.pos[f0, 1].max() + 0.5 * l0
+    pos, vel, t = w.pos.copy(), w.vel.copy(), w.ptype.copy()
+    acc, cnt = np.zeros(w.n), 0
+    for k in range(20):
+        st, pos, vel, t, p, fl = orc.run(w.params, pos, vel, t, 20)
+        assert st == 0
+        if k >= 10:
+            acc += p
+            cnt += 1
+    assert (t == W.GHOST).sum() == 0
+    pm = acc / cnt
+    x, y = w.pos[:, 0], w.pos[:, 1]
+    inner = f0 & (x > 5 * l0) & (x < 0.3 - 5 * l0) & (y > 4 * l0) & (y < H - 4 * l0)
+    depth = H - y[inner]
+    slope = np.linalg.lstsq(np.vstack([depth, np.ones_like(depth)]).T, pm[inner], rcond=None)[0][0]
+    ratio = (pm[inner] / (1000.0 * 9.81 * depth)).mean()
+    print("still tank: slope/(rho g)", slope / 9810.0, "mean p/(rho g h)", ratio)
+    assert 0.6 < slope / 9810.0 < 1.2
+    assert 0.8 < ratio < 1.4
