@@ -212,18 +212,23 @@ def pressure_gradient(params, rs, ptype, p):
     return st, phat, gp
 
 
-def rollout_grad(params, pos, vel, ptype, nsteps, direction, w_ke=1.0, w_var=9.81):
-    """(status, L, dL/dnu, dL/dgx, <dL/du0, direction>) by dual numbers."""
+def rollout_grad(params, pos, vel, ptype, nsteps, direction, w_ke=1.0, w_var=9.81, *,
+                 rho_s=None, nu_i=None):
+    """(status, L, dL/dnu, dL/dgx, <dL/du0, direction>) by dual numbers.
+    Two-phase model: rho_s (smoothed densities) and nu_i; dL/dnu is then the
+    derivative with respect to a common shift of all nu_i."""
     P, pos, ptype = _prep(params, pos, ptype)
     vel = np.ascontiguousarray(vel, dtype=np.float64)
     d = np.ascontiguousarray(direction, dtype=np.float64)
+    rs_, nu_ = _opt(rho_s), _opt(nu_i)
     out = np.zeros(4)
     L = lib()
     L.orc_rollout_grad.argtypes = [C.POINTER(OrcParams), C.c_int64, C.c_void_p, C.c_void_p,
                                    C.c_void_p, C.c_int32, C.c_void_p, C.c_double, C.c_double,
-                                   C.c_void_p]
+                                   C.c_void_p, C.c_void_p, C.c_void_p]
     st = L.orc_rollout_grad(C.byref(P), pos.shape[0], _ptr(pos), _ptr(vel), _ptr(ptype),
-                            int(nsteps), _ptr(d), float(w_ke), float(w_var), _ptr(out))
+                            int(nsteps), _ptr(d), float(w_ke), float(w_var), _ptr(rs_),
+                            _ptr(nu_), _ptr(out))
     return st, out[0], out[1], out[2], out[3]
 
 

@@ -498,7 +498,9 @@ int step(const orc_params* P, const Consts& C, const T& nu, const T g[3], int n,
         if (val(ss) > 0.0) nut = cs2 * sqrt(2.0 * ss);
       }
       tr.nut[i] = nut;
-      T nui = nu_i ? T(nu_i[i]) : nu;
+      // with per-particle viscosities, the derivative part of nu (value
+      // unused) shifts every laminar viscosity alike
+      T nui = nu_i ? T(nu_i[i]) + (nu - T(val(nu))) : nu;
       mu[i] = rho_of(i) * (nui + nut);
     }
   }
@@ -773,7 +775,7 @@ int orc_step(const orc_params* P, int64_t n, const double* pos, const double* ve
 
 int orc_rollout_grad(const orc_params* P, int64_t n, const double* pos, const double* vel,
                      const int8_t* type, int32_t nsteps, const double* dir, double w_ke,
-                     double w_var, double* out) {
+                     double w_var, const double* rho_s, const double* nu_i, double* out) {
   /* Forward-mode derivative of the loss after nsteps steps along three
    * directions: d/dnu, d/dg_x and <d/du0, dir> (dual numbers through the
    * whole rollout, the PPE solves differentiated exactly). */
@@ -794,7 +796,7 @@ int orc_rollout_grad(const orc_params* P, int64_t n, const double* pos, const do
   Trace<D> tr;
   int st = 0;
   for (int s = 0; s < nsteps; ++s) {
-    st = step<D>(P, C, nu, g, (int)n, x, u, t, nullptr, tr);
+    st = step<D>(P, C, nu, g, (int)n, x, u, t, nullptr, tr, rho_s, nu_i);
     if (st == -3 || st == -6) return st;
   }
   D L = final_loss<D>((int)n, dim, x, u, t, tr.flags, w_ke, w_var);

@@ -86,10 +86,14 @@ int orc_pressure_gradient(const orc_params* P, int64_t n, const double* rs,
 
 /* Loss after nsteps (w_ke * mean fluid kinetic energy + w_var * variance of
  * the free-surface height) and its forward-mode derivatives along d/dnu,
- * d/dg_x and <d/du0, dir>: out[4] = {L, dL/dnu, dL/dgx, <dL/du0, dir>}. */
+ * d/dg_x and <d/du0, dir>: out[4] = {L, dL/dnu, dL/dgx, <dL/du0, dir>}.
+ * rho_s, nu_i (may be NULL): the two-phase model's smoothed densities and
+ * laminar viscosities; d/dnu is then the derivative with respect to a shift
+ * of every particle's laminar viscosity by the same amount. */
 int orc_rollout_grad(const orc_params* P, int64_t n, const double* pos,
                      const double* vel, const int8_t* type, int32_t nsteps,
-                     const double* dir, double w_ke, double w_var, double* out);
+                     const double* dir, double w_ke, double w_var, const double* rho_s,
+                     const double* nu_i, double* out);
 /* The same loss of a given final state and last-step flags. */
 double orc_loss(const orc_params* P, int64_t n, const double* pos,
                 const double* vel, const int8_t* type, const int8_t* flags,

@@ -461,3 +461,59 @@ def test_still_tank_hydrostatic_level(orc):
     print("still tank: slope/(rho g)", slope / 9810.0, "mean p/(rho g h)", ratio)
     assert 0.6 < slope / 9810.0 < 1.2
     assert 0.8 < ratio < 1.4
+
+
+def _loss_after(orc, prm, w, vel, nsteps, rho_s=None, nu_i=None):
+    st, pos, v, t, p, fl = orc.run(prm, w.pos, vel, w.ptype, nsteps, rho_s=rho_s, nu_i=nu_i)
+    assert st == 0
+    return orc.loss(prm, pos, v, t, fl)
+
+
+@pytest.mark.parametrize("case", ["wc", "ppe", "two_phase"])
+def test_dual_rollout_matches_central_differences(orc, case):
+    """The forward-mode (dual-number) derivatives of the rollout loss, the
+    reference the GPU adjoint is checked against, equal central differences
+    of the oracle's own FP64 rollout: d/dnu, d/dg_x and <d/du0, v>.  Without
+    the pressure clamp (its kinks would spoil the differences)."""
+    rho_s = nu_i = None
+    if case == "wc":
+        w = W.sloshing_2d(0.01, precision=W.FP64)
+        nsteps = 10
+    elif case == "ppe":
+        w = W.jitter(W.config("cfg1"), vel_sigma=0.02)
+        w.params["dt"] = 2e-4
+        nsteps = 6
+    else:
+        w, rho_i, nu_i = _two_phase_block(12)
+        st, rho_s = orc.smoothed_density(w.params, w.pos, w.ptype, rho_i)
+        w.params["smag_cs"] = 0.12
+        nsteps = 6
+    prm = dict(w.params, clamp=0, cg_tol=1e-13)
+    rng = np.random.default_rng(7)
+    d = rng.normal(size=w.pos.shape)
+    d[w.ptype != W.FLUID] = 0.0
+    st, L, g_nu, g_gx, g_u = orc.rollout_grad(prm, w.pos, w.vel, w.ptype, nsteps, d,
+                                              rho_s=rho_s, nu_i=nu_i)
+    assert st == 0
+    assert L == pytest.approx(_loss_after(orc, prm, w, w.vel, nsteps, rho_s, nu_i), rel=1e-12)
+    if nu_i is None:
+        h = 1e-3 * prm["nu"]
+        fp = _loss_after(orc, dict(prm, nu=prm["nu"] + h), w, w.vel, nsteps)
+        fm = _loss_after(orc, dict(prm, nu=prm["nu"] - h), w, w.vel, nsteps)
+    else:
+        h = 1e-3 * nu_i.min()
+        fp = _loss_after(orc, prm, w, w.vel, nsteps, rho_s, nu_i + h)
+        fm = _loss_after(orc, prm, w, w.vel, nsteps, rho_s, nu_i - h)
+    fd_nu = (fp - fm) / (2 * h)
+    hg = 1e-4
+    gp = list(prm["g"]); gp[0] += hg
+    gm = list(prm["g"]); gm[0] -= hg
+    fd_gx = (_loss_after(orc, dict(prm, g=gp), w, w.vel, nsteps, rho_s, nu_i)
+             - _loss_after(orc, dict(prm, g=gm), w, w.vel, nsteps, rho_s, nu_i)) / (2 * hg)
+    hu = 1e-6
+    fd_u = (_loss_after(orc, prm, w, w.vel + hu * d, nsteps, rho_s, nu_i)
+            - _loss_after(orc, prm, w, w.vel - hu * d, nsteps, rho_s, nu_i)) / (2 * hu)
+    print(case, "nu", g_nu, fd_nu, "gx", g_gx, fd_gx, "u0", g_u, fd_u)
+    assert g_nu == pytest.approx(fd_nu, rel=1e-4)
+    assert g_gx == pytest.approx(fd_gx, rel=1e-4)
+    assert g_u == pytest.approx(fd_u, rel=1e-4)
