@@ -170,6 +170,40 @@ def run_3d(name, w, steps, warmup):
     return res
 
 
+def run_adjoint(w, nsteps, K):
+    """A checkpointed adjoint rollout (forward mixed, adjoint FP64) with the
+    final-state loss, its time and the peak device memory: the library's
+    context (state, work arrays, tape of ceil(nsteps/K) + K slots) plus
+    torch's peak for the binding's tensors and the gradients."""
+    import torch
+
+    from paper_2105_01677_amd import adjoint as A
+    dim = w.params["dim"]
+    u0 = torch.tensor(w.vel, dtype=torch.float64, device="cuda", requires_grad=True)
+    nu = torch.tensor(0.0 if w.nu_i is not None else w.params["nu"], dtype=torch.float64,
+                      requires_grad=True)
+    g = torch.tensor(w.params["g"][:dim], dtype=torch.float64, requires_grad=True)
+    torch.cuda.synchronize()
+    torch.cuda.reset_peak_memory_stats()
+    t0 = time.perf_counter()
+    pos, vel, fl, ty = A.rollout(u0, nu, g, w.params, w.pos, w.ptype, nsteps, K,
+                                 rho_i=w.rho_i, nu_i=w.nu_i)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    L = A.final_loss(pos, vel, fl, ty)
+    L.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    tp = torch.cuda.max_memory_allocated()
+    res = {"steps": nsteps, "checkpoint_every": K, "forward_s": t1 - t0, "backward_s": t2 - t1,
+           "library_device_bytes": A.last_device_bytes, "torch_peak_bytes": tp,
+           "peak_device_bytes": A.last_device_bytes + tp, "loss": float(L.detach()),
+           "dL_dnu": float(nu.grad), "dL_dgx": float(g.grad[0]),
+           "grads_finite": bool(torch.isfinite(u0.grad).all())}
+    log("adjoint", res)
+    return res
+
+
 def cpu_baseline(w, seconds):
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
@@ -201,6 +235,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3-D configurations")
     ap.add_argument("--steps-3d", type=int, default=20)
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the 50-step adjoint of the 3-D two-phase case")
     ap.add_argument("--only-headline", action="store_true",
                     help="time the headline configuration only (for profilers)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -303,6 +339,9 @@ def main():
         w5 = W.config("cfg5", precision=W.MIXED)
         w5.params["cg_pipelined"] = 1
         cfg3d["two_phase_3d_l0=0.005"] = run_3d("two_phase_3d", w5, max(args.steps_3d // 2, 2), 1)
+        if not args.no_adjoint:
+            wa = W.config("cfg5", precision=W.MIXED)
+            cfg3d["two_phase_3d_l0=0.005"]["adjoint"] = run_adjoint(wa, 50, 50)
 
     out = {
         "metric": METRIC,

@@ -215,7 +215,12 @@ mps_status mps_constants(const mps_ctx* ctx, double* n0_n, double* n0_lap,
  * flags, the p-hat argmin and the clamp masks of each step are frozen.  In
  * the PPE model the adjoint of the pressure solve is the transposed solve
  * A lambda = x-bar, run with the same CG kernels (A is symmetric).  The
- * standard pressure gradient is supported (grad = MPS_GRAD_STD).
+ * standard pressure gradient is supported (grad = MPS_GRAD_STD), in the
+ * single-phase and in the two-phase + Smagorinsky model (then nu_bar is
+ * the derivative with respect to a common shift of the per-particle
+ * laminar viscosities, and the reverse of the eddy viscosity, of the
+ * harmonic-mean pair viscosities and of the per-particle densities is
+ * included; the smoothed densities are constants).
  * Typical use (checkpointing every K steps): save a slot every K steps in
  * the forward run; for each segment in reverse, load its checkpoint,
  * re-run the K steps saving each step's input state, then walk back with
@@ -226,8 +231,10 @@ mps_status mps_constants(const mps_ctx* ctx, double* n0_n, double* n0_lap,
  * previous tape.  Errors: MPS_E_ARG, MPS_E_NOMEM. */
 mps_status mps_tape_alloc(mps_ctx* ctx, int32_t nslots);
 
-/* Copy the current state into / from a slot (stream-ordered, no sync).
- * Errors: MPS_E_ARG (bad slot, or loading a slot never saved). */
+/* Copy the current state into / from a slot (stream-ordered, no sync); a
+ * load also restores the slot's particle order of the two-phase densities
+ * and viscosities.  Errors: MPS_E_ARG (bad slot, or loading a slot never
+ * saved). */
 mps_status mps_tape_save(mps_ctx* ctx, int32_t slot);
 mps_status mps_tape_load(mps_ctx* ctx, int32_t slot);
 
@@ -245,7 +252,9 @@ mps_status mps_step_adjoint(mps_ctx* ctx, const double* pos_bar, const double* v
 
 /* Per-kernel timing: when bit k of class_mask is set, every launch of
  * kernel class k (MPS_KC_*) is bracketed by a pair of HIP events on the
- * context's stream and its duration accumulated.  A profiling aid for
+ * context's stream and its duration accumulated (the CG kernels, launched
+ * one per scope, record the events from their own dispatch, so their time
+ * excludes launch gaps).  A profiling aid for
  * roofline measurements; a mask of 0 switches it off.  Resets the totals.
  * Errors: MPS_E_DEVICE if events cannot be created. */
 mps_status mps_profile(mps_ctx* ctx, uint32_t class_mask);

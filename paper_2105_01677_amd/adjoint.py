@@ -10,6 +10,10 @@ re-run saving each step's input state, and the steps are walked back with
 mps_step_adjoint.  Gradients flow to u0, nu and g; neighbour lists,
 free-surface flags, p-hat argmins and clamp masks of every step are frozen
 at their forward values.  Device memory: (ceil(nsteps/K) + K) state slots.
+
+Two-phase model (rho_i, nu_i given): the per-particle laminar viscosities
+are nu_i + nu, so the gradient with respect to nu is that of a common shift
+of all of them (pass nu = 0 for the derivative at nu_i).
 """
 from __future__ import annotations
 
@@ -20,16 +24,26 @@ import torch
 from . import mps as _mps
 from .workloads import FLUID
 
+# device memory of the last rollout's library context (state, work arrays
+# and tape), bytes
+last_device_bytes = 0
+
 
 class MPSRollout(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, u0, nu, g, params, pos0, ptype, nsteps, K):
+    def forward(ctx, u0, nu, g, params, pos0, ptype, nsteps, K, rho_i=None, nu_i=None):
+        global last_device_bytes
         dim = int(params["dim"])
         gl = [float(x) for x in g.detach().cpu().tolist()] + [0.0] * (3 - dim)
-        prm = dict(params, nu=float(nu), g=gl)
-        sim = _mps.MPS(prm, pos0, u0.detach(), ptype)
+        if nu_i is not None:
+            prm = dict(params, g=gl)
+            sim = _mps.MPS(prm, pos0, u0.detach(), ptype, rho_i=rho_i, nu_i=nu_i + float(nu))
+        else:
+            prm = dict(params, nu=float(nu), g=gl)
+            sim = _mps.MPS(prm, pos0, u0.detach(), ptype, rho_i=rho_i)
         nseg = math.ceil(nsteps / K)
         sim.tape_alloc(nseg + K)
+        last_device_bytes = sim.device_bytes()
         for s in range(nsteps):
             if s % K == 0:
                 sim.tape_save(s // K)
@@ -67,7 +81,7 @@ class MPSRollout(torch.autograd.Function):
         ctx.sim = None
         g_nu = torch.tensor(nub, dtype=torch.float64)
         g_g = torch.tensor(gb, dtype=torch.float64)
-        return ub, g_nu, g_g, None, None, None, None, None
+        return ub, g_nu, g_g, None, None, None, None, None, None, None
 
 
 def final_loss(pos, vel, flags, ptype, w_ke: float = 1.0, w_var: float = 9.81):
@@ -84,5 +98,5 @@ def final_loss(pos, vel, flags, ptype, w_ke: float = 1.0, w_var: float = 9.81):
     return w_ke * ke + w_var * var
 
 
-def rollout(u0, nu, g, params, pos0, ptype, nsteps, K=50):
-    return MPSRollout.apply(u0, nu, g, params, pos0, ptype, nsteps, K)
+def rollout(u0, nu, g, params, pos0, ptype, nsteps, K=50, rho_i=None, nu_i=None):
+    return MPSRollout.apply(u0, nu, g, params, pos0, ptype, nsteps, K, rho_i, nu_i)

@@ -9,6 +9,14 @@
 //   phat_i = p_{a(i)},  a(i) = argmin over i and its neighbours (frozen)
 //   G_i  = d/n0 sum_j (p_j - phat_i) h(r*_ij) (r*_j - r*_i),  h = w_n/r^2
 //   u'_i = u*_i - dt/rho G_i,   r'_i = r*_i - dt^2/rho G_i        (fluid)
+// Two-phase / turbulence model (the forward of Section "Multiphase flow" and
+// "Turbulent flow"): nu C S_i becomes C/<rho>_i sum_j (u_j - u_i) w mu_ij with
+// mu_ij = 2 mu_i mu_j/(mu_i + mu_j), mu_i = <rho>_i (nu_i + nu_t,i),
+// nu_t,i = (Cs l0)^2 sqrt(2 S:S) from the velocity gradient
+// V_i = d/n0 sum_j (u_j - u_i) (r_j - r_i)^T h(r) over re_n at r^k; the
+// couplings of A carry 2/(<rho>_i + <rho>_j) and the update 1/<rho>_i (both
+// constant).  Its reverse adds mu-bar (gathered with the viscous pairs),
+// V-bar = nu_t-bar d nu_t/dV and the gather of V-bar into u-bar and r-bar.
 // Every reverse sweep is written as a gather: particle k visits its own list
 // and collects both ends of each pair (list symmetry: j in L(i) <=> i in
 // L(j)), so there are no floating-point atomics and the result is
@@ -122,9 +130,10 @@ __global__ __launch_bounds__(BLOCK) void k_adj_update(View v, AdjView a) {
   load_vec<DIM>(a.vel_bar, i, ub);
   load_vec<DIM>(a.pos_bar, i, rb);
   const bool fl = v.type[i] == MPS_FLUID;
+  const double rho = v.rho_s ? v.rho_s[i] : v.rho;
 #pragma unroll
   for (int q = 0; q < DIM; ++q)
-    gb[q] = fl ? -(v.dt / v.rho) * ub[q] - (v.dt * v.dt / v.rho) * rb[q] : 0.0;
+    gb[q] = fl ? -(v.dt / rho) * ub[q] - (v.dt * v.dt / rho) * rb[q] : 0.0;
   store_vec<DIM>(a.gbar, i, gb);
   store_vec<DIM>(a.rs_bar, i, rb);
   store_vec<DIM>(a.ut, i, ub);  // u*-bar so far (r*-bar added later)
@@ -233,7 +242,7 @@ __global__ __launch_bounds__(BLOCK) void k_adj_route(View v, AdjView a, int wc) 
   if (wc) {
     double nb = 0.0;
     if (ty == MPS_FLUID || ty == MPS_WALL) {
-      const double B = v.rho * v.c0 * v.c0 / (double)v.gamma_i;
+      const double B = (v.rho_s ? v.rho_s[m] : v.rho) * v.c0 * v.c0 / (double)v.gamma_i;
       const double q = v.nstar[m] / v.n0_n;
       double qg1 = 1.0;
       for (int e = 0; e < v.gamma_i - 1; ++e) qg1 *= q;
@@ -282,7 +291,9 @@ __global__ __launch_bounds__(BLOCK) void k_adj_ppe(View v, AdjView a) {
       const double lj = ij ? a.lam[j] : 0.0;
       const double xj = ij ? v.p[j] : 0.0;
       const double cbar = -(lk - lj) * (xk - xj);
-      const double f = cbar * cpp * dw / r;
+      // two-phase: 1/rho -> 2/(<rho>_k + <rho>_j) (constant per pair)
+      const double cp = v.rho_s ? cpp * v.rho * 2.0 / (v.rho_s[k] + v.rho_s[j]) : cpp;
+      const double f = cbar * cp * dw / r;
 #pragma unroll
       for (int q = 0; q < DIM; ++q) rb[q] -= f * d[q];  // r*_k is the "i" end
     }
@@ -352,10 +363,11 @@ __global__ __launch_bounds__(BLOCK) void k_adj_predict_a(View v, AdjView a) {
     load_vec<DIM>(a.ut, k, ut);
     load_vec<DIM>(a.rs_bar, k, rsb);
     const bool fl = v.type[k] == MPS_FLUID;
+    const bool multi = v.rho_s != nullptr;
     double S[DIM];
 #pragma unroll
     for (int q = 0; q < DIM; ++q) S[q] = 0.0;
-    if (fl) {
+    if (fl && !multi) {
       double xk[DIM], uk[DIM];
       load_vec<DIM>(v.pos, k, xk);
       load_vec<DIM>(v.vel, k, uk);
@@ -379,7 +391,8 @@ __global__ __launch_bounds__(BLOCK) void k_adj_predict_a(View v, AdjView a) {
     for (int q = 0; q < DIM; ++q) {
       ut[q] = fl ? ut[q] + v.dt * rsb[q] : ut[q];
       const double ab = fl ? v.dt * ut[q] : 0.0;
-      sb[q] = v.nu * clap * ab;
+      // two-phase: the pair factor mu_kj is applied in (5b), nu-bar there
+      sb[q] = (multi ? clap / v.rho_s[k] : v.nu * clap) * ab;
       if (t == 0) {
         nub += ab * clap * S[q];
         gb[q] += ab;
@@ -411,6 +424,9 @@ __global__ __launch_bounds__(BLOCK) void k_adj_predict_a(View v, AdjView a) {
 //             + sum_{fluid i in L(k)} S-bar_i w_ik
 //   r-bar_k = r*-bar_k + [fluid] sum_j -(S-bar_k . (u_j - u_k)) w'/r (r_j - r_k)
 //             + sum_{fluid i} (S-bar_i . (u_k - u_i)) w'/r (r_k - r_i)
+// Two-phase: every pair term carries mu_kj, and
+//   mu-bar_k = sum_j w_kj dmu_kj/dmu_k ([fluid k] S-bar_k . (u_j - u_k)
+//                                      + [fluid j] S-bar_j . (u_k - u_j)).
 template <int DIM>
 __global__ __launch_bounds__(BLOCK) void k_adj_predict_b(View v, AdjView a) {
   const int64_t k = arow();
@@ -426,7 +442,9 @@ __global__ __launch_bounds__(BLOCK) void k_adj_predict_b(View v, AdjView a) {
     ub[q] = 0.0;
     rb[q] = 0.0;
   }
-  double wsum = 0.0;
+  double wsum = 0.0, mub = 0.0;
+  const bool multi = v.rho_s != nullptr;
+  const double mk = multi ? v.mu[k] : 0.0;
   if (v.type[k] != MPS_GHOST) {
     const int cnt = v.nb_count[k];
     for (int l = t; l < cnt; l += TEAM) {
@@ -439,12 +457,21 @@ __global__ __launch_bounds__(BLOCK) void k_adj_predict_b(View v, AdjView a) {
       const double r = sqrt(dot3<DIM>(d, d));
       double w, dw;
       wdw(v.kernel, r, v.re_lap, &w, &dw);
+      double mkj = 1.0, dmk = 0.0;
+      if (multi) {
+        const double mj = v.mu[j], ms = mk + mj;
+        mkj = ms > 0.0 ? 2.0 * mk * mj / ms : 0.0;
+        dmk = ms > 0.0 ? 2.0 * mj * mj / (ms * ms) : 0.0;
+      }
+      double pair = 0.0;  // S-bar . du of both ends, for mu-bar
       if (fk) {
-        wsum += w;
+        wsum += w * mkj;
         double du[DIM];
 #pragma unroll
         for (int q = 0; q < DIM; ++q) du[q] = uj[q] - uk[q];
-        const double f = -dot3<DIM>(sk, du) * dw / r;
+        const double sd = dot3<DIM>(sk, du);
+        pair += sd;
+        const double f = -sd * mkj * dw / r;
 #pragma unroll
         for (int q = 0; q < DIM; ++q) rb[q] += f * d[q];
       }
@@ -453,15 +480,19 @@ __global__ __launch_bounds__(BLOCK) void k_adj_predict_b(View v, AdjView a) {
         load_vec<DIM>(a.sbar, j, sj);
 #pragma unroll
         for (int q = 0; q < DIM; ++q) {
-          ub[q] += sj[q] * w;
+          ub[q] += sj[q] * w * mkj;
           du[q] = uk[q] - uj[q];
         }
-        const double f = dot3<DIM>(sj, du) * dw / r;
+        const double sd = dot3<DIM>(sj, du);
+        pair += sd;
+        const double f = sd * mkj * dw / r;
 #pragma unroll
         for (int q = 0; q < DIM; ++q) rb[q] -= f * d[q];  // (r_k - r_j) = -d
       }
+      mub += w * dmk * pair;
     }
     wsum = team_sum(wsum);
+    if (multi) mub = team_sum(mub);
 #pragma unroll
     for (int q = 0; q < DIM; ++q) {
       ub[q] = team_sum(ub[q]);
@@ -479,6 +510,186 @@ __global__ __launch_bounds__(BLOCK) void k_adj_predict_b(View v, AdjView a) {
     }
     store_vec<DIM>(a.vel_bar_in, k, ub);
     store_vec<DIM>(a.pos_bar_in, k, rb);
+    if (multi) a.mubar[k] = v.type[k] == MPS_GHOST ? 0.0 : mub;
+  }
+}
+
+// (6a, two-phase) nu_t-bar_k = <rho>_k mu-bar_k and, for a fluid particle
+// with S:S > 0, V-bar_k = nu_t-bar_k d nu_t/dV = nu_t-bar 2 (Cs l0)^2 cg S/sqrt(2 S:S)
+// with S = cg (V + V^T)/2, cg = d/n0, V recomputed in FP64 at r^k.  nu-bar
+// (a common shift of the laminar viscosities): partials of sum <rho>_k mu-bar_k.
+template <int DIM>
+__global__ __launch_bounds__(BLOCK) void k_adj_smag_a(View v, AdjView a) {
+  const int64_t k = arow();
+  const int t = team_lane();
+  double nub = 0.0;
+  if (k < v.n) {
+    const int8_t tk = v.type[k];
+    const double nutb = tk == MPS_GHOST ? 0.0 : v.rho_s[k] * a.mubar[k];
+    nub = t == 0 ? nutb : 0.0;
+    double G[DIM][DIM];
+#pragma unroll
+    for (int p = 0; p < DIM; ++p)
+#pragma unroll
+      for (int q = 0; q < DIM; ++q) G[p][q] = 0.0;
+    if (tk == MPS_FLUID && v.smag_c2 > 0.0) {
+      double xk[DIM], uk[DIM];
+      load_vec<DIM>(v.pos, k, xk);
+      load_vec<DIM>(v.vel, k, uk);
+      const int cnt = v.nb_count[k];
+      for (int l = t; l < cnt; l += TEAM) {
+        const int32_t j = v.nb_list[sl_index(k, l, v.kpad)];
+        double xj[DIM], uj[DIM], d[DIM];
+        load_vec<DIM>(v.pos, j, xj);
+        load_vec<DIM>(v.vel, j, uj);
+#pragma unroll
+        for (int q = 0; q < DIM; ++q) d[q] = xj[q] - xk[q];
+        const double r = sqrt(dot3<DIM>(d, d));
+        if (!(r < v.re_n)) continue;
+        double h, dh;
+        hdh(v.kernel, r, v.re_n, &h, &dh);
+#pragma unroll
+        for (int p = 0; p < DIM; ++p)
+#pragma unroll
+          for (int q = 0; q < DIM; ++q) G[p][q] += (uj[p] - uk[p]) * d[q] * h;
+      }
+#pragma unroll
+      for (int p = 0; p < DIM; ++p)
+#pragma unroll
+        for (int q = 0; q < DIM; ++q) G[p][q] = team_sum(G[p][q]);
+      const double cg = (double)DIM / v.n0_n;
+      double S[DIM][DIM], ss = 0.0;
+#pragma unroll
+      for (int p = 0; p < DIM; ++p)
+#pragma unroll
+        for (int q = 0; q < DIM; ++q) {
+          S[p][q] = 0.5 * (G[p][q] + G[q][p]) * cg;
+          ss += S[p][q] * S[p][q];
+        }
+      const double c = ss > 0.0 ? nutb * 2.0 * v.smag_c2 * cg / sqrt(2.0 * ss) : 0.0;
+#pragma unroll
+      for (int p = 0; p < DIM; ++p)
+#pragma unroll
+        for (int q = 0; q < DIM; ++q) G[p][q] = c * S[p][q];
+    }
+    if (t == 0) {
+#pragma unroll
+      for (int p = 0; p < DIM; ++p)
+#pragma unroll
+        for (int q = 0; q < DIM; ++q) a.gsm[k * 9 + p * DIM + q] = G[p][q];
+    }
+  }
+  // nu-bar partial of this workgroup, added to the one of (5a)
+  double x = nub;
+  __shared__ double sh[BLOCK / WAVE];
+  for (int o = WAVE / 2; o > 0; o >>= 1) x += __shfl_down(x, o, WAVE);
+  if ((threadIdx.x & (WAVE - 1)) == 0) sh[threadIdx.x / WAVE] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s2 = 0.0;
+    for (int w = 0; w < BLOCK / WAVE; ++w) s2 += sh[w];
+    a.part[(int64_t)xcd_block() * 4] += s2;
+  }
+}
+
+// (6b, two-phase) V-bar gathered into u-bar and r-bar.  Pair (i, j), fluid
+// i, r < re_n at r^k: V_i += (u_j - u_i) d^T h, d = r_j - r_i; with
+// y = V-bar_i^T (u_j - u_i): u-bar_j += V-bar_i d h, u-bar_i -= V-bar_i d h,
+// r-bar_j += y h + (d . y) h'/r d, r-bar_i -= the same.
+template <int DIM>
+__global__ __launch_bounds__(BLOCK) void k_adj_smag_b(View v, AdjView a) {
+  const int64_t k = arow();
+  const int t = team_lane();
+  if (k >= v.n) return;
+  if (v.type[k] == MPS_GHOST || v.smag_c2 <= 0.0) return;
+  const bool fk = v.type[k] == MPS_FLUID;
+  double xk[DIM], uk[DIM], Gk[DIM][DIM], ub[DIM], rb[DIM];
+  load_vec<DIM>(v.pos, k, xk);
+  load_vec<DIM>(v.vel, k, uk);
+#pragma unroll
+  for (int p = 0; p < DIM; ++p) {
+    ub[p] = 0.0;
+    rb[p] = 0.0;
+#pragma unroll
+    for (int q = 0; q < DIM; ++q) Gk[p][q] = a.gsm[k * 9 + p * DIM + q];
+  }
+  const int cnt = v.nb_count[k];
+  for (int l = t; l < cnt; l += TEAM) {
+    const int32_t j = v.nb_list[sl_index(k, l, v.kpad)];
+    double xj[DIM], uj[DIM], d[DIM];
+    load_vec<DIM>(v.pos, j, xj);
+    load_vec<DIM>(v.vel, j, uj);
+#pragma unroll
+    for (int q = 0; q < DIM; ++q) d[q] = xj[q] - xk[q];  // r_j - r_k
+    const double r = sqrt(dot3<DIM>(d, d));
+    if (!(r < v.re_n)) continue;
+    double h, dh;
+    hdh(v.kernel, r, v.re_n, &h, &dh);
+    if (fk) {
+      // k is the owner i of pair (k, j)
+      double y[DIM], gd[DIM];
+#pragma unroll
+      for (int q = 0; q < DIM; ++q) {
+        y[q] = 0.0;
+        gd[q] = 0.0;
+      }
+#pragma unroll
+      for (int p = 0; p < DIM; ++p)
+#pragma unroll
+        for (int q = 0; q < DIM; ++q) {
+          y[q] += Gk[p][q] * (uj[p] - uk[p]);
+          gd[p] += Gk[p][q] * d[q];
+        }
+      const double yd = dot3<DIM>(y, d);
+#pragma unroll
+      for (int q = 0; q < DIM; ++q) {
+        ub[q] -= gd[q] * h;
+        rb[q] -= y[q] * h + yd * dh / r * d[q];
+      }
+    }
+    if (v.type[j] == MPS_FLUID) {
+      // k is the neighbour in pair (j, k): e = r_k - r_j = -d
+      double Gj[DIM][DIM], y[DIM], ge[DIM];
+#pragma unroll
+      for (int p = 0; p < DIM; ++p)
+#pragma unroll
+        for (int q = 0; q < DIM; ++q) Gj[p][q] = a.gsm[(int64_t)j * 9 + p * DIM + q];
+#pragma unroll
+      for (int q = 0; q < DIM; ++q) {
+        y[q] = 0.0;
+        ge[q] = 0.0;
+      }
+#pragma unroll
+      for (int p = 0; p < DIM; ++p)
+#pragma unroll
+        for (int q = 0; q < DIM; ++q) {
+          y[q] += Gj[p][q] * (uk[p] - uj[p]);
+          ge[p] -= Gj[p][q] * d[q];
+        }
+      const double ye = -dot3<DIM>(y, d);
+#pragma unroll
+      for (int q = 0; q < DIM; ++q) {
+        ub[q] += ge[q] * h;
+        rb[q] += y[q] * h - ye * dh / r * d[q];
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < DIM; ++q) {
+    ub[q] = team_sum(ub[q]);
+    rb[q] = team_sum(rb[q]);
+  }
+  if (t == 0) {
+    double u0[DIM], r0[DIM];
+    load_vec<DIM>(a.vel_bar_in, k, u0);
+    load_vec<DIM>(a.pos_bar_in, k, r0);
+#pragma unroll
+    for (int q = 0; q < DIM; ++q) {
+      u0[q] += ub[q];
+      r0[q] += rb[q];
+    }
+    store_vec<DIM>(a.vel_bar_in, k, u0);
+    store_vec<DIM>(a.pos_bar_in, k, r0);
   }
 }
 
@@ -516,14 +727,23 @@ int launch_adjoint_ppe(const View& v, const AdjView& a, int dim, hipStream_t s) 
 
 int launch_adjoint_tail(const View& v, const AdjView& a, int dim, hipStream_t s) {
   const unsigned nt = tb(v.n);
+  const bool multi = v.rho_s != nullptr;
   if (dim == 2) {
     k_adj_density<2><<<nt, BLOCK, 0, s>>>(v, a);
     k_adj_predict_a<2><<<nt, BLOCK, 0, s>>>(v, a);
     k_adj_predict_b<2><<<nt, BLOCK, 0, s>>>(v, a);
+    if (multi) {
+      k_adj_smag_a<2><<<nt, BLOCK, 0, s>>>(v, a);
+      k_adj_smag_b<2><<<nt, BLOCK, 0, s>>>(v, a);
+    }
   } else {
     k_adj_density<3><<<nt, BLOCK, 0, s>>>(v, a);
     k_adj_predict_a<3><<<nt, BLOCK, 0, s>>>(v, a);
     k_adj_predict_b<3><<<nt, BLOCK, 0, s>>>(v, a);
+    if (multi) {
+      k_adj_smag_a<3><<<nt, BLOCK, 0, s>>>(v, a);
+      k_adj_smag_b<3><<<nt, BLOCK, 0, s>>>(v, a);
+    }
   }
   return 0;
 }

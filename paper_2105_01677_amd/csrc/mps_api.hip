@@ -58,6 +58,8 @@ struct mps_ctx {
   bool multi = false;
   double* rho_s[2] = {nullptr, nullptr};
   double* nu_l[2] = {nullptr, nullptr};
+  double* rho_o = nullptr;  // <rho> and nu in the caller's order (tape reloads)
+  double* nu_o = nullptr;
   double* nut = nullptr;
   double* mu = nullptr;
   double* partA = nullptr;
@@ -658,7 +660,8 @@ void free_tape(mps_ctx* c) {
   c->ntape = 0;
   AdjView& a = c->adj;
   void* as[] = {(void*)a.pos_bar, (void*)a.vel_bar, a.gbar, a.phat_bar, a.pbar, a.nbar,
-                a.rs_bar, a.ut, a.sbar, a.pos_bar_in, a.vel_bar_in, a.arg, a.lam, a.part};
+                a.rs_bar, a.ut, a.sbar, a.pos_bar_in, a.vel_bar_in, a.arg, a.lam, a.part,
+                a.mubar, a.gsm};
   for (void* q : as)
     if (q) (void)hipFree(q);
   c->adj = AdjView{};
@@ -737,6 +740,8 @@ mps_status mps_init(const mps_params* params, int64_t n, const double* pos, cons
       A(dalloc(&c->nu_l[k], n));
     }
     A(dalloc(&c->nut, n));
+    A(dalloc(&c->rho_o, n));
+    A(dalloc(&c->nu_o, n));
     A(dalloc(&c->mu, n));
   }
   c->nspmv = cg_spmv_blocks(n);
@@ -792,6 +797,8 @@ mps_status mps_init(const mps_params* params, int64_t n, const double* pos, cons
     launch_smooth_density(w, c->rho_s[c->cur], c->rho_s[c->cur ^ 1], c->dim, s);
     A(hipMemcpyAsync(c->rho_s[c->cur], c->rho_s[c->cur ^ 1], n * sizeof(double),
                      hipMemcpyDeviceToDevice, s));
+    launch_scatter_orig(w, c->rho_s[c->cur], c->rho_o, 1, 1, s);
+    launch_scatter_orig(w, c->nu_l[c->cur], c->nu_o, 1, 1, s);
   }
   A(hipGetLastError());
   A(hipStreamSynchronize(s));
@@ -823,6 +830,7 @@ mps_status mps_free(mps_ctx* c) {
                   c->nb_list, c->a_nnz, c->a_col, c->a_val, c->diag, c->b, c->r, c->z,
                   c->q, c->p_save, c->partA, c->partB, c->sc, c->status, c->counts,
                   c->rho_s[0], c->rho_s[1], c->nu_l[0], c->nu_l[1], c->nut, c->mu,
+                  c->rho_o, c->nu_o,
                   c->pl_z, c->pl_s, c->pl_m[0], c->pl_m[1], c->pl_part[0], c->pl_part[1]};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -1071,6 +1079,10 @@ mps_status mps_tape_alloc(mps_ctx* c, int32_t nslots) {
   A(dalloc(&a.lam, n));
   const int nb = adj_partial_blocks(n);
   A(dalloc(&a.part, (size_t)nb * 4));
+  if (c->multi) {
+    A(dalloc(&a.mubar, n));
+    A(dalloc(&a.gsm, (size_t)n * 9));
+  }
   g_bytes = nullptr;
   (void)before;
   if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_part, (size_t)nb * 4 * sizeof(double), hipHostMallocDefault);
@@ -1108,6 +1120,12 @@ mps_status mps_tape_load(mps_ctx* c, int32_t slot) {
   HIPCHK(c, hipMemcpyAsync(c->pres[a], t.p, n * sizeof(double), hipMemcpyDeviceToDevice, c->s));
   HIPCHK(c, hipMemcpyAsync(c->type[a], t.type, n, hipMemcpyDeviceToDevice, c->s));
   HIPCHK(c, hipMemcpyAsync(c->id[a], t.id, n * sizeof(int32_t), hipMemcpyDeviceToDevice, c->s));
+  if (c->multi) {
+    // the per-particle phase data follow the slot's particle order
+    View v = make_view(c);
+    launch_gather_orig(v, c->rho_o, c->rho_s[a], 1, 1, c->s);
+    launch_gather_orig(v, c->nu_o, c->nu_l[a], 1, 1, c->s);
+  }
   c->ppe_valid = false;
   return MPS_OK;
 }
@@ -1118,7 +1136,6 @@ mps_status mps_step_adjoint(mps_ctx* c, const double* pos_bar, const double* vel
   if (!c || !pos_bar || !vel_bar || !pos_bar_prev || !vel_bar_prev) return MPS_E_ARG;
   if (!c->tape) return fail(c, MPS_E_ARG, "call mps_tape_alloc first");
   if (c->P.grad != MPS_GRAD_STD) return fail(c, MPS_E_ARG, "adjoint needs the standard gradient");
-  if (c->multi) return fail(c, MPS_E_ARG, "adjoint of the two-phase / turbulence model not built");
   if (c->poisoned) return fail(c, MPS_E_POISONED, "context poisoned; call mps_set_state");
   const bool wc = c->P.pmode == MPS_WC_EOS;
   // forward recompute of the step's stages from the current (taped) state

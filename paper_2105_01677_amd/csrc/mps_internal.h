@@ -186,6 +186,9 @@ struct AdjView {
   int32_t* arg;            // p-hat argmin (sorted index)
   double* lam;             // PPE adjoint solution (lambda)
   double* part;            // [blocks][4]: nu-bar, g-bar
+  // two-phase / turbulence (null when single phase)
+  double* mubar;           // mu-bar [n]
+  double* gsm;             // velocity-gradient bar of the Smagorinsky term [n][9]
 };
 
 // Packed cell coordinates: 10 bits per axis (x lowest); GHOST_CELL marks a
