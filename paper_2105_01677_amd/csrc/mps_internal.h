@@ -241,20 +241,69 @@ __device__ inline int xcd_block() {
 // Team helpers: lanes of one team are contiguous (lane = row * TEAM + t).
 __device__ inline int team_lane() { return threadIdx.x & (TEAM - 1); }
 
+// Cross-lane moves through DPP (a source modifier of a VALU move: no LDS
+// round trip, unlike a shuffle).  Lane-pattern controls of the GCN/CDNA DPP
+// encoding used here: quad_perm [1,0,3,2] (lane ^ 1) = 0xB1, quad_perm
+// [2,3,0,1] (lane ^ 2) = 0x4E, row_half_mirror (lane l <-> 7 - l within
+// each 8 lanes) = 0x141, row_mirror (l <-> 15 - l within each 16) = 0x140.
+// The source lanes of these patterns must be active.
+constexpr int DPP_XOR1 = 0xB1, DPP_XOR2 = 0x4E, DPP_HALF_MIRROR = 0x141, DPP_MIRROR = 0x140;
+
+template <int CTRL>
+__device__ inline uint32_t dpp_u32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL, class T>
+__device__ inline T dpp_move(T v) {
+  static_assert(sizeof(T) == 4 || sizeof(T) == 8, "4- or 8-byte lanes");
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, dpp_u32<CTRL>(__builtin_bit_cast(uint32_t, v)));
+  } else {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint64_t lo = dpp_u32<CTRL>((uint32_t)b), hi = dpp_u32<CTRL>((uint32_t)(b >> 32));
+    return __builtin_bit_cast(T, lo | (hi << 32));
+  }
+}
+template <class T>
+__device__ inline T read_lane(T v, int lane) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+  } else {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint64_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, lane);
+    const uint64_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), lane);
+    return __builtin_bit_cast(T, lo | (hi << 32));
+  }
+}
+
+// Sum over the 8 lanes of the team, valid in every lane of it: the
+// butterfly ((l0 + l1) + (l2 + l3)) + ((l4 + l5) + (l6 + l7)), the same bits
+// in all lanes (IEEE addition is commutative).
 template <class T>
 __device__ inline T team_sum(T v) {
-#pragma unroll
-  for (int o = 1; o < TEAM; o <<= 1) v += __shfl_xor(v, o, TEAM);
+  v += dpp_move<DPP_XOR1>(v);
+  v += dpp_move<DPP_XOR2>(v);
+  v += dpp_move<DPP_HALF_MIRROR>(v);
   return v;
 }
 template <class T>
 __device__ inline T team_min(T v) {
-#pragma unroll
-  for (int o = 1; o < TEAM; o <<= 1) {
-    T w = __shfl_xor(v, o, TEAM);
-    v = w < v ? w : v;
-  }
+  T w = dpp_move<DPP_XOR1>(v);
+  v = w < v ? w : v;
+  w = dpp_move<DPP_XOR2>(v);
+  v = w < v ? w : v;
+  w = dpp_move<DPP_HALF_MIRROR>(v);
+  v = w < v ? w : v;
   return v;
+}
+// Sum over the wavefront in a fixed order (team sums, pairs of teams, then
+// the four 16-lane rows ((r0 + r1) + (r2 + r3))), uniform result.  All 64
+// lanes must be active.
+template <class T>
+__device__ inline T wave_sum(T v) {
+  v = team_sum(v);
+  v += dpp_move<DPP_MIRROR>(v);
+  return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
 }
 // Bit mask of the team's lanes for which pred holds (bit t = lane t).
 __device__ inline uint32_t team_ballot(bool pred) {

@@ -74,30 +74,36 @@ struct PosRefP<DIM, true> {
   }
 };
 
-// Sum over the workgroup (NT threads) in a fixed tree; result valid in
-// thread 0.
-template <int NV, int NT = BLOCK>
-__device__ inline void block_sum(double (&x)[NV]) {
-  __shared__ double sh[NV][NT / WAVE];
-#pragma unroll
-  for (int k = 0; k < NV; ++k) {
-#pragma unroll
-    for (int o = WAVE / 2; o > 0; o >>= 1) x[k] += __shfl_down(x[k], o, WAVE);
-  }
+// Sum over the workgroup (NT threads) in a fixed order, valid in every
+// thread: wavefront sums, then the NT / WAVE of them in order.  sh holds
+// NV * NT / WAVE doubles; it is read after the barrier, so a second use of
+// the same sh needs a barrier first.
+template <int NV, int NT>
+__device__ inline void block_sum_all(double (&x)[NV], double* sh) {
+  constexpr int NW = NT / WAVE;
   const int w = threadIdx.x / WAVE;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) x[k] = wave_sum(x[k]);
   if ((threadIdx.x & (WAVE - 1)) == 0) {
 #pragma unroll
-    for (int k = 0; k < NV; ++k) sh[k][w] = x[k];
+    for (int k = 0; k < NV; ++k) sh[k * NW + w] = x[k];
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
 #pragma unroll
-    for (int k = 0; k < NV; ++k) {
-      double s = 0.0;
-      for (int q = 0; q < NT / WAVE; ++q) s += sh[k][q];
-      x[k] = s;
-    }
+  for (int k = 0; k < NV; ++k) {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) s += sh[k * NW + q];
+    x[k] = s;
   }
+}
+
+// The same with a buffer of its own and a closing barrier (may be called
+// again in the same kernel); result valid in every thread.
+template <int NV, int NT = BLOCK>
+__device__ inline void block_sum(double (&x)[NV]) {
+  __shared__ double sh[NV * (NT / WAVE)];
+  block_sum_all<NV, NT>(x, sh);
   __syncthreads();
 }
 
@@ -400,17 +406,41 @@ __device__ inline void reduce_partials(const double* part, int np, double (&tot)
       s[2] += q[k].z;
     }
   }
-  __shared__ double bc[3];
-  block_sum<3, NT>(s);
-  if (threadIdx.x == 0) {
-    bc[0] = s[0];
-    bc[1] = s[1];
-    bc[2] = s[2];
+  __shared__ double sh[3 * (NT / WAVE)];
+  block_sum_all<3, NT>(s, sh);
+  tot[0] = s[0];
+  tot[1] = s[1];
+  tot[2] = s[2];
+}
+
+// The same for np <= K * NT in two phases, so that the loads can be issued
+// before other work: load_partials (clamped index, no branch), then
+// sum_partials_loaded.
+template <int NT, int K>
+__device__ inline void load_partials(const double* part, int np, double4 (&q)[K]) {
+  const double4* p4 = reinterpret_cast<const double4*>(part);
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int b = threadIdx.x + k * NT;
+    q[k] = p4[b < np ? b : 0];
   }
-  __syncthreads();
-  tot[0] = bc[0];
-  tot[1] = bc[1];
-  tot[2] = bc[2];
+}
+template <int NT, int K>
+__device__ inline void sum_partials_loaded(const double4 (&q)[K], int np, double (&tot)[3],
+                                           double* sh) {
+  double s[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    if (threadIdx.x + k * NT < np) {
+      s[0] += q[k].x;
+      s[1] += q[k].y;
+      s[2] += q[k].z;
+    }
+  }
+  block_sum_all<3, NT>(s, sh);
+  tot[0] = s[0];
+  tot[1] = s[1];
+  tot[2] = s[2];
 }
 
 // Start of the solve from the assembly partials: (r0, r0), (b, b), the
@@ -526,13 +556,19 @@ template <class VT, int PAR, bool FUSED>
 __global__ __launch_bounds__(pcg_nt<FUSED>()) void k_pcg_iter(View v) {
   constexpr int U = CG_UNROLL;
   constexpr int NT = pcg_nt<FUSED>();
+  static_assert(PCG_PK * PCG_BLOCK >= PCG_MAX_BLOCKS, "one partial load per slot");
+  __shared__ double sh_in[3 * (NT / WAVE)], sh_out[3 * (NT / WAVE)];
   CGScalars* sc = v.sc;
   const int t = team_lane();
+
+  // -- loads that do not need this iteration's scalars, all issued before
+  //    the first wait: the previous partials, the row length, the first U
+  //    entries per lane, the row's own vectors (every lane: clamped row) --
+  double4 q[PCG_PK];
+  if constexpr (FUSED) load_partials<NT, PCG_PK>(v.pl_part[PAR], v.npcg, q);
   const double* __restrict__ M = v.pl_m[PAR];
   double* __restrict__ Mn = v.pl_m[PAR ^ 1];
   const VT* __restrict__ aval = reinterpret_cast<const VT*>(v.a_val);
-
-  // -- loads that do not need this iteration's scalars --
   const int conv = sc->converged;
   double gam_old = 0.0, alp_old = 0.0, bb = 0.0, alpha = 0.0, beta = 0.0;
   if constexpr (FUSED) {
@@ -545,75 +581,75 @@ __global__ __launch_bounds__(pcg_nt<FUSED>()) void k_pcg_iter(View v) {
   }
   const int64_t row = (int64_t)xcd_block() * (NT / TEAM) + threadIdx.x / TEAM;
   const bool live = row < v.n;
-  int nnz = 0;
+  const int64_t rc = live ? row : v.n - 1;
+  const int64_t e0 = sl_index(rc, t, v.kpad);
+  int nnz = v.a_nnz[rc];
   int32_t jj[U];
   VT aa[U];
-  double own[7];  // D, m, z, s, p, r, x of the row (team lane 0)
-  {
-    const int64_t e0 = sl_index(row, t, v.kpad);
-    if (live) nnz = v.a_nnz[row];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      // u * TEAM < kpad is uniform over the team (kpad is a multiple of
-      // TEAM); slots past the row length hold stale data and are masked
-      const bool ok = live && u * TEAM < v.kpad;
-      jj[u] = ok ? v.a_col[e0 + u * WAVE] : 0;
-      aa[u] = ok ? aval[e0 + u * WAVE] : VT(0);
-    }
-    if (live && t == 0) {
-      own[0] = v.diag[row]; own[1] = M[row]; own[2] = v.pl_z[row]; own[3] = v.pl_s[row];
-      own[4] = v.pd[0][row]; own[5] = v.r[row]; own[6] = v.p[row];
-    }
+  for (int u = 0; u < U; ++u) {
+    // slot u of the row exists (kpad is uniform); stale slots past the row
+    // length are masked below
+    const int64_t e = u * TEAM < v.kpad ? e0 + u * WAVE : e0;
+    jj[u] = v.a_col[e];
+    aa[u] = aval[e];
   }
+  const double o_d = v.diag[rc], o_m = M[rc], o_z = v.pl_z[rc], o_s = v.pl_s[rc],
+               o_p = v.pd[0][rc], o_r = v.r[rc], o_x = v.p[rc];
+  // every load above is issued before any of them is waited for: without
+  // this fence the compiler sinks slot loads behind the wait for the row
+  // length, or consumes the partials before issuing the rest (one more
+  // memory latency in the chain either way)
+#pragma unroll
+  for (int u = 0; u < U; ++u) asm volatile("" : "+v"(jj[u]), "+v"(aa[u])::"memory");
+  if (!live) nnz = 0;
   double xv[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    const bool in = live && t + u * TEAM < nnz;
-    xv[u] = in ? M[jj[u]] : 0.0;
-    if (!in) aa[u] = VT(0);
+    const bool in = t + u * TEAM < nnz;
+    xv[u] = M[in ? jj[u] : (int32_t)rc];
+    if (!in) {
+      xv[u] = 0.0;
+      aa[u] = VT(0);
+    }
   }
 
   // -- the scalars --
   if constexpr (FUSED) {
     double tot[3];
-    reduce_partials<NT, PCG_PK>(v.pl_part[PAR], v.npcg, tot);
+    sum_partials_loaded<NT, PCG_PK>(q, v.npcg, tot, sh_in);
     if (conv) return;
     if (pcg_scalars(v, tot, PAR, gam_old, alp_old, bb, blockIdx.x == 0, alpha, beta)) return;
   } else {
     if (conv) return;
   }
 
-  double g2 = 0.0, d2 = 0.0, r2 = 0.0;
-  if (live) {
-    double s = 0.0;
+  double s = 0.0;
 #pragma unroll
-    for (int u = 0; u < U; ++u) s += (double)aa[u] * xv[u];
-    // entries beyond the first U per lane
-    s += row_dot<4>(v.a_col, aval, row, nnz, v.kpad, t + U * TEAM,
-                    [&](int32_t j) { return M[j]; });
-    s = team_sum(s);
-    if (t == 0) {
-      const double dg = own[0], m = own[1];
-      const double w = dg * m;
-      const double z = (w + s) + beta * own[2];
-      const double sv = w + beta * own[3];
-      const double pv = own[5] / dg + beta * own[4];
-      const double r = own[5] - alpha * sv;
-      const double wn = w - alpha * z;
-      const double un = r / dg;
-      v.p[row] = own[6] + alpha * pv;
-      v.pl_z[row] = z;
-      v.pl_s[row] = sv;
-      v.pd[0][row] = pv;
-      v.r[row] = r;
-      Mn[row] = wn / dg;
-      g2 = r * un;
-      d2 = wn * un;
-      r2 = r * r;
-    }
+  for (int u = 0; u < U; ++u) s += (double)aa[u] * xv[u];
+  // entries beyond the first U per lane
+  s += row_dot<4>(v.a_col, aval, rc, nnz, v.kpad, t + U * TEAM,
+                  [&](int32_t j) { return M[j]; });
+  s = team_sum(s);
+  const double w = o_d * o_m;
+  const double z = (w + s) + beta * o_z;
+  const double sv = w + beta * o_s;
+  const double pv = o_r / o_d + beta * o_p;
+  const double r = o_r - alpha * sv;
+  const double wn = w - alpha * z;
+  const double un = r / o_d;
+  const bool lead = live && t == 0;
+  double x[3] = {lead ? r * un : 0.0, lead ? wn * un : 0.0, lead ? r * r : 0.0};
+  // the reduction before the stores: its barrier then waits for no store
+  block_sum_all<3, NT>(x, sh_out);
+  if (lead) {
+    v.p[row] = o_x + alpha * pv;
+    v.pl_z[row] = z;
+    v.pl_s[row] = sv;
+    v.pd[0][row] = pv;
+    v.r[row] = r;
+    Mn[row] = wn / o_d;
   }
-  double x[3] = {g2, d2, r2};
-  block_sum<3, NT>(x);
   if (threadIdx.x == 0) {
     const int lb = xcd_block();
 #pragma unroll
