@@ -89,8 +89,11 @@ constexpr int CG_UPD_BLOCKS = 1024;
 #define PCG_SPLIT_BLOCK 256
 #endif
 constexpr int RED_BLOCK = 1024;  // the one workgroup of a CG reduction kernel
+// Matrix entries per lane loaded ahead of the reduction in the pipelined
+// CG iteration (6 x 8 lanes cover a 2-D row: at most 44 inner neighbours on
+// a lattice at re = 4 l0)
 #ifndef CG_UNROLL
-#define CG_UNROLL 4
+#define CG_UNROLL 6
 #endif
 
 // Everything a kernel may touch, passed by value.

@@ -146,7 +146,7 @@ struct Chunk {
 // x0 = warm start (previous pressure) or 0, r0 = b - A x0, z0 = r0/diag,
 // p_old = 0 so that the first SpMV forms p = z0.  Per-workgroup partials of
 // (r0, z0), (r0, r0), (b, b) go to partA.
-template <int DIM, bool MIXED>
+template <int DIM, bool MIXED, bool MULTI>
 __global__ __launch_bounds__(BLOCK) void k_assemble(View v, const double* rhs, int zero_x0) {
   using P = PosRefP<DIM, MIXED>;
   using R = typename P::R;
@@ -155,50 +155,73 @@ __global__ __launch_bounds__(BLOCK) void k_assemble(View v, const double* rhs, i
   double rz = 0.0, rr = 0.0, bb = 0.0;
   VT* aval = reinterpret_cast<VT*>(v.a_val);
   const Chunk ch(v.n);
+  const int ng = v.kpad / TEAM;  // slot groups of a row
   for (int64_t g = ch.g0; g < ch.g1; ++g) {
     const int64_t row = g * ROWS_PER_BLOCK + threadIdx.x / TEAM;
     if (row >= v.n) continue;
+    // the row's own loads and its first list entries are issued together
+    // (no branch before the list)
     const bool inner = v.flags[row] == MPS_FLAG_INNER;
+    const int cnt_all = v.nb_count[row];
+    const P pi = P::load(v, row);
+    const double rho_i = MULTI ? v.rho_s[row] : 0.0;
+    const double p_row = v.p[row], ns_row = v.nstar[row];
+    const double rhs_row = rhs ? rhs[row] : 0.0;
+    const int cnt = inner ? cnt_all : 0;
     double dsum = 0.0, ax = 0.0;
     int nnz = 0;
-    if (inner) {
-      const P pi = P::load(v, row);
+    {
       const R re = (R)v.re_lap, re2 = (R)v.re_lap2;
       const R cpp = (R)(2.0 * DIM / (v.lam_lap * v.n0_lap * v.rho));
-      const int cnt = v.nb_count[row];
-      // ASM_UNROLL list entries per lane and step (loads and gathers of a
-      // step in flight together, then the ballots in list order); one per
-      // step measured fastest on MI355X
+      // ASM_UNROLL list entries per lane and step: the gathers of a step in
+      // flight together while the next step's list entries load (slot
+      // indices past kpad clamped to the row's first slot), then the
+      // ballots in list order
       constexpr int U = ASM_UNROLL;
-      for (int l0 = 0; l0 < cnt; l0 += U * TEAM) {
+      const int64_t e0 = sl_index(row, t, v.kpad);
+      int32_t jn[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) jn[u] = v.nb_list[e0 + (int64_t)(u < ng ? u : 0) * WAVE];
+      for (int k0 = 0; k0 * TEAM < cnt; k0 += U) {
         int32_t j[U];
         bool ok[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          const int lb = l0 + u * TEAM;  // uniform over the team
-          j[u] = lb < v.kpad ? v.nb_list[sl_index(row, lb + t, v.kpad)] : 0;
-          ok[u] = lb + t < cnt;
-          if (!ok[u]) j[u] = (int32_t)row;
+          ok[u] = t + (k0 + u) * TEAM < cnt;
+          j[u] = ok[u] ? jn[u] : (int32_t)row;
+        }
+        int8_t fj[U];
+        P pj_pos[U];
+        double pj[U], rhoj[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          fj[u] = v.flags[j[u]];
+          pj_pos[u] = P::load(v, j[u]);
+          pj[u] = v.p[j[u]];
+          rhoj[u] = MULTI ? v.rho_s[j[u]] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int k = k0 + U + u;
+          jn[u] = v.nb_list[e0 + (int64_t)(k < ng ? k : 0) * WAVE];
         }
         R c[U];
         bool keep[U];
-        double pj[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           // this step's flags mark exactly the dummy particles MPS_FLAG_DUMMY
-          const int8_t fj = v.flags[j[u]];
           R d[DIM];
-          pi.diff(P::load(v, j[u]), v.cs32, d);
+          pi.diff(pj_pos[u], v.cs32, d);
           R r2 = d[0] * d[0] + d[1] * d[1];
           if constexpr (DIM == 3) r2 += d[2] * d[2];
-          pj[u] = zero_x0 ? 0.0 : v.p[j[u]];
-          const bool in = ok[u] && fj != MPS_FLAG_DUMMY && r2 < re2;
+          if (zero_x0) pj[u] = 0.0;
+          const bool in = ok[u] && fj[u] != MPS_FLAG_DUMMY && r2 < re2;
           R cr = cpp * weight<R>(v.kernel, sqrt(r2), re);
           // two-phase: 1/rho -> 2/(<rho>_i + <rho>_j), symmetric
-          if (v.rho_s) cr *= (R)(v.rho * 2.0 / (v.rho_s[row] + v.rho_s[j[u]]));
+          if constexpr (MULTI) cr *= (R)(v.rho * 2.0 / (rho_i + rhoj[u]));
           c[u] = in ? cr : R(0);
           dsum += (double)c[u];
-          keep[u] = in && fj == MPS_FLAG_INNER;
+          keep[u] = in && fj[u] == MPS_FLAG_INNER;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -220,8 +243,8 @@ __global__ __launch_bounds__(BLOCK) void k_assemble(View v, const double* rhs, i
       double diag = 1.0, b = 0.0, x0 = 0.0;
       if (inner) {
         diag = dsum + v.alpha / (v.dt * v.dt);
-        b = rhs ? rhs[row] : (v.nstar[row] - v.n0_n) / (v.n0_n * v.dt * v.dt);
-        x0 = zero_x0 ? 0.0 : v.p[row];
+        b = rhs ? rhs_row : (ns_row - v.n0_n) / (v.n0_n * v.dt * v.dt);
+        x0 = zero_x0 ? 0.0 : p_row;
       }
       const double r0 = b - diag * x0 - ax;
       const double z0 = r0 / diag;
@@ -627,7 +650,8 @@ __global__ __launch_bounds__(pcg_nt<FUSED>()) void k_pcg_iter(View v) {
   double s = 0.0;
 #pragma unroll
   for (int u = 0; u < U; ++u) s += (double)aa[u] * xv[u];
-  // entries beyond the first U per lane
+  // entries beyond the first U per lane (measured: cheaper here than
+  // before the reduction)
   s += row_dot<4>(v.a_col, aval, rc, nnz, v.kpad, t + U * TEAM,
                   [&](int32_t j) { return M[j]; });
   s = team_sum(s);
@@ -639,9 +663,8 @@ __global__ __launch_bounds__(pcg_nt<FUSED>()) void k_pcg_iter(View v) {
   const double wn = w - alpha * z;
   const double un = r / o_d;
   const bool lead = live && t == 0;
-  double x[3] = {lead ? r * un : 0.0, lead ? wn * un : 0.0, lead ? r * r : 0.0};
-  // the reduction before the stores: its barrier then waits for no store
-  block_sum_all<3, NT>(x, sh_out);
+  // the stores go out before the reduction (its barrier waits for LDS
+  // only), so their latency overlaps it
   if (lead) {
     v.p[row] = o_x + alpha * pv;
     v.pl_z[row] = z;
@@ -650,6 +673,8 @@ __global__ __launch_bounds__(pcg_nt<FUSED>()) void k_pcg_iter(View v) {
     v.r[row] = r;
     Mn[row] = wn / o_d;
   }
+  double x[3] = {lead ? r * un : 0.0, lead ? wn * un : 0.0, lead ? r * r : 0.0};
+  block_sum_all<3, NT>(x, sh_out);
   if (threadIdx.x == 0) {
     const int lb = xcd_block();
 #pragma unroll
@@ -709,17 +734,28 @@ int cg_update_blocks(int64_t n) {
   return (int)(a < CG_UPD_BLOCKS ? a : CG_UPD_BLOCKS);
 }
 
+template <int DIM>
+static void assemble_t(const View& v, bool mx, unsigned nb, const double* rhs, int zx,
+                       hipStream_t s) {
+  const bool multi = v.rho_s != nullptr;
+  if (mx) {
+    if (multi) k_assemble<DIM, true, true><<<nb, BLOCK, 0, s>>>(v, rhs, zx);
+    else k_assemble<DIM, true, false><<<nb, BLOCK, 0, s>>>(v, rhs, zx);
+  } else {
+    if (multi) k_assemble<DIM, false, true><<<nb, BLOCK, 0, s>>>(v, rhs, zx);
+    else k_assemble<DIM, false, false><<<nb, BLOCK, 0, s>>>(v, rhs, zx);
+  }
+}
+
 int launch_assemble(const View& v, int dim, int precision, const double* rhs, bool zero_x0,
                     hipStream_t s) {
   const unsigned nb = (unsigned)v.nspmv;
   const int zx = zero_x0 ? 1 : 0;
   const bool mx = precision == MPS_MIXED;
   if (dim == 2) {
-    if (mx) k_assemble<2, true><<<nb, BLOCK, 0, s>>>(v, rhs, zx);
-    else k_assemble<2, false><<<nb, BLOCK, 0, s>>>(v, rhs, zx);
+    assemble_t<2>(v, mx, nb, rhs, zx, s);
   } else {
-    if (mx) k_assemble<3, true><<<nb, BLOCK, 0, s>>>(v, rhs, zx);
-    else k_assemble<3, false><<<nb, BLOCK, 0, s>>>(v, rhs, zx);
+    assemble_t<3>(v, mx, nb, rhs, zx, s);
   }
   return 0;
 }

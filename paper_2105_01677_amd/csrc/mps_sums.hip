@@ -113,73 +113,119 @@ __device__ inline int64_t team_row() {
 }
 
 // The list entries l = t, t + TEAM, ... < cnt of a row, U per lane and
-// step: the list loads of a step are issued together and its bodies are
-// straight-line code, so their gathers can be in flight together too.
-// Slots past cnt (stale, but inside the row's kpad slots) are replaced by
-// the row itself with ok = false; the body must then contribute nothing.
-// U per kernel as measured on MI355X (2 for the sums with the heaviest
-// gathers, 1 where the extra registers cost more than they hide).
-template <int U, class F>
-__device__ inline void for_list(const View& v, int64_t row, int cnt, int t, F&& body) {
-  for (int l0 = t; l0 < cnt; l0 += U * TEAM) {
+// step, in two phases per step so that all gathers of a step are in flight
+// together: load(j) issues the gathers of neighbour j (straight-line code),
+// body(j, rec, ok) consumes them.  The list entries of the next step are
+// loaded while this step's gathers are in flight (software pipelining:
+// one exposed memory latency per step).  Slots past cnt (stale, but inside
+// the row's kpad slots) are replaced by the row itself with ok = false; the
+// body must then contribute nothing.  Slot indices past kpad are clamped to
+// the row's first slot, so every load stays inside the row.
+#ifndef SUM_U_PREDICT
+#define SUM_U_PREDICT 2
+#endif
+#ifndef SUM_U_DENSITY
+#define SUM_U_DENSITY 2
+#endif
+#ifndef SUM_U_VISC
+#define SUM_U_VISC 2
+#endif
+#ifndef SUM_U_PHAT
+#define SUM_U_PHAT 2
+#endif
+#ifndef SUM_U_GRAD
+#define SUM_U_GRAD 2
+#endif
+template <int U, class LD, class F>
+__device__ inline void for_list(const View& v, int64_t row, int cnt, int t, LD&& load,
+                                F&& body) {
+  const int64_t e0 = sl_index(row, t, v.kpad);
+  const int ng = v.kpad / TEAM;  // slot groups of a row
+  int32_t jn[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) jn[u] = v.nb_list[e0 + (int64_t)(u < ng ? u : 0) * WAVE];
+  for (int k0 = 0; t + k0 * TEAM < cnt; k0 += U) {
     int32_t j[U];
+    bool ok[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int l = l0 + u * TEAM;
-      // l - t + TEAM <= kpad is uniform over the team (kpad % TEAM == 0)
-      j[u] = l - t < v.kpad ? v.nb_list[sl_index(row, l, v.kpad)] : 0;
-      if (l >= cnt) j[u] = (int32_t)row;
+      ok[u] = t + (k0 + u) * TEAM < cnt;
+      j[u] = ok[u] ? jn[u] : (int32_t)row;
+    }
+    decltype(load(j[0])) rec[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) rec[u] = load(j[u]);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = k0 + U + u;
+      jn[u] = v.nb_list[e0 + (int64_t)(k < ng ? k : 0) * WAVE];
     }
 #pragma unroll
-    for (int u = 0; u < U; ++u) body(j[u], l0 + u * TEAM < cnt);
+    for (int u = 0; u < U; ++u) body(j[u], rec[u], ok[u]);
   }
 }
 
 // a3: u* = u + dt (nu 2d/(lambda n0) sum_j (u_j - u_i) w(r_ij) + g),
 //     r* = r + dt u*  for fluid; other particles keep r and u.
-template <int DIM, bool MIXED>
+template <int DIM, bool MIXED, bool MULTI>
 __global__ __launch_bounds__(BLOCK) void k_predict(View v) {
   using P = PosRef<DIM, MIXED>;
   using R = typename P::R;
   const int64_t row = team_row();
   const int t = team_lane();
   if (row >= v.n) return;
+  // the row's own loads are issued together (no branch before the list)
   double ui[DIM], xi[DIM];
   load_vec<DIM>(v.vel, row, ui);
   load_vec<DIM>(v.pos, row, xi);
+  const bool fluid = v.type[row] == MPS_FLUID;
+  const int cnt_all = v.nb_count[row];
+  using K = KRec<DIM, MIXED>;
+  const K ri = K::load(v, row);
+  const double mi = MULTI ? v.mu[row] : 0.0;
+  const int cnt = fluid ? cnt_all : 0;
   double us[DIM], rs[DIM];
 #pragma unroll
   for (int a = 0; a < DIM; ++a) { us[a] = ui[a]; rs[a] = xi[a]; }
-  if (v.type[row] == MPS_FLUID) {
-    using K = KRec<DIM, MIXED>;
-    const K ri = K::load(v, row);
+  {
     const R re = (R)v.re_lap;
     R acc[DIM];
 #pragma unroll
     for (int a = 0; a < DIM; ++a) acc[a] = R(0);
-    const int cnt = v.nb_count[row];
-    const double mi = v.rho_s ? v.mu[row] : 0.0;
-    for_list<2>(v, row, cnt, t, [&](int32_t j, bool ok) {
-      const K rj = K::load(v, j);
-      R d[DIM];
-      ri.p.diff(rj.p, v.cs32, d);
-      const R wr = weight<R>(v.kernel, sqrt(norm2<DIM, R>(d)), re);
-      R w = ok ? wr : R(0);
-      if (v.rho_s) {
-        // two-phase: harmonic mean of the pair's dynamic viscosities
-        const double mj = v.mu[j], ms = mi + mj;
-        w *= (R)(ms > 0.0 ? 2.0 * mi * mj / ms : 0.0);
+    struct Rec {
+      K k;
+      double mj;
+    };
+    for_list<SUM_U_PREDICT>(
+        v, row, cnt, t,
+        [&](int32_t j) {
+          Rec r;
+          r.k = K::load(v, j);
+          r.mj = MULTI ? v.mu[j] : 0.0;
+          return r;
+        },
+        [&](int32_t, const Rec& rj, bool ok) {
+          R d[DIM];
+          ri.p.diff(rj.k.p, v.cs32, d);
+          const R wr = weight<R>(v.kernel, sqrt(norm2<DIM, R>(d)), re);
+          R w = ok ? wr : R(0);
+          if constexpr (MULTI) {
+            // two-phase: harmonic mean of the pair's dynamic viscosities
+            const double ms = mi + rj.mj;
+            w *= (R)(ms > 0.0 ? 2.0 * mi * rj.mj / ms : 0.0);
+          }
+#pragma unroll
+          for (int a = 0; a < DIM; ++a) acc[a] += (R)(rj.k.u[a] - ri.u[a]) * w;
+        });
+    if (fluid) {
+      const double clap = 2.0 * DIM / (v.lam_lap * v.n0_lap);
+      const double visc = MULTI ? clap / v.rho_s[row] : v.nu * clap;
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) {
+        const double lap = (double)team_sum(acc[a]);
+        us[a] = ui[a] + v.dt * (visc * lap + v.g[a]);
+        rs[a] = xi[a] + v.dt * us[a];
       }
-#pragma unroll
-      for (int a = 0; a < DIM; ++a) acc[a] += (R)(rj.u[a] - ri.u[a]) * w;
-    });
-    const double clap = 2.0 * DIM / (v.lam_lap * v.n0_lap);
-    const double visc = v.rho_s ? clap / v.rho_s[row] : v.nu * clap;
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-      const double lap = (double)team_sum(acc[a]);
-      us[a] = ui[a] + v.dt * (visc * lap + v.g[a]);
-      rs[a] = xi[a] + v.dt * us[a];
     }
   }
   if (t == 0) {
@@ -211,19 +257,23 @@ __global__ __launch_bounds__(BLOCK) void k_density(View v, int wc) {
   const int64_t row = team_row();
   const int t = team_lane();
   if (row >= v.n) return;
+  // the row's own loads are issued together (no branch before the list)
   const int8_t ty = v.type[row];
+  const int cnt_all = v.nb_count[row];
+  const P pi = P::load(v.rs, v.rsf, row);
+  const int cnt = ty != MPS_GHOST ? cnt_all : 0;
   R s = R(0);
-  if (ty != MPS_GHOST) {
-    const P pi = P::load(v.rs, v.rsf, row);
+  {
     const R re = (R)v.re_n, re2 = (R)v.re_n2;
-    const int cnt = v.nb_count[row];
-    for_list<2>(v, row, cnt, t, [&](int32_t j, bool ok) {
-      R d[DIM];
-      pi.diff(P::load(v.rs, v.rsf, j), v.cs32, d);
-      const R r2 = norm2<DIM, R>(d);
-      const R w = weight<R>(v.kernel, sqrt(r2), re);
-      s += (ok && r2 < re2) ? w : R(0);
-    });
+    for_list<SUM_U_DENSITY>(
+        v, row, cnt, t, [&](int32_t j) { return P::load(v.rs, v.rsf, j); },
+        [&](int32_t, const P& pj, bool ok) {
+          R d[DIM];
+          pi.diff(pj, v.cs32, d);
+          const R r2 = norm2<DIM, R>(d);
+          const R w = weight<R>(v.kernel, sqrt(r2), re);
+          s += (ok && r2 < re2) ? w : R(0);
+        });
     s = team_sum(s);
   }
   if (t != 0) return;
@@ -268,8 +318,8 @@ __global__ __launch_bounds__(BLOCK) void k_viscosity(View v) {
       for (int b = 0; b < DIM; ++b) G[a][b] = R(0);
     const R re = (R)v.re_n, re2 = (R)v.re_n2;
     const int cnt = v.nb_count[row];
-    for_list<2>(v, row, cnt, t, [&](int32_t j, bool ok) {
-      const K rj = K::load(v, j);
+    for_list<SUM_U_VISC>(v, row, cnt, t, [&](int32_t j) { return K::load(v, j); },
+                         [&](int32_t, const K& rj, bool ok) {
       R d[DIM];
       ri.p.diff(rj.p, v.cs32, d);
       const R r2 = norm2<DIM, R>(d);
@@ -350,19 +400,34 @@ __global__ __launch_bounds__(BLOCK) void k_phat(View v, double* phat) {
   const int64_t row = team_row();
   const int t = team_lane();
   if (row >= v.n) return;
+  // the row's own loads are issued together (no branch before the list)
   const int8_t ty = v.type[row];
   double m = v.p[row];
-  if (ty == MPS_FLUID || ty == MPS_WALL) {
-    const P pi = P::load(v.rs, v.rsf, row);
+  const int cnt_all = v.nb_count[row];
+  const P pi = P::load(v.rs, v.rsf, row);
+  const int cnt = ty == MPS_FLUID || ty == MPS_WALL ? cnt_all : 0;
+  {
     const R re2 = (R)v.re_n2;
-    const int cnt = v.nb_count[row];
-    for_list<1>(v, row, cnt, t, [&](int32_t j, bool ok) {
-      R d[DIM];
-      pi.diff(P::load(v.rs, v.rsf, j), v.cs32, d);
-      // flags mark exactly the dummy particles MPS_FLAG_DUMMY
-      const double pj = v.p[j];
-      if (ok && v.flags[j] != MPS_FLAG_DUMMY && norm2<DIM, R>(d) < re2) m = fmin(m, pj);
-    });
+    struct Rec {
+      P p;
+      double pj;
+      int8_t fj;
+    };
+    for_list<SUM_U_PHAT>(
+        v, row, cnt, t,
+        [&](int32_t j) {
+          Rec r;
+          r.p = P::load(v.rs, v.rsf, j);
+          r.pj = v.p[j];
+          r.fj = v.flags[j];
+          return r;
+        },
+        [&](int32_t, const Rec& rj, bool ok) {
+          R d[DIM];
+          pi.diff(rj.p, v.cs32, d);
+          // flags mark exactly the dummy particles MPS_FLAG_DUMMY
+          if (ok && rj.fj != MPS_FLAG_DUMMY && norm2<DIM, R>(d) < re2) m = fmin(m, rj.pj);
+        });
     m = team_min(m);
   }
   if (t == 0) phat[row] = m;
@@ -382,27 +447,48 @@ __global__ __launch_bounds__(BLOCK) void k_gradient(View v, const double* phat) 
   const int64_t row = team_row();
   const int t = team_lane();
   if (row >= v.n) return;
-  if (v.type[row] != MPS_FLUID) return;
+  // the row's own loads are issued together (no branch before the list)
+  const bool fluid = v.type[row] == MPS_FLUID;
   const P pi = P::load(v.rs, v.rsf, row);
   const R re = (R)v.re_n, re2 = (R)v.re_n2;
-  const int cnt = v.nb_count[row];
+  const int cnt_all = v.nb_count[row];
   const double p_i = v.p[row];
+  double us[DIM], rs[DIM], un[DIM], xn[DIM];
+  load_vec<DIM>(v.us, row, us);
+  load_vec<DIM>(v.rs, row, rs);
+  const double rho_i = v.rho_s ? v.rho_s[row] : v.rho;
+  const int cnt = fluid ? cnt_all : 0;
   double gs[DIM], bs[DIM];
 #pragma unroll
   for (int a = 0; a < DIM; ++a) gs[a] = bs[a] = 0.0;
   double m = p_i;
   const double ph_i = CMPS ? phat[row] : 0.0;
-  for_list<1>(v, row, cnt, t, [&](int32_t j, bool ok) {
+  struct Rec {
+    P p;
+    double pj, phj;
+    int8_t fj;
+  };
+  for_list<SUM_U_GRAD>(
+      v, row, cnt, t,
+      [&](int32_t j) {
+        Rec r;
+        r.p = P::load(v.rs, v.rsf, j);
+        r.pj = v.p[j];
+        r.phj = CMPS ? phat[j] : 0.0;
+        r.fj = v.flags[j];
+        return r;
+      },
+      [&](int32_t, const Rec& rj, bool ok) {
     R d[DIM];
-    pi.diff(P::load(v.rs, v.rsf, j), v.cs32, d);
+    pi.diff(rj.p, v.cs32, d);
     const R r2 = norm2<DIM, R>(d);
-    const double pj = v.p[j];
+    const double pj = rj.pj;
     // flags mark exactly the dummy particles MPS_FLAG_DUMMY
-    const bool in = ok && v.flags[j] != MPS_FLAG_DUMMY && r2 < re2;
+    const bool in = ok && rj.fj != MPS_FLAG_DUMMY && r2 < re2;
     const R wr = weight<R>(v.kernel, sqrt(r2), re) / r2;
     const R f = in ? wr : R(0);
     if constexpr (CMPS) {
-      const double num = (p_i + pj) - (ph_i + phat[j]);
+      const double num = (p_i + pj) - (ph_i + rj.phj);
       const R fn = (R)num * f;
 #pragma unroll
       for (int a = 0; a < DIM; ++a) gs[a] += (double)(fn * d[a]);
@@ -417,9 +503,6 @@ __global__ __launch_bounds__(BLOCK) void k_gradient(View v, const double* phat) 
     }
   });
   if constexpr (!CMPS) m = team_min(m);
-  double us[DIM], rs[DIM], un[DIM], xn[DIM];
-  load_vec<DIM>(v.us, row, us);
-  load_vec<DIM>(v.rs, row, rs);
   const double cg = (double)DIM / v.n0_n;
   bool finite = true;
 #pragma unroll
@@ -427,11 +510,11 @@ __global__ __launch_bounds__(BLOCK) void k_gradient(View v, const double* phat) 
     double sum = team_sum(gs[a]);
     if constexpr (!CMPS) sum -= m * team_sum(bs[a]);
     const double gp = cg * sum;
-    un[a] = us[a] - v.dt / (v.rho_s ? v.rho_s[row] : v.rho) * gp;
+    un[a] = us[a] - v.dt / rho_i * gp;
     xn[a] = rs[a] + v.dt * (un[a] - us[a]);
     finite = finite && isfinite(un[a]) && isfinite(xn[a]);
   }
-  if (t == 0) {
+  if (fluid && t == 0) {
     store_vec<DIM>(v.vel_w, row, un);
     store_vec<DIM>(v.pos_w, row, xn);
     if (!finite) atomicOr(v.status, ST_NONFINITE);
@@ -442,15 +525,25 @@ static inline unsigned team_blocks(int64_t n) {
   return (unsigned)((n + ROWS_PER_BLOCK - 1) / ROWS_PER_BLOCK);
 }
 
-int launch_predict(const View& v, int dim, int precision, hipStream_t s) {
+template <int DIM>
+static void predict_t(const View& v, bool mx, hipStream_t s) {
   const unsigned nb = team_blocks(v.n);
+  const bool multi = v.rho_s != nullptr;
+  if (mx) {
+    if (multi) k_predict<DIM, true, true><<<nb, BLOCK, 0, s>>>(v);
+    else k_predict<DIM, true, false><<<nb, BLOCK, 0, s>>>(v);
+  } else {
+    if (multi) k_predict<DIM, false, true><<<nb, BLOCK, 0, s>>>(v);
+    else k_predict<DIM, false, false><<<nb, BLOCK, 0, s>>>(v);
+  }
+}
+
+int launch_predict(const View& v, int dim, int precision, hipStream_t s) {
   const bool mx = precision == MPS_MIXED;
   if (dim == 2) {
-    if (mx) k_predict<2, true><<<nb, BLOCK, 0, s>>>(v);
-    else k_predict<2, false><<<nb, BLOCK, 0, s>>>(v);
+    predict_t<2>(v, mx, s);
   } else {
-    if (mx) k_predict<3, true><<<nb, BLOCK, 0, s>>>(v);
-    else k_predict<3, false><<<nb, BLOCK, 0, s>>>(v);
+    predict_t<3>(v, mx, s);
   }
   return 0;
 }
