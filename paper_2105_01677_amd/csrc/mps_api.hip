@@ -90,6 +90,17 @@ struct mps_ctx {
   static constexpr int CG_BATCH = 4;   // smallest CG graph; also 4x and 16x
   bool graphs_built = false;
   hipGraphExec_t g_pre[2] = {}, g_cg[2][3] = {}, g_post[2] = {}, g_wc2[2] = {};
+  // whole PPE steps as one graph each (pre, a fixed number of CG iterations,
+  // the CG scalars to the host, post), per buffer parity and iteration
+  // count; a few are kept, least recently used replaced
+  struct StepGraph {
+    int ncg = 0;
+    uint64_t used = 0;
+    hipGraphExec_t g = nullptr;
+  };
+  static constexpr int kStepGraphs = 6;
+  StepGraph g_step[2][kStepGraphs];
+  uint64_t step_clock = 0;
   // checkpoint tape: per slot the sorted state (pos, vel, p, type, id)
   struct Slot {
     double *pos = nullptr, *vel = nullptr, *p = nullptr;
@@ -621,8 +632,81 @@ mps_status steps_wc(mps_ctx* c, int nsteps) {
   return MPS_OK;
 }
 
+// The graph of a whole PPE step from buffer parity par with ncg CG
+// iterations (built on first use).
+mps_status step_graph(mps_ctx* c, int par, int ncg, hipGraphExec_t* out) {
+  mps_ctx::StepGraph* slot = nullptr;
+  for (auto& sg : c->g_step[par]) {
+    if (sg.g && sg.ncg == ncg) {
+      sg.used = ++c->step_clock;
+      *out = sg.g;
+      return MPS_OK;
+    }
+    if (!slot || !sg.g || (slot->g && sg.used < slot->used)) slot = &sg;
+  }
+  if (slot->g) (void)hipGraphExecDestroy(slot->g);
+  slot->g = nullptr;
+  const int cur0 = c->cur;
+  c->cur = par;
+  mps_status st = capture(c, &slot->g, [&] {
+    (void)hipMemcpyAsync(c->status + 1, c->status, sizeof(int32_t), hipMemcpyDeviceToDevice,
+                         c->s);
+    enqueue_pre(c);
+    enqueue_cg(c, ncg);
+    (void)hipMemcpyAsync(c->h_sc, c->sc, sizeof(CGScalars), hipMemcpyDeviceToHost, c->s);
+    enqueue_post(c);
+  });
+  c->cur = cur0;
+  if (st != MPS_OK) {
+    slot->g = nullptr;
+    return st;
+  }
+  slot->ncg = ncg;
+  slot->used = ++c->step_clock;
+  *out = slot->g;
+  return MPS_OK;
+}
+
+void record_cg(mps_ctx* c, mps_step_stats* st, int it, double rel) {
+  c->last_iters = it;
+  if (st) {
+    st->cg_iters_last = it;
+    st->cg_iters_total += it;
+    st->cg_relres_last = rel;
+  }
+}
+
 mps_status one_step_ppe(mps_ctx* c, mps_step_stats* st) {
   const bool graphs = use_graphs(c);
+  if (graphs && c->last_iters > 0) {
+    // speculative whole step: the previous step's iteration count plus a
+    // margin (launches after convergence return at once); if the solve
+    // did not converge within it, the step is discarded (its input state,
+    // the other buffer, is untouched) and redone with polled batches
+    const int B = mps_ctx::CG_BATCH;
+    const int ncg = std::min(((c->last_iters + B + B - 1) / B) * B,
+                             ((c->P.cg_maxit + B - 1) / B) * B);
+    hipGraphExec_t g = nullptr;
+    mps_status s0 = step_graph(c, c->cur, ncg, &g);
+    if (s0 != MPS_OK) return s0;
+    HIPCHK(c, hipGraphLaunch(g, c->s));
+    // the next step's launch waits for this answer: poll instead of a
+    // blocking wait (shorter wake-up)
+    hipError_t q;
+    while ((q = hipStreamQuery(c->s)) == hipErrorNotReady) {
+    }
+    if (q != hipSuccess) return hip_fail(c, q, "hipStreamQuery");
+    const CGScalars h = *c->h_sc;
+    if (h.converged) {
+      c->cur ^= 1;
+      c->ppe_valid = true;
+      record_cg(c, st, h.iter, h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0);
+      return MPS_OK;
+    }
+    // the discarded step's error flags go with it
+    HIPCHK(c, hipMemcpyAsync(c->status, c->status + 1, sizeof(int32_t),
+                             hipMemcpyDeviceToDevice, c->s));
+  }
   if (graphs) {
     mps_status s0 = build_graphs(c);
     if (s0 != MPS_OK) return s0;
@@ -637,12 +721,7 @@ mps_status one_step_ppe(mps_ctx* c, mps_step_stats* st) {
   double rel = 0;
   mps_status res = solve(c, &it, &rel, graphs);
   if (res != MPS_OK && res != MPS_E_CG_NOCONV) return res;
-  c->last_iters = it;
-  if (st) {
-    st->cg_iters_last = it;
-    st->cg_iters_total += it;
-    st->cg_relres_last = rel;
-  }
+  record_cg(c, st, it, rel);
   if (graphs) HIPCHK(c, hipGraphLaunch(c->g_post[c->cur], c->s));
   else enqueue_post(c);
   return res;
@@ -759,7 +838,7 @@ mps_status mps_init(const mps_params* params, int64_t n, const double* pos, cons
     }
   }
   A(dalloc(&c->sc, 1));
-  A(dalloc(&c->status, 1));
+  A(dalloc(&c->status, 2));  // [1]: copy taken before a speculative step
   A(dalloc(&c->counts, 4));
   g_bytes = nullptr;
   if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_sc, sizeof(CGScalars), hipHostMallocDefault);
@@ -839,6 +918,8 @@ mps_status mps_free(mps_ctx* c) {
                            c->g_post[k], c->g_wc2[k]};
     for (hipGraphExec_t g : gs)
       if (g) (void)hipGraphExecDestroy(g);
+    for (auto& sg : c->g_step[k])
+      if (sg.g) (void)hipGraphExecDestroy(sg.g);
   }
   if (c->ev_created)
     for (int k = 0; k < mps_ctx::kPool; ++k) {

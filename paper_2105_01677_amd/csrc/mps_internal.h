@@ -249,8 +249,11 @@ __device__ inline int team_lane() { return threadIdx.x & (TEAM - 1); }
 // encoding used here: quad_perm [1,0,3,2] (lane ^ 1) = 0xB1, quad_perm
 // [2,3,0,1] (lane ^ 2) = 0x4E, row_half_mirror (lane l <-> 7 - l within
 // each 8 lanes) = 0x141, row_mirror (l <-> 15 - l within each 16) = 0x140.
-// The source lanes of these patterns must be active.
+// row_shl:k (lane l takes lane l + k within each 16) = 0x100 + k.  The
+// source lanes of these patterns must be active.
 constexpr int DPP_XOR1 = 0xB1, DPP_XOR2 = 0x4E, DPP_HALF_MIRROR = 0x141, DPP_MIRROR = 0x140;
+constexpr int DPP_SHL1 = 0x101, DPP_SHL2 = 0x102, DPP_SHL3 = 0x103, DPP_SHL4 = 0x104,
+              DPP_SHL5 = 0x105, DPP_SHL6 = 0x106;
 
 template <int CTRL>
 __device__ inline uint32_t dpp_u32(uint32_t v) {

@@ -617,8 +617,13 @@ __global__ __launch_bounds__(pcg_nt<FUSED>()) void k_pcg_iter(View v) {
     jj[u] = v.a_col[e];
     aa[u] = aval[e];
   }
-  const double o_d = v.diag[rc], o_m = M[rc], o_z = v.pl_z[rc], o_s = v.pl_s[rc],
-               o_p = v.pd[0][rc], o_r = v.r[rc], o_x = v.p[rc];
+  // the row's own seven values, one per team lane (one load instruction;
+  // moved to lane 0 below)
+  const double* optr = t == 0 ? v.diag : t == 1 ? M : t == 2 ? v.pl_z : t == 3 ? v.pl_s
+                       : t == 4 ? v.pd[0] : t == 5 ? v.r : v.p;
+  const double ov = optr[rc];
+  // a launch after convergence ends here, without waiting for the loads
+  if (conv) return;
   // every load above is issued before any of them is waited for: without
   // this fence the compiler sinks slot loads behind the wait for the row
   // length, or consumes the partials before issuing the rest (one more
@@ -637,14 +642,16 @@ __global__ __launch_bounds__(pcg_nt<FUSED>()) void k_pcg_iter(View v) {
     }
   }
 
+  // lane 0 of the team takes lane k's value (DPP row_shl:k)
+  const double o_d = ov, o_m = dpp_move<DPP_SHL1>(ov), o_z = dpp_move<DPP_SHL2>(ov),
+               o_s = dpp_move<DPP_SHL3>(ov), o_p = dpp_move<DPP_SHL4>(ov),
+               o_r = dpp_move<DPP_SHL5>(ov), o_x = dpp_move<DPP_SHL6>(ov);
+
   // -- the scalars --
   if constexpr (FUSED) {
     double tot[3];
     sum_partials_loaded<NT, PCG_PK>(q, v.npcg, tot, sh_in);
-    if (conv) return;
     if (pcg_scalars(v, tot, PAR, gam_old, alp_old, bb, blockIdx.x == 0, alpha, beta)) return;
-  } else {
-    if (conv) return;
   }
 
   double s = 0.0;
