@@ -111,6 +111,8 @@ typedef struct {
   int64_t n_ghost;         /* ghost particles */
   int64_t list_entries;    /* neighbour-list entries of the last step */
   int64_t ppe_nnz;         /* off-diagonal matrix entries of the last step */
+  int32_t cg_redone;       /* steps whose speculative solve (see mps_step)
+                              did not converge and that were redone */
 } mps_step_stats;
 
 /* Kernel classes for mps_profile: cell binning + sort + permutation (a1),
@@ -158,6 +160,10 @@ mps_status mps_neighbors(mps_ctx* ctx, int32_t* cell_id, int32_t* count,
                          int32_t* list);
 
 /* Advance nsteps time steps (steps 1-5 above).  stats may be NULL.
+ * PPE model on a non-null stream: each step after the first is enqueued
+ * whole with a CG iteration count guessed from the previous step; a step
+ * whose solve did not converge within it is discarded and redone with
+ * polled CG batches (same results; counted in stats->cg_redone).
  * Errors: MPS_E_NEIGH_OVERFLOW, MPS_E_COINCIDENT, MPS_E_NONFINITE,
  * MPS_E_CG_NOCONV (the step still completes with the last iterate),
  * MPS_E_POISONED. */

@@ -706,6 +706,7 @@ mps_status one_step_ppe(mps_ctx* c, mps_step_stats* st) {
     // the discarded step's error flags go with it
     HIPCHK(c, hipMemcpyAsync(c->status, c->status + 1, sizeof(int32_t),
                              hipMemcpyDeviceToDevice, c->s));
+    if (st) st->cg_redone += 1;
   }
   if (graphs) {
     mps_status s0 = build_graphs(c);

@@ -46,7 +46,8 @@ class StepStats(C.Structure):
     _fields_ = [("steps", C.c_int32), ("cg_iters_last", C.c_int32),
                 ("cg_iters_total", C.c_int64), ("cg_relres_last", C.c_double),
                 ("n_surface", C.c_int64), ("n_ghost", C.c_int64),
-                ("list_entries", C.c_int64), ("ppe_nnz", C.c_int64)]
+                ("list_entries", C.c_int64), ("ppe_nnz", C.c_int64),
+                ("cg_redone", C.c_int32)]
 
 
 _lib = None
@@ -196,7 +197,8 @@ class MPS:
         return {"status": st, "steps": s.steps, "cg_iters_last": s.cg_iters_last,
                 "cg_iters_total": s.cg_iters_total, "cg_relres_last": s.cg_relres_last,
                 "n_surface": s.n_surface, "n_ghost": s.n_ghost,
-                "list_entries": s.list_entries, "ppe_nnz": s.ppe_nnz}
+                "list_entries": s.list_entries, "ppe_nnz": s.ppe_nnz,
+                "cg_redone": s.cg_redone}
 
     def profile(self, classes):
         """Time every launch of the named kernel classes with HIP events."""

@@ -38,7 +38,39 @@ def test_params_layout():
     P = mps.Params
     assert P.l0.offset == 48          # 12 int32 before the doubles
     assert ctypes.sizeof(P) == 48 + 8 * 19
-    assert ctypes.sizeof(mps.StepStats) == 56
+    assert ctypes.sizeof(mps.StepStats) == 64
+    assert mps.StepStats.cg_redone.offset == 56
+
+
+def test_struct_layouts_match_the_c_header(tmp_path):
+    """The ctypes mirrors against the header compiled by the host C
+    compiler: sizes and every field offset."""
+    import shutil
+    import subprocess
+    from paper_2105_01677_amd import mps
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "mps.h"', "int main(void) {"]
+    for cname, py in (("mps_params", mps.Params), ("mps_step_stats", mps.StepStats)):
+        lines.append(f'printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = {}
+    for line in out.splitlines():
+        cname, f, v = line.split()
+        got[(cname, f)] = int(v)
+    for cname, py in (("mps_params", mps.Params), ("mps_step_stats", mps.StepStats)):
+        assert got[(cname, "sizeof")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
 
 
 def test_binding_refuses_without_gpu():
