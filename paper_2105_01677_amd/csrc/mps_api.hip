@@ -47,7 +47,7 @@ struct mps_ctx {
   double* nstar = nullptr;
   int8_t* flags = nullptr;
   int32_t *cellid = nullptr, *slot = nullptr, *cell_count = nullptr, *cell_start = nullptr,
-          *perm = nullptr, *tile_sum = nullptr;
+          *perm = nullptr;
   int32_t *nb_count = nullptr, *nb_list = nullptr;
   int32_t *a_nnz = nullptr, *a_col = nullptr;
   void* a_val = nullptr;
@@ -238,7 +238,6 @@ View make_view(const mps_ctx* c) {
   v.slot = c->slot;
   v.cell_count = c->cell_count;
   v.cell_start = c->cell_start;
-  v.tile_sum = c->tile_sum;
   v.perm = c->perm;
   v.nb_count = c->nb_count;
   v.nb_list = c->nb_list;
@@ -513,10 +512,9 @@ void enqueue_cg(mps_ctx* c, int iters) {
   }
 }
 
-// Stages after the pressure: clamp (PPE) and a8.
+// Stages after the pressure: a8 (the gradient kernels clamp negative
+// pressure on read and write it back clamped).
 void enqueue_post(mps_ctx* c) {
-  View v = make_view(c);
-  if (c->P.pmode == MPS_PPE_CG && c->P.clamp_negative_p) launch_clamp(v, c->s);
   Prof pr(c, MPS_KC_GRADIENT);
   launch_gradient(make_view_inplace(c), c->dim, c->P.precision, c->s);
 }
@@ -796,9 +794,8 @@ mps_status mps_init(const mps_params* params, int64_t n, const double* pos, cons
   A(dalloc(&c->cellid, n));
   A(dalloc(&c->slot, n));
   A(dalloc(&c->perm, n));
-  A(dalloc(&c->cell_count, c->ncell + 1));
-  A(dalloc(&c->cell_start, c->ncell + 2));
-  A(dalloc(&c->tile_sum, (c->ncell + 1 + SCAN_TILE - 1) / SCAN_TILE));
+  A(dalloc(&c->cell_count, scan_cells_padded(c->ncell)));
+  A(dalloc(&c->cell_start, scan_cells_padded(c->ncell)));
   A(dalloc(&c->nb_count, n));
   A(dalloc(&c->nb_list, c->slots));
   A(dalloc(&c->a_nnz, n));
@@ -851,7 +848,7 @@ mps_status mps_init(const mps_params* params, int64_t n, const double* pos, cons
   }
   // initial state: identity order
   hipStream_t s = c->s;
-  A(hipMemsetAsync(c->cell_count, 0, (c->ncell + 1) * sizeof(int32_t), s));
+  A(hipMemsetAsync(c->cell_count, 0, scan_cells_padded(c->ncell) * sizeof(int32_t), s));
   A(hipMemsetAsync(c->status, 0, sizeof(int32_t), s));
   A(hipMemsetAsync(c->sc, 0, sizeof(CGScalars), s));
   A(hipMemsetAsync(c->nb_count, 0, n * sizeof(int32_t), s));
@@ -905,7 +902,7 @@ mps_status mps_free(mps_ctx* c) {
   void* ptrs[] = {c->pos[0], c->pos[1], c->vel[0], c->vel[1], c->pres[0], c->pres[1],
                   c->type[0], c->type[1], c->id[0], c->id[1], c->pd[0], c->pd[1],
                   c->pcell, c->posf, c->rsf, c->us, c->rs, c->nstar, c->flags,
-                  c->cellid, c->slot, c->perm, c->cell_count, c->cell_start, c->tile_sum,
+                  c->cellid, c->slot, c->perm, c->cell_count, c->cell_start,
                   c->nb_count,
                   c->nb_list, c->a_nnz, c->a_col, c->a_val, c->diag, c->b, c->r, c->z,
                   c->q, c->p_save, c->partA, c->partB, c->sc, c->status, c->counts,

@@ -33,7 +33,12 @@ constexpr int WAVE = 64;
 constexpr int SLICE = WAVE / TEAM;        // rows per wavefront
 constexpr int BLOCK = 256;
 constexpr int ROWS_PER_BLOCK = BLOCK / TEAM;
-constexpr int SCAN_TILE = 4096;  // cells per workgroup of the cell-count scan
+// cell-count scan: one workgroup of SCAN_NT threads, SCAN_PER cells each
+constexpr int SCAN_NT = 1024, SCAN_PER = 16, SCAN_CHUNK = SCAN_NT * SCAN_PER;
+// cells allocated for the counts and starts (whole scan chunks)
+inline int64_t scan_cells_padded(int ncell) {
+  return ((int64_t)ncell + 2 + SCAN_CHUNK - 1) / SCAN_CHUNK * SCAN_CHUNK;
+}
 
 // Status bits raised by kernels (one int32 word on the device).
 enum : int32_t {
@@ -132,7 +137,6 @@ struct View {
   int32_t* slot;      // old order
   int32_t* cell_count;
   int32_t* cell_start;
-  int32_t* tile_sum;  // per-tile cell counts of the scan
   int32_t* perm;      // unordered scatter of the particles by cell
   // lists
   int32_t* nb_count;
@@ -399,7 +403,6 @@ int pcg_fused_capacity();
 int launch_pcg_setup(const View& v, int precision, hipStream_t s);
 int launch_pcg_iter(const View& v, int precision, int parity, hipStream_t s);
 int launch_pcg_reduce(const View& v, int parity, hipStream_t s);
-int launch_clamp(const View& v, hipStream_t s);
 int launch_gradient(const View& v, int dim, int precision, hipStream_t s);
 int launch_scatter_orig(const View& v, const double* src, double* dst, int comps,
                         int stride, hipStream_t s);

@@ -35,102 +35,103 @@ __device__ inline double dist2_exact(const double (&a)[DIM], const double (&b)[D
 template <int DIM>
 __global__ __launch_bounds__(BLOCK) void k_bin(View v, int8_t* type_cur) {
   const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (i >= v.n) return;
+  const bool active = i < v.n;
   int c = v.ncell;
-  int8_t t = type_cur[i];
-  if (t != MPS_GHOST) {
-    double x[DIM];
-    load_vec<DIM>(v.pos, i, x);
-    const int nn[3] = {v.nx, v.ny, v.nz};
-    int ci[3] = {0, 0, 0};
-    bool in = true, finite = true;
+  if (active) {
+    int8_t t = type_cur[i];
+    if (t != MPS_GHOST) {
+      double x[DIM];
+      load_vec<DIM>(v.pos, i, x);
+      const int nn[3] = {v.nx, v.ny, v.nz};
+      int ci[3] = {0, 0, 0};
+      bool in = true, finite = true;
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-      finite = finite && isfinite(x[a]);
-      double f = floor((x[a] - v.lo[a]) * v.inv_cs);
-      if (!(f >= 0.0 && f < (double)nn[a])) in = false;
-      else ci[a] = (int)f;
+      for (int a = 0; a < DIM; ++a) {
+        finite = finite && isfinite(x[a]);
+        double f = floor((x[a] - v.lo[a]) * v.inv_cs);
+        if (!(f >= 0.0 && f < (double)nn[a])) in = false;
+        else ci[a] = (int)f;
+      }
+      if (!finite) atomicOr(v.status, ST_NONFINITE);
+      if (in) c = ci[0] + v.nx * (ci[1] + v.ny * ci[2]);
+      else type_cur[i] = MPS_GHOST;
     }
-    if (!finite) atomicOr(v.status, ST_NONFINITE);
-    if (in) c = ci[0] + v.nx * (ci[1] + v.ny * ci[2]);
-    else type_cur[i] = MPS_GHOST;
+    v.cellid[i] = c;
   }
-  v.cellid[i] = c;
-  // the ghost cell may collect many particles: one atomic per wavefront
-  const bool ghost = c == v.ncell;
-  const uint64_t gm = __ballot(ghost);
-  if (ghost) {
-    const int lane = threadIdx.x & (WAVE - 1);
-    const int leader = __ffsll((unsigned long long)gm) - 1;
-    int base = 0;
-    if (lane == leader) base = atomicAdd(&v.cell_count[c], __popcll(gm));
-    base = __shfl(base, leader, WAVE);
-    v.slot[i] = base + __popcll(gm & ((1ull << lane) - 1ull));
-  } else {
-    v.slot[i] = atomicAdd(&v.cell_count[c], 1);
-  }
+  // one atomic per run of consecutive lanes in the same cell (the input is
+  // the previous step's cell order, so runs are long): the run's first
+  // lane adds the run length, the others take consecutive slots after it
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int cprev = __shfl_up(c, 1, WAVE);
+  const bool head = active && (lane == 0 || cprev != c);
+  const uint64_t heads = __ballot(head);
+  const int nact = __popcll(__ballot(active));
+  const uint64_t upto = lane == WAVE - 1 ? ~0ull : ((2ull << lane) - 1ull);
+  const uint64_t hb = heads & upto;
+  const int h = hb ? 63 - __clzll(hb) : 0;
+  const uint64_t after = heads & ~upto;
+  const int next = after ? __ffsll((unsigned long long)after) - 1 : nact;
+  int base = 0;
+  if (head) base = atomicAdd(&v.cell_count[c], next - lane);
+  base = __shfl(base, h, WAVE);
+  if (active) v.slot[i] = base + (lane - h);
 }
 
-// Exclusive scan of the ncell+1 cell counts in tiles of SCAN_TILE cells:
-// k_scan_tiles sums each tile, k_scan_apply adds the sums of the preceding
-// tiles (at most a few ten) and scans its own tile.  Resets the counts for
-// the next step.
-__global__ __launch_bounds__(BLOCK) void k_scan_tiles(View v) {
+// Exclusive scan of the ncell+1 cell counts by one workgroup, in chunks of
+// SCAN_CHUNK cells (a thread scans SCAN_PER consecutive counts, then the
+// workgroup its thread totals); resets the counts for the next step.  The
+// count and start arrays are padded to whole chunks (padding counts stay
+// 0), so cell_start[ncell + 1] comes out as the total.
+__global__ __launch_bounds__(SCAN_NT) void k_scan_cells(View v) {
+  constexpr int NW = SCAN_NT / WAVE, Q = SCAN_PER / 4;
   const int m = v.ncell + 1;
-  const int base = blockIdx.x * SCAN_TILE;
-  int32_t s = 0;
-  for (int k = base + threadIdx.x; k < base + SCAN_TILE && k < m; k += BLOCK) s += v.cell_count[k];
-#pragma unroll
-  for (int o = WAVE / 2; o > 0; o >>= 1) s += __shfl_down(s, o, WAVE);
-  __shared__ int32_t sh[BLOCK / WAVE];
-  if ((threadIdx.x & (WAVE - 1)) == 0) sh[threadIdx.x / WAVE] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int32_t t = 0;
-    for (int w = 0; w < BLOCK / WAVE; ++w) t += sh[w];
-    v.tile_sum[blockIdx.x] = t;
-  }
-}
-
-__global__ __launch_bounds__(BLOCK) void k_scan_apply(View v) {
-  constexpr int PER = SCAN_TILE / BLOCK;
-  const int m = v.ncell + 1;
-  const int base = blockIdx.x * SCAN_TILE + threadIdx.x * PER;
-  __shared__ int32_t off_sh;
-  __shared__ int32_t wsum[BLOCK / WAVE];
-  if (threadIdx.x == 0) {
-    int32_t o = 0;
-    for (unsigned t = 0; t < blockIdx.x; ++t) o += v.tile_sum[t];
-    off_sh = o;
-  }
-  int32_t loc[PER];
-  int32_t s = 0;
-#pragma unroll
-  for (int k = 0; k < PER; ++k) {
-    loc[k] = base + k < m ? v.cell_count[base + k] : 0;
-    s += loc[k];
-  }
-  // inclusive scan of the thread sums: wave shuffles, then across waves
   const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
-  int32_t inc = s;
+  __shared__ int32_t wsum[2][NW];
+  int32_t carry = 0;
+  int par = 0;
+  for (int c0 = 0; c0 <= m; c0 += SCAN_CHUNK, par ^= 1) {
+    const int base = c0 + threadIdx.x * SCAN_PER;
+    const int4* src = reinterpret_cast<const int4*>(v.cell_count + base);
+    int4 q[Q];
 #pragma unroll
-  for (int o = 1; o < WAVE; o <<= 1) {
-    const int32_t y = __shfl_up(inc, o, WAVE);
-    if (lane >= o) inc += y;
-  }
-  if (lane == WAVE - 1) wsum[w] = inc;
-  __syncthreads();
-  int32_t run = off_sh + inc - s;
-  for (int q = 0; q < w; ++q) run += wsum[q];
+    for (int k = 0; k < Q; ++k) q[k] = src[k];
+    int32_t s = 0;
 #pragma unroll
-  for (int k = 0; k < PER; ++k) {
-    if (base + k < m) {
-      v.cell_start[base + k] = run;
-      v.cell_count[base + k] = 0;
+    for (int k = 0; k < Q; ++k) s += (q[k].x + q[k].y) + (q[k].z + q[k].w);
+    int32_t inc = s;
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+      const int32_t y = __shfl_up(inc, o, WAVE);
+      if (lane >= o) inc += y;
     }
-    run += loc[k];
+    if (lane == WAVE - 1) wsum[par][w] = inc;
+    __syncthreads();
+    int32_t run = carry + inc - s, total = 0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+      const int32_t x = wsum[par][k];
+      run += k < w ? x : 0;
+      total += x;
+    }
+    int4* dst = reinterpret_cast<int4*>(v.cell_start + base);
+    int4* cnt = reinterpret_cast<int4*>(v.cell_count + base);
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      int4 o;
+      o.x = run;
+      run += q[k].x;
+      o.y = run;
+      run += q[k].y;
+      o.z = run;
+      run += q[k].z;
+      o.w = run;
+      run += q[k].w;
+      dst[k] = o;
+      cnt[k] = make_int4(0, 0, 0, 0);
+    }
+    carry += total;
+    // wsum alternates between two buffers, so one barrier per chunk
   }
-  if (base + PER >= m && base < m) v.cell_start[m] = run;
 }
 
 __global__ __launch_bounds__(BLOCK) void k_scatter(View v) {
@@ -281,9 +282,7 @@ int launch_bin(const View& v, int dim, hipStream_t s) {
   int8_t* type_cur = const_cast<int8_t*>(v.type);
   if (dim == 2) k_bin<2><<<nblk(v.n, BLOCK), BLOCK, 0, s>>>(v, type_cur);
   else k_bin<3><<<nblk(v.n, BLOCK), BLOCK, 0, s>>>(v, type_cur);
-  const unsigned ntiles = (unsigned)((v.ncell + 1 + SCAN_TILE - 1) / SCAN_TILE);
-  k_scan_tiles<<<ntiles, BLOCK, 0, s>>>(v);
-  k_scan_apply<<<ntiles, BLOCK, 0, s>>>(v);
+  k_scan_cells<<<1, SCAN_NT, 0, s>>>(v);
   k_scatter<<<nblk(v.n, BLOCK), BLOCK, 0, s>>>(v);
   return 0;
 }

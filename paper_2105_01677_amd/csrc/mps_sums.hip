@@ -108,6 +108,12 @@ __device__ inline float4 to_rel(const View& v, const double (&x)[DIM], int32_t p
                   : make_float4(r[0], r[1], r[2], __int_as_float(pc));
 }
 
+// Pressure as the gradient stage uses it: clamped at 0 when negative
+// pressure is clamped (the solve's output is clamped on read here, and
+// written back clamped by k_gradient; a reader that sees either value
+// gets the same clamped number).
+__device__ inline double p_eff(const View& v, double x) { return (v.clamp && x < 0.0) ? 0.0 : x; }
+
 __device__ inline int64_t team_row() {
   return (int64_t)xcd_block() * ROWS_PER_BLOCK + threadIdx.x / TEAM;
 }
@@ -383,14 +389,6 @@ __global__ __launch_bounds__(BLOCK) void k_smooth_density(View v, const double* 
   if (t == 0) out[row] = sw > 0.0 ? srw / sw : rho[row];
 }
 
-// p <- max(p, 0) after the PPE solve.
-__global__ __launch_bounds__(BLOCK) void k_clamp(View v) {
-  const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (i >= v.n) return;
-  const double p = v.p[i];
-  if (p < 0.0) v.p[i] = 0.0;
-}
-
 // p-hat of every fluid and wall particle (needed by Eq. 18 for both ends of
 // a pair): minimum of p over i and its non-dummy neighbours within re_n.
 template <int DIM, bool MIXED>
@@ -402,7 +400,7 @@ __global__ __launch_bounds__(BLOCK) void k_phat(View v, double* phat) {
   if (row >= v.n) return;
   // the row's own loads are issued together (no branch before the list)
   const int8_t ty = v.type[row];
-  double m = v.p[row];
+  double m = p_eff(v, v.p[row]);
   const int cnt_all = v.nb_count[row];
   const P pi = P::load(v.rs, v.rsf, row);
   const int cnt = ty == MPS_FLUID || ty == MPS_WALL ? cnt_all : 0;
@@ -418,7 +416,7 @@ __global__ __launch_bounds__(BLOCK) void k_phat(View v, double* phat) {
         [&](int32_t j) {
           Rec r;
           r.p = P::load(v.rs, v.rsf, j);
-          r.pj = v.p[j];
+          r.pj = p_eff(v, v.p[j]);
           r.fj = v.flags[j];
           return r;
         },
@@ -452,7 +450,8 @@ __global__ __launch_bounds__(BLOCK) void k_gradient(View v, const double* phat) 
   const P pi = P::load(v.rs, v.rsf, row);
   const R re = (R)v.re_n, re2 = (R)v.re_n2;
   const int cnt_all = v.nb_count[row];
-  const double p_i = v.p[row];
+  const double p_raw = v.p[row];
+  const double p_i = p_eff(v, p_raw);
   double us[DIM], rs[DIM], un[DIM], xn[DIM];
   load_vec<DIM>(v.us, row, us);
   load_vec<DIM>(v.rs, row, rs);
@@ -473,7 +472,7 @@ __global__ __launch_bounds__(BLOCK) void k_gradient(View v, const double* phat) 
       [&](int32_t j) {
         Rec r;
         r.p = P::load(v.rs, v.rsf, j);
-        r.pj = v.p[j];
+        r.pj = p_eff(v, v.p[j]);
         r.phj = CMPS ? phat[j] : 0.0;
         r.fj = v.flags[j];
         return r;
@@ -514,6 +513,7 @@ __global__ __launch_bounds__(BLOCK) void k_gradient(View v, const double* phat) 
     xn[a] = rs[a] + v.dt * (un[a] - us[a]);
     finite = finite && isfinite(un[a]) && isfinite(xn[a]);
   }
+  if (t == 0 && p_i != p_raw) v.p[row] = p_i;
   if (fluid && t == 0) {
     store_vec<DIM>(v.vel_w, row, un);
     store_vec<DIM>(v.pos_w, row, xn);
@@ -576,11 +576,6 @@ int launch_smooth_density(const View& v, const double* rho_raw, double* rho_out,
   const unsigned nb = team_blocks(v.n);
   if (dim == 2) k_smooth_density<2><<<nb, BLOCK, 0, s>>>(v, rho_raw, rho_out);
   else k_smooth_density<3><<<nb, BLOCK, 0, s>>>(v, rho_raw, rho_out);
-  return 0;
-}
-
-int launch_clamp(const View& v, hipStream_t s) {
-  k_clamp<<<(unsigned)((v.n + BLOCK - 1) / BLOCK), BLOCK, 0, s>>>(v);
   return 0;
 }
 
