@@ -118,6 +118,33 @@ def run_gpu(w, steps, warmup, *, profile_all=False, profile_cls=None):
             "state_check": check}
 
 
+def run_drop(steps=1000):
+    """The elliptic water drop (Section "Water drop"; 1,257 particles, the
+    weakly-compressible model, mixed path) from the circle for `steps` steps
+    of 1e-5 s: time per step and the ellipse the drop has become (semi-axes
+    from the second moments of the positions)."""
+    import torch
+
+    from paper_2105_01677_amd import mps
+    from paper_2105_01677_amd import workloads as W
+    w = W.water_drop(precision=W.MIXED, steps=steps)
+    a0, b0 = W.drop_axes(w.pos)
+    m = mps.MPS(w.params, w.pos, w.vel, w.ptype)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    m.step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = m.state()
+    m.close()
+    typ = st["type"].cpu().numpy()
+    a, b = W.drop_axes(st["pos"].cpu().numpy()[typ != W.GHOST])
+    return {"n_particles": w.n, "steps": steps, "t_end_s": steps * w.params["dt"],
+            "ms_per_step": 1e3 * dt / steps, "value": w.n * steps / dt,
+            "b_over_b0": b / b0, "ab_over_a0b0": a * b / (a0 * b0),
+            "ghosts": int((typ == W.GHOST).sum())}
+
+
 def state_check(w, st):
     """The timed state must still be the physical flow: no particle left the
     grid (ghosts do no work) and every fluid speed below 10 sqrt(2 g H), H
@@ -323,6 +350,9 @@ def main():
                        "state_ok": r["state_check"]["ok"]}
         log(name, extra[name])
 
+    drop = run_drop()
+    log("water_drop", drop)
+
     cfg3d = {}
     if not args.only_headline and not args.no_3d:
         w3 = W.config("cfg3", precision=W.MIXED)
@@ -369,6 +399,7 @@ def main():
         "fp64_standard_cg": extra.get("ppe_fp64_standard_cg"),
         "wc_eos_mixed": extra.get("wc_mixed"),
         "wc_eos_fp64": extra.get("wc_fp64"),
+        "water_drop_2d": drop,
         "kernel_ms_per_step": {k: v / K for k, v in tot.items()},
         "kernel_avg_launch_us": {k: 1e3 * v[0] / max(v[1], 1) for k, v in br["profile"].items()},
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
