@@ -66,6 +66,10 @@ enum { MPS_PPE_CG = 0, MPS_WC_EOS = 1 };         /* pressure model */
 enum { MPS_K_KOSHIZUKA = 0, MPS_K_CUBIC = 1 };   /* Eq. 4 / cubic kernel */
 enum { MPS_FP64 = 0, MPS_MIXED = 1 };            /* precision of the path */
 enum { MPS_GRAD_STD = 0, MPS_GRAD_CMPS = 1 };    /* standard / Eq. 18 */
+/* PPE source term: (n* - n0)/(n0 dt^2) (Eq. 13); the higher-order source
+ * from Dn/Dt at r*, u* (Eq. 21, MPS-HS); the same plus the error-compensating
+ * parts of Eq. 24 (Eq. 25, ECS) */
+enum { MPS_SRC_STD = 0, MPS_SRC_HS = 1, MPS_SRC_HS_ECS = 2 };
 
 typedef struct {
   int32_t dim;              /* 2 or 3 */
@@ -100,6 +104,8 @@ typedef struct {
   double cell_size;         /* cell side, >= re_lap (m) */
   double smagorinsky_cs;    /* Smagorinsky constant Cs of the sub-particle-scale
                                eddy viscosity (0 = off; 0.12 typical) */
+  int32_t source;           /* MPS_SRC_*: PPE source term (PPE model only;
+                               the adjoint needs MPS_SRC_STD) */
 } mps_params;
 
 typedef struct {

@@ -39,7 +39,7 @@ class OrcParams(C.Structure):
         ("dt", C.c_double), ("beta", C.c_double), ("c0", C.c_double),
         ("gamma", C.c_double), ("alpha", C.c_double), ("cg_tol", C.c_double),
         ("grid_lo", C.c_double * 3), ("cell_size", C.c_double),
-        ("smag_cs", C.c_double),
+        ("smag_cs", C.c_double), ("source", C.c_int32),
     ]
 
 
@@ -92,6 +92,7 @@ def make_params(p: dict) -> OrcParams:
     for k in ("l0", "re_n", "re_lap", "rho", "nu", "dt", "beta", "c0", "gamma",
               "alpha", "cg_tol", "cell_size", "smag_cs"):
         setattr(o, k, float(p[k]))
+    o.source = int(p.get("source", 0))
     for a in range(3):
         o.g[a] = float(p["g"][a])
         o.grid_lo[a] = float(p["grid_lo"][a])

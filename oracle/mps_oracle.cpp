@@ -85,6 +85,44 @@ T weight(int kernel, const T& r, double re) {
   return q * q * q;
 }
 
+/* d w / d r of the two kernels (zero for r >= r_e): -r_e / r^2 and
+ * -3 (1 - r/r_e)^2 / r_e. */
+template <class T>
+T dweight(int kernel, const T& r, double re) {
+  if (!(val(r) < re)) return T(0.0);
+  if (kernel == 0) return -re / (r * r);
+  T q = 1.0 - r / re;
+  return -3.0 * q * q / re;
+}
+
+/* Rate of change of the particle number density of i (Eq. 5) along the
+ * motion, Dn_i/Dt = sum_j w'(r_ij) (r_ij . u_ij) / r_ij with r_ij = r_j - r_i,
+ * u_ij = u_j - u_i, over the list members within r_e; also n_i itself.  For
+ * the kernel of Eq. 4 this is the sum of Eq. 21 (r_e / r^3 times the pair's
+ * position and velocity differences, taken with opposite orientations). */
+template <class T>
+void dn_dt(const orc_params* P, int i, const std::vector<int>& Ls, const std::vector<int>& Lj,
+           const std::vector<T>& pos, const std::vector<T>& vel, T* n_out, T* dn_out) {
+  const int dim = P->dim;
+  T n(0.0), dn(0.0);
+  for (int e = Ls[i]; e < Ls[i + 1]; ++e) {
+    int j = Lj[e];
+    T d[3], du[3], d2(0.0), du_d(0.0);
+    for (int a = 0; a < dim; ++a) {
+      d[a] = pos[(size_t)j * dim + a] - pos[(size_t)i * dim + a];
+      du[a] = vel[(size_t)j * dim + a] - vel[(size_t)i * dim + a];
+      d2 = d2 + d[a] * d[a];
+      du_d = du_d + d[a] * du[a];
+    }
+    T r = sqrt(d2);
+    if (!(val(r) < P->re_n)) continue;
+    n = n + weight(P->kernel, r, P->re_n);
+    dn = dn + dweight(P->kernel, r, P->re_n) * du_d / r;
+  }
+  *n_out = n;
+  *dn_out = dn;
+}
+
 /* Squared distance between two points, each product and sum rounded in
  * turn: (dx*dx + dy*dy) + dz*dz with dx = x_j - x_i.  The neighbour
  * criterion d^2 < r_e^2 uses this expression on both sides of the parity
@@ -596,7 +634,28 @@ int step(const orc_params* P, const Consts& C, const T& nu, const T g[3], int n,
           }
         }
         tr.diag[i] = dsum + P->alpha / (dt * dt);
-        tr.b[i] = (tr.nstar[i] - C.n0_n) / (C.n0_n * dt * dt);
+        if (P->source == 0) {
+          tr.b[i] = (tr.nstar[i] - C.n0_n) / (C.n0_n * dt * dt);
+        } else {
+          /* Eq. 21 (HS): the source from Dn/Dt at r*, u*,
+           *   b_i = (Dn/Dt)*_i / (n0 dt);
+           * Eq. 24-25 (ECS) adds, with n and Dn/Dt at r^k, u^k,
+           *   |(n - n0)/n0| (Dn/Dt)/n0 + |dt (Dn/Dt)/n0| (n - n0)/(n0 dt)
+           * inside the bracket: b_i = ((Dn/Dt)*_i / n0 + ECS_i) / dt. */
+          T nst, dns;
+          dn_dt<T>(P, i, Ls, Lj, tr.rs, tr.us, &nst, &dns);
+          T q = dns / C.n0_n;
+          if (P->source == 2) {
+            T nk, dnk;
+            dn_dt<T>(P, i, Ls, Lj, pos, vel, &nk, &dnk);
+            T e = (nk - C.n0_n) / C.n0_n;
+            T g = dnk / C.n0_n;
+            T ae = val(e) < 0.0 ? -e : e;
+            T ag = val(g) < 0.0 ? -g * dt : g * dt;
+            q = q + ae * g + ag * e / dt;
+          }
+          tr.b[i] = q / dt;
+        }
       }
       start[i + 1] = (int)col.size();
     }

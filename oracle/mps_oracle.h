@@ -25,6 +25,7 @@ typedef struct {
   int32_t grid_n[3];
   double l0, re_n, re_lap, rho, nu, g[3], dt, beta, c0, gamma, alpha, cg_tol;
   double grid_lo[3], cell_size, smag_cs;
+  int32_t source; /* PPE source: 0 Eq. 13, 1 Eq. 21 (HS), 2 Eq. 25 (HS + ECS) */
 } orc_params;
 
 /* Every pointer may be NULL (that output is skipped).  list/aval are

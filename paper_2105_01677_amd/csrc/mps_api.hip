@@ -45,6 +45,7 @@ struct mps_ctx {
   double* us = nullptr;
   double* rs = nullptr;
   double* nstar = nullptr;
+  double* src = nullptr;  // PPE source from Dn/Dt (source != MPS_SRC_STD)
   int8_t* flags = nullptr;
   int32_t *cellid = nullptr, *slot = nullptr, *cell_count = nullptr, *cell_start = nullptr,
           *perm = nullptr;
@@ -233,6 +234,8 @@ View make_view(const mps_ctx* c) {
   v.us = c->us;
   v.rs = c->rs;
   v.nstar = c->nstar;
+  v.src = c->src;
+  v.source = P.source;
   v.flags = c->flags;
   v.cellid = c->cellid;
   v.slot = c->slot;
@@ -301,6 +304,8 @@ mps_status check_params(const mps_params* P, int64_t n) {
   if (P->cg_maxit < 1 || !(P->cg_tol > 0)) return MPS_E_ARG;
   if (P->cg_pipelined != 0 && P->cg_pipelined != 1) return MPS_E_ARG;
   if (!(P->smagorinsky_cs >= 0.0) || P->smagorinsky_cs > 1.0) return MPS_E_ARG;
+  if (P->source < MPS_SRC_STD || P->source > MPS_SRC_HS_ECS) return MPS_E_ARG;
+  if (P->source != MPS_SRC_STD && P->pmode != MPS_PPE_CG) return MPS_E_ARG;
   int64_t nc = 1;
   for (int a = 0; a < P->dim; ++a) {
     if (P->grid_n[a] < 1 || P->grid_n[a] > 1023) return MPS_E_ARG;
@@ -790,6 +795,7 @@ mps_status mps_init(const mps_params* params, int64_t n, const double* pos, cons
   A(dalloc(&c->us, nv));
   A(dalloc(&c->rs, nv));
   A(dalloc(&c->nstar, n));
+  if (params->source != MPS_SRC_STD) A(dalloc(&c->src, n));
   A(dalloc(&c->flags, n));
   A(dalloc(&c->cellid, n));
   A(dalloc(&c->slot, n));
@@ -901,7 +907,7 @@ mps_status mps_free(mps_ctx* c) {
   if (c->s) (void)hipStreamSynchronize(c->s);
   void* ptrs[] = {c->pos[0], c->pos[1], c->vel[0], c->vel[1], c->pres[0], c->pres[1],
                   c->type[0], c->type[1], c->id[0], c->id[1], c->pd[0], c->pd[1],
-                  c->pcell, c->posf, c->rsf, c->us, c->rs, c->nstar, c->flags,
+                  c->pcell, c->posf, c->rsf, c->us, c->rs, c->nstar, c->src, c->flags,
                   c->cellid, c->slot, c->perm, c->cell_count, c->cell_start,
                   c->nb_count,
                   c->nb_list, c->a_nnz, c->a_col, c->a_val, c->diag, c->b, c->r, c->z,
@@ -1215,6 +1221,7 @@ mps_status mps_step_adjoint(mps_ctx* c, const double* pos_bar, const double* vel
   if (!c || !pos_bar || !vel_bar || !pos_bar_prev || !vel_bar_prev) return MPS_E_ARG;
   if (!c->tape) return fail(c, MPS_E_ARG, "call mps_tape_alloc first");
   if (c->P.grad != MPS_GRAD_STD) return fail(c, MPS_E_ARG, "adjoint needs the standard gradient");
+  if (c->P.source != MPS_SRC_STD) return fail(c, MPS_E_ARG, "adjoint needs the source of Eq. 13");
   if (c->poisoned) return fail(c, MPS_E_POISONED, "context poisoned; call mps_set_state");
   const bool wc = c->P.pmode == MPS_WC_EOS;
   // forward recompute of the step's stages from the current (taped) state

@@ -117,6 +117,7 @@ struct View {
   double cg_tol2;
   double g[3];
   int gamma_i, kernel, grad, clamp;
+  int source;         // MPS_SRC_*: PPE source term
   // sorted state, current buffers
   const double* pos;  double* pos_w;
   const double* vel;  double* vel_w;
@@ -131,6 +132,7 @@ struct View {
   double* us;         // u*
   double* rs;         // r*
   double* nstar;
+  double* src;        // PPE right-hand side from Dn/Dt (source != MPS_SRC_STD)
   int8_t* flags;
   // binning
   int32_t* cellid;    // old order
@@ -351,6 +353,15 @@ __device__ inline double row_dot(const int32_t* __restrict__ col, const VT* __re
     s += (double)val[e] * x(col[e]);
   }
   return s;
+}
+
+// d w / d r of the two kernels, zero at and beyond re.
+template <class R>
+__device__ inline R dweight(int kernel, R r, R re) {
+  if (!(r < re)) return R(0);
+  if (kernel == MPS_K_KOSHIZUKA) return -re / (r * r);
+  R q = R(1) - r / re;
+  return R(-3) * q * q / re;
 }
 
 // Kernel weight (Eq. 4, or the cubic kernel), zero at and beyond re.

@@ -167,6 +167,7 @@ __global__ __launch_bounds__(BLOCK) void k_assemble(View v, const double* rhs, i
     const double rho_i = MULTI ? v.rho_s[row] : 0.0;
     const double p_row = v.p[row], ns_row = v.nstar[row];
     const double rhs_row = rhs ? rhs[row] : 0.0;
+    const double src_row = v.source != MPS_SRC_STD ? v.src[row] : 0.0;
     const int cnt = inner ? cnt_all : 0;
     double dsum = 0.0, ax = 0.0;
     int nnz = 0;
@@ -243,7 +244,9 @@ __global__ __launch_bounds__(BLOCK) void k_assemble(View v, const double* rhs, i
       double diag = 1.0, b = 0.0, x0 = 0.0;
       if (inner) {
         diag = dsum + v.alpha / (v.dt * v.dt);
-        b = rhs ? rhs_row : (ns_row - v.n0_n) / (v.n0_n * v.dt * v.dt);
+        b = rhs ? rhs_row
+                : v.source != MPS_SRC_STD ? src_row
+                                          : (ns_row - v.n0_n) / (v.n0_n * v.dt * v.dt);
         x0 = zero_x0 ? 0.0 : p_row;
       }
       const double r0 = b - diag * x0 - ax;

@@ -256,7 +256,7 @@ __device__ inline double ipow(double x, int e) {
 // n* - n0 is of the order of the FP32 rounding of n* itself.  In 2-D the
 // FP64 position (double2) is as wide as the FP32 copy (float4), so this
 // costs no extra bytes.
-template <int DIM>
+template <int DIM, int SRC>
 __global__ __launch_bounds__(BLOCK) void k_density(View v, int wc) {
   using P = PosRef<DIM, false>;
   using R = typename P::R;
@@ -267,20 +267,85 @@ __global__ __launch_bounds__(BLOCK) void k_density(View v, int wc) {
   const int8_t ty = v.type[row];
   const int cnt_all = v.nb_count[row];
   const P pi = P::load(v.rs, v.rsf, row);
+  double ui[DIM], xk[DIM], uk[DIM];
+  if constexpr (SRC >= MPS_SRC_HS) load_vec<DIM>(v.us, row, ui);
+  if constexpr (SRC == MPS_SRC_HS_ECS) {
+    load_vec<DIM>(v.pos, row, xk);
+    load_vec<DIM>(v.vel, row, uk);
+  }
   const int cnt = ty != MPS_GHOST ? cnt_all : 0;
+  // n* at r*; with a Dn/Dt source also Dn/Dt at r*, u* (Eq. 21) and, for
+  // ECS, n and Dn/Dt at r^k, u^k (Eq. 24):
+  //   Dn_i/Dt = sum_j w'(r_ij) ((r_j - r_i) . (u_j - u_i)) / r_ij
   R s = R(0);
+  double dns = 0.0, nk = 0.0, dnk = 0.0;
   {
     const R re = (R)v.re_n, re2 = (R)v.re_n2;
+    struct Rec {
+      P p;
+      double u[DIM], x[DIM], w[DIM];
+    };
     for_list<SUM_U_DENSITY>(
-        v, row, cnt, t, [&](int32_t j) { return P::load(v.rs, v.rsf, j); },
-        [&](int32_t, const P& pj, bool ok) {
+        v, row, cnt, t,
+        [&](int32_t j) {
+          Rec r;
+          r.p = P::load(v.rs, v.rsf, j);
+          if constexpr (SRC >= MPS_SRC_HS) load_vec<DIM>(v.us, j, r.u);
+          if constexpr (SRC == MPS_SRC_HS_ECS) {
+            load_vec<DIM>(v.pos, j, r.x);
+            load_vec<DIM>(v.vel, j, r.w);
+          }
+          return r;
+        },
+        [&](int32_t, const Rec& rj, bool ok) {
           R d[DIM];
-          pi.diff(pj, v.cs32, d);
+          pi.diff(rj.p, v.cs32, d);
           const R r2 = norm2<DIM, R>(d);
-          const R w = weight<R>(v.kernel, sqrt(r2), re);
-          s += (ok && r2 < re2) ? w : R(0);
+          const R rr = sqrt(r2);
+          const bool in = ok && r2 < re2;
+          const R w = weight<R>(v.kernel, rr, re);
+          s += in ? w : R(0);
+          if constexpr (SRC >= MPS_SRC_HS) {
+            double dud = 0.0;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) dud += d[a] * (rj.u[a] - ui[a]);
+            const double f = dweight<double>(v.kernel, rr, re) * dud / rr;
+            dns += in ? f : 0.0;
+          }
+          if constexpr (SRC == MPS_SRC_HS_ECS) {
+            double dk[DIM], dud = 0.0;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+              dk[a] = rj.x[a] - xk[a];
+              dud += dk[a] * (rj.w[a] - uk[a]);
+            }
+            const double rk2 = norm2<DIM, double>(dk);
+            const double rk = sqrt(rk2);
+            const bool ink = ok && rk2 < v.re_n2;
+            const double wk = weight<double>(v.kernel, rk, v.re_n);
+            const double fk = dweight<double>(v.kernel, rk, v.re_n) * dud / rk;
+            nk += ink ? wk : 0.0;
+            dnk += ink ? fk : 0.0;
+          }
         });
     s = team_sum(s);
+    if constexpr (SRC >= MPS_SRC_HS) dns = team_sum(dns);
+    if constexpr (SRC == MPS_SRC_HS_ECS) {
+      nk = team_sum(nk);
+      dnk = team_sum(dnk);
+    }
+  }
+  if constexpr (SRC >= MPS_SRC_HS) {
+    if (t == 0) {
+      // b_i = ((Dn/Dt)*_i / n0 + ECS_i) / dt, ECS_i = |e| g + |g dt| e / dt
+      // with e = (n_i - n0)/n0 and g = (Dn/Dt)_i / n0 at r^k, u^k
+      double q = dns / v.n0_n;
+      if constexpr (SRC == MPS_SRC_HS_ECS) {
+        const double e = (nk - v.n0_n) / v.n0_n, g = dnk / v.n0_n;
+        q += fabs(e) * g + fabs(g * v.dt) * e / v.dt;
+      }
+      v.src[row] = q / v.dt;
+    }
   }
   if (t != 0) return;
   const double ns = (double)s;
@@ -548,13 +613,20 @@ int launch_predict(const View& v, int dim, int precision, hipStream_t s) {
   return 0;
 }
 
+template <int DIM>
+static void density_t(const View& v, unsigned nb, int wc, hipStream_t s) {
+  if (v.source == MPS_SRC_HS) k_density<DIM, MPS_SRC_HS><<<nb, BLOCK, 0, s>>>(v, wc);
+  else if (v.source == MPS_SRC_HS_ECS) k_density<DIM, MPS_SRC_HS_ECS><<<nb, BLOCK, 0, s>>>(v, wc);
+  else k_density<DIM, MPS_SRC_STD><<<nb, BLOCK, 0, s>>>(v, wc);
+}
+
 int launch_density(const View& v, int dim, int precision, int pmode, hipStream_t s) {
   const unsigned nb = team_blocks(v.n);
   const bool mx = precision == MPS_MIXED;
   const int wc = pmode == MPS_WC_EOS;
   (void)mx;
-  if (dim == 2) k_density<2><<<nb, BLOCK, 0, s>>>(v, wc);
-  else k_density<3><<<nb, BLOCK, 0, s>>>(v, wc);
+  if (dim == 2) density_t<2>(v, nb, wc, s);
+  else density_t<3>(v, nb, wc, s);
   return 0;
 }
 

@@ -476,3 +476,37 @@ def test_water_drop_follows_the_inviscid_ellipse_gpu(gpu):
         assert abs(b / b0 - eb[k * 1000]) < 0.03 * eb[k * 1000]
         assert 0.98 < a * b / (a0 * b0) < 1.08
     m.close()
+
+
+@pytest.mark.parametrize("source", [W.SRC_HS, W.SRC_HS_ECS])
+@pytest.mark.parametrize("precision,cg_tol,tol", PRECISIONS)
+def test_one_step_dn_dt_sources(gpu, orc, source, precision, cg_tol, tol):
+    """The PPE driven by Dn/Dt (Eq. 21, MPS-HS) and with the error-
+    compensating parts (Eq. 24-25, ECS): one step against the oracle in
+    2-D (1,432 particles) and 3-D (8,000 + walls), jittered."""
+    w3 = W.jitter(W.lattice_block(3, [20, 20, 20], walls_below=True, dt=2e-4))
+    for w in (W.jitter(W.config("cfg1", precision=precision)), w3):
+        w.params.update(precision=precision, cg_tol=cg_tol, source=source)
+        _compare_step(gpu, orc, w, tol)
+
+
+def test_dn_dt_source_full_size(gpu, orc):
+    """HS + ECS on the mixed path at the 44,832-particle size, jittered."""
+    w = W.jitter(W.config("cfg2", precision=W.MIXED))
+    w.params.update(source=W.SRC_HS_ECS)
+    _compare_step(gpu, orc, w, 1e-4)
+
+
+def test_dn_dt_source_refused_by_the_adjoint(gpu):
+    w = W.config("cfg1")
+    w.params.update(source=W.SRC_HS)
+    m = gpu.MPS(w.params, w.pos, w.vel, w.ptype)
+    m.tape_alloc(2)
+    m.tape_save(0)
+    m.step(1)
+    m.tape_load(0)
+    import torch
+    z = torch.zeros((w.n, 2), dtype=torch.float64, device="cuda")
+    with pytest.raises(gpu.MPSError):
+        m.step_adjoint(z, z)
+    m.close()

@@ -37,7 +37,8 @@ def test_params_layout():
     from paper_2105_01677_amd import mps
     P = mps.Params
     assert P.l0.offset == 48          # 12 int32 before the doubles
-    assert ctypes.sizeof(P) == 48 + 8 * 19
+    assert ctypes.sizeof(P) == 48 + 8 * 19 + 8   # + int32 source, padded
+    assert P.source.offset == 48 + 8 * 19
     assert ctypes.sizeof(mps.StepStats) == 64
     assert mps.StepStats.cg_redone.offset == 56
 

@@ -464,6 +464,52 @@ def test_still_tank_hydrostatic_level(orc):
     assert 0.8 < ratio < 1.4
 
 
+def _n_all_pairs(pos, re, kernel):
+    """Eq. 5 by numpy over all pairs (j != i, r < re)."""
+    d = pos[None, :, :] - pos[:, None, :]
+    r = np.sqrt((d * d).sum(axis=2))
+    np.fill_diagonal(r, np.inf)
+    with np.errstate(divide="ignore"):
+        w = np.where(r < re, re / r - 1.0 if kernel == 0 else (1.0 - r / re) ** 3, 0.0)
+    return w.sum(axis=1)
+
+
+@pytest.mark.parametrize("source", [W.SRC_HS, W.SRC_HS_ECS])
+def test_dn_dt_sources_against_central_differences(orc, source):
+    """Eq. 21 (HS) drives the PPE by Dn/Dt, the rate of change of Eq. 5 along
+    the motion: b_i = (Dn/Dt)*_i / (n0 dt) at r*, u*.  ECS (Eq. 24-25) adds
+    |e| g + |g dt| e / dt inside the bracket, e = (n - n0)/n0 and g =
+    (Dn/Dt)/n0 at r^k, u^k.  The oracle's right-hand side against numpy
+    all-pairs central differences n(r + h u) - n(r - h u) at the oracle's
+    own r*, u* (a sign or orientation slip, a wrong kernel derivative or a
+    dropped term fails it)."""
+    w = W.jitter(W.config("cfg1"), vel_sigma=0.3)
+    prm = dict(w.params, source=source)
+    st, o = orc.step(prm, w.pos, w.vel, w.ptype, want_lists=False)
+    assert st == 0
+    live = w.ptype != W.GHOST
+    re, kern, dt = prm["re_n"], prm["kernel"], prm["dt"]
+    n0 = orc.lattice_constants(2, prm["l0"], re, kern)[0]
+
+    def ddt(x, u):
+        h = 1e-6 / np.abs(u).max()
+        return (_n_all_pairs(x + h * u, re, kern) - _n_all_pairs(x - h * u, re, kern)) / (2 * h)
+
+    rs, us = o["rs"][live], o["us"][live]
+    q = ddt(rs, us) / n0
+    if source == W.SRC_HS_ECS:
+        x, u = w.pos[live], w.vel[live]
+        e = (_n_all_pairs(x, re, kern) - n0) / n0
+        g = ddt(x, u) / n0
+        q = q + np.abs(e) * g + np.abs(g * dt) * e / dt
+    ref = q / dt
+    inner = o["flags"][live] == 0
+    got = o["b"][live][inner]
+    err = np.abs(got - ref[inner]).max() / np.abs(ref[inner]).max()
+    print("Dn/Dt source", source, "rel err", err)
+    assert err < 1e-6
+
+
 def test_ellipse_ode_invariants():
     """The reference itself: ab is an invariant of the ODE (d(ab)/dt = 0),
     and at early times A stays ~A0 (dA/dt = 0 at a = b), so b ~ R e^{A0 t}."""
