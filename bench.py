@@ -337,13 +337,16 @@ def main():
     # precisions with the two-kernel textbook CG, and the weakly-compressible
     # model
     extra = {}
-    for name, prec, pm, pl in (("ppe_fp64", W.FP64, W.PPE_CG, 1),
+    for name, prec, pm, pl in (("ppe_mixed_hs_ecs", W.MIXED, W.PPE_CG, 1),
+                               ("ppe_fp64", W.FP64, W.PPE_CG, 1),
                                ("ppe_mixed_standard_cg", W.MIXED, W.PPE_CG, 0),
                                ("ppe_fp64_standard_cg", W.FP64, W.PPE_CG, 0),
                                ("wc_mixed", W.MIXED, W.WC_EOS, 0),
                                ("wc_fp64", W.FP64, W.WC_EOS, 0)):
         wx = W.config("cfg2", precision=prec, pmode=pm)
         wx.params["cg_pipelined"] = pl
+        if name.endswith("hs_ecs"):
+            wx.params["source"] = W.SRC_HS_ECS
         r = run_gpu(wx, K, Wm)
         extra[name] = {"value": r["particle_steps_per_s"], "ms_per_step": r["ms_per_step"],
                        "cg_iters_mean": r["stats"]["cg_iters_total"] / K,
@@ -397,6 +400,7 @@ def main():
         "mixed_vs_fp64_plain": hd["particle_steps_per_s"] / extra["ppe_fp64"]["value"],
         "mixed_standard_cg": extra.get("ppe_mixed_standard_cg"),
         "fp64_standard_cg": extra.get("ppe_fp64_standard_cg"),
+        "mixed_hs_ecs_source": extra.get("ppe_mixed_hs_ecs"),
         "wc_eos_mixed": extra.get("wc_mixed"),
         "wc_eos_fp64": extra.get("wc_fp64"),
         "water_drop_2d": drop,

@@ -36,7 +36,7 @@ def gpu_grads(torch, w, nsteps, K, direction, w_var=9.81, rho_i=None, nu_i=None)
     d = torch.tensor(direction, dtype=torch.float64, device="cuda")
     fluid = torch.tensor(w.ptype == W.FLUID, device="cuda")
     du = float((u0.grad * d)[fluid].sum())
-    return float(L), float(nu.grad), float(g.grad[0]), du
+    return float(L.detach()), float(nu.grad), float(g.grad[0]), du
 
 
 def gpu_loss(torch, w, nsteps, params=None, vel=None, w_var=9.81):
