@@ -510,3 +510,60 @@ def test_dn_dt_source_refused_by_the_adjoint(gpu):
     with pytest.raises(gpu.MPSError):
         m.step_adjoint(z, z)
     m.close()
+
+
+def test_degenerate_inputs(gpu, orc):
+    """Tiny and empty-of-work inputs against the oracle: one fluid particle
+    in free fall (a free-surface particle, p = 0), two fluid particles
+    within each other's radius, and a block of walls and dummies without
+    fluid (at rest every source is zero up to rounding); an empty input is
+    refused."""
+    base = W.config("cfg1")
+    prm = dict(base.params)
+    lo, cs = prm["grid_lo"], prm["cell_size"]
+    centre = np.array([lo[0] + 5.5 * cs, lo[1] + 5.5 * cs])
+    cases = {
+        "one": (centre[None, :], np.array([[0.1, 0.0]]), np.array([W.FLUID], np.int8)),
+        "two": (np.stack([centre, centre + [0.5 * prm["l0"], 0.3 * prm["l0"]]]),
+                np.array([[0.1, 0.0], [-0.1, 0.05]]), np.array([W.FLUID, W.FLUID], np.int8)),
+        "walls_only": (base.pos[base.ptype != W.FLUID], np.zeros(((base.ptype != W.FLUID).sum(), 2)),
+                       base.ptype[base.ptype != W.FLUID]),
+    }
+    for name, (pos, vel, typ) in cases.items():
+        for pmode in (W.PPE_CG, W.WC_EOS):
+            p = dict(prm, pmode=pmode)
+            m = gpu.MPS(p, pos, vel, typ)
+            s = m.step(3)
+            g = {k: _np(v) for k, v in m.state().items()}
+            m.close()
+            st, opos, ovel, ot, op, ofl = orc.run(p, pos, vel, typ, 3)
+            assert st == 0
+            np.testing.assert_array_equal(g["type"], ot)
+            assert np.abs(g["pos"] - opos).max() < 1e-12, name
+            assert np.abs(g["vel"] - ovel).max() < 1e-12, name
+            assert np.abs(g["p"] - op).max() <= 1e-9 * max(1.0, np.abs(op).max()), name
+            if name == "walls_only" and pmode == W.PPE_CG:
+                # at rest every source is zero up to the rounding of n*
+                assert np.abs(g["p"]).max() < 1e-3
+            if name == "one":
+                # free fall: three steps of u += g dt
+                assert g["vel"][0, 1] == pytest.approx(-9.81 * 3 * p["dt"], rel=1e-12)
+    with pytest.raises(gpu.MPSError):
+        gpu.MPS(prm, np.zeros((0, 2)), np.zeros((0, 2)), np.zeros(0, np.int8))
+
+
+def test_neighbor_cap_boundary(gpu):
+    """A cap equal to the largest list is accepted; one less overflows."""
+    w = W.config("cfg1")
+    m = gpu.MPS(w.params, w.pos, w.vel, w.ptype)
+    cnt = _np(m.neighbors()[1]).max()
+    m.close()
+    for cap, ok in ((int(cnt), True), (int(cnt) - 1, False)):
+        m = gpu.MPS(dict(w.params, max_neigh=cap), w.pos, w.vel, w.ptype)
+        if ok:
+            m.step(1)
+        else:
+            with pytest.raises(gpu.MPSError) as e:
+                m.step(1)
+            assert e.value.status == gpu.E_NEIGH_OVERFLOW
+        m.close()
