@@ -66,7 +66,7 @@ struct mps_ctx {
   double* partA = nullptr;
   double* partB = nullptr;
   double *pl_z = nullptr, *pl_s = nullptr, *pl_m[2] = {nullptr, nullptr},
-         *pl_part[2] = {nullptr, nullptr};
+         *pl_part[2] = {nullptr, nullptr}, *pl_part2[2] = {nullptr, nullptr};
   int nspmv = 0, nupd = 0, npcg = 0, pcg_fused = 0;
   CGScalars* sc = nullptr;
   int32_t* status = nullptr;
@@ -263,6 +263,9 @@ View make_view(const mps_ctx* c) {
   v.pl_m[1] = c->pl_m[1];
   v.pl_part[0] = c->pl_part[0];
   v.pl_part[1] = c->pl_part[1];
+  v.pl_part2[0] = c->pl_part2[0];
+  v.pl_part2[1] = c->pl_part2[1];
+  v.npcg2 = std::min(c->npcg, PCG_SPLIT_G);
   v.nspmv = c->nspmv;
   v.nupd = c->nupd;
   v.npcg = c->npcg;
@@ -839,6 +842,7 @@ mps_status mps_init(const mps_params* params, int64_t n, const double* pos, cons
     for (int k = 0; k < 2; ++k) {
       A(dalloc(&c->pl_m[k], n));
       A(dalloc(&c->pl_part[k], (size_t)c->npcg * 4));
+      A(dalloc(&c->pl_part2[k], (size_t)PCG_SPLIT_G * 4));
     }
   }
   A(dalloc(&c->sc, 1));
@@ -914,7 +918,8 @@ mps_status mps_free(mps_ctx* c) {
                   c->q, c->p_save, c->partA, c->partB, c->sc, c->status, c->counts,
                   c->rho_s[0], c->rho_s[1], c->nu_l[0], c->nu_l[1], c->nut, c->mu,
                   c->rho_o, c->nu_o,
-                  c->pl_z, c->pl_s, c->pl_m[0], c->pl_m[1], c->pl_part[0], c->pl_part[1]};
+                  c->pl_z, c->pl_s, c->pl_m[0], c->pl_m[1], c->pl_part[0], c->pl_part[1],
+                  c->pl_part2[0], c->pl_part2[1]};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (int k = 0; k < 2; ++k) {

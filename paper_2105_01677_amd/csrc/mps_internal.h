@@ -70,9 +70,6 @@ struct CGScalars {
   // by workgroup 0 of iteration k and read by iteration k + 1 only
   double gam[2];
   double alp[2];
-  // split pipelined variant: alpha and beta of the running iteration,
-  // written by the reduction kernel and read by the iteration kernel
-  double ab[2];
 };
 
 // Grid caps of the CG kernels: every workgroup of one kernel sums all the
@@ -94,6 +91,10 @@ constexpr int CG_UPD_BLOCKS = 1024;
 #define PCG_SPLIT_BLOCK 256
 #endif
 constexpr int RED_BLOCK = 1024;  // the one workgroup of a CG reduction kernel
+// split schedule: the per-workgroup partials of an iteration are first
+// summed by PCG_SPLIT_G workgroups of RED2_BLOCK threads (contiguous slices,
+// fixed order); the next iteration's workgroups sum those few
+constexpr int PCG_SPLIT_G = 64, RED2_BLOCK = 256;
 // Matrix entries per lane loaded ahead of the reduction in the pipelined
 // CG iteration (6 x 8 lanes cover a 2-D row: at most 44 inner neighbours on
 // a lattice at re = 4 l0)
@@ -168,6 +169,8 @@ struct View {
   double* pl_s;
   double* pl_m[2];
   double* pl_part[2]; // per-workgroup (r,u), (w,u), (r,r), double buffered
+  double* pl_part2[2];// split schedule: sums of slices of pl_part (npcg2 each)
+  int npcg2;
   int32_t* status;
   // two-phase / turbulence (null when single phase)
   const double* rho_s;   // smoothed density <rho>_i, sorted

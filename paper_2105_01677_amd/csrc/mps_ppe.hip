@@ -398,8 +398,9 @@ __global__ __launch_bounds__(BLOCK) void k_cg_update(View v) {
 //   fused  (grid <= pcg_fused_capacity(), all workgroups resident): one
 //          kernel per iteration; every workgroup reduces all partials of
 //          the previous iteration itself, in the same fixed order;
-//   split  (larger grids): a one-workgroup reduction kernel, then the
-//          iteration kernel reading alpha and beta from the device scalars.
+//   split  (larger grids): PCG_SPLIT_G workgroups first sum contiguous
+//          slices of the partials (fixed order), then every workgroup of
+//          the iteration kernel sums those slice sums itself.
 // In both, every load that does not depend on the scalars (the row length,
 // its first matrix entries, the gathers of m, the row's own vectors) is
 // issued first, so their latencies overlap.
@@ -543,7 +544,7 @@ __global__ __launch_bounds__(pcg_nt<FUSED>()) void k_pcg_setup(View v) {
 }
 
 // Scalars of iteration k from (r,u), (w,u), (r,r) of its partials: the
-// convergence test, beta and alpha; workgroup 0 (or the reduction kernel)
+// convergence test, beta and alpha; workgroup 0 of the iteration kernel
 // records them.
 __device__ inline bool pcg_scalars(const View& v, const double (&tot)[3], int par,
                                    double gam_old, double alp_old, double bb, bool write,
@@ -560,22 +561,27 @@ __device__ inline bool pcg_scalars(const View& v, const double (&tot)[3], int pa
     } else {
       sc->gam[par] = gam;
       sc->alp[par] = alpha;
-      sc->ab[0] = alpha;
-      sc->ab[1] = beta;
       sc->iter += 1;
     }
   }
   return done;
 }
 
-// split schedule: reduction of iteration k's partials
+// split schedule: workgroup g sums slice g of iteration k's partials (a
+// contiguous range, fixed order) into pl_part2; the iteration kernel sums
+// the npcg2 slice sums
 template <int PAR>
-__global__ __launch_bounds__(RED_BLOCK) void k_pcg_reduce(View v) {
-  CGScalars* sc = v.sc;
-  if (sc->converged) return;
-  double tot[3], alpha, beta;
-  reduce_partials<RED_BLOCK, 4>(v.pl_part[PAR], v.npcg, tot);
-  pcg_scalars(v, tot, PAR, sc->gam[PAR ^ 1], sc->alp[PAR ^ 1], sc->bb, true, alpha, beta);
+__global__ __launch_bounds__(RED2_BLOCK) void k_pcg_reduce(View v) {
+  if (v.sc->converged) return;
+  const int per = (v.npcg + v.npcg2 - 1) / v.npcg2;
+  const int b0 = blockIdx.x * per;
+  const int nb = min(per, v.npcg - b0);
+  double tot[3];
+  reduce_partials<RED2_BLOCK, 4>(v.pl_part[PAR] + (int64_t)b0 * 4, nb > 0 ? nb : 0, tot);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) v.pl_part2[PAR][(int64_t)blockIdx.x * 4 + k] = tot[k];
+  }
 }
 
 template <class VT, int PAR, bool FUSED>
@@ -583,6 +589,7 @@ __global__ __launch_bounds__(pcg_nt<FUSED>()) void k_pcg_iter(View v) {
   constexpr int U = CG_UNROLL;
   constexpr int NT = pcg_nt<FUSED>();
   static_assert(PCG_PK * PCG_BLOCK >= PCG_MAX_BLOCKS, "one partial load per slot");
+  static_assert(PCG_SPLIT_G <= PCG_SPLIT_BLOCK, "one slice sum per thread");
   __shared__ double sh_in[3 * (NT / WAVE)], sh_out[3 * (NT / WAVE)];
   CGScalars* sc = v.sc;
   const int t = team_lane();
@@ -590,21 +597,18 @@ __global__ __launch_bounds__(pcg_nt<FUSED>()) void k_pcg_iter(View v) {
   // -- loads that do not need this iteration's scalars, all issued before
   //    the first wait: the previous partials, the row length, the first U
   //    entries per lane, the row's own vectors (every lane: clamped row) --
-  double4 q[PCG_PK];
-  if constexpr (FUSED) load_partials<NT, PCG_PK>(v.pl_part[PAR], v.npcg, q);
+  // fused: every partial of the previous iteration; split: the slice sums
+  constexpr int PK = FUSED ? PCG_PK : 1;
+  const double* part = FUSED ? v.pl_part[PAR] : v.pl_part2[PAR];
+  const int npart = FUSED ? v.npcg : v.npcg2;
+  double4 q[PK];
+  load_partials<NT, PK>(part, npart, q);
   const double* __restrict__ M = v.pl_m[PAR];
   double* __restrict__ Mn = v.pl_m[PAR ^ 1];
   const VT* __restrict__ aval = reinterpret_cast<const VT*>(v.a_val);
   const int conv = sc->converged;
-  double gam_old = 0.0, alp_old = 0.0, bb = 0.0, alpha = 0.0, beta = 0.0;
-  if constexpr (FUSED) {
-    gam_old = sc->gam[PAR ^ 1];
-    alp_old = sc->alp[PAR ^ 1];
-    bb = sc->bb;
-  } else {
-    alpha = sc->ab[0];
-    beta = sc->ab[1];
-  }
+  const double gam_old = sc->gam[PAR ^ 1], alp_old = sc->alp[PAR ^ 1], bb = sc->bb;
+  double alpha = 0.0, beta = 0.0;
   const int64_t row = (int64_t)xcd_block() * (NT / TEAM) + threadIdx.x / TEAM;
   const bool live = row < v.n;
   const int64_t rc = live ? row : v.n - 1;
@@ -650,10 +654,10 @@ __global__ __launch_bounds__(pcg_nt<FUSED>()) void k_pcg_iter(View v) {
                o_s = dpp_move<DPP_SHL3>(ov), o_p = dpp_move<DPP_SHL4>(ov),
                o_r = dpp_move<DPP_SHL5>(ov), o_x = dpp_move<DPP_SHL6>(ov);
 
-  // -- the scalars --
-  if constexpr (FUSED) {
+  // -- the scalars (every workgroup alike; workgroup 0 records them) --
+  {
     double tot[3];
-    sum_partials_loaded<NT, PCG_PK>(q, v.npcg, tot, sh_in);
+    sum_partials_loaded<NT, PK>(q, npart, tot, sh_in);
     if (pcg_scalars(v, tot, PAR, gam_old, alp_old, bb, blockIdx.x == 0, alpha, beta)) return;
   }
 
@@ -816,8 +820,9 @@ int launch_pcg_setup(const View& v, int precision, hipStream_t s) {
 }
 
 int launch_pcg_reduce(const View& v, int parity, hipStream_t s) {
-  if (parity) launch_k(k_pcg_reduce<1>, 1, RED_BLOCK, s, v);
-  else launch_k(k_pcg_reduce<0>, 1, RED_BLOCK, s, v);
+  const unsigned g = (unsigned)v.npcg2;
+  if (parity) launch_k(k_pcg_reduce<1>, g, RED2_BLOCK, s, v);
+  else launch_k(k_pcg_reduce<0>, g, RED2_BLOCK, s, v);
   return 0;
 }
 
