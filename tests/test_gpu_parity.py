@@ -47,6 +47,8 @@ def _list_inputs():
         "random3d": W.random_box(2500, 3, seed=12),
         "cfg1_jitter": W.jitter(W.config("cfg1")),
         "block3d_jitter": W.jitter(W.lattice_block(3, [14, 12, 10], walls_below=True)),
+        "cfg1_lattice": W.config("cfg1"),
+        "block3d_lattice": W.lattice_block(3, [14, 12, 10], walls_below=True),
     }
     w = W.random_box(1200, 2, seed=13)
     cs, lo = w.params["cell_size"], w.params["grid_lo"]
@@ -57,10 +59,16 @@ def _list_inputs():
     return cases
 
 
+@pytest.mark.parametrize("precision", [W.FP64, W.MIXED])
 @pytest.mark.parametrize("name", ["random2d", "random3d", "cfg1_jitter", "block3d_jitter",
-                                  "cell_faces"])
-def test_neighbor_lists_bit_exact(gpu, orc, name):
+                                  "cell_faces", "cfg1_lattice", "block3d_lattice"])
+def test_neighbor_lists_bit_exact(gpu, orc, name, precision):
+    """Lists against the oracle's cell-linked list, bit for bit.  The mixed
+    path tests candidates in FP32 first and re-decides those near re_lap in
+    FP64; the unjittered lattices put many pairs at exactly 4 l0 (2-D) or
+    near 3.1 l0 (3-D), where that re-decision is what keeps them out."""
     w = _list_inputs()[name]
+    w.params["precision"] = precision
     print(f"case {name} n={w.n}", flush=True)
     st, cell_o, cnt_o, lst_o = orc.neighbors_cells(w.params, w.pos, w.ptype)
     assert st == 0
