@@ -31,13 +31,17 @@ struct mps_ctx {
   int ncell = 0;
   hipStream_t s = nullptr;
   double n0_n = 0, n0_lap = 0, lam_lap = 0;
+  // state buffers: a step reads buffer cur and writes the next one of a ring
+  // of NBUF (three, so that a step's input survives while the step after
+  // it is already enqueued)
+  static constexpr int NBUF = 3;
   int cur = 0;
   // state, double-buffered
-  double* pos[2] = {nullptr, nullptr};
-  double* vel[2] = {nullptr, nullptr};
-  double* pres[2] = {nullptr, nullptr};
-  int8_t* type[2] = {nullptr, nullptr};
-  int32_t* id[2] = {nullptr, nullptr};
+  double* pos[NBUF] = {};
+  double* vel[NBUF] = {};
+  double* pres[NBUF] = {};
+  int8_t* type[NBUF] = {};
+  int32_t* id[NBUF] = {};
   // per-step
   int32_t* pcell = nullptr;
   float4* posf = nullptr;
@@ -57,8 +61,8 @@ struct mps_ctx {
   double* p_save = nullptr;
   // two-phase / turbulence
   bool multi = false;
-  double* rho_s[2] = {nullptr, nullptr};
-  double* nu_l[2] = {nullptr, nullptr};
+  double* rho_s[NBUF] = {};
+  double* nu_l[NBUF] = {};
   double* rho_o = nullptr;  // <rho> and nu in the caller's order (tape reloads)
   double* nu_o = nullptr;
   double* nut = nullptr;
@@ -90,7 +94,7 @@ struct mps_ctx {
   // a8; wc2: two whole weakly-compressible steps)
   static constexpr int CG_BATCH = 4;   // smallest CG graph; also 4x and 16x
   bool graphs_built = false;
-  hipGraphExec_t g_pre[2] = {}, g_cg[2][3] = {}, g_post[2] = {}, g_wc2[2] = {};
+  hipGraphExec_t g_pre[NBUF] = {}, g_cg[NBUF][3] = {}, g_post[NBUF] = {}, g_wc2[NBUF] = {};
   // whole PPE steps as one graph each (pre, a fixed number of CG iterations,
   // the CG scalars to the host, post), per buffer parity and iteration
   // count; a few are kept, least recently used replaced
@@ -100,7 +104,9 @@ struct mps_ctx {
     hipGraphExec_t g = nullptr;
   };
   static constexpr int kStepGraphs = 6;
-  StepGraph g_step[2][kStepGraphs];
+  StepGraph g_step[NBUF][kStepGraphs];
+  hipEvent_t ev_step[NBUF] = {};  // end of the whole-step graph from buffer b
+  bool ev_step_created = false;
   uint64_t step_clock = 0;
   // checkpoint tape: per slot the sorted state (pos, vel, p, type, id)
   struct Slot {
@@ -179,6 +185,9 @@ hipError_t dalloc(T** p, size_t count) {
   return e;
 }
 
+// The buffer a step from buffer cur writes.
+inline int nxt(const mps_ctx* c) { return (c->cur + 1) % mps_ctx::NBUF; }
+
 View make_view(const mps_ctx* c) {
   View v;
   std::memset(&v, 0, sizeof(v));
@@ -217,7 +226,7 @@ View make_view(const mps_ctx* c) {
   v.kernel = P.kernel;
   v.grad = P.grad;
   v.clamp = P.clamp_negative_p;
-  const int a = c->cur, o = c->cur ^ 1;
+  const int a = c->cur, o = nxt(c);
   v.pos = c->pos[a];
   v.pos_w = c->pos[o];
   v.vel = c->vel[a];
@@ -452,7 +461,7 @@ mps_status search(mps_ctx* c) {
     launch_bin(v, c->dim, c->s);
     launch_permute(v, c->dim, c->P.precision, c->s);
   }
-  c->cur ^= 1;
+  c->cur = nxt(c);
   v = make_view(c);
   {
     Prof pr(c, MPS_KC_NEIGH);
@@ -546,7 +555,7 @@ bool use_graphs(const mps_ctx* c) { return c->s != nullptr && c->prof_mask == 0;
 mps_status build_graphs(mps_ctx* c) {
   if (c->graphs_built) return MPS_OK;
   const int cur0 = c->cur;
-  for (int par = 0; par < 2; ++par) {
+  for (int par = 0; par < mps_ctx::NBUF; ++par) {
     c->cur = par;
     mps_status st = capture(c, &c->g_pre[par], [&] { enqueue_pre(c); });
     if (st != MPS_OK) return st;
@@ -623,12 +632,15 @@ mps_status steps_wc(mps_ctx* c, int nsteps) {
   }
   int k = 0;
   if (graphs) {
-    for (; k + 2 <= nsteps; k += 2) HIPCHK(c, hipGraphLaunch(c->g_wc2[c->cur], c->s));
+    for (; k + 2 <= nsteps; k += 2) {
+      HIPCHK(c, hipGraphLaunch(c->g_wc2[c->cur], c->s));
+      c->cur = (c->cur + 2) % mps_ctx::NBUF;
+    }
   }
   for (; k < nsteps; ++k) {
     if (graphs) {
       HIPCHK(c, hipGraphLaunch(c->g_pre[c->cur], c->s));
-      c->cur ^= 1;
+      c->cur = nxt(c);
       HIPCHK(c, hipGraphLaunch(c->g_post[c->cur], c->s));
     } else {
       enqueue_pre(c);
@@ -655,11 +667,12 @@ mps_status step_graph(mps_ctx* c, int par, int ncg, hipGraphExec_t* out) {
   const int cur0 = c->cur;
   c->cur = par;
   mps_status st = capture(c, &slot->g, [&] {
-    (void)hipMemcpyAsync(c->status + 1, c->status, sizeof(int32_t), hipMemcpyDeviceToDevice,
-                         c->s);
+    (void)hipMemcpyAsync(c->status + 1 + par, c->status, sizeof(int32_t),
+                         hipMemcpyDeviceToDevice, c->s);
     enqueue_pre(c);
     enqueue_cg(c, ncg);
-    (void)hipMemcpyAsync(c->h_sc, c->sc, sizeof(CGScalars), hipMemcpyDeviceToHost, c->s);
+    (void)hipMemcpyAsync(c->h_sc + 1 + par, c->sc, sizeof(CGScalars), hipMemcpyDeviceToHost,
+                         c->s);
     enqueue_post(c);
   });
   c->cur = cur0;
@@ -682,43 +695,13 @@ void record_cg(mps_ctx* c, mps_step_stats* st, int it, double rel) {
   }
 }
 
-mps_status one_step_ppe(mps_ctx* c, mps_step_stats* st) {
+mps_status one_step_polled(mps_ctx* c, mps_step_stats* st) {
   const bool graphs = use_graphs(c);
-  if (graphs && c->last_iters > 0) {
-    // speculative whole step: the previous step's iteration count plus a
-    // margin (launches after convergence return at once); if the solve
-    // did not converge within it, the step is discarded (its input state,
-    // the other buffer, is untouched) and redone with polled batches
-    const int B = mps_ctx::CG_BATCH;
-    const int ncg = std::min(((c->last_iters + B + B - 1) / B) * B,
-                             ((c->P.cg_maxit + B - 1) / B) * B);
-    hipGraphExec_t g = nullptr;
-    mps_status s0 = step_graph(c, c->cur, ncg, &g);
-    if (s0 != MPS_OK) return s0;
-    HIPCHK(c, hipGraphLaunch(g, c->s));
-    // the next step's launch waits for this answer: poll instead of a
-    // blocking wait (shorter wake-up)
-    hipError_t q;
-    while ((q = hipStreamQuery(c->s)) == hipErrorNotReady) {
-    }
-    if (q != hipSuccess) return hip_fail(c, q, "hipStreamQuery");
-    const CGScalars h = *c->h_sc;
-    if (h.converged) {
-      c->cur ^= 1;
-      c->ppe_valid = true;
-      record_cg(c, st, h.iter, h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0);
-      return MPS_OK;
-    }
-    // the discarded step's error flags go with it
-    HIPCHK(c, hipMemcpyAsync(c->status, c->status + 1, sizeof(int32_t),
-                             hipMemcpyDeviceToDevice, c->s));
-    if (st) st->cg_redone += 1;
-  }
   if (graphs) {
     mps_status s0 = build_graphs(c);
     if (s0 != MPS_OK) return s0;
     HIPCHK(c, hipGraphLaunch(c->g_pre[c->cur], c->s));
-    c->cur ^= 1;
+    c->cur = nxt(c);
     c->ppe_valid = true;
   } else {
     enqueue_pre(c);
@@ -731,6 +714,119 @@ mps_status one_step_ppe(mps_ctx* c, mps_step_stats* st) {
   record_cg(c, st, it, rel);
   if (graphs) HIPCHK(c, hipGraphLaunch(c->g_post[c->cur], c->s));
   else enqueue_post(c);
+  return res;
+}
+
+// CG iterations of a speculative whole step: the previous step's count
+// plus a margin (launches after convergence return at once).
+int spec_ncg(const mps_ctx* c) {
+  const int B = mps_ctx::CG_BATCH;
+  return std::min(((c->last_iters + B + B - 1) / B) * B, ((c->P.cg_maxit + B - 1) / B) * B);
+}
+
+// Spin on an event (the host's next decision waits for it: a blocking
+// wait wakes up later).
+mps_status spin_wait(mps_ctx* c, hipEvent_t ev) {
+  hipError_t q;
+  while ((q = hipEventQuery(ev)) == hipErrorNotReady) {
+  }
+  if (q != hipSuccess) return hip_fail(c, q, "hipEventQuery");
+  return MPS_OK;
+}
+
+mps_status launch_step_graph(mps_ctx* c, int b, int ncg) {
+  hipGraphExec_t g = nullptr;
+  mps_status s0 = step_graph(c, b, ncg, &g);
+  if (s0 != MPS_OK) return s0;
+  if (!c->ev_step_created) {
+    for (int k = 0; k < mps_ctx::NBUF; ++k)
+      HIPCHK(c, hipEventCreateWithFlags(&c->ev_step[k], hipEventDisableTiming));
+    c->ev_step_created = true;
+  }
+  HIPCHK(c, hipGraphLaunch(g, c->s));
+  HIPCHK(c, hipEventRecord(c->ev_step[b], c->s));
+  return MPS_OK;
+}
+
+// A step whose whole-step graph did not converge: wait for everything
+// enqueued, restore the error flags from before it, and take it again
+// from its input buffer b (untouched: the buffers after it are the only
+// ones written since) with polled CG batches.
+mps_status redo_step(mps_ctx* c, int b, mps_step_stats* st) {
+  HIPCHK(c, hipStreamSynchronize(c->s));
+  HIPCHK(c, hipMemcpyAsync(c->status, c->status + 1 + b, sizeof(int32_t),
+                           hipMemcpyDeviceToDevice, c->s));
+  c->cur = b;
+  if (st) st->cg_redone += 1;
+  return one_step_polled(c, st);
+}
+
+// Accepts step results from the CG scalars the whole-step graph from buffer
+// b left in pinned memory; false if the solve did not converge in it.
+bool accept_step(mps_ctx* c, int b, mps_step_stats* st) {
+  const CGScalars h = c->h_sc[1 + b];
+  if (!h.converged) return false;
+  c->cur = (b + 1) % mps_ctx::NBUF;
+  c->ppe_valid = true;
+  record_cg(c, st, h.iter, h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0);
+  return true;
+}
+
+mps_status one_step_ppe(mps_ctx* c, mps_step_stats* st) {
+  if (use_graphs(c) && c->last_iters > 0) {
+    // speculative whole step; if the solve did not converge within it, the
+    // step is discarded and redone with polled batches
+    const int b = c->cur;
+    mps_status s0 = launch_step_graph(c, b, spec_ncg(c));
+    if (s0 != MPS_OK) return s0;
+    s0 = spin_wait(c, c->ev_step[b]);
+    if (s0 != MPS_OK) return s0;
+    if (accept_step(c, b, st)) return MPS_OK;
+    return redo_step(c, b, st);
+  }
+  return one_step_polled(c, st);
+}
+
+// nsteps PPE steps with up to two whole-step graphs in flight: step k + 1
+// is enqueued before step k's CG result is read, so the device never waits
+// for the host between steps; the three-buffer ring keeps step k's input
+// until then.  A step found unconverged is redone from its input and the
+// step after it, already run, discarded.
+mps_status steps_ppe(mps_ctx* c, int nsteps, mps_step_stats* st) {
+  mps_status res = MPS_OK;
+  int k = 0;
+  while (k < nsteps) {
+    if (!use_graphs(c) || c->last_iters == 0 || nsteps - k == 1) {
+      mps_status r = one_step_ppe(c, st);
+      if (r == MPS_E_CG_NOCONV) res = r;
+      else if (r != MPS_OK) return r;
+      ++k;
+      continue;
+    }
+    int b = c->cur, inflight = 1;
+    mps_status r = launch_step_graph(c, b, spec_ncg(c));
+    if (r != MPS_OK) return r;
+    for (;;) {
+      if (inflight == 1 && k + 1 < nsteps) {
+        r = launch_step_graph(c, (b + 1) % mps_ctx::NBUF, spec_ncg(c));
+        if (r != MPS_OK) return r;
+        inflight = 2;
+      }
+      r = spin_wait(c, c->ev_step[b]);
+      if (r != MPS_OK) return r;
+      if (!accept_step(c, b, st)) {
+        r = redo_step(c, b, st);
+        if (r == MPS_E_CG_NOCONV) res = r;
+        else if (r != MPS_OK) return r;
+        ++k;
+        break;
+      }
+      ++k;
+      --inflight;
+      b = (b + 1) % mps_ctx::NBUF;
+      if (inflight == 0) break;
+    }
+  }
   return res;
 }
 
@@ -784,14 +880,14 @@ mps_status mps_init(const mps_params* params, int64_t n, const double* pos, cons
   hipError_t e = hipSuccess;
   auto A = [&](hipError_t x) { if (e == hipSuccess) e = x; };
   g_bytes = &c->bytes;
-  for (int k = 0; k < 2; ++k) {
+  for (int k = 0; k < mps_ctx::NBUF; ++k) {
     A(dalloc(&c->pos[k], nv));
     A(dalloc(&c->vel[k], nv));
     A(dalloc(&c->pres[k], n));
     A(dalloc(&c->type[k], n));
     A(dalloc(&c->id[k], n));
-    A(dalloc(&c->pd[k], n));
   }
+  for (int k = 0; k < 2; ++k) A(dalloc(&c->pd[k], n));
   A(dalloc(&c->pcell, n));
   A(dalloc(&c->posf, 2 * n));
   A(dalloc(&c->rsf, n));
@@ -821,7 +917,7 @@ mps_status mps_init(const mps_params* params, int64_t n, const double* pos, cons
   A(dalloc(&c->q, n));
   A(dalloc(&c->p_save, n));
   if (c->multi) {
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < mps_ctx::NBUF; ++k) {
       A(dalloc(&c->rho_s[k], n));
       A(dalloc(&c->nu_l[k], n));
     }
@@ -846,10 +942,14 @@ mps_status mps_init(const mps_params* params, int64_t n, const double* pos, cons
     }
   }
   A(dalloc(&c->sc, 1));
-  A(dalloc(&c->status, 2));  // [1]: copy taken before a speculative step
+  // [1 + b]: copy taken before a whole-step graph from buffer b
+  A(dalloc(&c->status, 1 + mps_ctx::NBUF));
   A(dalloc(&c->counts, 4));
   g_bytes = nullptr;
-  if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_sc, sizeof(CGScalars), hipHostMallocDefault);
+  // [0]: polled solves; [1 + b]: the whole-step graph from buffer b
+  if (e == hipSuccess)
+    e = hipHostMalloc((void**)&c->h_sc, (1 + mps_ctx::NBUF) * sizeof(CGScalars),
+                      hipHostMallocDefault);
   if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_status, sizeof(int32_t), hipHostMallocDefault);
   if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_counts, 4 * sizeof(int64_t), hipHostMallocDefault);
   if (e != hipSuccess) {
@@ -881,8 +981,8 @@ mps_status mps_init(const mps_params* params, int64_t n, const double* pos, cons
     // the smoothed density is fixed before the run, from the initial lists
     search(c);
     View w = make_view(c);
-    launch_smooth_density(w, c->rho_s[c->cur], c->rho_s[c->cur ^ 1], c->dim, s);
-    A(hipMemcpyAsync(c->rho_s[c->cur], c->rho_s[c->cur ^ 1], n * sizeof(double),
+    launch_smooth_density(w, c->rho_s[c->cur], c->rho_s[nxt(c)], c->dim, s);
+    A(hipMemcpyAsync(c->rho_s[c->cur], c->rho_s[nxt(c)], n * sizeof(double),
                      hipMemcpyDeviceToDevice, s));
     launch_scatter_orig(w, c->rho_s[c->cur], c->rho_o, 1, 1, s);
     launch_scatter_orig(w, c->nu_l[c->cur], c->nu_o, 1, 1, s);
@@ -909,20 +1009,25 @@ void free_tape(mps_ctx* c);
 mps_status mps_free(mps_ctx* c) {
   if (!c) return MPS_OK;
   if (c->s) (void)hipStreamSynchronize(c->s);
-  void* ptrs[] = {c->pos[0], c->pos[1], c->vel[0], c->vel[1], c->pres[0], c->pres[1],
-                  c->type[0], c->type[1], c->id[0], c->id[1], c->pd[0], c->pd[1],
+  for (int k = 0; k < mps_ctx::NBUF; ++k) {
+    void* st[] = {c->pos[k], c->vel[k], c->pres[k], c->type[k], c->id[k], c->rho_s[k],
+                  c->nu_l[k]};
+    for (void* p : st)
+      if (p) (void)hipFree(p);
+  }
+  void* ptrs[] = {c->pd[0], c->pd[1],
                   c->pcell, c->posf, c->rsf, c->us, c->rs, c->nstar, c->src, c->flags,
                   c->cellid, c->slot, c->perm, c->cell_count, c->cell_start,
                   c->nb_count,
                   c->nb_list, c->a_nnz, c->a_col, c->a_val, c->diag, c->b, c->r, c->z,
                   c->q, c->p_save, c->partA, c->partB, c->sc, c->status, c->counts,
-                  c->rho_s[0], c->rho_s[1], c->nu_l[0], c->nu_l[1], c->nut, c->mu,
+                  c->nut, c->mu,
                   c->rho_o, c->nu_o,
                   c->pl_z, c->pl_s, c->pl_m[0], c->pl_m[1], c->pl_part[0], c->pl_part[1],
                   c->pl_part2[0], c->pl_part2[1]};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
-  for (int k = 0; k < 2; ++k) {
+  for (int k = 0; k < mps_ctx::NBUF; ++k) {
     hipGraphExec_t gs[] = {c->g_pre[k], c->g_cg[k][0], c->g_cg[k][1], c->g_cg[k][2],
                            c->g_post[k], c->g_wc2[k]};
     for (hipGraphExec_t g : gs)
@@ -935,6 +1040,8 @@ mps_status mps_free(mps_ctx* c) {
       (void)hipEventDestroy(c->ev_a[k]);
       (void)hipEventDestroy(c->ev_b[k]);
     }
+  if (c->ev_step_created)
+    for (hipEvent_t ev : c->ev_step) (void)hipEventDestroy(ev);
   free_tape(c);
   if (c->h_sc) (void)hipHostFree(c->h_sc);
   if (c->h_status) (void)hipHostFree(c->h_status);
@@ -978,11 +1085,8 @@ mps_status mps_step(mps_ctx* c, int32_t nsteps, mps_step_stats* stats) {
     res = steps_wc(c, nsteps);
     if (res != MPS_OK) return res;
   } else {
-    for (int k = 0; k < nsteps; ++k) {
-      mps_status r1 = one_step_ppe(c, stats);
-      if (r1 == MPS_E_CG_NOCONV) res = r1;
-      else if (r1 != MPS_OK) return r1;
-    }
+    res = steps_ppe(c, nsteps, stats);
+    if (res != MPS_OK && res != MPS_E_CG_NOCONV) return res;
   }
   HIPCHK(c, hipGetLastError());
   mps_status st = read_status(c);

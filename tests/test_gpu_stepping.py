@@ -1,8 +1,10 @@
 """Whole-step graphs of the PPE model: each step after the first is enqueued
-as one graph with a CG iteration count guessed from the previous step; a
-step whose solve needs more is discarded (its input buffer is untouched)
-and redone with polled CG batches.  Both must give the same bits as the
-steps taken with direct, polled launches (profiling mode runs no graphs)."""
+as one graph with a CG iteration count guessed from the previous step, and
+within one mps_step call the next step's graph is enqueued before the
+previous step's result is read; a step whose solve needs more is discarded
+(its input buffer is untouched) and redone with polled CG batches.  Every
+way must give the same bits as the steps taken with direct, polled launches
+(profiling mode runs no graphs)."""
 import numpy as np
 import pytest
 
@@ -20,14 +22,14 @@ def gpu():
     return mps
 
 
-def _run(mps, w, steps, graphs, maxit=None):
+def _run(mps, w, steps, graphs, maxit=None, per_call=1):
     prm = dict(w.params)
     if maxit is not None:
         prm["cg_maxit"] = maxit
     m = mps.MPS(prm, w.pos, w.vel, w.ptype)
     if not graphs:
         m.profile(["cg_spmv"])
-    stats = [m.step(1, allow_noconv=True) for _ in range(steps)]
+    stats = [m.step(per_call, allow_noconv=True) for _ in range(steps // per_call)]
     st = m.state()
     out = {k: st[k].detach().cpu().numpy() for k in ("pos", "vel", "p", "flags")}
     m.close()
@@ -45,6 +47,20 @@ def test_speculative_steps_match_polled(gpu, precision):
         assert np.array_equal(a[k], b[k]), k
 
 
+@pytest.mark.parametrize("precision", [W.MIXED, W.FP64])
+def test_pipelined_steps_match_polled(gpu, precision):
+    """30 steps in one call (two step graphs in flight) against 30 polled
+    single steps, and against 3 calls of 10."""
+    w = W.jitter(W.config("cfg1", precision=precision))
+    a, sa = _run(gpu, w, 30, True, per_call=30)
+    b, _ = _run(gpu, w, 30, False)
+    c, _ = _run(gpu, w, 30, True, per_call=10)
+    assert sa[0]["status"] == gpu.OK and sa[0]["steps"] == 30
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+        assert np.array_equal(c[k], b[k]), k
+
+
 def test_speculative_step_redone_when_solve_needs_more(gpu):
     # the solve is capped below what it needs: every speculative step after
     # the first fails to converge, is discarded and redone, and ends with
@@ -57,3 +73,8 @@ def test_speculative_step_redone_when_solve_needs_more(gpu):
     assert all(s["cg_redone"] == 0 for s in sb)
     for k in a:
         assert np.array_equal(a[k], b[k]), k
+    # the same five steps in one call: steps 2-5 fail inside the pipeline
+    p, sp = _run(gpu, w, 5, True, maxit=12, per_call=5)
+    assert sp[0]["status"] == gpu.E_CG_NOCONV and sp[0]["cg_redone"] == 4
+    for k in a:
+        assert np.array_equal(p[k], b[k]), k
