@@ -32,8 +32,10 @@
 #include "mps_internal.h"
 
 
+// list entries per lane and step of the assembly (measured on MI355X: 2
+// beats 1 by 13 % at 441,282 particles and 4 % at 44,832)
 #ifndef ASM_UNROLL
-#define ASM_UNROLL 1
+#define ASM_UNROLL 2
 #endif
 
 namespace mps {
