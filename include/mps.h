@@ -167,9 +167,11 @@ mps_status mps_neighbors(mps_ctx* ctx, int32_t* cell_id, int32_t* count,
 
 /* Advance nsteps time steps (steps 1-5 above).  stats may be NULL.
  * PPE model on a non-null stream: each step after the first is enqueued
- * whole with a CG iteration count guessed from the previous step; a step
- * whose solve did not converge within it is discarded and redone with
- * polled CG batches (same results; counted in stats->cg_redone).
+ * whole with a CG iteration count guessed from the previous steps, and the
+ * next step is enqueued before the previous one's solve is checked; a step
+ * whose solve did not converge within its count is redone from its input
+ * with polled CG batches, the step after it discarded (same results;
+ * counted in stats->cg_redone).
  * Errors: MPS_E_NEIGH_OVERFLOW, MPS_E_COINCIDENT, MPS_E_NONFINITE,
  * MPS_E_CG_NOCONV (the step still completes with the last iterate),
  * MPS_E_POISONED. */

@@ -114,22 +114,14 @@ __device__ inline void block_sum(double (&x)[NV]) {
 // data obtain the same bits.
 template <int NV, int NT = BLOCK>
 __device__ inline void sum_partials(const double* part, int np, int stride, double (&tot)[NV]) {
-  __shared__ double bc[NV];
-  double s[NV];
+  __shared__ double sh[NV * (NT / WAVE)];
 #pragma unroll
-  for (int k = 0; k < NV; ++k) s[k] = 0.0;
+  for (int k = 0; k < NV; ++k) tot[k] = 0.0;
   for (int b = threadIdx.x; b < np; b += NT) {
 #pragma unroll
-    for (int k = 0; k < NV; ++k) s[k] += part[(int64_t)b * stride + k];
+    for (int k = 0; k < NV; ++k) tot[k] += part[(int64_t)b * stride + k];
   }
-  block_sum<NV, NT>(s);
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int k = 0; k < NV; ++k) bc[k] = s[k];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < NV; ++k) tot[k] = bc[k];
+  block_sum_all<NV, NT>(tot, sh);
 }
 
 // Contiguous chunk of row groups (rpb rows each) handled by this workgroup
