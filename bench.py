@@ -273,8 +273,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        msg = ("this build runs on one GPU only: the MPS path is measured on a single "
-               "MI355X (multi-GPU domain decomposition is a design note, not built)")
+        msg = ("bench.py runs on one GPU only: the MPS path is measured on a single "
+               "MI355X (the slab decomposition over several GPUs is not implemented)")
         print(msg, file=sys.stderr)
         sys.exit(2)
 
@@ -296,14 +296,14 @@ def main():
         del a, b, flush
     if args.only:
         pm, pr = args.only.split(":")
-        wo = W.config("cfg2", pmode=W.PPE_CG if pm == "ppe" else W.WC_EOS,
+        wo = W.config("dam_break_2d_44832", pmode=W.PPE_CG if pm == "ppe" else W.WC_EOS,
                       precision=W.MIXED if pr == "mixed" else W.FP64)
         r = run_gpu(wo, K, Wm)
         print(json.dumps({"only": args.only, "value": r["particle_steps_per_s"],
                           "ms_per_step": r["ms_per_step"], "steps": K}), flush=True)
         return
 
-    w = W.config("cfg2", precision=W.MIXED, pmode=W.PPE_CG)
+    w = W.config("dam_break_2d_44832", precision=W.MIXED, pmode=W.PPE_CG)
     c = w.counts()
     workload = "dam_break_2d_l0=0.00125"
     log(f"workload {workload}: {c}")
@@ -343,7 +343,7 @@ def main():
                                ("ppe_fp64_standard_cg", W.FP64, W.PPE_CG, 0),
                                ("wc_mixed", W.MIXED, W.WC_EOS, 0),
                                ("wc_fp64", W.FP64, W.WC_EOS, 0)):
-        wx = W.config("cfg2", precision=prec, pmode=pm)
+        wx = W.config("dam_break_2d_44832", precision=prec, pmode=pm)
         wx.params["cg_pipelined"] = pl
         if name.endswith("hs_ecs"):
             wx.params["source"] = W.SRC_HS_ECS
@@ -356,25 +356,25 @@ def main():
     drop = run_drop()
     log("water_drop", drop)
 
-    cfg3d = {}
+    runs_3d = {}
     if not args.only_headline and not args.no_3d:
-        w3 = W.config("cfg3", precision=W.MIXED)
+        w3 = W.config("dam_break_3d_441282", precision=W.MIXED)
         w3.params["cg_pipelined"] = 1
-        cfg3d["dam_break_3d_l0=0.007"] = run_3d("dam_break_3d", w3, args.steps_3d, 2)
+        runs_3d["dam_break_3d_l0=0.007"] = run_3d("dam_break_3d", w3, args.steps_3d, 2)
         # the same 3-D case on the plain FP64 path (same solver): the
         # bandwidth-bound comparison of the two precisions
-        w3d = W.config("cfg3", precision=W.FP64)
+        w3d = W.config("dam_break_3d_441282", precision=W.FP64)
         w3d.params["cg_pipelined"] = 1
         f64 = run_3d("dam_break_3d_fp64", w3d, args.steps_3d, 2)
-        cfg3d["dam_break_3d_l0=0.007_fp64_plain"] = f64
-        cfg3d["dam_break_3d_l0=0.007"]["mixed_vs_fp64_plain"] = (
-            cfg3d["dam_break_3d_l0=0.007"]["value"] / f64["value"])
-        w5 = W.config("cfg5", precision=W.MIXED)
+        runs_3d["dam_break_3d_l0=0.007_fp64_plain"] = f64
+        runs_3d["dam_break_3d_l0=0.007"]["mixed_vs_fp64_plain"] = (
+            runs_3d["dam_break_3d_l0=0.007"]["value"] / f64["value"])
+        w5 = W.config("two_phase_3d_2314616", precision=W.MIXED)
         w5.params["cg_pipelined"] = 1
-        cfg3d["two_phase_3d_l0=0.005"] = run_3d("two_phase_3d", w5, max(args.steps_3d // 2, 2), 1)
+        runs_3d["two_phase_3d_l0=0.005"] = run_3d("two_phase_3d", w5, max(args.steps_3d // 2, 2), 1)
         if not args.no_adjoint:
-            wa = W.config("cfg5", precision=W.MIXED)
-            cfg3d["two_phase_3d_l0=0.005"]["adjoint"] = run_adjoint(wa, 50, 50)
+            wa = W.config("two_phase_3d_2314616", precision=W.MIXED)
+            runs_3d["two_phase_3d_l0=0.005"]["adjoint"] = run_adjoint(wa, 50, 50)
 
     out = {
         "metric": METRIC,
@@ -412,11 +412,11 @@ def main():
                      "bytes_per_launch": nbytes, "avg_launch_ms": avg_ms,
                      "launches": n_dom},
         "cpu_baseline": None,
-        "configs_3d": cfg3d,
+        "configs_3d": runs_3d,
     }
     if not args.no_cpu and not args.only_headline:
         log("cpu baseline ...")
-        out["cpu_baseline"] = cpu_baseline(W.config("cfg2", precision=W.FP64), args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(W.config("dam_break_2d_44832", precision=W.FP64), args.cpu_seconds)
         log(out["cpu_baseline"])
     print(json.dumps(out), flush=True)
 

@@ -12,7 +12,8 @@
  *   equation of state    Eq. 16
  *   pressure gradient    standard MPS form, or Eq. 18 (CMPS)
  *   time integration     semi-implicit predictor-corrector, first-order Euler
- * Readings where the paper is silent are listed in the design doc.
+ * Where the paper is silent or garbled, the reading taken is stated in a
+ * comment at the code it concerns.
  *
  * The step is a template on the scalar type so that the same code runs in
  * double and with forward-mode dual numbers (the reference gradient).

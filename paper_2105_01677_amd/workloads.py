@@ -278,21 +278,22 @@ def random_box(n, dim, *, l0=0.01, seed=SEED, re_lap_over_l0=None) -> Workload:
 
 
 def config(name: str, **kw) -> Workload:
-    """The five benchmark configurations of the 2-D/3-D dam break, sloshing
-    and two-phase cases (sizes in the design doc)."""
-    if name == "cfg1":
+    """The five benchmark workloads, named by case and particle count: the
+    2-D dam break at 1,432 and 44,832, the 3-D dam break at 441,282, the
+    2-D sloshing tank at 24,932 and the 3-D two-phase box at 2,314,616."""
+    if name == "dam_break_2d_1432":
         return dam_break_2d(0.01, dt=kw.pop("dt", 5e-4), steps=200, **kw)
-    if name == "cfg2":
+    if name == "dam_break_2d_44832":
         # The plain method (no collision model, no source-term stabiliser)
         # blows up on this case near t = 0.03 s whatever the step: near
         # step 270 at dt = 1e-4 (the FP64 oracle as well as the GPU), step
         # ~850 at 3e-5.  Runs of it stay within the first 250 steps.
         return dam_break_2d(0.00125, dt=kw.pop("dt", 1e-4), steps=1000, **kw)
-    if name == "cfg3":
+    if name == "dam_break_3d_441282":
         return dam_break_3d(0.007, **kw)
-    if name == "cfg4":
+    if name == "sloshing_2d_24932":
         return sloshing_2d(0.002, **kw)
-    if name == "cfg5":
+    if name == "two_phase_3d_2314616":
         return two_phase_3d(0.005, **kw)
     raise KeyError(name)
 

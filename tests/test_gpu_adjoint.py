@@ -67,7 +67,7 @@ def test_adjoint_matches_oracle_dual(torch_gpu, orc, pmode):
         w = W.sloshing_2d(0.01, precision=W.FP64)
         nsteps, K = 20, 6
     else:
-        w = W.jitter(W.config("cfg1"), vel_sigma=0.02)
+        w = W.jitter(W.config("dam_break_2d_1432"), vel_sigma=0.02)
         w.params.update(cg_tol=1e-12, dt=2e-4)
         nsteps, K = 8, 3
     d = _direction(w)
@@ -123,7 +123,7 @@ def test_adjoint_sloshing_full_size(torch_gpu, orc):
     differ from the FP64 ones because the FP32 forward trajectory itself
     differs; that deviation is reported and bounded loosely."""
     torch = torch_gpu
-    w = W.config("cfg4", precision=W.FP64)
+    w = W.config("sloshing_2d_24932", precision=W.FP64)
     assert w.counts()["fluid"] == 22500
     nsteps, K = 500, 50
     d = _direction(w)
@@ -135,7 +135,7 @@ def test_adjoint_sloshing_full_size(torch_gpu, orc):
     assert rel(g_nu, o_nu) < 1e-3
     assert rel(g_gx, o_gx) < 1e-3
     assert rel(g_u, o_u) < 1e-3
-    wm = W.config("cfg4", precision=W.MIXED)
+    wm = W.config("sloshing_2d_24932", precision=W.MIXED)
     Lm, m_nu, m_gx, m_u = gpu_grads(torch, wm, nsteps, K, d)
     dev = max(rel(m_nu, o_nu), rel(m_gx, o_gx), rel(m_u, o_u))
     print("mixed L", Lm, "nu", m_nu, "gx", m_gx, "u0", m_u, "max deviation from FP64", dev,

@@ -45,9 +45,9 @@ def _list_inputs():
     cases = {
         "random2d": W.random_box(3000, 2, seed=11),
         "random3d": W.random_box(2500, 3, seed=12),
-        "cfg1_jitter": W.jitter(W.config("cfg1")),
+        "db2d_1432_jitter": W.jitter(W.config("dam_break_2d_1432")),
         "block3d_jitter": W.jitter(W.lattice_block(3, [14, 12, 10], walls_below=True)),
-        "cfg1_lattice": W.config("cfg1"),
+        "db2d_1432_lattice": W.config("dam_break_2d_1432"),
         "block3d_lattice": W.lattice_block(3, [14, 12, 10], walls_below=True),
     }
     w = W.random_box(1200, 2, seed=13)
@@ -60,8 +60,8 @@ def _list_inputs():
 
 
 @pytest.mark.parametrize("precision", [W.FP64, W.MIXED])
-@pytest.mark.parametrize("name", ["random2d", "random3d", "cfg1_jitter", "block3d_jitter",
-                                  "cell_faces", "cfg1_lattice", "block3d_lattice"])
+@pytest.mark.parametrize("name", ["random2d", "random3d", "db2d_1432_jitter", "block3d_jitter",
+                                  "cell_faces", "db2d_1432_lattice", "block3d_lattice"])
 def test_neighbor_lists_bit_exact(gpu, orc, name, precision):
     """Lists against the oracle's cell-linked list, bit for bit.  The mixed
     path tests candidates in FP32 first and re-decides those near re_lap in
@@ -80,9 +80,9 @@ def test_neighbor_lists_bit_exact(gpu, orc, name, precision):
     m.close()
 
 
-def test_neighbor_lists_bit_exact_cfg2_full(gpu, orc):
+def test_neighbor_lists_bit_exact_dam_break_2d_44832(gpu, orc):
     """The full 44,832-particle 2-D dam break (bench size), jittered."""
-    w = W.jitter(W.config("cfg2", precision=W.MIXED))
+    w = W.jitter(W.config("dam_break_2d_44832", precision=W.MIXED))
     st, cnt_o, lst_o = orc.neighbors_brute(w.params, w.pos, w.ptype)
     assert st == 0
     m = gpu.MPS(w.params, w.pos, w.vel, w.ptype)
@@ -131,8 +131,8 @@ PRECISIONS = [(W.FP64, 1e-12, 1e-8), (W.MIXED, 1e-9, 1e-4)]
 
 @pytest.mark.parametrize("precision,cg_tol,tol", PRECISIONS)
 @pytest.mark.parametrize("pmode", [W.PPE_CG, W.WC_EOS])
-def test_one_step_cfg1_jittered(gpu, orc, precision, cg_tol, pmode, tol):
-    w = W.jitter(W.config("cfg1", pmode=pmode, precision=precision))
+def test_one_step_dam_break_2d_1432_jittered(gpu, orc, precision, cg_tol, pmode, tol):
+    w = W.jitter(W.config("dam_break_2d_1432", pmode=pmode, precision=precision))
     w.params["cg_tol"] = cg_tol
     _compare_step(gpu, orc, w, tol)
 
@@ -140,19 +140,19 @@ def test_one_step_cfg1_jittered(gpu, orc, precision, cg_tol, pmode, tol):
 def test_one_step_fp64_production_tolerance(gpu, orc):
     """FP64 path at the production CG tolerance 1e-9: within the bound the
     stopping criterion allows."""
-    for w in (W.jitter(W.config("cfg2")), W.config("cfg2")):
+    for w in (W.jitter(W.config("dam_break_2d_44832")), W.config("dam_break_2d_44832")):
         _compare_step(gpu, orc, w, 1e-5)
 
 
 @pytest.mark.parametrize("precision,cg_tol,tol", PRECISIONS)
 @pytest.mark.parametrize("pmode", [W.PPE_CG, W.WC_EOS])
-def test_one_step_cfg2_full(gpu, orc, precision, cg_tol, pmode, tol):
+def test_one_step_dam_break_2d_44832(gpu, orc, precision, cg_tol, pmode, tol):
     """Bench size: 44,832 particles, both pressure models, both precisions,
     jittered so that every term is active, and from rest as benchmarked."""
-    w = W.jitter(W.config("cfg2", pmode=pmode, precision=precision))
+    w = W.jitter(W.config("dam_break_2d_44832", pmode=pmode, precision=precision))
     w.params["cg_tol"] = cg_tol
     _compare_step(gpu, orc, w, tol)
-    w = W.config("cfg2", pmode=pmode, precision=precision)
+    w = W.config("dam_break_2d_44832", pmode=pmode, precision=precision)
     w.params["cg_tol"] = cg_tol
     _compare_step(gpu, orc, w, tol)
 
@@ -178,19 +178,19 @@ def test_one_step_3d_split_cg(gpu, orc, precision, cg_tol, tol):
 
 
 @pytest.mark.parametrize("precision,cg_tol,tol", PRECISIONS)
-def test_one_step_cfg3_full(gpu, orc, precision, cg_tol, tol):
+def test_one_step_dam_break_3d_441282(gpu, orc, precision, cg_tol, tol):
     """3-D bench size: the 441,282-particle dam break from rest, as
     benchmarked (split CG schedule), every particle against the oracle."""
-    w = W.config("cfg3", precision=precision)
+    w = W.config("dam_break_3d_441282", precision=precision)
     w.params["cg_tol"] = cg_tol
     _compare_step(gpu, orc, w, tol)
 
 
-def test_one_step_cfg5_full(gpu, orc):
+def test_one_step_two_phase_3d_2314616(gpu, orc):
     """Two-phase + Smagorinsky bench size (2,314,616 particles), mixed path
     as benchmarked: smoothed density, eddy viscosity and one step, every
     particle against the oracle."""
-    w = W.config("cfg5", precision=W.MIXED)
+    w = W.config("two_phase_3d_2314616", precision=W.MIXED)
     prm = dict(w.params)
     st, rs = orc.smoothed_density(prm, w.pos, w.ptype, w.rho_i)
     assert st == 0
@@ -213,20 +213,20 @@ def test_one_step_cfg5_full(gpu, orc):
                          want_lists=False, rho_s=rs, nu_i=w.nu_i)
     errs = {"disp": rel_err(g["pos"] - w.pos, o["pos"] - w.pos), "vel": rel_err(g["vel"], o["vel"]),
             "p": rel_err(g["p"], o["p"]), "nut": rel_err(_np(nut), o["nut"])}
-    print("cfg5 errors", errs, "cg", s["cg_iters_last"], flush=True)
+    print("two-phase errors", errs, "cg", s["cg_iters_last"], flush=True)
     for k, e in errs.items():
         assert e < 1e-4, (k, e)
 
 
 @pytest.mark.parametrize("grad", [W.GRAD_STD, W.GRAD_CMPS])
 def test_one_step_cmps(gpu, orc, grad):
-    w = W.jitter(W.config("cfg1"))
+    w = W.jitter(W.config("dam_break_2d_1432"))
     w.params.update(grad=grad, cg_tol=1e-12)
     _compare_step(gpu, orc, w, 1e-8)
 
 
 def test_twenty_steps_fp64(gpu, orc):
-    w = W.config("cfg1")
+    w = W.config("dam_break_2d_1432")
     w.params["cg_tol"] = 1e-12
     _compare_step(gpu, orc, w, 1e-6, steps=20)
 
@@ -235,7 +235,7 @@ def test_twenty_steps_fp64(gpu, orc):
 def test_ppe_matrix_and_solve(gpu, orc, precision):
     """Assembled system (mps_get_ppe) against the oracle's, and
     mps_pressure_solve against the exact (dense) solution."""
-    w = W.jitter(W.config("cfg1", precision=precision))
+    w = W.jitter(W.config("dam_break_2d_1432", precision=precision))
     m = gpu.MPS(w.params, w.pos, w.vel, w.ptype)
     p, it, rr = m.pressure_solve()
     A = {k: _np(v) for k, v in m.get_ppe().items()}
@@ -276,7 +276,7 @@ def test_ppe_matrix_and_solve(gpu, orc, precision):
 
 
 def test_bitwise_determinism(gpu):
-    w = W.jitter(W.config("cfg2", precision=W.MIXED))
+    w = W.jitter(W.config("dam_break_2d_44832", precision=W.MIXED))
     outs = []
     for _ in range(2):
         m = gpu.MPS(w.params, w.pos, w.vel, w.ptype)
@@ -290,7 +290,7 @@ def test_bitwise_determinism(gpu):
 def test_state_roundtrip_and_resume(gpu):
     """get_state/set_state give a bitwise resume: 2K steps == K, save,
     restore into a fresh context, K."""
-    w = W.config("cfg1", pmode=W.WC_EOS)
+    w = W.config("dam_break_2d_1432", pmode=W.WC_EOS)
     m = gpu.MPS(w.params, w.pos, w.vel, w.ptype)
     m.step(6)
     ref = {k: _np(v) for k, v in m.state().items()}
@@ -342,7 +342,7 @@ def test_error_paths(gpu):
     assert e.value.status == gpu.E_NONFINITE
     m.close()
     # CG iteration limit: the step completes and reports it
-    wj = W.jitter(W.config("cfg1"))
+    wj = W.jitter(W.config("dam_break_2d_1432"))
     prm = dict(wj.params, cg_maxit=1)
     m = gpu.MPS(prm, wj.pos, wj.vel, wj.ptype)
     s = m.step(1, allow_noconv=True)
@@ -356,7 +356,7 @@ def test_error_paths(gpu):
 
 
 def test_ghosts(gpu, orc):
-    w = W.config("cfg1")
+    w = W.config("dam_break_2d_1432")
     vel = w.vel.copy()
     f = np.nonzero(w.ptype == W.FLUID)[0]
     vel[f[:5], 0] = 1e3
@@ -371,7 +371,7 @@ def test_ghosts(gpu, orc):
 
 
 def test_constants(gpu, orc):
-    w = W.config("cfg2")
+    w = W.config("dam_break_2d_44832")
     m = gpu.MPS(w.params, w.pos, w.vel, w.ptype)
     n0n, n0l, lam = m.constants()
     m.close()
@@ -422,8 +422,8 @@ def test_two_phase_smagorinsky_one_step(gpu, orc, case, precision, cg_tol, tol):
 def test_pipelined_cg_one_step(gpu, orc, precision, cg_tol, tol):
     """The single-reduction (pipelined) CG reaches the same pressure: one
     step at bench size, jittered and from rest, against the oracle."""
-    for w in (W.jitter(W.config("cfg2", precision=precision)),
-              W.config("cfg2", precision=precision)):
+    for w in (W.jitter(W.config("dam_break_2d_44832", precision=precision)),
+              W.config("dam_break_2d_44832", precision=precision)):
         w.params.update(cg_tol=cg_tol, cg_pipelined=1)
         _compare_step(gpu, orc, w, tol)
 
@@ -431,7 +431,7 @@ def test_pipelined_cg_one_step(gpu, orc, precision, cg_tol, tol):
 def test_pipelined_cg_pressure_solve(gpu):
     """mps_pressure_solve with both CG variants on the same system: the same
     solution to the solver tolerance; 3-D as well."""
-    for w in (W.jitter(W.config("cfg1", precision=W.MIXED)),
+    for w in (W.jitter(W.config("dam_break_2d_1432", precision=W.MIXED)),
               W.jitter(W.lattice_block(3, [14, 12, 10], walls_below=True, dt=2e-4))):
         out = []
         for pl in (0, 1):
@@ -493,20 +493,20 @@ def test_one_step_dn_dt_sources(gpu, orc, source, precision, cg_tol, tol):
     compensating parts (Eq. 24-25, ECS): one step against the oracle in
     2-D (1,432 particles) and 3-D (8,000 + walls), jittered."""
     w3 = W.jitter(W.lattice_block(3, [20, 20, 20], walls_below=True, dt=2e-4))
-    for w in (W.jitter(W.config("cfg1", precision=precision)), w3):
+    for w in (W.jitter(W.config("dam_break_2d_1432", precision=precision)), w3):
         w.params.update(precision=precision, cg_tol=cg_tol, source=source)
         _compare_step(gpu, orc, w, tol)
 
 
 def test_dn_dt_source_full_size(gpu, orc):
     """HS + ECS on the mixed path at the 44,832-particle size, jittered."""
-    w = W.jitter(W.config("cfg2", precision=W.MIXED))
+    w = W.jitter(W.config("dam_break_2d_44832", precision=W.MIXED))
     w.params.update(source=W.SRC_HS_ECS)
     _compare_step(gpu, orc, w, 1e-4)
 
 
 def test_dn_dt_source_refused_by_the_adjoint(gpu):
-    w = W.config("cfg1")
+    w = W.config("dam_break_2d_1432")
     w.params.update(source=W.SRC_HS)
     m = gpu.MPS(w.params, w.pos, w.vel, w.ptype)
     m.tape_alloc(2)
@@ -526,7 +526,7 @@ def test_degenerate_inputs(gpu, orc):
     within each other's radius, and a block of walls and dummies without
     fluid (at rest every source is zero up to rounding); an empty input is
     refused."""
-    base = W.config("cfg1")
+    base = W.config("dam_break_2d_1432")
     prm = dict(base.params)
     lo, cs = prm["grid_lo"], prm["cell_size"]
     centre = np.array([lo[0] + 5.5 * cs, lo[1] + 5.5 * cs])
@@ -562,7 +562,7 @@ def test_degenerate_inputs(gpu, orc):
 
 def test_neighbor_cap_boundary(gpu):
     """A cap equal to the largest list is accepted; one less overflows."""
-    w = W.config("cfg1")
+    w = W.config("dam_break_2d_1432")
     m = gpu.MPS(w.params, w.pos, w.vel, w.ptype)
     cnt = _np(m.neighbors()[1]).max()
     m.close()

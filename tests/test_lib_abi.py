@@ -79,6 +79,6 @@ def test_binding_refuses_without_gpu():
     if torch.cuda.is_available():
         pytest.skip("a GPU is present")
     from paper_2105_01677_amd import mps, workloads as W
-    w = W.config("cfg1")
+    w = W.config("dam_break_2d_1432")
     with pytest.raises(RuntimeError):
         mps.MPS(w.params, w.pos, w.vel, w.ptype)

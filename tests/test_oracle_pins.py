@@ -88,7 +88,7 @@ def _inputs_for_lists():
     w = W.random_box(700, 2, seed=1)
     cases.append(w)
     cases.append(W.random_box(900, 3, seed=2))
-    cases.append(W.jitter(W.config("cfg1")))
+    cases.append(W.jitter(W.config("dam_break_2d_1432")))
     # particles exactly on cell faces
     w = W.random_box(400, 2, seed=3)
     cs, lo = w.params["cell_size"], w.params["grid_lo"]
@@ -143,7 +143,7 @@ def test_neighbor_overflow_and_coincident(orc):
 def test_first_step_from_rest(orc):
     """From rest the viscous term vanishes: u* = g dt and r* = r + g dt^2 for
     fluid; walls and dummies do not move."""
-    w = W.config("cfg1")
+    w = W.config("dam_break_2d_1432")
     st, o = orc.step(w.params, w.pos, w.vel, w.ptype)
     assert st == 0
     f = w.ptype == W.FLUID
@@ -268,7 +268,7 @@ def test_ppe_dense_solve_and_structure(orc):
     """The assembled PPE (Eq. 13 with the Laplacian of Eq. 7) is symmetric,
     strictly diagonally dominant by alpha/dt^2, and the oracle's pressure is
     its unique solution (dense LAPACK solve)."""
-    w = W.jitter(W.config("cfg1"))
+    w = W.jitter(W.config("dam_break_2d_1432"))
     st, o = orc.step(w.params, w.pos, w.vel, w.ptype, want_matrix=True)
     assert st == 0
     n = w.n
@@ -310,7 +310,7 @@ def test_ppe_rows_are_the_laplacian(orc):
 
 def test_equation_of_state(orc):
     """Eq. 16 with gamma = 7, clamped at zero: p = rho c0^2/7 ((n*/n0)^7 - 1)."""
-    w = W.jitter(W.config("cfg1", pmode=W.WC_EOS))
+    w = W.jitter(W.config("dam_break_2d_1432", pmode=W.WC_EOS))
     st, o = orc.step(w.params, w.pos, w.vel, w.ptype)
     assert st == 0
     n0, _, _ = shells_constants(SHELLS_2D, 2.1, 1)
@@ -329,7 +329,7 @@ def test_equation_of_state(orc):
 
 def test_number_density_brute_force(orc):
     """n*_i = sum_{j != i} w(|r*_j - r*_i|) over all pairs (Eq. 5), numpy."""
-    w = W.jitter(W.config("cfg1"))
+    w = W.jitter(W.config("dam_break_2d_1432"))
     st, o = orc.step(w.params, w.pos, w.vel, w.ptype)
     rs = o["rs"]
     re = w.params["re_n"]
@@ -342,7 +342,7 @@ def test_number_density_brute_force(orc):
 def test_ghosts_and_particle_count(orc):
     """Particles that leave the grid become ghosts; the count per type plus
     ghosts is conserved and ghosts never move again."""
-    w = W.config("cfg1")
+    w = W.config("dam_break_2d_1432")
     pos = w.pos.copy()
     vel = w.vel.copy()
     f = np.nonzero(w.ptype == W.FLUID)[0]
@@ -401,7 +401,7 @@ def test_smagorinsky_linear_shear(orc):
 
 
 def test_two_phase_reduces_to_single_phase(orc):
-    w = W.jitter(W.config("cfg1"))
+    w = W.jitter(W.config("dam_break_2d_1432"))
     st, a = orc.step(w.params, w.pos, w.vel, w.ptype)
     st, b = orc.step(w.params, w.pos, w.vel, w.ptype,
                      rho_s=np.full(w.n, w.params["rho"]), nu_i=np.full(w.n, w.params["nu"]))
@@ -483,7 +483,7 @@ def test_dn_dt_sources_against_central_differences(orc, source):
     all-pairs central differences n(r + h u) - n(r - h u) at the oracle's
     own r*, u* (a sign or orientation slip, a wrong kernel derivative or a
     dropped term fails it)."""
-    w = W.jitter(W.config("cfg1"), vel_sigma=0.3)
+    w = W.jitter(W.config("dam_break_2d_1432"), vel_sigma=0.3)
     prm = dict(w.params, source=source)
     st, o = orc.step(prm, w.pos, w.vel, w.ptype, want_lists=False)
     assert st == 0
@@ -562,7 +562,7 @@ def test_dual_rollout_matches_central_differences(orc, case):
         w = W.sloshing_2d(0.01, precision=W.FP64)
         nsteps = 10
     elif case == "ppe":
-        w = W.jitter(W.config("cfg1"), vel_sigma=0.02)
+        w = W.jitter(W.config("dam_break_2d_1432"), vel_sigma=0.02)
         w.params["dt"] = 2e-4
         nsteps = 6
     else:
