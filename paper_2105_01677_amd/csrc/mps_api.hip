@@ -12,10 +12,12 @@
 // The only host synchronisations are the CG convergence polls (batches of
 // iterations, sized from the previous step's count) and one status read at
 // the end of each call.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "mps_internal.h"
 
@@ -71,7 +73,7 @@ struct mps_ctx {
   double* partB = nullptr;
   double *pl_z = nullptr, *pl_s = nullptr, *pl_m[2] = {nullptr, nullptr},
          *pl_part[2] = {nullptr, nullptr}, *pl_part2[2] = {nullptr, nullptr};
-  int nspmv = 0, nupd = 0, npcg = 0, pcg_fused = 0;
+  int nspmv = 0, nupd = 0, npcg = 0, pcg_fused = 0, pcg_pred = 0;
   CGScalars* sc = nullptr;
   int32_t* status = nullptr;
   int64_t* counts = nullptr;   // [4]: surface, ghost, list entries, matrix nnz
@@ -279,6 +281,7 @@ View make_view(const mps_ctx* c) {
   v.nupd = c->nupd;
   v.npcg = c->npcg;
   v.pcg_fused = c->pcg_fused;
+  v.pcg_pred = c->pcg_pred;
   v.sc = c->sc;
   v.status = c->status;
   if (c->multi) {
@@ -997,6 +1000,19 @@ mps_status mps_init(const mps_params* params, int64_t n, const double* pos, cons
   if (st != MPS_OK) {
     mps_free(c);
     return MPS_E_ARG;
+  }
+  if (!c->pcg_fused) {
+    // Dummy particles are never unknowns and their rows hold no entries.
+    // Where they are one row in five or more (the 3-D tanks with two dummy
+    // layers), the split iteration kernel loads only the slots a row holds;
+    // with fewer, loading the first slots unconditionally is faster.
+    std::vector<int8_t> ht((size_t)n);
+    if (hipMemcpy(ht.data(), c->type[0], (size_t)n, hipMemcpyDeviceToHost) != hipSuccess) {
+      mps_free(c);
+      return MPS_E_DEVICE;
+    }
+    const int64_t nd = std::count(ht.begin(), ht.end(), (int8_t)MPS_DUMMY);
+    c->pcg_pred = nd * 5 >= n ? 1 : 0;
   }
   *out = c;
   return MPS_OK;

@@ -162,6 +162,7 @@ struct View {
   int nspmv, nupd;    // grid sizes of the SpMV / assembly and update kernels
   int npcg;           // grid size of the pipelined CG kernels (one row group each)
   int pcg_fused;      // 1: one kernel per iteration; 0: reduction + iteration
+  int pcg_pred;       // split schedule: slot loads predicated on the row length
   CGScalars* sc;
   // pipelined CG (one kernel per iteration): m = D^-1 w (double buffered),
   // z, s; the direction p reuses pd[0]

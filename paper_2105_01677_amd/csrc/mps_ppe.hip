@@ -578,12 +578,17 @@ __global__ __launch_bounds__(RED2_BLOCK) void k_pcg_reduce(View v) {
   }
 }
 
-template <class VT, int PAR, bool FUSED>
+// PRED: slots past the row length are neither loaded nor gathered (the
+// loads then wait for the row length).  Without it every lane loads its
+// first U slots whatever the row length, which keeps the load chain short
+// but reads padding for rows with few or no entries (dummy particles).
+template <class VT, int PAR, bool FUSED, bool PRED>
 __global__ __launch_bounds__(pcg_nt<FUSED>()) void k_pcg_iter(View v) {
   constexpr int U = CG_UNROLL;
   constexpr int NT = pcg_nt<FUSED>();
   static_assert(PCG_PK * PCG_BLOCK >= PCG_MAX_BLOCKS, "one partial load per slot");
   static_assert(PCG_SPLIT_G <= PCG_SPLIT_BLOCK, "one slice sum per thread");
+  static_assert(!(FUSED && PRED), "the small fused systems are latency-bound");
   __shared__ double sh_in[3 * (NT / WAVE)], sh_out[3 * (NT / WAVE)];
   CGScalars* sc = v.sc;
   const int t = team_lane();
@@ -615,8 +620,14 @@ __global__ __launch_bounds__(pcg_nt<FUSED>()) void k_pcg_iter(View v) {
     // slot u of the row exists (kpad is uniform); stale slots past the row
     // length are masked below
     const int64_t e = u * TEAM < v.kpad ? e0 + u * WAVE : e0;
-    jj[u] = v.a_col[e];
-    aa[u] = aval[e];
+    if constexpr (PRED) {
+      const bool in = t + u * TEAM < nnz;
+      jj[u] = in ? v.a_col[e] : 0;
+      aa[u] = in ? aval[e] : VT(0);
+    } else {
+      jj[u] = v.a_col[e];
+      aa[u] = aval[e];
+    }
   }
   // the row's own seven values, one per team lane (one load instruction;
   // moved to lane 0 below)
@@ -636,7 +647,8 @@ __global__ __launch_bounds__(pcg_nt<FUSED>()) void k_pcg_iter(View v) {
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const bool in = t + u * TEAM < nnz;
-    xv[u] = M[in ? jj[u] : (int32_t)rc];
+    if constexpr (PRED) xv[u] = in ? M[jj[u]] : 0.0;
+    else xv[u] = M[in ? jj[u] : (int32_t)rc];
     if (!in) {
       xv[u] = 0.0;
       aa[u] = VT(0);
@@ -790,7 +802,8 @@ int pcg_fused_capacity() {
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return 0;
   int worst = 1 << 30;
-  const void* ks[] = {(const void*)k_pcg_iter<float, 0, true>, (const void*)k_pcg_iter<double, 0, true>};
+  const void* ks[] = {(const void*)k_pcg_iter<float, 0, true, false>,
+                      (const void*)k_pcg_iter<double, 0, true, false>};
   for (const void* k : ks) {
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, PCG_BLOCK, 0) != hipSuccess) return 0;
     worst = per < worst ? per : worst;
@@ -825,12 +838,30 @@ int launch_pcg_iter(const View& v, int precision, int parity, hipStream_t s) {
   const bool mx = precision == MPS_MIXED;
   if (v.pcg_fused) {
     const unsigned nt = PCG_BLOCK;
-    if (mx) launch_k(parity ? k_pcg_iter<float, 1, true> : k_pcg_iter<float, 0, true>, nb, nt, s, v);
-    else launch_k(parity ? k_pcg_iter<double, 1, true> : k_pcg_iter<double, 0, true>, nb, nt, s, v);
+    if (mx)
+      launch_k(parity ? k_pcg_iter<float, 1, true, false> : k_pcg_iter<float, 0, true, false>,
+               nb, nt, s, v);
+    else
+      launch_k(parity ? k_pcg_iter<double, 1, true, false> : k_pcg_iter<double, 0, true, false>,
+               nb, nt, s, v);
+    return 0;
+  }
+  const unsigned nt = PCG_SPLIT_BLOCK;
+  if (v.pcg_pred) {
+    if (mx)
+      launch_k(parity ? k_pcg_iter<float, 1, false, true> : k_pcg_iter<float, 0, false, true>,
+               nb, nt, s, v);
+    else
+      launch_k(parity ? k_pcg_iter<double, 1, false, true> : k_pcg_iter<double, 0, false, true>,
+               nb, nt, s, v);
   } else {
-    const unsigned nt = PCG_SPLIT_BLOCK;
-    if (mx) launch_k(parity ? k_pcg_iter<float, 1, false> : k_pcg_iter<float, 0, false>, nb, nt, s, v);
-    else launch_k(parity ? k_pcg_iter<double, 1, false> : k_pcg_iter<double, 0, false>, nb, nt, s, v);
+    if (mx)
+      launch_k(parity ? k_pcg_iter<float, 1, false, false> : k_pcg_iter<float, 0, false, false>,
+               nb, nt, s, v);
+    else
+      launch_k(parity ? k_pcg_iter<double, 1, false, false>
+                      : k_pcg_iter<double, 0, false, false>,
+               nb, nt, s, v);
   }
   return 0;
 }
