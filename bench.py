@@ -395,6 +395,9 @@ def main():
                    "dt": w.params["dt"], "dim": 2},
         "fluid_particle_steps_per_s": c["fluid"] * K / hd["seconds"],
         "cg_iters_mean": s["cg_iters_total"] / K,
+        # steps whose speculative whole-step graph did not converge and were
+        # taken again with polled CG batches
+        "cg_steps_redone": s["cg_redone"],
         "state_check": hd["state_check"],
         "fp64_plain": extra.get("ppe_fp64"),
         "mixed_vs_fp64_plain": hd["particle_steps_per_s"] / extra["ppe_fp64"]["value"],

@@ -54,7 +54,7 @@ struct mps_ctx {
   double* src = nullptr;  // PPE source from Dn/Dt (source != MPS_SRC_STD)
   int8_t* flags = nullptr;
   int32_t *cellid = nullptr, *slot = nullptr, *cell_count = nullptr, *cell_start = nullptr,
-          *perm = nullptr;
+          *cell_local = nullptr, *tile_sum = nullptr, *perm = nullptr;
   int32_t *nb_count = nullptr, *nb_list = nullptr;
   int32_t *a_nnz = nullptr, *a_col = nullptr;
   void* a_val = nullptr;
@@ -251,6 +251,9 @@ View make_view(const mps_ctx* c) {
   v.cellid = c->cellid;
   v.slot = c->slot;
   v.cell_count = c->cell_count;
+  v.cell_local = c->cell_local;
+  v.tile_sum = c->tile_sum;
+  v.ntile = scan_tiles(c->ncell);
   v.cell_start = c->cell_start;
   v.perm = c->perm;
   v.nb_count = c->nb_count;
@@ -904,6 +907,8 @@ mps_status mps_init(const mps_params* params, int64_t n, const double* pos, cons
   A(dalloc(&c->perm, n));
   A(dalloc(&c->cell_count, scan_cells_padded(c->ncell)));
   A(dalloc(&c->cell_start, scan_cells_padded(c->ncell)));
+  A(dalloc(&c->cell_local, scan_cells_padded(c->ncell)));
+  A(dalloc(&c->tile_sum, scan_tiles(c->ncell)));
   A(dalloc(&c->nb_count, n));
   A(dalloc(&c->nb_list, c->slots));
   A(dalloc(&c->a_nnz, n));
@@ -1034,6 +1039,7 @@ mps_status mps_free(mps_ctx* c) {
   void* ptrs[] = {c->pd[0], c->pd[1],
                   c->pcell, c->posf, c->rsf, c->us, c->rs, c->nstar, c->src, c->flags,
                   c->cellid, c->slot, c->perm, c->cell_count, c->cell_start,
+                  c->cell_local, c->tile_sum,
                   c->nb_count,
                   c->nb_list, c->a_nnz, c->a_col, c->a_val, c->diag, c->b, c->r, c->z,
                   c->q, c->p_save, c->partA, c->partB, c->sc, c->status, c->counts,

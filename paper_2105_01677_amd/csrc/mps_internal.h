@@ -33,12 +33,14 @@ constexpr int WAVE = 64;
 constexpr int SLICE = WAVE / TEAM;        // rows per wavefront
 constexpr int BLOCK = 256;
 constexpr int ROWS_PER_BLOCK = BLOCK / TEAM;
-// cell-count scan: one workgroup of SCAN_NT threads, SCAN_PER cells each
-constexpr int SCAN_NT = 1024, SCAN_PER = 16, SCAN_CHUNK = SCAN_NT * SCAN_PER;
-// cells allocated for the counts and starts (whole scan chunks)
+// cell-count scan: tiles of SCAN_TILE cells, one workgroup of SCAN_NT
+// threads (SCAN_PER cells each) per tile
+constexpr int SCAN_NT = 256, SCAN_PER = 16, SCAN_TILE = SCAN_NT * SCAN_PER;
+// cells allocated for the counts and starts (ncell + 2, in whole tiles)
 inline int64_t scan_cells_padded(int ncell) {
-  return ((int64_t)ncell + 2 + SCAN_CHUNK - 1) / SCAN_CHUNK * SCAN_CHUNK;
+  return ((int64_t)ncell + 2 + SCAN_TILE - 1) / SCAN_TILE * SCAN_TILE;
 }
+inline int scan_tiles(int ncell) { return (int)(scan_cells_padded(ncell) / SCAN_TILE); }
 
 // Status bits raised by kernels (one int32 word on the device).
 enum : int32_t {
@@ -139,7 +141,10 @@ struct View {
   int32_t* cellid;    // old order
   int32_t* slot;      // old order
   int32_t* cell_count;
+  int32_t* cell_local;  // exclusive scan of the counts inside each tile
+  int32_t* tile_sum;    // total count of each tile
   int32_t* cell_start;
+  int ntile;
   int32_t* perm;      // unordered scatter of the particles by cell
   // lists
   int32_t* nb_count;

@@ -8,8 +8,9 @@
 // original particle id, so that the layout -- and every floating-point sum
 // over a list -- is independent of the order in which atomics resolved.
 // Sorting = cell of each particle + atomic slot (k_bin), exclusive scan of
-// the cell counts (k_scan_tiles, k_scan_apply), unordered scatter (k_scatter), rank inside the
-// cell and permutation of the state (k_rank_permute).
+// the cell counts inside tiles of cells (k_scan_tiles), tile offsets and
+// unordered scatter (k_scatter), rank inside the cell and permutation of the
+// state (k_rank_permute).
 #include "mps_internal.h"
 
 namespace mps {
@@ -77,67 +78,88 @@ __global__ __launch_bounds__(BLOCK) void k_bin(View v, int8_t* type_cur) {
   if (active) v.slot[i] = base + (lane - h);
 }
 
-// Exclusive scan of the ncell+1 cell counts by one workgroup, in chunks of
-// SCAN_CHUNK cells (a thread scans SCAN_PER consecutive counts, then the
-// workgroup its thread totals); resets the counts for the next step.  The
-// count and start arrays are padded to whole chunks (padding counts stay
-// 0), so cell_start[ncell + 1] comes out as the total.
-__global__ __launch_bounds__(SCAN_NT) void k_scan_cells(View v) {
+// Exclusive scan of the cell counts inside each tile of SCAN_TILE cells,
+// one workgroup per tile (a thread scans SCAN_PER consecutive counts, then
+// the workgroup its thread totals), and the tile's total; resets the counts
+// for the next step.  The arrays are padded to whole tiles (padding counts
+// stay 0) and cover ncell + 2 cells, so the start of cell ncell + 1 comes
+// out as the total.
+__global__ __launch_bounds__(SCAN_NT) void k_scan_tiles(View v) {
   constexpr int NW = SCAN_NT / WAVE, Q = SCAN_PER / 4;
-  const int m = v.ncell + 1;
   const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
-  __shared__ int32_t wsum[2][NW];
-  int32_t carry = 0;
-  int par = 0;
-  for (int c0 = 0; c0 <= m; c0 += SCAN_CHUNK, par ^= 1) {
-    const int base = c0 + threadIdx.x * SCAN_PER;
-    const int4* src = reinterpret_cast<const int4*>(v.cell_count + base);
-    int4 q[Q];
+  __shared__ int32_t wsum[NW];
+  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_PER;
+  const int4* src = reinterpret_cast<const int4*>(v.cell_count + base);
+  int4 q[Q];
 #pragma unroll
-    for (int k = 0; k < Q; ++k) q[k] = src[k];
-    int32_t s = 0;
+  for (int k = 0; k < Q; ++k) q[k] = src[k];
+  int32_t s = 0;
 #pragma unroll
-    for (int k = 0; k < Q; ++k) s += (q[k].x + q[k].y) + (q[k].z + q[k].w);
-    int32_t inc = s;
+  for (int k = 0; k < Q; ++k) s += (q[k].x + q[k].y) + (q[k].z + q[k].w);
+  int32_t inc = s;
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    const int32_t y = __shfl_up(inc, o, WAVE);
+    if (lane >= o) inc += y;
+  }
+  if (lane == WAVE - 1) wsum[w] = inc;
+  __syncthreads();
+  int32_t run = inc - s, total = 0;
+#pragma unroll
+  for (int k = 0; k < NW; ++k) {
+    const int32_t x = wsum[k];
+    run += k < w ? x : 0;
+    total += x;
+  }
+  int4* dst = reinterpret_cast<int4*>(v.cell_local + base);
+  int4* cnt = reinterpret_cast<int4*>(v.cell_count + base);
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    int4 o;
+    o.x = run;
+    run += q[k].x;
+    o.y = run;
+    run += q[k].y;
+    o.z = run;
+    run += q[k].z;
+    o.w = run;
+    run += q[k].w;
+    dst[k] = o;
+    cnt[k] = make_int4(0, 0, 0, 0);
+  }
+  if (threadIdx.x == 0) v.tile_sum[blockIdx.x] = total;
+}
+
+// Thread i scatters particle i (if i < n) to its cell's start + its atomic
+// slot, and writes the start of cell i (if i < ncell + 2).  A start is the
+// in-tile start plus the sum of the earlier tiles' totals, which every
+// wavefront scans itself, 64 tiles at a time (one pass up to 262,144 cells).
+__global__ __launch_bounds__(BLOCK) void k_scatter(View v) {
+  const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  const int lane = threadIdx.x & (WAVE - 1);
+  const bool part = i < v.n, cell = i < (int64_t)v.ncell + 2;
+  const int c = part ? v.cellid[i] : 0;
+  const int tp = c / SCAN_TILE, tc = cell ? (int)(i / SCAN_TILE) : 0;
+  const int32_t lp = part ? v.cell_local[c] : 0, lc = cell ? v.cell_local[i] : 0;
+  int32_t bp = 0, bc = 0, carry = 0;
+  for (int g0 = 0; g0 < v.ntile; g0 += WAVE) {
+    const int g = g0 + lane;
+    const int32_t x = g < v.ntile ? v.tile_sum[g] : 0;
+    int32_t inc = x;
 #pragma unroll
     for (int o = 1; o < WAVE; o <<= 1) {
       const int32_t y = __shfl_up(inc, o, WAVE);
       if (lane >= o) inc += y;
     }
-    if (lane == WAVE - 1) wsum[par][w] = inc;
-    __syncthreads();
-    int32_t run = carry + inc - s, total = 0;
-#pragma unroll
-    for (int k = 0; k < NW; ++k) {
-      const int32_t x = wsum[par][k];
-      run += k < w ? x : 0;
-      total += x;
-    }
-    int4* dst = reinterpret_cast<int4*>(v.cell_start + base);
-    int4* cnt = reinterpret_cast<int4*>(v.cell_count + base);
-#pragma unroll
-    for (int k = 0; k < Q; ++k) {
-      int4 o;
-      o.x = run;
-      run += q[k].x;
-      o.y = run;
-      run += q[k].y;
-      o.z = run;
-      run += q[k].z;
-      o.w = run;
-      run += q[k].w;
-      dst[k] = o;
-      cnt[k] = make_int4(0, 0, 0, 0);
-    }
-    carry += total;
-    // wsum alternates between two buffers, so one barrier per chunk
+    const int32_t ex = carry + inc - x;
+    const int32_t ep = __shfl(ex, (tp - g0) & (WAVE - 1), WAVE);
+    const int32_t ec = __shfl(ex, (tc - g0) & (WAVE - 1), WAVE);
+    if (tp >= g0 && tp < g0 + WAVE) bp = ep;
+    if (tc >= g0 && tc < g0 + WAVE) bc = ec;
+    carry += __shfl(inc, WAVE - 1, WAVE);
   }
-}
-
-__global__ __launch_bounds__(BLOCK) void k_scatter(View v) {
-  const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (i >= v.n) return;
-  v.perm[v.cell_start[v.cellid[i]] + v.slot[i]] = (int32_t)i;
+  if (part) v.perm[lp + bp + v.slot[i]] = (int32_t)i;
+  if (cell) v.cell_start[i] = lc + bc;
 }
 
 // Final position of every particle and the permutation of the state in one
@@ -282,8 +304,8 @@ int launch_bin(const View& v, int dim, hipStream_t s) {
   int8_t* type_cur = const_cast<int8_t*>(v.type);
   if (dim == 2) k_bin<2><<<nblk(v.n, BLOCK), BLOCK, 0, s>>>(v, type_cur);
   else k_bin<3><<<nblk(v.n, BLOCK), BLOCK, 0, s>>>(v, type_cur);
-  k_scan_cells<<<1, SCAN_NT, 0, s>>>(v);
-  k_scatter<<<nblk(v.n, BLOCK), BLOCK, 0, s>>>(v);
+  k_scan_tiles<<<v.ntile, SCAN_NT, 0, s>>>(v);
+  k_scatter<<<std::max(nblk(v.n, BLOCK), nblk((int64_t)v.ncell + 2, BLOCK)), BLOCK, 0, s>>>(v);
   return 0;
 }
 
