@@ -56,17 +56,28 @@ def _list_inputs():
     pos[::3, 0] = lo[0] + cs * np.floor((pos[::3, 0] - lo[0]) / cs)
     pos[1::3, 1] = lo[1] + cs * np.floor((pos[1::3, 1] - lo[1]) / cs)
     cases["cell_faces"] = W.Workload("faces", pos, w.vel, w.ptype, w.params)
+    # a 70^3 grid (343,000 cells: the cell-count scan takes 84 tiles of
+    # 4,096, two passes of the tile offsets) with two random clusters, one at
+    # each end of the cell order
+    w = W.random_box(1500, 3, seed=14)
+    prm = dict(w.params)
+    prm["grid_n"] = [70, 70, 70]
+    far = w.pos + 62 * prm["cell_size"]
+    pos = np.concatenate([w.pos, far])
+    cases["big_grid_3d"] = W.Workload("big_grid", pos, np.zeros_like(pos),
+                                      np.zeros(len(pos), np.int8), prm)
     return cases
 
 
 @pytest.mark.parametrize("precision", [W.FP64, W.MIXED])
 @pytest.mark.parametrize("name", ["random2d", "random3d", "db2d_1432_jitter", "block3d_jitter",
-                                  "cell_faces", "db2d_1432_lattice", "block3d_lattice"])
+                                  "cell_faces", "db2d_1432_lattice", "block3d_lattice",
+                                  "big_grid_3d"])
 def test_neighbor_lists_bit_exact(gpu, orc, name, precision):
-    """Lists against the oracle's cell-linked list, bit for bit.  The mixed
-    path tests candidates in FP32 first and re-decides those near re_lap in
-    FP64; the unjittered lattices put many pairs at exactly 4 l0 (2-D) or
-    near 3.1 l0 (3-D), where that re-decision is what keeps them out."""
+    """Lists against the oracle's cell-linked list, bit for bit.  Both
+    paths decide d^2 < re_lap^2 on the same FP64 expression; the unjittered
+    lattices put many pairs at exactly 4 l0 (2-D) or near 3.1 l0 (3-D),
+    where any other rounding would let some of them in."""
     w = _list_inputs()[name]
     w.params["precision"] = precision
     print(f"case {name} n={w.n}", flush=True)
