@@ -181,7 +181,8 @@ def test_one_step_3d(gpu, orc, precision, cg_tol, tol):
 @pytest.mark.parametrize("precision,cg_tol,tol", PRECISIONS)
 def test_one_step_3d_split_cg(gpu, orc, precision, cg_tol, tol):
     """73,344 particles: more row groups than one fused CG kernel takes
-    (1,146 > 1,024), so the solve runs as reduction + iteration kernels."""
+    (1,146 > 1,024), so the solve runs as reduction + iteration kernels;
+    7 % dummies, so the iteration loads its first slots unconditionally."""
     w = W.jitter(W.lattice_block(3, [44, 40, 36], walls_below=True, dt=2e-4))
     assert (w.n + 63) // 64 > 1024
     w.params.update(precision=precision, cg_tol=cg_tol)
@@ -191,7 +192,9 @@ def test_one_step_3d_split_cg(gpu, orc, precision, cg_tol, tol):
 @pytest.mark.parametrize("precision,cg_tol,tol", PRECISIONS)
 def test_one_step_dam_break_3d_441282(gpu, orc, precision, cg_tol, tol):
     """3-D bench size: the 441,282-particle dam break from rest, as
-    benchmarked (split CG schedule), every particle against the oracle."""
+    benchmarked (split CG schedule; 35 % dummies, so the iteration's slot
+    loads are predicated on the row length), every particle against the
+    oracle."""
     w = W.config("dam_break_3d_441282", precision=precision)
     w.params["cg_tol"] = cg_tol
     _compare_step(gpu, orc, w, tol)
