@@ -269,7 +269,8 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="first copy a cold 1 GiB buffer once (reference kernel for HBM counters)")
     ap.add_argument("--only", default=None,
-                    help="time one configuration only, e.g. ppe:mixed, wc:fp64 (for profilers)")
+                    help="time one configuration only, e.g. ppe:mixed, wc:fp64, ppe3d:mixed "
+                         "(the 441,282-particle 3-D dam break; for profilers)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -296,8 +297,12 @@ def main():
         del a, b, flush
     if args.only:
         pm, pr = args.only.split(":")
-        wo = W.config("dam_break_2d_44832", pmode=W.PPE_CG if pm == "ppe" else W.WC_EOS,
-                      precision=W.MIXED if pr == "mixed" else W.FP64)
+        prec = W.MIXED if pr == "mixed" else W.FP64
+        if pm == "ppe3d":
+            wo = W.config("dam_break_3d_441282", precision=prec)
+        else:
+            wo = W.config("dam_break_2d_44832", pmode=W.PPE_CG if pm == "ppe" else W.WC_EOS,
+                          precision=prec)
         r = run_gpu(wo, K, Wm)
         print(json.dumps({"only": args.only, "value": r["particle_steps_per_s"],
                           "ms_per_step": r["ms_per_step"], "steps": K}), flush=True)
