@@ -118,6 +118,49 @@ def run_gpu(w, steps, warmup, *, profile_all=False, profile_cls=None):
             "state_check": check}
 
 
+def run_full_length():
+    """Each of the five workloads from rest for its configured number of
+    steps, in calls of 10 steps: wall time per step (the pipeline drains at
+    every call), CG iterations, and where the run stops being the physical
+    flow (a library error, the first ghost, the speed bound at the end)."""
+    import torch
+
+    from paper_2105_01677_amd import mps
+    from paper_2105_01677_amd import workloads as W
+    cases = [("dam_break_2d_1432", W.FP64), ("dam_break_2d_44832", W.MIXED),
+             ("sloshing_2d_24932", W.MIXED), ("dam_break_3d_441282", W.MIXED),
+             ("two_phase_3d_2314616", W.MIXED)]
+    out = {}
+    for name, prec in cases:
+        w = W.config(name, precision=prec)
+        m = mps.MPS(w.params, w.pos, w.vel, w.ptype, rho_i=w.rho_i, nu_i=w.nu_i)
+        done, iters, err, first_ghost = 0, 0, None, None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        while done < w.steps:
+            k = min(10, w.steps - done)
+            try:
+                s = m.step(k)
+            except mps.MPSError as e:
+                err = str(e)
+                break
+            done += k
+            iters += s["cg_iters_total"]
+            if first_ghost is None and s["n_ghost"] > 0:
+                first_ghost = done
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        chk = state_check(w, m.state()) if err is None else None
+        m.close()
+        out[name] = {"n_particles": w.n, "pressure": "WC" if w.params["pmode"] == W.WC_EOS else "PPE",
+                     "configured_steps": w.steps, "steps_run": done,
+                     "ms_per_step": 1e3 * dt / max(done, 1),
+                     "cg_iters_mean": iters / max(done, 1), "error": err,
+                     "first_ghost_by_step": first_ghost, "state_check": chk}
+        log(name, out[name])
+    return out
+
+
 def run_drop(steps=1000):
     """The elliptic water drop (Section "Water drop"; 1,257 particles, the
     weakly-compressible model, mixed path) from the circle for `steps` steps
@@ -268,6 +311,9 @@ def main():
                     help="time the headline configuration only (for profilers)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first copy a cold 1 GiB buffer once (reference kernel for HBM counters)")
+    ap.add_argument("--full-length", action="store_true",
+                    help="instead of the bench: every workload for its configured number "
+                         "of steps (one JSON line)")
     ap.add_argument("--only", default=None,
                     help="time one configuration only, e.g. ppe:mixed, wc:fp64, ppe3d:mixed "
                          "(the 441,282-particle 3-D dam break; for profilers)")
@@ -295,6 +341,9 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b, flush
+    if args.full_length:
+        print(json.dumps({"full_length": run_full_length()}), flush=True)
+        return
     if args.only:
         pm, pr = args.only.split(":")
         prec = W.MIXED if pr == "mixed" else W.FP64
