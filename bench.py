@@ -274,26 +274,53 @@ def run_adjoint(w, nsteps, K):
     return res
 
 
-def cpu_baseline(w, seconds):
-    import oracle
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
-    os.environ.setdefault("OMP_NUM_THREADS", str(threads))
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_rate(w, seconds, max_steps):
+    """Oracle steps of w from rest until `seconds` have passed: (steps,
+    seconds, particle-steps/s)."""
     import numpy as np
+
+    import oracle
     pos, vel, t = w.pos.copy(), w.vel.copy(), w.ptype.copy()
-    # one step first (also loads the library), then as many as fit the budget
     steps, t0 = 0, time.perf_counter()
     while True:
         st, pos, vel, t, p, fl = oracle.run(w.params, pos, vel, t, 1)
         steps += 1
         el = time.perf_counter() - t0
-        if el >= seconds or steps >= 400:
+        if el >= seconds or steps >= max_steps:
             break
     assert np.isfinite(pos).all()
-    return {"value": w.n * steps / el, "unit": "particle-steps/s", "cores": threads,
+    return steps, el, w.n * steps / el
+
+
+def cpu_baseline(w, seconds):
+    """The FP64 oracle on the host: all threads for `seconds`, then one
+    thread for half as long (the first steps of the same workload from
+    rest)."""
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    oracle.set_threads(threads)
+    _oracle_rate(w, 0.0, 1)                      # loads the library, warms up
+    steps, el, rate = _oracle_rate(w, seconds, 400)
+    oracle.set_threads(1)
+    s1, e1, r1 = _oracle_rate(w, seconds / 2, 400)
+    oracle.set_threads(threads)
+    return {"value": rate, "unit": "particle-steps/s", "cores": threads,
             "kind": "oracle",
             "sample": f"first {steps} steps of the same workload from rest "
                       f"({el:.1f} s on {threads} host threads, FP64 C++ oracle, "
-                      f"cell-linked-list neighbours, Jacobi-CG to 1e-13)"}
+                      f"cell-linked-list neighbours, Jacobi-CG to 1e-13)",
+            "single_thread": {"value": r1, "steps": s1, "seconds": e1},
+            "nproc": os.cpu_count(), "cpu_model": _cpu_model()}
 
 
 def main():

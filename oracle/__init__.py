@@ -81,8 +81,14 @@ def lib():
                               C.c_void_p]
         L.orc_smoothed_density.argtypes = [C.POINTER(OrcParams), C.c_int64, C.c_void_p,
                                            C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_set_threads.argtypes = [C.c_int]
         _lib = L
     return _lib
+
+
+def set_threads(n: int) -> int:
+    """Host threads of the oracle's OpenMP loops; returns the count in effect."""
+    return int(lib().orc_set_threads(int(n)))
 
 
 def make_params(p: dict) -> OrcParams:

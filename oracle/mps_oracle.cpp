@@ -22,6 +22,8 @@
  */
 #include "mps_oracle.h"
 
+#include <omp.h>
+
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -744,6 +746,11 @@ void to_params(const orc_params* P, double* nu, double g[3]) {
 
 /* ---------------------------------------------------------------- C API */
 extern "C" {
+
+int orc_set_threads(int n) {
+  if (n >= 1) omp_set_num_threads(n);
+  return omp_get_max_threads();
+}
 
 double orc_weight(int kernel, double r, double re) { return weight(kernel, r, re); }
 

@@ -99,6 +99,8 @@ int orc_rollout_grad(const orc_params* P, int64_t n, const double* pos,
 double orc_loss(const orc_params* P, int64_t n, const double* pos,
                 const double* vel, const int8_t* type, const int8_t* flags,
                 double w_ke, double w_var);
+/* Host threads of the OpenMP loops (n >= 1); returns the count in effect. */
+int orc_set_threads(int n);
 
 #ifdef __cplusplus
 }
