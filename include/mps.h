@@ -23,8 +23,11 @@
  *  - Work is enqueued on the stream given to mps_init.  Calls that return
  *    host scalars (iteration counts, residuals, statistics) or a status
  *    detected on the device synchronise that stream before returning.
- *  - The library owns all its scratch memory, allocated once in mps_init;
- *    mps_step and mps_pressure_solve never allocate.
+ *  - The library owns all its scratch memory, allocated once in mps_init
+ *    (and mps_tape_alloc); mps_step and mps_pressure_solve make no device
+ *    allocation of their own.  mps_step captures its stages into HIP graphs
+ *    the first time a stage shape is needed (a few per context, cached until
+ *    mps_free); instantiating one is left to the HIP runtime.
  *  - Every function returns an mps_status and never aborts or prints.
  *    Argument errors leave the context untouched.  A numerical error
  *    (NEIGH_OVERFLOW, COINCIDENT, NONFINITE) marks the context poisoned:
