@@ -225,6 +225,7 @@ __global__ __launch_bounds__(BLOCK) void k_rank_permute(View v) {
 // appends hits in candidate order with a ballot, so the list order is fixed.
 template <int DIM>
 __global__ __launch_bounds__(BLOCK) void k_neighbors(View v) {
+  constexpr int NR = DIM == 3 ? 9 : 3;  // cell rows of the 3^DIM block
   const int64_t row = (int64_t)xcd_block() * ROWS_PER_BLOCK + threadIdx.x / TEAM;
   const int t = team_lane();
   if (row >= v.n) return;
@@ -235,30 +236,37 @@ __global__ __launch_bounds__(BLOCK) void k_neighbors(View v) {
     load_vec<DIM>(v.pos, row, xi);
     const int cx = ucx(pc), cy = ucy(pc), cz = ucz(pc);
     const int x0 = max(cx - 1, 0), x1 = min(cx + 1, v.nx - 1);
-    const int zlo = DIM == 3 ? max(cz - 1, 0) : 0;
-    const int zhi = DIM == 3 ? min(cz + 1, v.nz - 1) : 0;
+    // every row range first (no dependent wait per range); rows outside
+    // the grid get an empty range
+    int jb[NR], je[NR];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      const int y = cy - 1 + q % 3, z = DIM == 3 ? cz - 1 + q / 3 : 0;
+      const bool in = y >= 0 && y < v.ny && z >= 0 && z < v.nz;
+      const int base = v.nx * ((in ? y : cy) + v.ny * (in ? z : cz));
+      jb[q] = v.cell_start[base + x0];
+      je[q] = in ? v.cell_start[base + x1 + 1] : 0;
+    }
     bool coinc = false;
-    for (int z = zlo; z <= zhi; ++z) {
-      for (int y = max(cy - 1, 0); y <= min(cy + 1, v.ny - 1); ++y) {
-        const int base = v.nx * (y + v.ny * z);
-        const int jb = v.cell_start[base + x0], je = v.cell_start[base + x1 + 1];
-        for (int jj = jb; jj < je; jj += TEAM) {
-          const int j = jj + t;
-          bool hit = false;
-          if (j < je && j != row) {
-            double xj[DIM];
-            load_vec<DIM>(v.pos, j, xj);
-            const double d2 = dist2_exact<DIM>(xi, xj);
-            hit = d2 < v.re_lap2;
-            coinc = coinc || (hit && d2 == 0.0);
-          }
-          const uint32_t m = team_ballot(hit);
-          if (hit) {
-            const int l = count + __popc(m & ((1u << t) - 1u));
-            if (l < v.max_neigh) v.nb_list[sl_index(row, l, v.kpad)] = j;
-          }
-          count += __popc(m);
+    const int64_t slot0 = sl_index(row, 0, v.kpad);
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      const int b = jb[q], e = je[q];
+      for (int jj = b; jj < e; jj += TEAM) {
+        const int j = jj + t;
+        // branch-free: a lane past the range tests its own particle
+        double xj[DIM];
+        load_vec<DIM>(v.pos, j < e ? j : row, xj);
+        const double d2 = dist2_exact<DIM>(xi, xj);
+        const bool hit = j < e && j != row && d2 < v.re_lap2;
+        coinc = coinc || (hit && d2 == 0.0);
+        const uint32_t m = team_ballot(hit);
+        if (hit) {
+          const unsigned l = (unsigned)(count + __popc(m & ((1u << t) - 1u)));
+          if (l < (unsigned)v.max_neigh)
+            v.nb_list[slot0 + (int64_t)(l / TEAM) * WAVE + (l % TEAM)] = j;
         }
+        count += __popc(m);
       }
     }
     if (coinc) atomicOr(v.status, ST_COINCIDENT);
