@@ -182,7 +182,15 @@ __global__ __launch_bounds__(BLOCK) void k_rank_permute(View v) {
   } else {
     const int e = v.cell_start[c + 1];
     int rank = 0;
-    for (int m = b; m < e; ++m) rank += v.id[v.perm[m]] < key ? 1 : 0;
+    // four members per step, all loads issued before the compares (a member
+    // past the cell end is read as the cell's first and not counted)
+    for (int m = b; m < e; m += 4) {
+      int32_t pm[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) pm[u] = v.perm[m + u < e ? m + u : b];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) rank += (m + u < e && v.id[pm[u]] < key) ? 1 : 0;
+    }
     k = b + rank;
   }
   double x[DIM], u[DIM];
