@@ -73,7 +73,7 @@ struct mps_ctx {
   double* partB = nullptr;
   double *pl_z = nullptr, *pl_s = nullptr, *pl_m[2] = {nullptr, nullptr},
          *pl_part[2] = {nullptr, nullptr}, *pl_part2[2] = {nullptr, nullptr};
-  int nspmv = 0, nupd = 0, npcg = 0, pcg_fused = 0, pcg_pred = 0;
+  int nspmv = 0, nupd = 0, nasmb = 0, npcg = 0, pcg_fused = 0, pcg_pred = 0;
   CGScalars* sc = nullptr;
   int32_t* status = nullptr;
   int64_t* counts = nullptr;   // [4]: surface, ghost, list entries, matrix nnz
@@ -281,6 +281,7 @@ View make_view(const mps_ctx* c) {
   v.pl_part2[1] = c->pl_part2[1];
   v.npcg2 = std::min(c->npcg, PCG_SPLIT_G);
   v.nspmv = c->nspmv;
+  v.nasmb = c->nasmb;
   v.nupd = c->nupd;
   v.npcg = c->npcg;
   v.pcg_fused = c->pcg_fused;
@@ -935,8 +936,9 @@ mps_status mps_init(const mps_params* params, int64_t n, const double* pos, cons
     A(dalloc(&c->mu, n));
   }
   c->nspmv = cg_spmv_blocks(n);
+  c->nasmb = assemble_blocks(n, params->cg_pipelined != 0);
   c->nupd = cg_update_blocks(n);
-  A(dalloc(&c->partA, (size_t)std::max(c->nspmv, c->nupd) * 4));
+  A(dalloc(&c->partA, (size_t)std::max({c->nspmv, c->nupd, c->nasmb}) * 4));
   A(dalloc(&c->partB, (size_t)c->nspmv));
   c->pcg_fused = pcg_blocks(n, true) <= pcg_fused_capacity() ? 1 : 0;
   c->npcg = pcg_blocks(n, c->pcg_fused != 0);

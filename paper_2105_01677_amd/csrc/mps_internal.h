@@ -164,7 +164,8 @@ struct View {
   double* q;
   double* partA;      // [blocks][4]: (r,z), (r,r), (b,b) of assembly / update
   double* partB;      // [blocks]: (p, A p) of the SpMV workgroups
-  int nspmv, nupd;    // grid sizes of the SpMV / assembly and update kernels
+  int nspmv, nupd;    // grid sizes of the textbook SpMV and update kernels
+  int nasmb;          // grid size of the assembly
   int npcg;           // grid size of the pipelined CG kernels (one row group each)
   int pcg_fused;      // 1: one kernel per iteration; 0: reduction + iteration
   int pcg_pred;       // split schedule: slot loads predicated on the row length
@@ -431,6 +432,8 @@ int launch_gather_orig(const View& v, const double* src, double* dst, int comps,
 int launch_export_ppe(const View& v, int precision, double* diag, double* b,
                       int32_t* nnz, int32_t* cols, double* vals, hipStream_t s);
 int cg_spmv_blocks(int64_t n);
+// Workgroups of the assembly (its partials start the solve).
+int assemble_blocks(int64_t n, bool pipelined);
 int adj_partial_blocks(int64_t n);
 int launch_adjoint_head(const View& v, const AdjView& a, int dim, int precision, int wc,
                         hipStream_t s);

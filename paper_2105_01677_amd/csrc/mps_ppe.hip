@@ -749,6 +749,16 @@ int cg_spmv_blocks(int64_t n) {
   const int64_t a = nb_team(n);
   return (int)(a < CG_SPMV_BLOCKS ? a : CG_SPMV_BLOCKS);
 }
+// The pipelined solve reduces the assembly partials once per solve, so the
+// assembly takes one 32-row group per workgroup (the hardware balances dense
+// and sparse regions); the textbook SpMV re-reduces them in every
+// workgroup and keeps the capped grid.
+#ifndef ASM_GRID_FULL
+#define ASM_GRID_FULL 1
+#endif
+int assemble_blocks(int64_t n, bool pipelined) {
+  return pipelined && ASM_GRID_FULL ? (int)nb_team(n) : cg_spmv_blocks(n);
+}
 int cg_update_blocks(int64_t n) {
   const int64_t a = nb_flat(n);
   return (int)(a < CG_UPD_BLOCKS ? a : CG_UPD_BLOCKS);
@@ -769,7 +779,7 @@ static void assemble_t(const View& v, bool mx, unsigned nb, const double* rhs, i
 
 int launch_assemble(const View& v, int dim, int precision, const double* rhs, bool zero_x0,
                     hipStream_t s) {
-  const unsigned nb = (unsigned)v.nspmv;
+  const unsigned nb = (unsigned)v.nasmb;
   const int zx = zero_x0 ? 1 : 0;
   const bool mx = precision == MPS_MIXED;
   if (dim == 2) {
