@@ -8,6 +8,12 @@
  * the CPU-baseline leg of the benchmark may load it.  It shares no code with
  * the HIP library and must never be linked into it.
  *
+ * Pins (tests/test_oracle_pins.py): each function is checked against
+ * closed forms, brute force, library routines or invariants.  Parity
+ * unpinned: multi-step dam-break trajectories (orc_run) beyond a few dozen
+ * steps, which are chaotic; the tests compare them over 20 steps only (the
+ * smooth water drop over 300).
+ *
  * Every array is in original particle order, row-major [n][dim], FP64.
  * Particle types: 0 fluid, 1 wall, 2 dummy, 3 ghost (left the grid).
  * Flags: -2 ghost, -1 dummy, 0 inner, 1 free surface.
