@@ -589,3 +589,26 @@ def test_neighbor_cap_boundary(gpu):
                 m.step(1)
             assert e.value.status == gpu.E_NEIGH_OVERFLOW
         m.close()
+
+
+@pytest.mark.parametrize("precision,tol", [(W.FP64, 1e-12), (W.MIXED, 1e-5)])
+def test_cmps_conserves_momentum_gpu(gpu, precision, tol):
+    """g = 0, no walls, CMPS gradient (Eq. 18) and viscosity: every pair term
+    is antisymmetric, so one GPU step leaves total momentum unchanged (up to
+    the rounding of the per-particle sums; FP32 sums on the mixed path); the
+    standard gradient moves it."""
+    w = W.jitter(W.lattice_block(2, 16, dt=1e-4))
+    prm = dict(w.params, grad=W.GRAD_CMPS, nu=1e-3, precision=precision)
+    scale = np.abs(w.vel).sum(0).max()
+    p0 = w.vel.sum(0)
+    m = gpu.MPS(prm, w.pos, w.vel, w.ptype)
+    m.step(1)
+    st = m.state()
+    m.close()
+    assert np.abs(_np(st["p"])).max() > 0
+    np.testing.assert_allclose(_np(st["vel"]).sum(0), p0, rtol=0, atol=tol * scale)
+    m = gpu.MPS(dict(prm, grad=W.GRAD_STD), w.pos, w.vel, w.ptype)
+    m.step(1)
+    v_std = _np(m.state()["vel"])
+    m.close()
+    assert np.abs(v_std.sum(0) - p0).max() > 10 * tol * scale
