@@ -591,16 +591,17 @@ def test_neighbor_cap_boundary(gpu):
         m.close()
 
 
+@pytest.mark.parametrize("g", [0.0, 9.81])
 @pytest.mark.parametrize("precision,tol", [(W.FP64, 1e-12), (W.MIXED, 1e-5)])
-def test_cmps_conserves_momentum_gpu(gpu, precision, tol):
-    """g = 0, no walls, CMPS gradient (Eq. 18) and viscosity: every pair term
-    is antisymmetric, so one GPU step leaves total momentum unchanged (up to
-    the rounding of the per-particle sums; FP32 sums on the mixed path); the
-    standard gradient moves it."""
-    w = W.jitter(W.lattice_block(2, 16, dt=1e-4))
+def test_cmps_conserves_momentum_gpu(gpu, precision, tol, g):
+    """No walls, CMPS gradient (Eq. 18) and viscosity: every pair term is
+    antisymmetric, so one GPU step changes total momentum by exactly the body
+    force, N g dt (free flight; up to the rounding of the per-particle sums,
+    FP32 sums on the mixed path); the standard gradient moves it more."""
+    w = W.jitter(W.lattice_block(2, 16, dt=1e-4, g=g))
     prm = dict(w.params, grad=W.GRAD_CMPS, nu=1e-3, precision=precision)
     scale = np.abs(w.vel).sum(0).max()
-    p0 = w.vel.sum(0)
+    p0 = w.vel.sum(0) + w.n * np.array(w.params["g"][:2]) * w.params["dt"]
     m = gpu.MPS(prm, w.pos, w.vel, w.ptype)
     m.step(1)
     st = m.state()
