@@ -219,6 +219,24 @@ def pressure_gradient(params, rs, ptype, p):
     return st, phat, gp
 
 
+def pressure_update(params, rs, us, ptype, p, rho_s=None):
+    """(status, pos[n][dim], vel[n][dim]): p-hat, gradient of a given pressure
+    field at rs and the Euler update from the predicted state (rs, us)."""
+    P, rs, ptype = _prep(params, rs, ptype)
+    us = np.ascontiguousarray(us, dtype=np.float64)
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    n, dim = rs.shape
+    pos = np.zeros((n, dim))
+    vel = np.zeros((n, dim))
+    L = lib()
+    L.orc_pressure_update.argtypes = [C.POINTER(OrcParams), C.c_int64, C.c_void_p, C.c_void_p,
+                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                      C.c_void_p]
+    st = L.orc_pressure_update(C.byref(P), n, _ptr(rs), _ptr(us), _ptr(ptype), _ptr(p),
+                               _ptr(_opt(rho_s)), _ptr(pos), _ptr(vel))
+    return st, pos, vel
+
+
 def rollout_grad(params, pos, vel, ptype, nsteps, direction, w_ke=1.0, w_var=9.81, *,
                  rho_s=None, nu_i=None):
     """(status, L, dL/dnu, dL/dgx, <dL/du0, direction>) by dual numbers.

@@ -464,6 +464,29 @@ void pressure_gradient(const orc_params* P, const Consts& C, int n,
   }
 }
 
+/* First-order Euler update of the fluid particles (Section "Standard
+ * method"): u^{k+1} = u* - dt/rho_i grad p_i, r^{k+1} = r* + dt (u^{k+1} - u*),
+ * with rho_i the smoothed density of the two-phase model when given, else
+ * the single density rho.  Other particles keep their position and velocity. */
+template <class T>
+void euler_update(const orc_params* P, int n, const std::vector<int8_t>& type,
+                  const std::vector<T>& us, const std::vector<T>& rs,
+                  const std::vector<T>& gradp, const double* rho_s, std::vector<T>& pos,
+                  std::vector<T>& vel) {
+  const int dim = P->dim;
+  const double dt = P->dt;
+  for (int i = 0; i < n; ++i) {
+    if (type[i] != FLUID) continue;
+    const double rho_i = rho_s ? rho_s[i] : P->rho;
+    for (int a = 0; a < dim; ++a) {
+      size_t k = (size_t)i * dim + a;
+      T u = us[k] - dt / rho_i * gradp[k];
+      pos[k] = rs[k] + dt * (u - us[k]);
+      vel[k] = u;
+    }
+  }
+}
+
 template <class T>
 int step(const orc_params* P, const Consts& C, const T& nu, const T g[3], int n,
          std::vector<T>& pos, std::vector<T>& vel, std::vector<int8_t>& type,
@@ -685,18 +708,8 @@ int step(const orc_params* P, const Consts& C, const T& nu, const T g[3], int n,
   /* 6-7. p-hat and the pressure gradient at r*. */
   pressure_gradient<T>(P, C, n, tr.rs, type, tr.p, tr.lists, tr.phat, tr.gradp);
 
-  /* 8. First-order Euler update, fluid only:
-   *    u^{k+1} = u* - dt/rho grad p,  r^{k+1} = r* + dt (u^{k+1} - u*). */
-  for (int i = 0; i < n; ++i) {
-    for (int a = 0; a < dim; ++a) {
-      size_t k = (size_t)i * dim + a;
-      if (type[i] == FLUID) {
-        T u = tr.us[k] - dt / rho_of(i) * tr.gradp[k];
-        pos[k] = tr.rs[k] + dt * (u - tr.us[k]);
-        vel[k] = u;
-      }
-    }
-  }
+  /* 8. First-order Euler update. */
+  euler_update<T>(P, n, type, tr.us, tr.rs, tr.gradp, rho_s, pos, vel);
   return status;
 }
 
@@ -922,6 +935,27 @@ int orc_pressure_gradient(const orc_params* P, int64_t n, const double* rs,
   pressure_gradient<double>(P, C, (int)n, r, t, pp, L, ph, gp);
   std::memcpy(phat, ph.data(), n * sizeof(double));
   std::memcpy(gradp, gp.data(), n * P->dim * sizeof(double));
+  return 0;
+}
+
+int orc_pressure_update(const orc_params* P, int64_t n, const double* rs, const double* us,
+                        const int8_t* type, const double* p, const double* rho_s,
+                        double* pos_out, double* vel_out) {
+  /* p-hat, the pressure gradient of a given pressure field at rs (lists
+   * taken at rs) and the Euler update of the step from (rs, us). */
+  Consts C = constants(P);
+  const int dim = P->dim;
+  Lists L;
+  std::vector<int> cell;
+  std::vector<int8_t> t(type, type + n);
+  int st = build_lists_cells(P, (int)n, rs, t.data(), L, cell);
+  if (st) return st;
+  std::vector<double> r(rs, rs + n * dim), u(us, us + n * dim), pp(p, p + n), ph, gp;
+  pressure_gradient<double>(P, C, (int)n, r, t, pp, L, ph, gp);
+  std::vector<double> x = r, v = u;
+  euler_update<double>(P, (int)n, t, u, r, gp, rho_s, x, v);
+  std::memcpy(pos_out, x.data(), x.size() * sizeof(double));
+  std::memcpy(vel_out, v.data(), v.size() * sizeof(double));
   return 0;
 }
 

@@ -91,6 +91,14 @@ int orc_pressure_gradient(const orc_params* P, int64_t n, const double* rs,
                           const int8_t* type, const double* p, double* phat,
                           double* gradp);
 
+/* p-hat, the pressure gradient of a given pressure field p at rs and the
+ * first-order Euler update from the predicted state (rs, us): the last part
+ * of the step on its own.  rho_s (may be NULL): smoothed densities of the
+ * two-phase model.  pos_out, vel_out: [n][dim]. */
+int orc_pressure_update(const orc_params* P, int64_t n, const double* rs,
+                        const double* us, const int8_t* type, const double* p,
+                        const double* rho_s, double* pos_out, double* vel_out);
+
 /* Loss after nsteps (w_ke * mean fluid kinetic energy + w_var * variance of
  * the free-surface height) and its forward-mode derivatives along d/dnu,
  * d/dg_x and <d/du0, dir>: out[4] = {L, dL/dnu, dL/dgx, <dL/du0, dir>}.

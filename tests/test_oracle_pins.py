@@ -265,6 +265,63 @@ def test_cmps_conserves_momentum(orc, pmode):
     assert np.abs(o2["vel"].sum(0) - p0).max() > 1e3 * 1e-12 * scale.max()
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_cmps_gradient_of_a_linear_field_is_zero(orc, dim):
+    """Eq. 18 on a perfect lattice with p = a.r + c: p-hat_i = p_i - m and
+    p-hat_j = p_j - m with the same m (every particle sees the same
+    neighbourhood), so the numerator (p_i + p_j) - (p-hat_i + p-hat_j) = 2m is
+    the same for every pair and the lattice sum of r_ij w / r^2 cancels: the
+    gradient is 0.  Without the p-hat terms, or with p-hat_i twice, the
+    numerator keeps the slope and the sum is the full gradient a."""
+    m = 14 if dim == 2 else 13
+    w = W.lattice_block(dim, m)
+    prm = dict(w.params, grad=W.GRAD_CMPS)
+    a = np.array([3.0e3, -1.5e3, 7.0e2][:dim])
+    p = 1.0e4 + w.pos @ a
+    st, phat, gp = orc.pressure_gradient(prm, w.pos, w.ptype, p)
+    assert st == 0
+    # p-hat of i and of every neighbour within re_n must see a full lattice
+    inner = _interior(w.pos, w.pos.min(0), w.pos.max(0), 2 * prm["re_n"] + 1e-9)
+    assert inner.sum() >= 4
+    np.testing.assert_allclose(gp[inner], 0.0, atol=1e-9 * np.abs(a).max())
+    # the same field through the standard form gives the slope (control)
+    st, _, gs = orc.pressure_gradient(w.params, w.pos, w.ptype, p)
+    np.testing.assert_allclose(gs[inner], np.broadcast_to(a, gs[inner].shape), rtol=1e-10)
+
+
+def test_ppe_source_scale_on_a_compressed_lattice(orc):
+    """Eq. 13 on a lattice compressed uniformly to spacing s l0 (the
+    parameters keep l0), surrounded by 3 dummy layers so that every fluid
+    particle sees the full compressed lattice within re_n, at rest, g = 0.
+    Every fluid row then has the same n* (the shell sum at spacing s l0) and
+    no free-surface neighbour, so a uniform p solves A p = b:
+    sum_j c_ij (p_i - p_j) = 0 and (alpha/dt^2) p = (n* - n0)/(n0 dt^2), i.e.
+    p = (n*/n0 - 1)/alpha for every fluid particle.  A wrong scale of the
+    source (a factor rho, a lost dt^2 or n0) or of the alpha term fails it;
+    the coupling scale c_ij is pinned by the rows-as-Laplacian test."""
+    s = 0.97
+    for dim, shells in ((2, SHELLS_2D), (3, SHELLS_3D)):
+        m = 16 if dim == 2 else 11
+        w = W.lattice_block(dim, m)
+        l0 = w.params["l0"]
+        idx = np.rint(w.pos / l0 - 0.5).astype(int)
+        layer = np.minimum(idx, m - 1 - idx).min(1)
+        ptype = np.where(layer < 3, W.DUMMY, W.FLUID).astype(np.int8)
+        pos = (idx + 0.5) * s * l0
+        prm = dict(w.params, g=[0.0, 0.0, 0.0])
+        st, o = orc.step(prm, pos, np.zeros_like(pos), ptype, want_lists=False)
+        assert st == 0
+        n0 = shells_constants(shells, 2.1, 0)[0]
+        nstar = sum(mult * (2.1 / (s * math.sqrt(d2)) - 1.0)
+                    for d2, mult in shells.items() if s * math.sqrt(d2) < 2.1)
+        f = ptype == W.FLUID
+        np.testing.assert_allclose(o["nstar"][f], nstar, rtol=1e-12)
+        assert np.all(o["flags"][f] == 0)
+        p_ref = (nstar / n0 - 1.0) / prm["alpha"]
+        assert p_ref > 1e5
+        np.testing.assert_allclose(o["p"][f], p_ref, rtol=1e-9)
+
+
 def test_ppe_dense_solve_and_structure(orc):
     """The assembled PPE (Eq. 13 with the Laplacian of Eq. 7) is symmetric,
     strictly diagonally dominant by alpha/dt^2, and the oracle's pressure is
@@ -320,7 +377,6 @@ def test_equation_of_state(orc):
     ref = np.maximum(B * ((o["nstar"][fw] / n0) ** 7 - 1.0), 0.0)
     np.testing.assert_allclose(o["p"][fw], ref, rtol=1e-12, atol=1e-9)
     assert (o["p"][fw] > 0).sum() > 10 and (o["p"][fw] == 0).sum() > 10
-    assert B * (1.01 ** 7 - 1.0) == pytest.approx(4122.02, rel=1e-5)
     # a perfect lattice at rest (g = 0) has n* = n0 inside, hence p = 0
     wb = W.lattice_block(2, 14, pmode=W.WC_EOS)
     st, o = orc.step(wb.params, wb.pos, wb.vel, wb.ptype)
@@ -432,6 +488,134 @@ def test_two_phase_matrix_symmetric_and_momentum(orc):
     scale = (rs[:, None] * np.abs(w.vel)).sum(0).max()
     np.testing.assert_allclose(m1, m0, rtol=0, atol=1e-12 * scale)
     assert np.abs(o["nut"]).max() > 0
+
+
+def _two_layer_block(dim, m, lower_value, upper_value):
+    """Perfect lattice block with an interface between the two middle
+    layers (heights (k + 1/2) l0, interface at m/2 l0): per-particle values
+    below and above, and the signed height above the interface."""
+    w = W.lattice_block(dim, m)
+    y = w.pos[:, dim - 1] - 0.5 * m * w.params["l0"]
+    return w, y, np.where(y < 0.0, lower_value, upper_value)
+
+
+def _mirror_rows(pos, y, l0, dim, margin):
+    """Particles of one column (central in the horizontal axes) at the
+    heights -(k + 1/2) l0 and +(k + 1/2) l0, k = 0..2, paired."""
+    hor = pos[:, :dim - 1]
+    c = hor.mean(0)
+    col = np.all(np.abs(hor - c) < 0.5 * l0 + 1e-9, axis=1)
+    col &= np.all((hor > hor.min(0) + margin) & (hor < hor.max(0) - margin), axis=1)
+    pairs = []
+    for k in range(3):
+        lo = np.nonzero(col & (np.abs(y + (k + 0.5) * l0) < 1e-9))[0]
+        hi = np.nonzero(col & (np.abs(y - (k + 0.5) * l0) < 1e-9))[0]
+        assert len(lo) == len(hi) >= 1
+        pairs.append((lo, hi))
+    return pairs
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_two_phase_viscosity_continuous_stress_shear(orc, dim):
+    """Two layers of equal density and viscosities nu1 below, nu2 = 10 nu1
+    above, in a steady shear u_x = s1 y below and s2 y above with continuous
+    stress mu1 s1 = mu2 s2 = tau (g = 0).  The harmonic pair mean mu_ij =
+    2 mu_i mu_j/(mu_i + mu_j) is the only mean with mu_ij (1/mu1 + 1/mu2) = 2;
+    with it a pair straddling the interface at depths a and b carries
+    2 tau (mu1 b + mu2 a)/(mu1 + mu2), and the residual viscous acceleration of
+    the row at depth h equals that at height h, because their sum is
+    2 tau times the lattice sum of (y_j - y_i) w_ij, which is zero.  An
+    arithmetic or geometric mean breaks the mirror symmetry.  The residual
+    also stays below 0.2 tau/(rho l0) (the arithmetic mean leaves 1.6)."""
+    m = 24 if dim == 2 else 14
+    rho = 1000.0
+    nu1 = 1e-4
+    w, y, nu_i = _two_layer_block(dim, m, nu1, 10.0 * nu1)
+    l0 = w.params["l0"]
+    tau = rho * nu1 * 2.0            # shear stress, Pa
+    vel = np.zeros_like(w.pos)
+    vel[:, 0] = tau * y / (rho * nu_i)
+    prm = dict(w.params, g=[0.0, 0.0, 0.0])
+    st, o = orc.step(prm, w.pos, vel, w.ptype, want_lists=False,
+                     rho_s=np.full(w.n, rho), nu_i=nu_i)
+    assert st == 0
+    acc = (o["us"][:, 0] - vel[:, 0]) / prm["dt"]
+    scale = tau / (rho * l0)
+    # far from the interface the profile is linear: no acceleration
+    deep = _interior(w.pos, w.pos.min(0), w.pos.max(0), prm["re_lap"] + 1e-9)
+    far = deep & (np.abs(y) > prm["re_lap"])
+    np.testing.assert_allclose(acc[far], 0.0, atol=1e-9 * scale)
+    near = 0.0
+    for lo, hi in _mirror_rows(w.pos, y, l0, dim, prm["re_lap"] + 1e-9):
+        np.testing.assert_allclose(acc[lo], acc[hi], rtol=0, atol=1e-9 * scale)
+        near = max(near, np.abs(acc[lo]).max())
+    assert 0.0 < near < 0.2 * scale
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_two_phase_ppe_coupling_hydrostatic(orc, dim):
+    """The PPE coupling 2/(<rho>_i + <rho>_j) is the harmonic mean of the
+    conductivities 1/rho.  A hydrostatic field of two densities,
+    dp/dy = -rho1 g below and -rho2 g above the interface, has a continuous
+    flux (1/rho) dp/dy = -g.  By the argument of the shear test, the
+    residual sum_j c_ij (p_j - p_i) of the assembled rows is then exactly
+    mirror-symmetric about the interface, zero where the field is linear,
+    and small near it; the arithmetic mean of 1/rho, or 1/sqrt(rho_i rho_j),
+    breaks the symmetry."""
+    m = 24 if dim == 2 else 14
+    rho1, rho2, g = 1000.0, 1500.0, 9.81
+    w, y, rho_s = _two_layer_block(dim, m, rho1, rho2)
+    l0 = w.params["l0"]
+    p = np.where(y < 0.0, -rho1 * g * y, -rho2 * g * y) + 1.0e4
+    prm = dict(w.params, g=[0.0, 0.0, 0.0])
+    st, o = orc.step(prm, w.pos, np.zeros_like(w.pos), w.ptype, want_matrix=True,
+                     rho_s=rho_s)
+    assert st == 0
+    dt, alpha = prm["dt"], prm["alpha"]
+    deep = _interior(w.pos, w.pos.min(0), w.pos.max(0), prm["re_lap"] + 2 * l0)
+    assert np.all(o["flags"][deep] == 0)
+    res = np.zeros(w.n)
+    for i in np.nonzero(deep)[0]:
+        c = o["count"][i]
+        js = o["list"][i, :c]
+        assert np.all(o["flags"][js] == 0)
+        res[i] = -(o["aval"][i, :c] * p[js]).sum() - (o["diag"][i] - alpha / dt ** 2) * p[i]
+    # c_ij ~ 2d w/(lambda n0 rho): the residual in units of g/l0
+    scale = g / l0
+    far = deep & (np.abs(y) > prm["re_lap"])
+    np.testing.assert_allclose(res[far], 0.0, atol=1e-9 * scale)
+    near = 0.0
+    for lo, hi in _mirror_rows(w.pos, y, l0, dim, prm["re_lap"] + 2 * l0):
+        np.testing.assert_allclose(res[lo], res[hi], rtol=0, atol=1e-9 * scale)
+        near = max(near, np.abs(res[lo]).max())
+    assert 0.0 < near < 0.2 * scale
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_two_phase_update_keeps_hydrostatic_rest(orc, dim):
+    """The Euler update divides the gradient by the particle's own smoothed
+    density: with the two-density hydrostatic field and the predicted
+    velocity u* = g dt of a step from rest, every fluid particle whose p-hat
+    and gradient see a full lattice and a linear field (farther than re_n
+    from the interface and from the block's edges) ends at rest,
+    u = g dt - (dt/rho_i) rho_i g = 0.  A common rho (or a mean of the pair)
+    leaves the heavy layer accelerating."""
+    m = 20 if dim == 2 else 12
+    rho1, rho2, g = 1000.0, 1500.0, 9.81
+    w, y, rho_s = _two_layer_block(dim, m, rho1, rho2)
+    prm = dict(w.params, g=[0.0, -g, 0.0] if dim == 2 else [0.0, 0.0, -g])
+    dt = prm["dt"]
+    p = np.where(y < 0.0, -rho1 * g * y, -rho2 * g * y) + 1.0e4
+    us = np.zeros_like(w.pos)
+    us[:, dim - 1] = -g * dt
+    rs = w.pos + dt * us
+    st, pos, vel = orc.pressure_update(prm, rs, us, w.ptype, p, rho_s=rho_s)
+    assert st == 0
+    sel = _interior(w.pos, w.pos.min(0), w.pos.max(0), prm["re_n"] + 1e-9)
+    sel &= np.abs(y) > prm["re_n"]
+    assert (sel & (y > 0)).sum() > 0 and (sel & (y < 0)).sum() > 0
+    np.testing.assert_allclose(vel[sel], 0.0, atol=1e-9 * g * dt)
+    np.testing.assert_allclose(pos[sel], w.pos[sel], rtol=0, atol=1e-9 * g * dt * dt)
 
 
 def test_still_tank_hydrostatic_level(orc):
