@@ -39,7 +39,8 @@ class OrcParams(C.Structure):
         ("dt", C.c_double), ("beta", C.c_double), ("c0", C.c_double),
         ("gamma", C.c_double), ("alpha", C.c_double), ("cg_tol", C.c_double),
         ("grid_lo", C.c_double * 3), ("cell_size", C.c_double),
-        ("smag_cs", C.c_double), ("source", C.c_int32),
+        ("smag_cs", C.c_double), ("source", C.c_int32), ("laplacian", C.c_int32),
+        ("cg_warm", C.c_int32),
     ]
 
 
@@ -78,7 +79,7 @@ def lib():
                                C.POINTER(OrcStepOut)]
         L.orc_run.argtypes = [C.POINTER(OrcParams), C.c_int64, C.c_void_p, C.c_void_p,
                               C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
-                              C.c_void_p]
+                              C.c_void_p, C.c_void_p]
         L.orc_smoothed_density.argtypes = [C.POINTER(OrcParams), C.c_int64, C.c_void_p,
                                            C.c_void_p, C.c_void_p, C.c_void_p]
         L.orc_set_threads.argtypes = [C.c_int]
@@ -99,6 +100,8 @@ def make_params(p: dict) -> OrcParams:
               "alpha", "cg_tol", "cell_size", "smag_cs"):
         setattr(o, k, float(p[k]))
     o.source = int(p.get("source", 0))
+    o.laplacian = int(p.get("laplacian", 0))
+    o.cg_warm = int(p.get("cg_warm", 0))
     for a in range(3):
         o.g[a] = float(p["g"][a])
         o.grid_lo[a] = float(p["grid_lo"][a])
@@ -189,18 +192,26 @@ def step(params, pos, vel, ptype, flags_override=None, *, want_lists=True,
     return st, out
 
 
-def run(params, pos, vel, ptype, nsteps, *, rho_s=None, nu_i=None):
-    """nsteps time steps; returns (status, pos, vel, type, p, flags)."""
+def run(params, pos, vel, ptype, nsteps, *, rho_s=None, nu_i=None, return_iters=False,
+        p0=None):
+    """nsteps time steps; returns (status, pos, vel, type, p, flags), plus the
+    CG iterations summed over the steps when return_iters.  With
+    params["cg_warm"] = 1 each solve starts from the previous step's pressure
+    (p0 for the first step, if given) and stops at params["cg_tol"] (the GPU
+    path's rule) instead of starting from zero and stopping at 1e-13."""
     P, pos, ptype = _prep(params, pos, ptype)
     pos = pos.copy()
     ptype = ptype.copy()
     vel = np.ascontiguousarray(vel, dtype=np.float64).copy()
     n = pos.shape[0]
-    p = np.zeros(n)
+    p = np.zeros(n) if p0 is None else np.array(p0, dtype=np.float64)
     fl = np.zeros(n, np.int8)
+    it = C.c_int64(0)
     rs_, nu_ = _opt(rho_s), _opt(nu_i)
     st = lib().orc_run(C.byref(P), n, _ptr(pos), _ptr(vel), _ptr(ptype), int(nsteps),
-                       _ptr(rs_), _ptr(nu_), _ptr(p), _ptr(fl))
+                       _ptr(rs_), _ptr(nu_), _ptr(p), _ptr(fl), C.byref(it))
+    if return_iters:
+        return st, pos, vel, ptype, p, fl, int(it.value)
     return st, pos, vel, ptype, p, fl
 
 

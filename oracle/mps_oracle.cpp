@@ -8,7 +8,9 @@
  *   Laplacian model      Eq. 7 (also the PPE coefficients)
  *   PPE                  Eq. 13 -> A x = b, assembled row-wise as in the
  *                        listing "PPE assemble GPU code" (dummy neighbours
- *                        give no coupling; alpha/dt^2 on the diagonal)
+ *                        give no coupling; alpha/dt^2 on the diagonal);
+ *                        sources Eq. 21 (HS) and Eq. 24-25 (ECS); Laplacian
+ *                        of pressure Eq. 7 or Eq. 23 (HL)
  *   equation of state    Eq. 16
  *   pressure gradient    standard MPS form, or Eq. 18 (CMPS)
  *   time integration     semi-implicit predictor-corrector, first-order Euler
@@ -297,11 +299,13 @@ double dot(const std::vector<double>& a, const std::vector<double>& b) {
   return s;
 }
 
-/* Conjugate gradients with diagonal (Jacobi) preconditioning, from x = 0,
- * to ||b - A x|| <= tol ||b||.  The method's own solver (ICCG) only reaches
- * the same unique solution faster; the oracle needs the solution. */
+/* Conjugate gradients with diagonal (Jacobi) preconditioning, from x = 0
+ * (or from x0 when given), to ||b - A x|| <= tol ||b||.  The method's own
+ * solver (ICCG) only reaches the same unique solution faster; the oracle
+ * needs the solution. */
 int cg_solve(const Sparse& A, const std::vector<double>& b, std::vector<double>& x,
-             double tol, int maxit, int* iters, double* relres) {
+             double tol, int maxit, int* iters, double* relres,
+             const std::vector<double>* x0 = nullptr) {
   int n = (int)b.size();
   x.assign(n, 0.0);
   double bn = std::sqrt(dot(b, b));
@@ -309,6 +313,14 @@ int cg_solve(const Sparse& A, const std::vector<double>& b, std::vector<double>&
   *relres = 0.0;
   if (bn == 0.0) return 0;
   std::vector<double> r = b, z(n), p(n), q(n);
+  if (x0) {
+    x = *x0;
+    spmv(A, x, q);
+    for (int i = 0; i < n; ++i) r[i] = b[i] - q[i];
+    double rn = std::sqrt(dot(r, r));
+    *relres = rn / bn;
+    if (rn <= tol * bn) return 0;
+  }
   for (int i = 0; i < n; ++i) z[i] = r[i] / A.diag[i];
   p = z;
   double rz = dot(r, z);
@@ -341,9 +353,10 @@ struct PPESolve<double> {
   static int run(const std::vector<int>& start, const std::vector<int>& col,
                  const std::vector<double>& off, const std::vector<double>& diag,
                  const std::vector<double>& b, std::vector<double>& p, double tol,
-                 int maxit, int* iters, double* relres) {
+                 int maxit, int* iters, double* relres,
+                 const std::vector<double>* x0 = nullptr) {
     Sparse A{start, col, off, diag};
-    return cg_solve(A, b, p, tol, maxit, iters, relres);
+    return cg_solve(A, b, p, tol, maxit, iters, relres, x0);
   }
 };
 
@@ -353,7 +366,7 @@ struct PPESolve<Dual<K>> {
   static int run(const std::vector<int>& start, const std::vector<int>& col,
                  const std::vector<T>& off, const std::vector<T>& diag,
                  const std::vector<T>& b, std::vector<T>& p, double tol, int maxit,
-                 int* iters, double* relres) {
+                 int* iters, double* relres, const std::vector<double>* = nullptr) {
     int n = (int)diag.size();
     Sparse A;
     A.start = start;
@@ -628,6 +641,9 @@ int step(const orc_params* P, const Consts& C, const T& nu, const T g[3], int n,
   }
 
   /* 5. Pressure. */
+  std::vector<double> p_prev;
+  if (P->cg_warm && tr.p.size() == (size_t)n)
+    for (int i = 0; i < n; ++i) p_prev.push_back(tr.flags[i] == FL_INNER ? val(tr.p[i]) : 0.0);
   tr.p.assign(n, T(0.0));
   tr.diag.assign(n, T(1.0));
   tr.b.assign(n, T(0.0));
@@ -640,6 +656,13 @@ int step(const orc_params* P, const Consts& C, const T& nu, const T g[3], int n,
      * A free-surface neighbour (p = 0, Dirichlet) keeps its c_ij on the
      * diagonal only.  Rows that are not inner are the identity (p = 0). */
     const double cpp = 2.0 * dim / (C.lam_lap * C.n0_lap * rho);
+    /* Eq. 23 (HL), printed as (1/n0) sum_j 2 phi_ij r_e / r_ij with a power
+     * of r_ij lost: read as (1/n0) sum_j 2 r_e phi_ij / r_ij^3, the one power
+     * that gives a Laplacian its units (1/length^2); with the printed factor
+     * 2 the sum then reproduces lap |r|^2 = 2d in the continuum limit in two
+     * and three dimensions alike (n0 of Eq. 4 at r_e).  Coupling
+     * c_ij = 2 r_e / (n0 rho r_ij^3) for r_ij < re_lap. */
+    const double chl = 2.0 * P->re_lap / (C.n0_lap * rho);
     std::vector<int> start(n + 1, 0), col;
     std::vector<T> off;
     for (int i = 0; i < n; ++i) {
@@ -650,7 +673,8 @@ int step(const orc_params* P, const Consts& C, const T& nu, const T g[3], int n,
           if (type[j] == DUMMY) continue;
           T r = dist(i, j);
           if (!(val(r) < P->re_lap)) continue;
-          T c = cpp * weight(P->kernel, r, P->re_lap);
+          T c = P->laplacian == 0 ? cpp * weight(P->kernel, r, P->re_lap)
+                                  : chl / (r * r * r);
           if (multi) c = c * (rho * 2.0 / (rho_of(i) + rho_of(j)));
           dsum = dsum + c;
           if (tr.flags[j] == FL_INNER) {
@@ -685,9 +709,10 @@ int step(const orc_params* P, const Consts& C, const T& nu, const T g[3], int n,
       }
       start[i + 1] = (int)col.size();
     }
-    int sst = PPESolve<T>::run(start, col, off, tr.diag, tr.b, tr.p, 1e-13,
+    int sst = PPESolve<T>::run(start, col, off, tr.diag, tr.b, tr.p,
+                               P->cg_warm ? P->cg_tol : 1e-13,
                                std::max(P->cg_maxit, 100000), &tr.cg_iters,
-                               &tr.cg_relres);
+                               &tr.cg_relres, p_prev.empty() ? nullptr : &p_prev);
     if (sst) status = sst;
     for (int i = 0; i < n; ++i)
       if (tr.flags[i] != FL_INNER) tr.p[i] = T(0.0);
@@ -961,7 +986,7 @@ int orc_pressure_update(const orc_params* P, int64_t n, const double* rs, const 
 
 int orc_run(const orc_params* P, int64_t n, double* pos, double* vel, int8_t* type,
             int32_t nsteps, const double* rho_s, const double* nu_i, double* p_out,
-            int8_t* flags_out) {
+            int8_t* flags_out, int64_t* cg_iters_out) {
   Consts C = constants(P);
   const int dim = P->dim;
   std::vector<double> x(pos, pos + n * dim), u(vel, vel + n * dim);
@@ -970,10 +995,15 @@ int orc_run(const orc_params* P, int64_t n, double* pos, double* vel, int8_t* ty
   to_params(P, &nu, g);
   int st = 0;
   Trace<double> tr;
+  /* warm start: p_out brings the pressure of the step before the first */
+  if (P->cg_warm && p_out) tr.p.assign(p_out, p_out + n);
+  int64_t iters = 0;
   for (int s = 0; s < nsteps; ++s) {
     st = step<double>(P, C, nu, g, (int)n, x, u, t, nullptr, tr, rho_s, nu_i);
+    iters += tr.cg_iters;
     if (st == -3 || st == -6) break;
   }
+  if (cg_iters_out) *cg_iters_out = iters;
   std::memcpy(pos, x.data(), x.size() * sizeof(double));
   std::memcpy(vel, u.data(), u.size() * sizeof(double));
   std::memcpy(type, t.data(), n);

@@ -32,6 +32,12 @@ typedef struct {
   double l0, re_n, re_lap, rho, nu, g[3], dt, beta, c0, gamma, alpha, cg_tol;
   double grid_lo[3], cell_size, smag_cs;
   int32_t source; /* PPE source: 0 Eq. 13, 1 Eq. 21 (HS), 2 Eq. 25 (HS + ECS) */
+  int32_t laplacian; /* PPE Laplacian: 0 Eq. 7, 1 Eq. 23 (HL) */
+  /* PPE solve: 0 CG from p = 0 to a relative residual of 1e-13 (the
+   * reference for parity checks); 1 CG from the previous step's pressure to
+   * cg_tol, the stopping rule of the GPU path (for timing the oracle on the
+   * same work per step; needs orc_run, which keeps the pressure) */
+  int32_t cg_warm;
 } orc_params;
 
 /* Every pointer may be NULL (that output is skipped).  list/aval are
@@ -76,10 +82,13 @@ int orc_step(const orc_params* P, int64_t n, const double* pos,
 
 /* nsteps time steps; state arrays are updated in place.  rho_s (smoothed
  * density) and nu_i (laminar viscosity) per particle select the two-phase
- * model (NULL: single phase with P->rho, P->nu). */
+ * model (NULL: single phase with P->rho, P->nu).  p_out, flags_out: the last
+ * step's pressure and flags (or NULL); with P->cg_warm, p_out also brings
+ * in the pressure of the step before the first (the first solve's start).
+ * cg_iters_out: CG iterations summed over the steps (or NULL). */
 int orc_run(const orc_params* P, int64_t n, double* pos, double* vel,
             int8_t* type, int32_t nsteps, const double* rho_s, const double* nu_i,
-            double* p_out, int8_t* flags_out);
+            double* p_out, int8_t* flags_out, int64_t* cg_iters_out);
 
 /* Smoothed density of the two-phase model, fixed before the run. */
 int orc_smoothed_density(const orc_params* P, int64_t n, const double* pos,

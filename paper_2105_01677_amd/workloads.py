@@ -27,6 +27,7 @@ K_KOSHIZUKA, K_CUBIC = 0, 1
 FP64, MIXED = 0, 1
 GRAD_STD, GRAD_CMPS = 0, 1
 SRC_STD, SRC_HS, SRC_HS_ECS = 0, 1, 2
+LAP_STD, LAP_HL = 0, 1
 
 SEED = 2105
 
@@ -54,7 +55,7 @@ def default_params(dim: int, l0: float, *, re_n_over_l0: float = 2.1,
         rho=rho, nu=nu, g=gvec, dt=dt, beta=0.97, c0=c0, gamma=7.0,
         alpha=1e-7, cg_tol=1e-9, cg_maxit=10000, max_neigh=300,
         pmode=pmode, kernel=kernel, precision=precision, grad=GRAD_STD,
-        clamp=1, smag_cs=0.0, cg_pipelined=1, source=SRC_STD,
+        clamp=1, smag_cs=0.0, cg_pipelined=1, source=SRC_STD, laplacian=LAP_STD,
         grid_lo=[0.0, 0.0, 0.0], grid_n=[1, 1, 1], cell_size=0.0,
     )
 

@@ -366,6 +366,56 @@ def test_ppe_rows_are_the_laplacian(orc):
         assert abs(o["b"][i]) < 1e-6
 
 
+@pytest.mark.parametrize("dim,cases", [
+    (2, ((4.2, 0.21), (8.2, 0.09), (12.2, 0.065))),
+    (3, ((3.1, 0.085), (6.2, 0.04))),
+])
+def test_hl_laplacian_continuum_limit(orc, dim, cases):
+    """Eq. 23 (HL) read as lap phi_i = (1/n0) sum_j 2 r_e phi_ij / r_ij^3
+    (the print lost the power of r_ij).  The reading is fixed by the
+    continuum: with number density rho_N, n0 -> pi rho_N re^2 (2-D) or
+    (2 pi/3) rho_N re^3 (3-D) for the kernel of Eq. 4, and the sum for
+    phi = |r|^2 -> 4 pi rho_N re^2 or 4 pi rho_N re^3, so lap |r|^2 -> 4 and 6
+    = 2d, and lap x^2 -> 2 in both dimensions.  On a lattice the sum
+    approaches that limit as re/l0 grows (lattice error ~ l0/re; the radii
+    avoid lattice shells, on which the sum, not continuous at r_e, would
+    depend on the rounding of the positions): observed
+    through the assembled PPE rows, (A p)_i - alpha/dt^2 p_i = -(1/rho) lap p_i
+    for p = x^2.  A lost factor 2, a wrong power of r or the n0 of the other
+    radius misses the limit by a factor; a linear field gives 0."""
+    devs = []
+    for re, bound in cases:
+        m = int(2 * re + 2 * 2.1) + 4
+        w = W.lattice_block(dim, m)
+        l0 = w.params["l0"]
+        prm = dict(w.params, laplacian=W.LAP_HL, re_lap=re * l0, max_neigh=1200)
+        W._set_grid(prm, w.pos, l0, [m] * dim, 0, 2)
+        st, o = orc.step(prm, w.pos, w.vel, w.ptype, want_matrix=True)
+        assert st == 0
+        pos = o["rs"]
+        inner = _interior(pos, pos.min(0), pos.max(0), prm["re_lap"] + prm["re_n"] + 1e-9)
+        assert inner.sum() >= 1
+        rho, dt, alpha = prm["rho"], prm["dt"], prm["alpha"]
+        for field, expect in (((pos[:, 0] - pos[:, 0].mean()) ** 2, None),
+                              (3.0 * pos[:, 0] - 2.0 * pos[:, dim - 1], 0.0)):
+            laps = []
+            for i in np.nonzero(inner)[0]:
+                c = o["count"][i]
+                js = o["list"][i, :c]
+                assert np.all(o["flags"][js] == 0)
+                Ap = o["diag"][i] * field[i] + (o["aval"][i, :c] * field[js]).sum()
+                laps.append(-rho * (Ap - alpha / dt ** 2 * field[i]))
+            laps = np.array(laps)
+            if expect is None:
+                dev = laps[0] / 2.0 - 1.0
+                np.testing.assert_allclose(laps, laps[0], rtol=1e-9)
+                assert abs(dev) < bound, (dim, re, dev)
+                devs.append(abs(dev))
+            else:
+                np.testing.assert_allclose(laps, 0.0, atol=1e-6 / l0)
+    assert all(a > b for a, b in zip(devs, devs[1:])), devs
+
+
 def test_equation_of_state(orc):
     """Eq. 16 with gamma = 7, clamped at zero: p = rho c0^2/7 ((n*/n0)^7 - 1)."""
     w = W.jitter(W.config("dam_break_2d_1432", pmode=W.WC_EOS))
