@@ -37,6 +37,7 @@
  */
 #ifndef MPS_H
 #define MPS_H
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -54,7 +55,9 @@ typedef enum {
   MPS_E_NONFINITE = -5,      /* NaN or Inf in positions or velocities */
   MPS_E_COINCIDENT = -6,     /* two particles at distance 0 (Eq. 4 diverges) */
   MPS_E_DEVICE = -7,         /* HIP runtime error */
-  MPS_E_POISONED = -8        /* an earlier numerical error; call mps_set_state */
+  MPS_E_POISONED = -8,       /* an earlier numerical error; call mps_set_state */
+  MPS_E_SCRATCH = -9         /* the input needs more than the fixed scratch of an
+                                allocation-free entry point */
 } mps_status;
 
 /* Particle types (int8 per particle).  Wall particles are pressure unknowns
@@ -155,7 +158,8 @@ mps_status mps_init(const mps_params* params, int64_t n, const double* pos,
 /* Release every resource of the context (NULL is allowed). */
 mps_status mps_free(mps_ctx* ctx);
 
-/* Text of the last error of the context (static storage; never NULL). */
+/* Text of the last error of the context (static storage; never NULL); for
+ * ctx = NULL, that of this thread's last call made without a context. */
 const char* mps_last_error(const mps_ctx* ctx);
 
 /* Build the neighbour lists at the current positions (step 1) and export
@@ -167,6 +171,36 @@ const char* mps_last_error(const mps_ctx* ctx);
  * Errors: MPS_E_NEIGH_OVERFLOW, MPS_E_COINCIDENT, MPS_E_POISONED. */
 mps_status mps_neighbors(mps_ctx* ctx, int32_t* cell_id, int32_t* count,
                          int32_t* list);
+
+/* Allocation-free variant of mps_neighbors, for callers that cannot
+ * allocate device memory (code under stream capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same cell sort and neighbour lists,
+ * for n particles at positions the caller passes, without a context.  No
+ * device or host allocation is made: the work arrays are carved out of a
+ * fixed device array of MPS_NOALLOC_SCRATCH_BYTES (64 MiB) that each GPU
+ * holds from the library's load until the process ends (its address is
+ * looked up once per device on the first call there).
+ * params: as for mps_init (only dim, l0, radii, grid and max_neigh are
+ * used); pos: [n][dim] FP64, type: [n] int8 (MPS_FLUID..MPS_GHOST), device
+ * pointers, read only.  cell_id, count, list: outputs as for mps_neighbors
+ * (device pointers, each may be NULL).  hip_stream: hipStream_t (NULL = the
+ * default stream); the call synchronises it to read the status.
+ * Work needed: about n (16 ps + 30 + 4 kpad) bytes (ps = 2 in 2-D, 4 in
+ * 3-D; kpad = max_neigh rounded up to 8) plus 12 bytes per cell; e.g. the
+ * 44,832-particle 2-D dam break at max_neigh = 300 takes 57 MB.
+ * Every call on one GPU uses that GPU's one array: concurrent calls on the
+ * same GPU (other streams or threads) race and must be serialised by the
+ * caller; a call leaves its data in the array, and clears what must start
+ * at zero itself.
+ * Errors: MPS_E_ARG (parameters, NULL pos/type, a type outside
+ * MPS_FLUID..MPS_GHOST), MPS_E_SCRATCH (n, max_neigh and the grid need more
+ * than the fixed array; nothing is launched), MPS_E_NEIGH_OVERFLOW,
+ * MPS_E_COINCIDENT, MPS_E_NONFINITE, MPS_E_DEVICE.  mps_last_error(NULL)
+ * gives the text of this thread's last such error. */
+#define MPS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+mps_status mps_neighbors_noalloc(const mps_params* params, int64_t n, const double* pos,
+                                 const int8_t* type, int32_t* cell_id, int32_t* count,
+                                 int32_t* list, void* hip_stream);
 
 /* Advance nsteps time steps (steps 1-5 above).  stats may be NULL.
  * PPE model on a non-null stream: each step after the first is enqueued

@@ -133,8 +133,6 @@ struct mps_ctx {
 
 namespace {
 
-const char* kNoCtx = "no context";
-
 mps_status fail(mps_ctx* c, mps_status st, const char* msg) {
   if (c) std::snprintf(c->err, sizeof(c->err), "%s", msg);
   return st;
@@ -308,6 +306,9 @@ View make_view_inplace(const mps_ctx* c) {
   return v;
 }
 
+}  // namespace
+
+namespace mps {
 mps_status check_params(const mps_params* P, int64_t n) {
   if (!P || n < 1 || n > (int64_t)INT32_MAX / 2) return MPS_E_ARG;
   if (P->dim != 2 && P->dim != 3) return MPS_E_ARG;
@@ -333,6 +334,9 @@ mps_status check_params(const mps_params* P, int64_t n) {
   if (nc > (int64_t)1 << 28) return MPS_E_ARG;
   return MPS_OK;
 }
+}  // namespace mps
+
+namespace {
 
 // Element type scatter/gather for int8 state.
 __global__ void k_i8_to_orig(int64_t n, const int32_t* id, const int8_t* src, int8_t* dst) {
@@ -354,7 +358,7 @@ __global__ void k_iota(int64_t n, int32_t* id) {
 // Input types are FLUID/WALL/DUMMY; anything else is rejected by a status bit.
 __global__ void k_check_types(int64_t n, const int8_t* t, int32_t* status) {
   const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (k < n && (t[k] < MPS_FLUID || t[k] > MPS_GHOST)) atomicOr(status, 8);
+  if (k < n && (t[k] < MPS_FLUID || t[k] > MPS_GHOST)) atomicOr(status, ST_BADTYPE);
 }
 __global__ __launch_bounds__(256) void k_count_flags(int64_t n, const int8_t* flags,
                                                      const int32_t* nb_count,
@@ -1074,7 +1078,7 @@ mps_status mps_free(mps_ctx* c) {
   return MPS_OK;
 }
 
-const char* mps_last_error(const mps_ctx* c) { return c ? c->err : kNoCtx; }
+const char* mps_last_error(const mps_ctx* c) { return c ? c->err : mps::noctx_error(); }
 
 mps_status mps_device_bytes(const mps_ctx* c, int64_t* bytes) {
   if (!c || !bytes) return MPS_E_ARG;

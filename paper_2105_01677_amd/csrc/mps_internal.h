@@ -47,6 +47,7 @@ enum : int32_t {
   ST_OVERFLOW = 1,
   ST_COINCIDENT = 2,
   ST_NONFINITE = 4,
+  ST_BADTYPE = 8,
 };
 
 __host__ __device__ inline int64_t sl_index(int64_t row, int l, int kpad) {
@@ -403,6 +404,11 @@ inline void launch_k(K kernel, unsigned grid, unsigned block, hipStream_t s, A..
     kernel<<<grid, block, 0, s>>>(args...);
   }
 }
+
+// Parameter validation shared by the entry points (MPS_OK or MPS_E_ARG).
+mps_status check_params(const mps_params* P, int64_t n);
+// Text of the last error of a call made without a context (this thread).
+const char* noctx_error();
 
 // ---------------------------------------------------------------- launchers
 int launch_bin(const View& v, int dim, hipStream_t s);

@@ -193,14 +193,17 @@ __global__ __launch_bounds__(BLOCK) void k_rank_permute(View v) {
     }
     k = b + rank;
   }
-  double x[DIM], u[DIM];
+  double x[DIM], u[DIM] = {};
   load_vec<DIM>(v.pos, i, x);
-  load_vec<DIM>(v.vel, i, u);
   store_vec<DIM>(v.pos_w, k, x);
-  store_vec<DIM>(v.vel_w, k, u);
+  // velocity and pressure are absent for a search of positions alone
+  if (v.vel) {
+    load_vec<DIM>(v.vel, i, u);
+    store_vec<DIM>(v.vel_w, k, u);
+  }
   v.type_w[k] = v.type[i];
   v.id_w[k] = key;
-  v.p_w[k] = v.p_in[i];
+  if (v.p_in) v.p_w[k] = v.p_in[i];
   if (v.rho_s) {
     v.rho_s_w[k] = v.rho_s[i];
     v.nu_l_w[k] = v.nu_l[i];

@@ -15,10 +15,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmps_hip.so")
 
 OK, E_ARG, E_NOMEM, E_NEIGH_OVERFLOW, E_CG_NOCONV = 0, -1, -2, -3, -4
-E_NONFINITE, E_COINCIDENT, E_DEVICE, E_POISONED = -5, -6, -7, -8
+E_NONFINITE, E_COINCIDENT, E_DEVICE, E_POISONED, E_SCRATCH = -5, -6, -7, -8, -9
 STATUS_NAMES = {0: "OK", -1: "E_ARG", -2: "E_NOMEM", -3: "E_NEIGH_OVERFLOW",
                 -4: "E_CG_NOCONV", -5: "E_NONFINITE", -6: "E_COINCIDENT",
-                -7: "E_DEVICE", -8: "E_POISONED"}
+                -7: "E_DEVICE", -8: "E_POISONED", -9: "E_SCRATCH"}
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class MPSError(RuntimeError):
@@ -67,6 +68,8 @@ def lib() -> C.CDLL:
         L.mps_last_error.argtypes = [_VP]
         L.mps_last_error.restype = C.c_char_p
         L.mps_neighbors.argtypes = [_VP, _VP, _VP, _VP]
+        L.mps_neighbors_noalloc.argtypes = [C.POINTER(Params), C.c_int64, _VP, _VP, _VP, _VP,
+                                            _VP, _VP]
         L.mps_step.argtypes = [_VP, C.c_int32, C.POINTER(StepStats)]
         L.mps_pressure_solve.argtypes = [_VP, _VP, _VP, C.POINTER(C.c_int32),
                                          C.POINTER(C.c_double)]
@@ -86,7 +89,8 @@ def lib() -> C.CDLL:
         for f in ("mps_init", "mps_free", "mps_neighbors", "mps_step", "mps_pressure_solve",
                   "mps_get_ppe", "mps_get_state", "mps_set_state", "mps_constants",
                   "mps_profile", "mps_profile_read", "mps_tape_alloc", "mps_tape_save",
-                  "mps_tape_load", "mps_step_adjoint", "mps_get_phase", "mps_device_bytes"):
+                  "mps_tape_load", "mps_step_adjoint", "mps_get_phase", "mps_device_bytes",
+                  "mps_neighbors_noalloc"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -96,7 +100,7 @@ EXPORTED = ["mps_init", "mps_free", "mps_last_error", "mps_neighbors", "mps_step
             "mps_pressure_solve", "mps_get_ppe", "mps_get_state", "mps_set_state",
             "mps_constants", "mps_profile", "mps_profile_read", "mps_tape_alloc",
             "mps_tape_save", "mps_tape_load", "mps_step_adjoint", "mps_get_phase",
-            "mps_device_bytes"]
+            "mps_device_bytes", "mps_neighbors_noalloc"]
 
 KERNEL_CLASSES = ["sort", "neighbors", "predict", "density", "assemble", "cg_spmv",
                   "cg_update", "gradient"]
@@ -133,6 +137,34 @@ def _dev(x, dtype):
     if isinstance(x, torch.Tensor):
         return x.detach().to(device="cuda", dtype=dtype).contiguous()
     return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype).to("cuda")
+
+
+def neighbors_noalloc(params: dict, pos, ptype, *, out=None, stream=None):
+    """mps_neighbors_noalloc: cell ids, counts and lists (original ids,
+    ascending, padded with -1) of the particles at pos, without a context;
+    the library allocates nothing (its work arrays live in a fixed device
+    array).  out: optional (cell [n] int32, count [n] int32, list
+    [n][max_neigh] int32) device tensors to write, else allocated here by
+    torch.  stream: a torch stream (default: the current one)."""
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("the MPS library needs a HIP device")
+    pos = _dev(pos, torch.float64)
+    typ = _dev(ptype, torch.int8)
+    n = pos.shape[0]
+    K = int(params["max_neigh"])
+    if out is None:
+        out = (torch.empty(n, dtype=torch.int32, device="cuda"),
+               torch.empty(n, dtype=torch.int32, device="cuda"),
+               torch.empty((n, K), dtype=torch.int32, device="cuda"))
+    cell, cnt, lst = out
+    P = make_params(params)
+    s = stream if stream is not None else torch.cuda.current_stream()
+    st = lib().mps_neighbors_noalloc(C.byref(P), n, _ptr(pos), _ptr(typ), _ptr(cell),
+                                     _ptr(cnt), _ptr(lst), C.c_void_p(s.cuda_stream))
+    if st != OK:
+        raise MPSError(st, "mps_neighbors_noalloc: " + lib().mps_last_error(None).decode())
+    return cell, cnt, lst
 
 
 class MPS:
