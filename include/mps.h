@@ -76,6 +76,13 @@ enum { MPS_GRAD_STD = 0, MPS_GRAD_CMPS = 1 };    /* standard / Eq. 18 */
  * from Dn/Dt at r*, u* (Eq. 21, MPS-HS); the same plus the error-compensating
  * parts of Eq. 24 (Eq. 25, ECS) */
 enum { MPS_SRC_STD = 0, MPS_SRC_HS = 1, MPS_SRC_HS_ECS = 2 };
+/* Laplacian of pressure in the PPE: Eq. 7, 2d/(lambda n0) sum_j p_ij w_ij;
+ * or the higher-order form of Eq. 23 (MPS-HL), (1/n0) sum_j 2 r_e p_ij /
+ * r_ij^3 over r_ij < re_lap (the printed equation lost the power of r_ij;
+ * this one has the units of a Laplacian and, with the printed factor 2,
+ * tends to the exact Laplacian of a quadratic field in two and three
+ * dimensions as re_lap/l0 grows) */
+enum { MPS_LAP_STD = 0, MPS_LAP_HL = 1 };
 
 typedef struct {
   int32_t dim;              /* 2 or 3 */
@@ -112,6 +119,9 @@ typedef struct {
                                eddy viscosity (0 = off; 0.12 typical) */
   int32_t source;           /* MPS_SRC_*: PPE source term (PPE model only;
                                the adjoint needs MPS_SRC_STD) */
+  int32_t laplacian;        /* MPS_LAP_*: Laplacian of pressure in the PPE
+                               (PPE model only; the adjoint needs
+                               MPS_LAP_STD) */
 } mps_params;
 
 typedef struct {

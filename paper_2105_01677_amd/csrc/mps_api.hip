@@ -245,6 +245,7 @@ View make_view(const mps_ctx* c) {
   v.nstar = c->nstar;
   v.src = c->src;
   v.source = P.source;
+  v.laplacian = P.laplacian;
   v.flags = c->flags;
   v.cellid = c->cellid;
   v.slot = c->slot;
@@ -326,6 +327,8 @@ mps_status check_params(const mps_params* P, int64_t n) {
   if (!(P->smagorinsky_cs >= 0.0) || P->smagorinsky_cs > 1.0) return MPS_E_ARG;
   if (P->source < MPS_SRC_STD || P->source > MPS_SRC_HS_ECS) return MPS_E_ARG;
   if (P->source != MPS_SRC_STD && P->pmode != MPS_PPE_CG) return MPS_E_ARG;
+  if (P->laplacian != MPS_LAP_STD && P->laplacian != MPS_LAP_HL) return MPS_E_ARG;
+  if (P->laplacian != MPS_LAP_STD && P->pmode != MPS_PPE_CG) return MPS_E_ARG;
   int64_t nc = 1;
   for (int a = 0; a < P->dim; ++a) {
     if (P->grid_n[a] < 1 || P->grid_n[a] > 1023) return MPS_E_ARG;
@@ -1359,6 +1362,8 @@ mps_status mps_step_adjoint(mps_ctx* c, const double* pos_bar, const double* vel
   if (!c->tape) return fail(c, MPS_E_ARG, "call mps_tape_alloc first");
   if (c->P.grad != MPS_GRAD_STD) return fail(c, MPS_E_ARG, "adjoint needs the standard gradient");
   if (c->P.source != MPS_SRC_STD) return fail(c, MPS_E_ARG, "adjoint needs the source of Eq. 13");
+  if (c->P.laplacian != MPS_LAP_STD)
+    return fail(c, MPS_E_ARG, "adjoint needs the Laplacian of Eq. 7");
   if (c->poisoned) return fail(c, MPS_E_POISONED, "context poisoned; call mps_set_state");
   const bool wc = c->P.pmode == MPS_WC_EOS;
   // forward recompute of the step's stages from the current (taped) state

@@ -122,6 +122,7 @@ struct View {
   double g[3];
   int gamma_i, kernel, grad, clamp;
   int source;         // MPS_SRC_*: PPE source term
+  int laplacian;      // MPS_LAP_*: Laplacian of pressure in the PPE
   // sorted state, current buffers
   const double* pos;  double* pos_w;
   const double* vel;  double* vel_w;

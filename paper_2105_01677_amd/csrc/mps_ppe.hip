@@ -1,6 +1,7 @@
 // Pressure Poisson equation of the fully incompressible model (arXiv
-// 2105.01677, Eq. 13 with the Laplacian model of Eq. 7): assembly (a5) and
-// Jacobi-preconditioned conjugate gradients (a6).
+// 2105.01677, Eq. 13 with the Laplacian model of Eq. 7, or Eq. 23 (HL) with
+// c_ij = 2 r_e / (n0 rho r_ij^3)): assembly (a5) and Jacobi-preconditioned
+// conjugate gradients (a6).
 //
 // Matrix.  Row-wise as in the listing "PPE assemble GPU code": for a
 // pressure unknown i (fluid or wall, not on the free surface) and every
@@ -168,6 +169,9 @@ __global__ __launch_bounds__(BLOCK) void k_assemble(View v, const double* rhs, i
     {
       const R re = (R)v.re_lap, re2 = (R)v.re_lap2;
       const R cpp = (R)(2.0 * DIM / (v.lam_lap * v.n0_lap * v.rho));
+      // Eq. 23 (HL): c_ij = 2 r_e / (n0 rho r_ij^3)
+      const R chl = (R)(2.0 * v.re_lap / (v.n0_lap * v.rho));
+      const bool hl = v.laplacian == MPS_LAP_HL;
       // ASM_UNROLL list entries per lane and step: the gathers of a step in
       // flight together while the next step's list entries load (slot
       // indices past kpad clamped to the row's first slot), then the
@@ -210,8 +214,24 @@ __global__ __launch_bounds__(BLOCK) void k_assemble(View v, const double* rhs, i
           R r2 = d[0] * d[0] + d[1] * d[1];
           if constexpr (DIM == 3) r2 += d[2] * d[2];
           if (zero_x0) pj[u] = 0.0;
-          const bool in = ok[u] && fj[u] != MPS_FLAG_DUMMY && r2 < re2;
-          R cr = cpp * weight<R>(v.kernel, sqrt(r2), re);
+          const bool cand = ok[u] && fj[u] != MPS_FLAG_DUMMY;
+          bool in = cand && r2 < re2;
+          if constexpr (MIXED) {
+            // the HL coupling does not vanish at r_e: a pair within the FP32
+            // rounding of the cut-off is decided on the FP64 positions r*,
+            // as the FP64 path decides it (rare: a thin shell)
+            if (hl && cand && fabsf(r2 - re2) < 1e-5f * re2) {
+              double a[DIM], b[DIM];
+              load_vec<DIM>(v.rs, row, a);
+              load_vec<DIM>(v.rs, j[u], b);
+              double s2 = 0.0;
+#pragma unroll
+              for (int q = 0; q < DIM; ++q) s2 += (b[q] - a[q]) * (b[q] - a[q]);
+              in = s2 < v.re_lap2;
+            }
+          }
+          const R r = sqrt(r2);
+          R cr = hl ? chl / (r2 * r) : cpp * weight<R>(v.kernel, r, re);
           // two-phase: 1/rho -> 2/(<rho>_i + <rho>_j), symmetric
           if constexpr (MULTI) cr *= (R)(v.rho * 2.0 / (rho_i + rhoj[u]));
           c[u] = in ? cr : R(0);

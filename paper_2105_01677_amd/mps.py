@@ -39,7 +39,7 @@ class Params(C.Structure):
         ("dt", C.c_double), ("beta", C.c_double), ("c0", C.c_double),
         ("gamma", C.c_double), ("alpha", C.c_double), ("cg_tol", C.c_double),
         ("grid_lo", C.c_double * 3), ("cell_size", C.c_double),
-        ("smagorinsky_cs", C.c_double), ("source", C.c_int32),
+        ("smagorinsky_cs", C.c_double), ("source", C.c_int32), ("laplacian", C.c_int32),
     ]
 
 
@@ -118,6 +118,7 @@ def make_params(p: dict) -> Params:
         setattr(o, k, float(p[k]))
     o.smagorinsky_cs = float(p.get("smag_cs", 0.0))
     o.source = int(p.get("source", 0))
+    o.laplacian = int(p.get("laplacian", 0))
     for a in range(3):
         o.g[a] = float(p["g"][a])
         o.grid_lo[a] = float(p["grid_lo"][a])

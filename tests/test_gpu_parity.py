@@ -519,6 +519,81 @@ def test_dn_dt_source_full_size(gpu, orc):
     _compare_step(gpu, orc, w, 1e-4)
 
 
+@pytest.mark.parametrize("source", [W.SRC_STD, W.SRC_HS])
+@pytest.mark.parametrize("precision,cg_tol,tol", PRECISIONS)
+def test_one_step_hl_laplacian(gpu, orc, source, precision, cg_tol, tol):
+    """The PPE with the higher-order Laplacian of Eq. 23 (MPS-HL), alone and
+    with the HS source of Eq. 21: one step against the oracle in 2-D (1,432
+    particles) and 3-D (8,000 + walls), jittered."""
+    w3 = W.jitter(W.lattice_block(3, [20, 20, 20], walls_below=True, dt=2e-4))
+    for w in (W.jitter(W.config("dam_break_2d_1432", precision=precision)), w3):
+        w.params.update(precision=precision, cg_tol=cg_tol, source=source,
+                        laplacian=W.LAP_HL)
+        _compare_step(gpu, orc, w, tol)
+
+
+@pytest.mark.parametrize("precision,cg_tol,tol", PRECISIONS)
+def test_hl_full_size(gpu, orc, precision, cg_tol, tol):
+    """HS + HL at the 44,832-particle size, jittered and from rest."""
+    for w in (W.jitter(W.config("dam_break_2d_44832", precision=precision)),
+              W.config("dam_break_2d_44832", precision=precision)):
+        w.params.update(source=W.SRC_HS, laplacian=W.LAP_HL, cg_tol=cg_tol)
+        _compare_step(gpu, orc, w, tol)
+
+
+@pytest.mark.parametrize("precision", [W.FP64, W.MIXED])
+def test_hl_matrix_entries(gpu, orc, precision):
+    """The HL system (mps_get_ppe) entry by entry against the oracle's, and
+    its solution; the pair set agrees exactly, the cut-off being decided on
+    FP64 positions near r_e on the mixed path too."""
+    w = W.jitter(W.config("dam_break_2d_1432", precision=precision))
+    w.params.update(laplacian=W.LAP_HL)
+    m = gpu.MPS(w.params, w.pos, w.vel, w.ptype)
+    p, it, rr = m.pressure_solve()
+    A = {k: _np(v) for k, v in m.get_ppe().items()}
+    m.close()
+    st, o = orc.step(dict(w.params, clamp=0), w.pos, w.vel, w.ptype, want_matrix=True)
+    inner = np.nonzero(o["flags"] == 0)[0]
+    tolv = 1e-12 if precision == W.FP64 else 2e-6
+    assert rel_err(A["diag"][inner], o["diag"][inner]) < tolv
+    for i in inner:
+        c = o["count"][i]
+        ref = {int(j): v for j, v in zip(o["list"][i, :c], o["aval"][i, :c]) if v != 0.0}
+        k = A["nnz"][i]
+        got = {int(j): v for j, v in zip(A["cols"][i, :k], A["vals"][i, :k])}
+        assert set(got) == set(ref)
+        keys = sorted(ref)
+        assert rel_err([got[j] for j in keys], [ref[j] for j in keys]) < tolv
+    assert rel_err(_np(p), o["p"]) < (1e-8 if precision == W.FP64 else 1e-4)
+
+
+@pytest.mark.parametrize("precision,cg_tol,tol", PRECISIONS)
+def test_one_step_textbook_cg(gpu, orc, precision, cg_tol, tol):
+    """The two-kernel CG (cg_pipelined = 0: SpMV and update kernels, the
+    capped assembly grid) in a whole step against the oracle, at 1,432
+    (jittered) and 44,832 particles (jittered and from rest)."""
+    for w in (W.jitter(W.config("dam_break_2d_1432", precision=precision)),
+              W.jitter(W.config("dam_break_2d_44832", precision=precision)),
+              W.config("dam_break_2d_44832", precision=precision)):
+        w.params.update(cg_pipelined=0, cg_tol=cg_tol)
+        _compare_step(gpu, orc, w, tol)
+
+
+def test_hl_refused_by_the_adjoint(gpu):
+    w = W.config("dam_break_2d_1432")
+    w.params.update(laplacian=W.LAP_HL)
+    m = gpu.MPS(w.params, w.pos, w.vel, w.ptype)
+    m.tape_alloc(2)
+    m.tape_save(0)
+    m.step(1)
+    m.tape_load(0)
+    import torch
+    z = torch.zeros((w.n, 2), dtype=torch.float64, device="cuda")
+    with pytest.raises(gpu.MPSError):
+        m.step_adjoint(z, z)
+    m.close()
+
+
 def test_dn_dt_source_refused_by_the_adjoint(gpu):
     w = W.config("dam_break_2d_1432")
     w.params.update(source=W.SRC_HS)
