@@ -135,11 +135,14 @@ def run_full_length():
     from paper_2105_01677_amd import mps
     from paper_2105_01677_amd import workloads as W
     cases = [("dam_break_2d_1432", W.FP64), ("dam_break_2d_44832", W.MIXED),
+             ("dam_break_2d_44832:hs_hl", W.MIXED),
              ("sloshing_2d_24932", W.MIXED), ("dam_break_3d_441282", W.MIXED),
              ("two_phase_3d_2314616", W.MIXED)]
     out = {}
     for name, prec in cases:
-        w = W.config(name, precision=prec)
+        w = W.config(name.split(":")[0], precision=prec)
+        if name.endswith(":hs_hl"):
+            w.params.update(source=W.SRC_HS, laplacian=W.LAP_HL)
         m = mps.MPS(w.params, w.pos, w.vel, w.ptype, rho_i=w.rho_i, nu_i=w.nu_i)
         done, iters, err, first_ghost = 0, 0, None, None
         torch.cuda.synchronize()
@@ -435,7 +438,9 @@ def main():
     # precisions with the two-kernel textbook CG, and the weakly-compressible
     # model
     extra = {}
-    for name, prec, pm, pl in (("ppe_mixed_hs_ecs", W.MIXED, W.PPE_CG, 1),
+    for name, prec, pm, pl in (("ppe_mixed_hs_hl", W.MIXED, W.PPE_CG, 1),
+                               ("ppe_fp64_hs_hl", W.FP64, W.PPE_CG, 1),
+                               ("ppe_mixed_hs_ecs", W.MIXED, W.PPE_CG, 1),
                                ("ppe_fp64", W.FP64, W.PPE_CG, 1),
                                ("ppe_mixed_standard_cg", W.MIXED, W.PPE_CG, 0),
                                ("ppe_fp64_standard_cg", W.FP64, W.PPE_CG, 0),
@@ -445,11 +450,26 @@ def main():
         wx.params["cg_pipelined"] = pl
         if name.endswith("hs_ecs"):
             wx.params["source"] = W.SRC_HS_ECS
+        if name.endswith("hs_hl"):
+            wx.params.update(source=W.SRC_HS, laplacian=W.LAP_HL)
         r = run_gpu(wx, K, Wm)
         extra[name] = {"value": r["particle_steps_per_s"], "ms_per_step": r["ms_per_step"],
                        "cg_iters_mean": r["stats"]["cg_iters_total"] / K,
                        "state_ok": r["state_check"]["ok"]}
         log(name, extra[name])
+
+    # the same workload with the HS source and the HL Laplacian (Eq. 21,
+    # Eq. 23) for its configured 1,000 steps from rest, timed whole: the
+    # plain method leaves the physical flow near step 270, this pipeline
+    # does not
+    wl = W.config("dam_break_2d_44832", precision=W.MIXED)
+    wl.params.update(source=W.SRC_HS, laplacian=W.LAP_HL)
+    rl = run_gpu(wl, wl.steps, 0)
+    full_hs_hl = {"steps": wl.steps, "value": rl["particle_steps_per_s"],
+                  "ms_per_step": rl["ms_per_step"],
+                  "cg_iters_mean": rl["stats"]["cg_iters_total"] / wl.steps,
+                  "state_check": rl["state_check"]}
+    log("full length HS + HL", full_hs_hl)
 
     drop = run_drop()
     log("water_drop", drop)
@@ -506,6 +526,9 @@ def main():
         "mixed_standard_cg": extra.get("ppe_mixed_standard_cg"),
         "fp64_standard_cg": extra.get("ppe_fp64_standard_cg"),
         "mixed_hs_ecs_source": extra.get("ppe_mixed_hs_ecs"),
+        "mixed_hs_hl": extra.get("ppe_mixed_hs_hl"),
+        "fp64_hs_hl": extra.get("ppe_fp64_hs_hl"),
+        "mixed_hs_hl_1000_steps": full_hs_hl,
         "wc_eos_mixed": extra.get("wc_mixed"),
         "wc_eos_fp64": extra.get("wc_fp64"),
         "water_drop_2d": drop,

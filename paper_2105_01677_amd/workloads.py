@@ -285,10 +285,10 @@ def config(name: str, **kw) -> Workload:
     if name == "dam_break_2d_1432":
         return dam_break_2d(0.01, dt=kw.pop("dt", 5e-4), steps=200, **kw)
     if name == "dam_break_2d_44832":
-        # The plain method (no collision model, no source-term stabiliser)
-        # blows up on this case near t = 0.03 s whatever the step: near
-        # step 270 at dt = 1e-4 (the FP64 oracle as well as the GPU), step
-        # ~850 at 3e-5.  Runs of it stay within the first 250 steps.
+        # The plain method (Eq. 13 source, Eq. 7 Laplacian) blows up on this
+        # case near step 274 at dt = 1e-4 (the FP64 oracle as well as the
+        # GPU); with the HS source and the HL Laplacian (source=SRC_HS,
+        # laplacian=LAP_HL) it runs all 1,000 steps.
         return dam_break_2d(0.00125, dt=kw.pop("dt", 1e-4), steps=1000, **kw)
     if name == "dam_break_3d_441282":
         return dam_break_3d(0.007, **kw)
