@@ -669,34 +669,41 @@ def test_two_phase_update_keeps_hydrostatic_rest(orc, dim):
 
 
 def test_still_tank_hydrostatic_level(orc):
-    """Still water, 0.3 m wide and 0.2 m deep at l0 = 0.01 m, 400 steps of
-    dt = 5e-4 s: the pressure averaged over the second half follows
-    rho g (H - y) in the interior.  A loose check, as the plain method is
-    noisy (the pressure from rest is ~0 and builds up, and spurious
-    velocities grow to ~0.6 m/s), but a lost factor (2d, rho, lambda, n0 or
-    dt^2) or a sign error in the pressure chain fails it."""
+    """Still water, 0.3 m wide and 0.2 m deep at l0 = 0.01 m, dt = 5e-4 s,
+    plain method (Eq. 13, Eq. 7, standard gradient): from rest the pressure
+    builds up within ~30 steps (the column compresses until the PPE
+    balances gravity), and over steps 31-70, while every fluid speed stays
+    below 0.03 m/s, the time-mean pressure of the interior follows
+    rho g (H - y) to 5 %: both its least-squares slope against the depth and
+    the mean of p/(rho g h).  At rest the gradient must cancel gravity, so a
+    lost or extra factor in the gradient or the update (d, n0, rho) changes
+    the equilibrium pressure by that factor; the scales of the Laplacian and
+    of the source only set how much compression carries it (pinned by the
+    rows-as-Laplacian and compressed-lattice tests).  (Later the plain
+    method grows noisy, the instability of the dam break.)"""
     l0 = 0.01
     w = W.dam_break_2d(l0, tank=(0.3, 0.3), column=(0.3, 0.2), dt=5e-4)
     f0 = w.ptype == W.FLUID
     H = w.pos[f0, 1].max() + 0.5 * l0
-    pos, vel, t = w.pos.copy(), w.vel.copy(), w.ptype.copy()
-    acc, cnt = np.zeros(w.n), 0
-    for k in range(20):
-        st, pos, vel, t, p, fl = orc.run(w.params, pos, vel, t, 20)
+    st, pos, vel, t, p, fl = orc.run(w.params, w.pos, w.vel, w.ptype, 30)
+    assert st == 0
+    acc, vmax = np.zeros(w.n), 0.0
+    for k in range(40):
+        st, pos, vel, t, p, fl = orc.run(w.params, pos, vel, t, 1)
         assert st == 0
-        if k >= 10:
-            acc += p
-            cnt += 1
+        acc += p
+        vmax = max(vmax, np.linalg.norm(vel[t == W.FLUID], axis=1).max())
     assert (t == W.GHOST).sum() == 0
-    pm = acc / cnt
+    assert vmax < 0.03
+    pm = acc / 40
     x, y = w.pos[:, 0], w.pos[:, 1]
     inner = f0 & (x > 5 * l0) & (x < 0.3 - 5 * l0) & (y > 4 * l0) & (y < H - 4 * l0)
     depth = H - y[inner]
     slope = np.linalg.lstsq(np.vstack([depth, np.ones_like(depth)]).T, pm[inner], rcond=None)[0][0]
     ratio = (pm[inner] / (1000.0 * 9.81 * depth)).mean()
-    print("still tank: slope/(rho g)", slope / 9810.0, "mean p/(rho g h)", ratio)
-    assert 0.6 < slope / 9810.0 < 1.2
-    assert 0.8 < ratio < 1.4
+    print("still tank: slope/(rho g)", slope / 9810.0, "mean p/(rho g h)", ratio, "vmax", vmax)
+    assert abs(slope / 9810.0 - 1.0) < 0.05
+    assert abs(ratio - 1.0) < 0.05
 
 
 def _n_all_pairs(pos, re, kernel):
