@@ -114,14 +114,44 @@ def test_adjoint_matches_finite_differences(torch_gpu, clamp):
         assert rel(g_u, fd_u) < 1e-3
 
 
+def test_mixed_adjoint_matches_mixed_finite_differences(torch_gpu):
+    """The configuration's precision (FP32 forward sums, FP64 adjoint) held
+    to the adjoint bar against central differences of its own forward:
+    the adjoint is the FP64 derivative along the mixed trajectory, with
+    that trajectory's frozen decisions.  The FP32 forward's rounding noise
+    (~1e-7 of the loss) needs wider steps than the FP64 check: h = 0.1 nu
+    and 1e-2 m/s^2, whose truncation error on the FP64 path is 3e-9 and
+    7e-7 of the derivative."""
+    w = W.sloshing_2d(0.005, precision=W.MIXED)
+    nsteps, K = 40, 10
+    d = _direction(w)
+    L, g_nu, g_gx, g_u = gpu_grads(torch_gpu, w, nsteps, K, d)
+    nu = w.params["nu"]
+    h = 0.1 * nu
+    fd_nu = (gpu_loss(torch_gpu, w, nsteps, dict(w.params, nu=nu + h))
+             - gpu_loss(torch_gpu, w, nsteps, dict(w.params, nu=nu - h))) / (2 * h)
+    hg = 1e-2
+    gp = list(w.params["g"]); gp[0] += hg
+    gm = list(w.params["g"]); gm[0] -= hg
+    fd_gx = (gpu_loss(torch_gpu, w, nsteps, dict(w.params, g=gp))
+             - gpu_loss(torch_gpu, w, nsteps, dict(w.params, g=gm))) / (2 * hg)
+    print("mixed nu", g_nu, fd_nu, "gx", g_gx, fd_gx, flush=True)
+    assert rel(g_nu, fd_nu) < 1e-3
+    assert rel(g_gx, fd_gx) < 1e-3
+
+
 def test_adjoint_sloshing_full_size(torch_gpu, orc):
     """22,500 fluid particles, 500 steps, checkpoints every 50 steps.
     FP64 path: all three gradients against the oracle's exact dual-number
     derivative of the same 500-step rollout (finite differences are not a
     usable reference over 500 steps: the pressure clamp's kinks dominate
-    them).  Mixed path (FP32 forward sums, FP64 adjoint): its gradients
-    differ from the FP64 ones because the FP32 forward trajectory itself
-    differs; that deviation is reported and bounded loosely."""
+    them).  Mixed path (FP32 forward sums, FP64 adjoint): within 1e-3 of
+    the FP64 gradients over 400 steps.  Over 500 steps the gradient itself
+    is ill-conditioned: perturbing u0 by one FP32 rounding (2^-24 relative,
+    seeded) moves the FP64 gradients by up to ~1.6 %, so no FP32 forward
+    can be held to 1e-3 there; the mixed deviation is held to four times
+    the larger such FP64 spread of two seeds, per gradient (the FP32
+    forward rounds every step, not once)."""
     torch = torch_gpu
     w = W.config("sloshing_2d_24932", precision=W.FP64)
     assert w.counts()["fluid"] == 22500
@@ -136,11 +166,26 @@ def test_adjoint_sloshing_full_size(torch_gpu, orc):
     assert rel(g_gx, o_gx) < 1e-3
     assert rel(g_u, o_u) < 1e-3
     wm = W.config("sloshing_2d_24932", precision=W.MIXED)
-    Lm, m_nu, m_gx, m_u = gpu_grads(torch, wm, nsteps, K, d)
-    dev = max(rel(m_nu, o_nu), rel(m_gx, o_gx), rel(m_u, o_u))
-    print("mixed L", Lm, "nu", m_nu, "gx", m_gx, "u0", m_u, "max deviation from FP64", dev,
-          flush=True)
-    assert dev < 5e-2
+    # 400 steps: the adjoint bar
+    ref4 = gpu_grads(torch, w, 400, K, d)[1:]
+    mix4 = gpu_grads(torch, wm, 400, K, d)[1:]
+    dev4 = [rel(a, b) for a, b in zip(mix4, ref4)]
+    print("400 steps: mixed deviation from FP64 (nu, gx, u0)", dev4, flush=True)
+    assert max(dev4) < 1e-3
+    # 500 steps: against the conditioning of the FP64 gradient
+    spread = [0.0, 0.0, 0.0]
+    for seed in (1, 2):
+        rng = np.random.default_rng(seed)
+        wp = W.config("sloshing_2d_24932", precision=W.FP64)
+        wp.vel = w.vel * (1.0 + 2.0 ** -24 * rng.uniform(-1.0, 1.0, size=w.vel.shape))
+        gq = gpu_grads(torch, wp, nsteps, K, d)[1:]
+        spread = [max(s_, rel(a, b)) for s_, a, b in zip(spread, gq, (g_nu, g_gx, g_u))]
+    mix = gpu_grads(torch, wm, nsteps, K, d)[1:]
+    dev = [rel(a, b) for a, b in zip(mix, (g_nu, g_gx, g_u))]
+    print("500 steps: FP64 spread under 2^-24 perturbations", spread,
+          "mixed deviation", dev, flush=True)
+    for dv, sp in zip(dev, spread):
+        assert dv < max(1e-3, 4.0 * sp)
 
 
 def _two_phase(dim):
