@@ -219,6 +219,10 @@ mps_status mps_neighbors_noalloc(const mps_params* params, int64_t n, const doub
  * whose solve did not converge within its count is redone from its input
  * with polled CG batches, the step after it discarded (same results;
  * counted in stats->cg_redone).
+ * A numerical error (NEIGH_OVERFLOW, COINCIDENT, NONFINITE) raised in the
+ * k-th step of the call ends the call there: stats->steps = k - 1 steps
+ * were completed, and the context's state (mps_get_state) is the failing
+ * step's input; no step behind it writes state.
  * Errors: MPS_E_NEIGH_OVERFLOW, MPS_E_COINCIDENT, MPS_E_NONFINITE,
  * MPS_E_CG_NOCONV (the step still completes with the last iterate),
  * MPS_E_POISONED. */

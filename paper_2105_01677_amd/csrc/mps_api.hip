@@ -76,10 +76,14 @@ struct mps_ctx {
   int nspmv = 0, nupd = 0, nasmb = 0, npcg = 0, pcg_fused = 0, pcg_pred = 0;
   CGScalars* sc = nullptr;
   int32_t* status = nullptr;
+  int32_t* step_count = nullptr;   // steps of a call begun with a clean status
   int64_t* counts = nullptr;   // [4]: surface, ghost, list entries, matrix nnz
   // pinned host mirrors
   CGScalars* h_sc = nullptr;
   int32_t* h_status = nullptr;
+  // status word at the end of the whole-step graph from buffer b ([b]) and
+  // of a polled step ([NBUF]); [NBUF + 1]: the step counter
+  int32_t* h_step_status = nullptr;
   int64_t* h_counts = nullptr;
   // profiling: event pairs around launches of the selected kernel classes
   static constexpr int kPool = 2048;
@@ -128,6 +132,7 @@ struct mps_ctx {
   bool poisoned = false;
   bool ppe_valid = false;
   int last_iters = 0;
+  int32_t steps_ok = 0;    // steps of the running mps_step call completed
   char err[256] = {0};
 };
 
@@ -395,18 +400,29 @@ unsigned flat_blocks(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 void prof_flush(mps_ctx* c);
 
-mps_status read_status(mps_ctx* c) {
-  HIPCHK(c, hipMemcpyAsync(c->h_status, c->status, sizeof(int32_t), hipMemcpyDeviceToHost, c->s));
-  HIPCHK(c, hipStreamSynchronize(c->s));
-  prof_flush(c);
-  const int32_t st = *c->h_status;
-  if (st == 0) return MPS_OK;
+// The error of a raised status word st (!= 0): the device word is cleared
+// and the context poisoned.
+mps_status status_error(mps_ctx* c, int32_t st) {
   HIPCHK(c, hipMemsetAsync(c->status, 0, sizeof(int32_t), c->s));
   c->poisoned = true;
   if (st & ST_OVERFLOW) return fail(c, MPS_E_NEIGH_OVERFLOW, "more than max_neigh neighbours");
   if (st & ST_COINCIDENT) return fail(c, MPS_E_COINCIDENT, "two particles at distance 0");
   if (st & ST_NONFINITE) return fail(c, MPS_E_NONFINITE, "non-finite position or velocity");
   return fail(c, MPS_E_ARG, "invalid particle type");
+}
+
+mps_status read_status(mps_ctx* c) {
+  HIPCHK(c, hipMemcpyAsync(c->h_status, c->status, sizeof(int32_t), hipMemcpyDeviceToHost, c->s));
+  HIPCHK(c, hipStreamSynchronize(c->s));
+  prof_flush(c);
+  const int32_t st = *c->h_status;
+  if (st == 0) return MPS_OK;
+  return status_error(c, st);
+}
+
+// Counts a step begun with a clean status word (one thread).
+__global__ void k_step_begin(const int32_t* status, int32_t* count) {
+  if (threadIdx.x == 0 && *status == 0) *count += 1;
 }
 
 // Accumulate the recorded event pairs (the stream must be synchronised).
@@ -501,6 +517,7 @@ void enqueue_assemble(mps_ctx* c, const View& v, const double* rhs, bool zero_x0
 // Stages before the pressure solve: a1-a5 (PPE) or a1-a4 + a7 (EOS).
 // Leaves the context in the new sorted order (flips cur).
 void enqueue_pre(mps_ctx* c) {
+  k_step_begin<<<1, 64, 0, c->s>>>(c->status, c->step_count);
   search(c);
   View v = make_view(c);
   if (c->multi) {
@@ -688,6 +705,8 @@ mps_status step_graph(mps_ctx* c, int par, int ncg, hipGraphExec_t* out) {
     (void)hipMemcpyAsync(c->h_sc + 1 + par, c->sc, sizeof(CGScalars), hipMemcpyDeviceToHost,
                          c->s);
     enqueue_post(c);
+    (void)hipMemcpyAsync(c->h_step_status + par, c->status, sizeof(int32_t),
+                         hipMemcpyDeviceToHost, c->s);
   });
   c->cur = cur0;
   if (st != MPS_OK) {
@@ -702,6 +721,7 @@ mps_status step_graph(mps_ctx* c, int par, int ncg, hipGraphExec_t* out) {
 
 void record_cg(mps_ctx* c, mps_step_stats* st, int it, double rel) {
   c->last_iters = it;
+  c->steps_ok += 1;
   if (st) {
     st->cg_iters_last = it;
     st->cg_iters_total += it;
@@ -709,7 +729,17 @@ void record_cg(mps_ctx* c, mps_step_stats* st, int it, double rel) {
   }
 }
 
+// A step that raised the status word st: wait for everything enqueued
+// (a step enqueued behind it writes no state, see k_rank_permute), go back
+// to its input buffer b and report the error.
+mps_status fail_step(mps_ctx* c, int b, int32_t st) {
+  HIPCHK(c, hipStreamSynchronize(c->s));
+  c->cur = b;
+  return status_error(c, st);
+}
+
 mps_status one_step_polled(mps_ctx* c, mps_step_stats* st) {
+  const int b_in = c->cur;
   const bool graphs = use_graphs(c);
   if (graphs) {
     mps_status s0 = build_graphs(c);
@@ -725,9 +755,15 @@ mps_status one_step_polled(mps_ctx* c, mps_step_stats* st) {
   double rel = 0;
   mps_status res = solve(c, &it, &rel, graphs);
   if (res != MPS_OK && res != MPS_E_CG_NOCONV) return res;
-  record_cg(c, st, it, rel);
   if (graphs) HIPCHK(c, hipGraphLaunch(c->g_post[c->cur], c->s));
   else enqueue_post(c);
+  // the step's own status, before the next step is enqueued
+  int32_t* hs = c->h_step_status + mps_ctx::NBUF;
+  HIPCHK(c, hipMemcpyAsync(hs, c->status, sizeof(int32_t), hipMemcpyDeviceToHost, c->s));
+  HIPCHK(c, hipStreamSynchronize(c->s));
+  prof_flush(c);
+  if (*hs) return fail_step(c, b_in, *hs);
+  record_cg(c, st, it, rel);
   return res;
 }
 
@@ -775,15 +811,17 @@ mps_status redo_step(mps_ctx* c, int b, mps_step_stats* st) {
   return one_step_polled(c, st);
 }
 
-// Accepts step results from the CG scalars the whole-step graph from buffer
-// b left in pinned memory; false if the solve did not converge in it.
-bool accept_step(mps_ctx* c, int b, mps_step_stats* st) {
+// Accepts step results from the CG scalars and the status word the
+// whole-step graph from buffer b left in pinned memory: 1 accepted, 0 the
+// solve did not converge in it, -1 the step raised an error.
+int accept_step(mps_ctx* c, int b, mps_step_stats* st) {
+  if (c->h_step_status[b]) return -1;
   const CGScalars h = c->h_sc[1 + b];
-  if (!h.converged) return false;
+  if (!h.converged) return 0;
   c->cur = (b + 1) % mps_ctx::NBUF;
   c->ppe_valid = true;
   record_cg(c, st, h.iter, h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0);
-  return true;
+  return 1;
 }
 
 mps_status one_step_ppe(mps_ctx* c, mps_step_stats* st) {
@@ -795,7 +833,9 @@ mps_status one_step_ppe(mps_ctx* c, mps_step_stats* st) {
     if (s0 != MPS_OK) return s0;
     s0 = spin_wait(c, c->ev_step[b]);
     if (s0 != MPS_OK) return s0;
-    if (accept_step(c, b, st)) return MPS_OK;
+    const int a = accept_step(c, b, st);
+    if (a > 0) return MPS_OK;
+    if (a < 0) return fail_step(c, b, c->h_step_status[b]);
     return redo_step(c, b, st);
   }
   return one_step_polled(c, st);
@@ -828,7 +868,9 @@ mps_status steps_ppe(mps_ctx* c, int nsteps, mps_step_stats* st) {
       }
       r = spin_wait(c, c->ev_step[b]);
       if (r != MPS_OK) return r;
-      if (!accept_step(c, b, st)) {
+      const int a = accept_step(c, b, st);
+      if (a < 0) return fail_step(c, b, c->h_step_status[b]);
+      if (a == 0) {
         r = redo_step(c, b, st);
         if (r == MPS_E_CG_NOCONV) res = r;
         else if (r != MPS_OK) return r;
@@ -961,6 +1003,7 @@ mps_status mps_init(const mps_params* params, int64_t n, const double* pos, cons
   A(dalloc(&c->sc, 1));
   // [1 + b]: copy taken before a whole-step graph from buffer b
   A(dalloc(&c->status, 1 + mps_ctx::NBUF));
+  A(dalloc(&c->step_count, 1));
   A(dalloc(&c->counts, 4));
   g_bytes = nullptr;
   // [0]: polled solves; [1 + b]: the whole-step graph from buffer b
@@ -968,6 +1011,9 @@ mps_status mps_init(const mps_params* params, int64_t n, const double* pos, cons
     e = hipHostMalloc((void**)&c->h_sc, (1 + mps_ctx::NBUF) * sizeof(CGScalars),
                       hipHostMallocDefault);
   if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_status, sizeof(int32_t), hipHostMallocDefault);
+  if (e == hipSuccess)
+    e = hipHostMalloc((void**)&c->h_step_status, (mps_ctx::NBUF + 2) * sizeof(int32_t),
+                      hipHostMallocDefault);
   if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_counts, 4 * sizeof(int64_t), hipHostMallocDefault);
   if (e != hipSuccess) {
     mps_free(c);
@@ -977,6 +1023,7 @@ mps_status mps_init(const mps_params* params, int64_t n, const double* pos, cons
   hipStream_t s = c->s;
   A(hipMemsetAsync(c->cell_count, 0, scan_cells_padded(c->ncell) * sizeof(int32_t), s));
   A(hipMemsetAsync(c->status, 0, sizeof(int32_t), s));
+  A(hipMemsetAsync(c->step_count, 0, sizeof(int32_t), s));
   A(hipMemsetAsync(c->sc, 0, sizeof(CGScalars), s));
   A(hipMemsetAsync(c->nb_count, 0, n * sizeof(int32_t), s));
   A(hipMemsetAsync(c->a_nnz, 0, n * sizeof(int32_t), s));
@@ -1051,7 +1098,8 @@ mps_status mps_free(mps_ctx* c) {
                   c->cell_local, c->tile_sum,
                   c->nb_count,
                   c->nb_list, c->a_nnz, c->a_col, c->a_val, c->diag, c->b, c->r, c->z,
-                  c->q, c->p_save, c->partA, c->partB, c->sc, c->status, c->counts,
+                  c->q, c->p_save, c->partA, c->partB, c->sc, c->status, c->step_count,
+                  c->counts,
                   c->nut, c->mu,
                   c->rho_o, c->nu_o,
                   c->pl_z, c->pl_s, c->pl_m[0], c->pl_m[1], c->pl_part[0], c->pl_part[1],
@@ -1076,6 +1124,7 @@ mps_status mps_free(mps_ctx* c) {
   free_tape(c);
   if (c->h_sc) (void)hipHostFree(c->h_sc);
   if (c->h_status) (void)hipHostFree(c->h_status);
+  if (c->h_step_status) (void)hipHostFree(c->h_step_status);
   if (c->h_counts) (void)hipHostFree(c->h_counts);
   delete c;
   return MPS_OK;
@@ -1112,18 +1161,40 @@ mps_status mps_step(mps_ctx* c, int32_t nsteps, mps_step_stats* stats) {
   if (c->poisoned) return fail(c, MPS_E_POISONED, "context poisoned; call mps_set_state");
   if (stats) std::memset(stats, 0, sizeof(*stats));
   mps_status res = MPS_OK;
+  c->steps_ok = 0;
   if (c->P.pmode == MPS_WC_EOS) {
+    // no host synchronisation between the steps: each step counts itself
+    // on the device when it begins with a clean status, and once a step has
+    // raised an error the steps behind it write no state, so the failing
+    // step's input is the buffer after (count - 1) steps
+    const int cur0 = c->cur;
+    HIPCHK(c, hipMemsetAsync(c->step_count, 0, sizeof(int32_t), c->s));
     res = steps_wc(c, nsteps);
     if (res != MPS_OK) return res;
+    HIPCHK(c, hipGetLastError());
+    int32_t* hs = c->h_step_status;
+    HIPCHK(c, hipMemcpyAsync(hs, c->status, sizeof(int32_t), hipMemcpyDeviceToHost, c->s));
+    HIPCHK(c, hipMemcpyAsync(hs + mps_ctx::NBUF + 1, c->step_count, sizeof(int32_t),
+                             hipMemcpyDeviceToHost, c->s));
+    HIPCHK(c, hipStreamSynchronize(c->s));
+    prof_flush(c);
+    if (hs[0]) {
+      const int begun = std::max(1, (int)hs[mps_ctx::NBUF + 1]);
+      c->cur = (cur0 + begun - 1) % mps_ctx::NBUF;
+      if (stats) stats->steps = begun - 1;
+      return status_error(c, hs[0]);
+    }
+    c->steps_ok = nsteps;
   } else {
     res = steps_ppe(c, nsteps, stats);
+    if (stats) stats->steps = c->steps_ok;
     if (res != MPS_OK && res != MPS_E_CG_NOCONV) return res;
   }
   HIPCHK(c, hipGetLastError());
   mps_status st = read_status(c);
   if (st != MPS_OK) return st;
   if (stats) {
-    stats->steps = nsteps;
+    stats->steps = c->steps_ok;
     HIPCHK(c, hipMemsetAsync(c->counts, 0, 4 * sizeof(int64_t), c->s));
     k_count_flags<<<flat_blocks(c->n), 256, 0, c->s>>>(c->n, c->flags, c->nb_count, c->a_nnz,
                                                        c->P.pmode == MPS_PPE_CG, c->counts);

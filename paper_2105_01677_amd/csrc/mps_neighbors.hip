@@ -163,7 +163,7 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(View v) {
 }
 
 // Final position of every particle and the permutation of the state in one
-// pass: inside its cell a particle's rank is the number of cell members with
+// pass (skipped once an error has been raised): inside its cell a particle's rank is the number of cell members with
 // a smaller original id (cells hold a few tens of particles, read from the
 // unordered scatter in perm), so the order does not depend on how the
 // counting atomics resolved.  Ghosts keep their atomic slot: they take part
@@ -172,7 +172,10 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(View v) {
 template <int DIM, bool MIXED>
 __global__ __launch_bounds__(BLOCK) void k_rank_permute(View v) {
   const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (i >= v.n) return;
+  // after an error raised earlier in this call no step writes state any
+  // more, so the failing step's input buffer survives the steps enqueued
+  // behind it
+  if (i >= v.n || *v.status) return;
   const int c = v.cellid[i];
   const int b = v.cell_start[c];
   const int32_t key = v.id[i];

@@ -266,6 +266,7 @@ __global__ __launch_bounds__(BLOCK) void k_density(View v, int wc) {
   // the row's own loads are issued together (no branch before the list)
   const int8_t ty = v.type[row];
   const int cnt_all = v.nb_count[row];
+  const int32_t err = *v.status;
   const P pi = P::load(v.rs, v.rsf, row);
   double ui[DIM], xk[DIM], uk[DIM];
   if constexpr (SRC >= MPS_SRC_HS) load_vec<DIM>(v.us, row, ui);
@@ -353,6 +354,8 @@ __global__ __launch_bounds__(BLOCK) void k_density(View v, int wc) {
   if (ty == MPS_GHOST) fl = MPS_FLAG_GHOST;
   else if (ty == MPS_DUMMY) fl = MPS_FLAG_DUMMY;
   else fl = ns < v.beta * v.n0_n ? MPS_FLAG_SURFACE : MPS_FLAG_INNER;
+  // no state is written after an error raised earlier in the call
+  if (err) return;
   v.nstar[row] = ns;
   v.flags[row] = fl;
   if (wc) {
@@ -516,6 +519,7 @@ __global__ __launch_bounds__(BLOCK) void k_gradient(View v, const double* phat) 
   const R re = (R)v.re_n, re2 = (R)v.re_n2;
   const int cnt_all = v.nb_count[row];
   const double p_raw = v.p[row];
+  const int32_t err = *v.status;
   const double p_i = p_eff(v, p_raw);
   double us[DIM], rs[DIM], un[DIM], xn[DIM];
   load_vec<DIM>(v.us, row, us);
@@ -578,6 +582,8 @@ __global__ __launch_bounds__(BLOCK) void k_gradient(View v, const double* phat) 
     xn[a] = rs[a] + v.dt * (un[a] - us[a]);
     finite = finite && isfinite(un[a]) && isfinite(xn[a]);
   }
+  // no state is written after an error raised earlier in the call
+  if (err) return;
   if (t == 0 && p_i != p_raw) v.p[row] = p_i;
   if (fluid && t == 0) {
     store_vec<DIM>(v.vel_w, row, un);

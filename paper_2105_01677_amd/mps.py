@@ -223,16 +223,23 @@ class MPS:
                     "mps_constants")
         return a.value, b.value, c.value
 
-    def step(self, nsteps: int = 1, *, allow_noconv=False) -> dict:
+    def step_status(self, nsteps: int = 1):
+        """mps_step without raising: (status, statistics).  After an error,
+        statistics["steps"] is the number of steps completed before the
+        failing one, and the state is that step's input."""
         s = StepStats()
         st = lib().mps_step(self.h, int(nsteps), C.byref(s))
+        return st, {"status": st, "steps": s.steps, "cg_iters_last": s.cg_iters_last,
+                    "cg_iters_total": s.cg_iters_total, "cg_relres_last": s.cg_relres_last,
+                    "n_surface": s.n_surface, "n_ghost": s.n_ghost,
+                    "list_entries": s.list_entries, "ppe_nnz": s.ppe_nnz,
+                    "cg_redone": s.cg_redone}
+
+    def step(self, nsteps: int = 1, *, allow_noconv=False) -> dict:
+        st, stats = self.step_status(nsteps)
         if not (allow_noconv and st == E_CG_NOCONV):
             self._check(st, "mps_step")
-        return {"status": st, "steps": s.steps, "cg_iters_last": s.cg_iters_last,
-                "cg_iters_total": s.cg_iters_total, "cg_relres_last": s.cg_relres_last,
-                "n_surface": s.n_surface, "n_ghost": s.n_ghost,
-                "list_entries": s.list_entries, "ppe_nnz": s.ppe_nnz,
-                "cg_redone": s.cg_redone}
+        return stats
 
     def profile(self, classes):
         """Time every launch of the named kernel classes with HIP events."""

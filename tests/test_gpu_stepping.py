@@ -100,3 +100,68 @@ def test_dam_break_3d_runs_physical(gpu):
     assert np.isfinite(vel).all()
     assert speed.max() < 10 * np.sqrt(2 * 9.81 * h)
     assert speed.max() > 0.1       # g t = 0.196 m/s after 100 steps of 2e-4 s
+
+
+def _ring_scene(pmode, precision):
+    """A ring of fluid particles converging on a particle at its centre, in
+    the air of the 2-D tank: the centre's list outgrows the cap at a known
+    step (the eighth in the oracle as well), every earlier step clean.  For
+    the PPE model the resting water column stays beside it (its solve keeps
+    the whole-step graphs in use; the ring's pressure stays mild); for the
+    equation of state the ring is alone, 24 particles against a cap of 20,
+    so that its spacing stays above l0 and its pressure at zero."""
+    w = W.config("dam_break_2d_1432", pmode=pmode, precision=precision)
+    dt, l0 = w.params["dt"], w.params["l0"]
+    c = np.array([0.5, 0.45])
+    m, speed, cap = (64, 0.5, 50) if pmode == W.PPE_CG else (24, 0.45, 20)
+    ang = 2 * np.pi * np.arange(m) / m
+    e = np.stack([np.cos(ang), np.sin(ang)], 1)
+    ring, rv = c + 7 * l0 * e, -speed * l0 / dt * e
+    if pmode == W.PPE_CG:
+        pos = np.vstack([w.pos, ring, c[None]])
+        vel = np.vstack([w.vel, rv, [[0.0, 0.0]]])
+        typ = np.concatenate([w.ptype, np.zeros(m + 1, np.int8)])
+    else:
+        pos, vel = np.vstack([ring, c[None]]), np.vstack([rv, [[0.0, 0.0]]])
+        typ = np.zeros(m + 1, np.int8)
+    return dict(w.params, max_neigh=cap), pos, vel, typ
+
+
+def _state(m):
+    st = m.state()
+    return {k: st[k].detach().cpu().numpy() for k in ("pos", "vel", "p", "type")}
+
+
+@pytest.mark.parametrize("precision", [W.MIXED, W.FP64])
+@pytest.mark.parametrize("pmode", [W.PPE_CG, W.WC_EOS])
+def test_error_stops_at_the_failing_step(gpu, pmode, precision):
+    """An error raised in step k of a call ends the call there: the status
+    names it, stats.steps counts the k - 1 steps completed before it, and
+    the context's state is step k's input, bit for bit as after k - 1 clean
+    steps.  PPE: whole-step graphs, two in flight; EOS: graphs of two steps
+    with no host synchronisation in between."""
+    prm, pos, vel, typ = _ring_scene(pmode, precision)
+    m = gpu.MPS(prm, pos, vel, typ)
+    before = []
+    for k in range(1, 12):
+        st, _ = m.step_status(1)
+        if st != gpu.OK:
+            break
+        before.append(_state(m))
+    m.close()
+    assert st == gpu.E_NEIGH_OVERFLOW
+    k_fail = len(before) + 1
+    assert k_fail == 8
+    for done in (0, 3):
+        m = gpu.MPS(prm, pos, vel, typ)
+        if done:
+            assert m.step_status(done)[0] == gpu.OK
+        st, stats = m.step_status(10)
+        assert st == gpu.E_NEIGH_OVERFLOW
+        assert stats["steps"] == k_fail - 1 - done
+        got = _state(m)
+        for key, a in before[k_fail - 2].items():
+            assert np.array_equal(got[key], a), (done, key)
+        # poisoned until the state is set again
+        assert m.step_status(1)[0] == gpu.E_POISONED
+        m.close()
