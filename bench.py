@@ -137,14 +137,17 @@ def run_full_length():
     cases = [("dam_break_2d_1432", W.FP64), ("dam_break_2d_44832", W.MIXED),
              ("dam_break_2d_44832:hs_hl", W.MIXED),
              ("sloshing_2d_24932", W.MIXED), ("dam_break_3d_441282", W.MIXED),
+             ("dam_break_3d_441282:kept_lists", W.MIXED),
              ("two_phase_3d_2314616", W.MIXED)]
     out = {}
     for name, prec in cases:
         w = W.config(name.split(":")[0], precision=prec)
         if name.endswith(":hs_hl"):
             w.params.update(source=W.SRC_HS, laplacian=W.LAP_HL)
+        if name.endswith(":kept_lists"):
+            w = W.with_skin(w, 0.2)
         m = mps.MPS(w.params, w.pos, w.vel, w.ptype, rho_i=w.rho_i, nu_i=w.nu_i)
-        done, iters, err, first_ghost = 0, 0, None, None
+        done, iters, err, first_ghost, builds = 0, 0, None, None, 0
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         while done < w.steps:
@@ -156,6 +159,7 @@ def run_full_length():
                 break
             done += k
             iters += s["cg_iters_total"]
+            builds += s["list_builds"]
             if first_ghost is None and s["n_ghost"] > 0:
                 first_ghost = done
         torch.cuda.synchronize()
@@ -166,6 +170,7 @@ def run_full_length():
                      "configured_steps": w.steps, "steps_run": done,
                      "ms_per_step": 1e3 * dt / max(done, 1),
                      "cg_iters_mean": iters / max(done, 1), "error": err,
+                     "list_builds": builds,
                      "first_ghost_by_step": first_ghost, "state_check": chk}
         log(name, out[name])
     return out
@@ -242,6 +247,7 @@ def run_3d(name, w, steps, warmup):
     res = {"n_particles": w.n, "n_fluid": c["fluid"], "steps": steps,
            "value": r["particle_steps_per_s"], "ms_per_step": r["ms_per_step"],
            "cg_iters_mean": r["stats"]["cg_iters_total"] / steps,
+           "list_builds": r["stats"]["list_builds"],
            "state_ok": r["state_check"]["ok"],
            "kernels": kernel_bandwidth(w, br, mixed, w.params["pmode"] == 1)}
     log(name, {k: v for k, v in res.items() if k != "kernels"})
@@ -487,6 +493,11 @@ def main():
         runs_3d["dam_break_3d_l0=0.007_fp64_plain"] = f64
         runs_3d["dam_break_3d_l0=0.007"]["mixed_vs_fp64_plain"] = (
             runs_3d["dam_break_3d_l0=0.007"]["value"] / f64["value"])
+        # lists kept over steps with a skin of 0.2 l0 (rebuilt when a
+        # particle has moved 0.1 l0 since the build)
+        w3k = W.with_skin(W.config("dam_break_3d_441282", precision=W.MIXED), 0.2)
+        runs_3d["dam_break_3d_l0=0.007_kept_lists"] = run_3d("dam_break_3d_kept_lists", w3k,
+                                                            args.steps_3d, 2)
         w5 = W.config("two_phase_3d_2314616", precision=W.MIXED)
         w5.params["cg_pipelined"] = 1
         runs_3d["two_phase_3d_l0=0.005"] = run_3d("two_phase_3d", w5, max(args.steps_3d // 2, 2), 1)

@@ -122,6 +122,19 @@ typedef struct {
   int32_t laplacian;        /* MPS_LAP_*: Laplacian of pressure in the PPE
                                (PPE model only; the adjoint needs
                                MPS_LAP_STD) */
+  double skin;              /* 0: neighbour lists built every step.  > 0
+                               (m, below re_lap; cell_size >= re_lap + skin):
+                               lists kept over steps - a superset at radius
+                               re_lap + skin is built with a fresh cell sort
+                               and filtered every step to the exact list;
+                               it is rebuilt when a particle has moved
+                               skin/2 since the build or left the grid.  The
+                               lists are the same sets; only the order of
+                               the particles and of the list entries, hence
+                               the rounding of the sums, differs.  A
+                               superset row beyond 1.2 max_neigh ((re_lap +
+                               skin)/re_lap)^dim entries is reported as
+                               MPS_E_NEIGH_OVERFLOW.  The adjoint needs 0. */
 } mps_params;
 
 typedef struct {
@@ -135,6 +148,8 @@ typedef struct {
   int64_t ppe_nnz;         /* off-diagonal matrix entries of the last step */
   int32_t cg_redone;       /* steps whose speculative solve (see mps_step)
                               did not converge and that were redone */
+  int32_t list_builds;     /* steps that built their neighbour lists with a
+                              cell sort (all of them when skin = 0) */
 } mps_step_stats;
 
 /* Kernel classes for mps_profile: cell binning + sort + permutation (a1),

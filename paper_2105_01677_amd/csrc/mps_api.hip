@@ -56,6 +56,13 @@ struct mps_ctx {
   int32_t *cellid = nullptr, *slot = nullptr, *cell_count = nullptr, *cell_start = nullptr,
           *cell_local = nullptr, *tile_sum = nullptr, *perm = nullptr;
   int32_t *nb_count = nullptr, *nb_list = nullptr;
+  // lists kept over steps (skin > 0): superset lists, positions at the
+  // build, the device record of the decisions
+  int32_t *sk_count = nullptr, *sk_list = nullptr;
+  double* r_build = nullptr;
+  ListState* ls = nullptr;
+  int kpad_s = 0, cap_s = 0;
+  int64_t slots_s = 0;
   int32_t *a_nnz = nullptr, *a_col = nullptr;
   void* a_val = nullptr;
   double *diag = nullptr, *b = nullptr;
@@ -251,6 +258,16 @@ View make_view(const mps_ctx* c) {
   v.src = c->src;
   v.source = P.source;
   v.laplacian = P.laplacian;
+  if (P.skin > 0.0) {
+    v.ls = c->ls;
+    v.half_skin2 = 0.25 * P.skin * P.skin;
+    v.re_s2 = (P.re_lap + P.skin) * (P.re_lap + P.skin);
+    v.kpad_s = c->kpad_s;
+    v.cap_s = c->cap_s;
+    v.sk_list = c->sk_list;
+    v.sk_count = c->sk_count;
+    v.r_build = c->r_build;
+  }
   v.flags = c->flags;
   v.cellid = c->cellid;
   v.slot = c->slot;
@@ -334,6 +351,8 @@ mps_status check_params(const mps_params* P, int64_t n) {
   if (P->source != MPS_SRC_STD && P->pmode != MPS_PPE_CG) return MPS_E_ARG;
   if (P->laplacian != MPS_LAP_STD && P->laplacian != MPS_LAP_HL) return MPS_E_ARG;
   if (P->laplacian != MPS_LAP_STD && P->pmode != MPS_PPE_CG) return MPS_E_ARG;
+  if (!(P->skin >= 0.0) || !(P->skin < P->re_lap)) return MPS_E_ARG;
+  if (P->skin > 0.0 && !(P->cell_size >= P->re_lap + P->skin)) return MPS_E_ARG;
   int64_t nc = 1;
   for (int a = 0; a < P->dim; ++a) {
     if (P->grid_n[a] < 1 || P->grid_n[a] > 1023) return MPS_E_ARG;
@@ -483,9 +502,18 @@ struct Prof {
 };
 
 // a1 + a2 at the current state; leaves the context in the new sorted order.
+// With a skin the step first decides on the device whether to build: if so
+// the cell sort and a search at radius re_lap + skin write the superset
+// lists, if not the state is copied in its order; then the superset is
+// filtered to the exact lists at the step's positions.
 mps_status search(mps_ctx* c) {
   c->ppe_valid = false;
+  const bool keep = c->P.skin > 0.0;
   View v = make_view(c);
+  if (keep) {
+    Prof pr(c, MPS_KC_NEIGH);
+    launch_list_check(v, c->dim, c->s);
+  }
   {
     Prof pr(c, MPS_KC_SORT);
     launch_bin(v, c->dim, c->s);
@@ -495,9 +523,26 @@ mps_status search(mps_ctx* c) {
   v = make_view(c);
   {
     Prof pr(c, MPS_KC_NEIGH);
-    launch_neighbors(v, c->dim, c->P.precision, c->s);
+    if (keep) {
+      View vs = v;
+      vs.nb_list = c->sk_list;
+      vs.nb_count = c->sk_count;
+      vs.kpad = c->kpad_s;
+      vs.max_neigh = c->cap_s;
+      vs.re_lap2 = vs.re_s2;
+      launch_neighbors(vs, c->dim, c->P.precision, c->s);
+      launch_list_filter(v, c->dim, c->s);
+    } else {
+      launch_neighbors(v, c->dim, c->P.precision, c->s);
+    }
   }
   return MPS_OK;
+}
+
+// The next step builds its lists afresh (the state or its order changed
+// other than by a step).
+void force_build(mps_ctx* c) {
+  if (c->ls) launch_list_force(make_view(c), c->s);
 }
 
 // --------------------------------------------------------------- stages
@@ -807,6 +852,8 @@ mps_status redo_step(mps_ctx* c, int b, mps_step_stats* st) {
   HIPCHK(c, hipMemcpyAsync(c->status, c->status + 1 + b, sizeof(int32_t),
                            hipMemcpyDeviceToDevice, c->s));
   c->cur = b;
+  // the discarded steps may have rebuilt the lists in another order
+  force_build(c);
   if (st) st->cg_redone += 1;
   return one_step_polled(c, st);
 }
@@ -961,6 +1008,18 @@ mps_status mps_init(const mps_params* params, int64_t n, const double* pos, cons
   A(dalloc(&c->tile_sum, scan_tiles(c->ncell)));
   A(dalloc(&c->nb_count, n));
   A(dalloc(&c->nb_list, c->slots));
+  if (params->skin > 0.0) {
+    // superset capacity: the cap scaled by the volume of the larger ball,
+    // with a fifth more for density fluctuations
+    const double f = std::pow((params->re_lap + params->skin) / params->re_lap, c->dim);
+    c->cap_s = (int)std::ceil(1.2 * f * params->max_neigh);
+    c->kpad_s = (c->cap_s + TEAM - 1) / TEAM * TEAM;
+    c->slots_s = ((n + SLICE - 1) / SLICE) * (int64_t)c->kpad_s * SLICE;
+    A(dalloc(&c->sk_count, n));
+    A(dalloc(&c->sk_list, c->slots_s));
+    A(dalloc(&c->r_build, nv));
+    A(dalloc(&c->ls, 1));
+  }
   A(dalloc(&c->a_nnz, n));
   A(dalloc(&c->a_col, c->slots));
   {
@@ -1026,6 +1085,12 @@ mps_status mps_init(const mps_params* params, int64_t n, const double* pos, cons
   A(hipMemsetAsync(c->step_count, 0, sizeof(int32_t), s));
   A(hipMemsetAsync(c->sc, 0, sizeof(CGScalars), s));
   A(hipMemsetAsync(c->nb_count, 0, n * sizeof(int32_t), s));
+  if (c->ls) {
+    A(hipMemsetAsync(c->ls, 0, sizeof(ListState), s));
+    A(hipMemsetAsync(c->sk_count, 0, n * sizeof(int32_t), s));
+    A(hipMemsetAsync(c->r_build, 0, nv * sizeof(double), s));
+    force_build(c);
+  }
   A(hipMemsetAsync(c->a_nnz, 0, n * sizeof(int32_t), s));
   A(hipMemsetAsync(c->nstar, 0, n * sizeof(double), s));
   A(hipMemsetAsync(c->flags, 0, n, s));
@@ -1099,6 +1164,7 @@ mps_status mps_free(mps_ctx* c) {
                   c->nb_count,
                   c->nb_list, c->a_nnz, c->a_col, c->a_val, c->diag, c->b, c->r, c->z,
                   c->q, c->p_save, c->partA, c->partB, c->sc, c->status, c->step_count,
+                  c->sk_count, c->sk_list, c->r_build, c->ls,
                   c->counts,
                   c->nut, c->mu,
                   c->rho_o, c->nu_o,
@@ -1162,6 +1228,8 @@ mps_status mps_step(mps_ctx* c, int32_t nsteps, mps_step_stats* stats) {
   if (stats) std::memset(stats, 0, sizeof(*stats));
   mps_status res = MPS_OK;
   c->steps_ok = 0;
+  if (c->ls)
+    HIPCHK(c, hipMemsetAsync(&c->ls->builds, 0, sizeof(int32_t), c->s));
   if (c->P.pmode == MPS_WC_EOS) {
     // no host synchronisation between the steps: each step counts itself
     // on the device when it begins with a clean status, and once a step has
@@ -1204,6 +1272,13 @@ mps_status mps_step(mps_ctx* c, int32_t nsteps, mps_step_stats* stats) {
     stats->n_ghost = c->h_counts[1];
     stats->list_entries = c->h_counts[2];
     stats->ppe_nnz = c->h_counts[3];
+    stats->list_builds = nsteps;
+    if (c->ls) {
+      int32_t* hb = c->h_step_status + mps_ctx::NBUF + 1;
+      HIPCHK(c, hipMemcpyAsync(hb, &c->ls->builds, sizeof(int32_t), hipMemcpyDeviceToHost, c->s));
+      HIPCHK(c, hipStreamSynchronize(c->s));
+      stats->list_builds = *hb;
+    }
   }
   return res;
 }
@@ -1281,6 +1356,7 @@ mps_status mps_set_state(mps_ctx* c, const double* pos, const double* vel, const
     k_check_types<<<flat_blocks(c->n), 256, 0, c->s>>>(c->n, c->type[c->cur], c->status);
   }
   HIPCHK(c, hipMemsetAsync(c->pres[c->cur], 0, c->n * sizeof(double), c->s));
+  force_build(c);
   HIPCHK(c, hipGetLastError());
   c->poisoned = false;
   c->ppe_valid = false;
@@ -1422,6 +1498,7 @@ mps_status mps_tape_load(mps_ctx* c, int32_t slot) {
     launch_gather_orig(v, c->rho_o, c->rho_s[a], 1, 1, c->s);
     launch_gather_orig(v, c->nu_o, c->nu_l[a], 1, 1, c->s);
   }
+  force_build(c);
   c->ppe_valid = false;
   return MPS_OK;
 }
@@ -1435,6 +1512,7 @@ mps_status mps_step_adjoint(mps_ctx* c, const double* pos_bar, const double* vel
   if (c->P.source != MPS_SRC_STD) return fail(c, MPS_E_ARG, "adjoint needs the source of Eq. 13");
   if (c->P.laplacian != MPS_LAP_STD)
     return fail(c, MPS_E_ARG, "adjoint needs the Laplacian of Eq. 7");
+  if (c->P.skin > 0.0) return fail(c, MPS_E_ARG, "adjoint needs lists built every step (skin 0)");
   if (c->poisoned) return fail(c, MPS_E_POISONED, "context poisoned; call mps_set_state");
   const bool wc = c->P.pmode == MPS_WC_EOS;
   // forward recompute of the step's stages from the current (taped) state

@@ -75,6 +75,21 @@ struct CGScalars {
   double alp[2];
 };
 
+// Neighbour lists kept over several steps (skin > 0): the cell search
+// writes a superset list at radius re_lap + skin, and every step filters
+// it to the exact list at its own positions.  The superset is rebuilt (with
+// a fresh cell sort) when a particle has moved skin/2 or more since the
+// build, or left the grid; in between the particle order stays fixed.  One
+// record on the device, written by the check and decision kernels of a step.
+struct ListState {
+  unsigned long long disp2;  // largest squared displacement since the build
+                             // this step (bits of a non-negative double)
+  int32_t force;             // rebuild at the next decision
+  int32_t rebuild;           // decision of the running step
+  int32_t since;             // steps since the last build
+  int32_t builds;            // builds since the host last cleared it
+};
+
 // Grid caps of the CG kernels: every workgroup of one kernel sums all the
 // per-workgroup partials of the previous kernel, so their number is bounded.
 constexpr int CG_SPMV_BLOCKS = 2048;
@@ -123,6 +138,14 @@ struct View {
   int gamma_i, kernel, grad, clamp;
   int source;         // MPS_SRC_*: PPE source term
   int laplacian;      // MPS_LAP_*: Laplacian of pressure in the PPE
+  // lists kept over steps (null ls: a fresh list every step)
+  ListState* ls;
+  double half_skin2;  // (skin / 2)^2
+  double re_s2;       // (re_lap + skin)^2, the superset's radius
+  int kpad_s, cap_s;  // superset row capacity (slots, entries)
+  int32_t* sk_list;   // superset lists (sliced, kpad_s slots per row)
+  int32_t* sk_count;
+  double* r_build;    // sorted positions at the last build
   // sorted state, current buffers
   const double* pos;  double* pos_w;
   const double* vel;  double* vel_w;
@@ -415,6 +438,9 @@ const char* noctx_error();
 int launch_bin(const View& v, int dim, hipStream_t s);
 int launch_permute(const View& v, int dim, int precision, hipStream_t s);
 int launch_neighbors(const View& v, int dim, int precision, hipStream_t s);
+int launch_list_check(const View& v, int dim, hipStream_t s);
+int launch_list_filter(const View& v, int dim, hipStream_t s);
+int launch_list_force(const View& v, hipStream_t s);
 int launch_export_lists(const View& v, int32_t* cell_out, int32_t* count_out,
                         int32_t* list_out, int dim, hipStream_t s);
 int launch_predict(const View& v, int dim, int precision, hipStream_t s);

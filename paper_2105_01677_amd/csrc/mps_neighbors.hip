@@ -15,6 +15,10 @@
 
 namespace mps {
 
+// With lists kept over steps, the cell sort and the superset search run
+// only in the steps whose decision kernel asked for a build.
+__device__ inline bool skip_build(const View& v) { return v.ls && !v.ls->rebuild; }
+
 // Squared distance rounded term by term: (dx*dx + dy*dy) + dz*dz.  The
 // neighbour criterion d2 < re_lap^2 is evaluated on exactly this expression,
 // so the lists are reproducible bit for bit on any IEEE machine.
@@ -35,6 +39,7 @@ __device__ inline double dist2_exact(const double (&a)[DIM], const double (&b)[D
 // A particle outside the grid becomes a ghost and goes to cell ncell.
 template <int DIM>
 __global__ __launch_bounds__(BLOCK) void k_bin(View v, int8_t* type_cur) {
+  if (skip_build(v)) return;
   const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   const bool active = i < v.n;
   int c = v.ncell;
@@ -85,6 +90,7 @@ __global__ __launch_bounds__(BLOCK) void k_bin(View v, int8_t* type_cur) {
 // stay 0) and cover ncell + 2 cells, so the start of cell ncell + 1 comes
 // out as the total.
 __global__ __launch_bounds__(SCAN_NT) void k_scan_tiles(View v) {
+  if (skip_build(v)) return;
   constexpr int NW = SCAN_NT / WAVE, Q = SCAN_PER / 4;
   const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
   __shared__ int32_t wsum[NW];
@@ -135,6 +141,7 @@ __global__ __launch_bounds__(SCAN_NT) void k_scan_tiles(View v) {
 // in-tile start plus the sum of the earlier tiles' totals, which every
 // wavefront scans itself, 64 tiles at a time (one pass up to 262,144 cells).
 __global__ __launch_bounds__(BLOCK) void k_scatter(View v) {
+  if (skip_build(v)) return;
   const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   const int lane = threadIdx.x & (WAVE - 1);
   const bool part = i < v.n, cell = i < (int64_t)v.ncell + 2;
@@ -176,25 +183,35 @@ __global__ __launch_bounds__(BLOCK) void k_rank_permute(View v) {
   // more, so the failing step's input buffer survives the steps enqueued
   // behind it
   if (i >= v.n || *v.status) return;
-  const int c = v.cellid[i];
-  const int b = v.cell_start[c];
   const int32_t key = v.id[i];
+  // a step that keeps the lists keeps the order: a plain copy into the
+  // next buffer, with the cell each particle was binned in at the build
+  const bool build = !skip_build(v);
   int64_t k;
-  if (c == v.ncell) {
-    k = b + v.slot[i];
-  } else {
-    const int e = v.cell_start[c + 1];
-    int rank = 0;
-    // four members per step, all loads issued before the compares (a member
-    // past the cell end is read as the cell's first and not counted)
-    for (int m = b; m < e; m += 4) {
-      int32_t pm[4];
+  int32_t pc = GHOST_CELL;
+  if (build) {
+    const int c = v.cellid[i];
+    const int b = v.cell_start[c];
+    if (c == v.ncell) {
+      k = b + v.slot[i];
+    } else {
+      const int e = v.cell_start[c + 1];
+      int rank = 0;
+      // four members per step, all loads issued before the compares (a
+      // member past the cell end is read as the cell's first and not counted)
+      for (int m = b; m < e; m += 4) {
+        int32_t pm[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) pm[u] = v.perm[m + u < e ? m + u : b];
+        for (int u = 0; u < 4; ++u) pm[u] = v.perm[m + u < e ? m + u : b];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) rank += (m + u < e && v.id[pm[u]] < key) ? 1 : 0;
+        for (int u = 0; u < 4; ++u) rank += (m + u < e && v.id[pm[u]] < key) ? 1 : 0;
+      }
+      k = b + rank;
+      pc = pack_cell(c % v.nx, (c / v.nx) % v.ny, c / (v.nx * v.ny));
     }
-    k = b + rank;
+  } else {
+    k = i;
+    pc = v.pcell[i];
   }
   double x[DIM], u[DIM] = {};
   load_vec<DIM>(v.pos, i, x);
@@ -211,15 +228,14 @@ __global__ __launch_bounds__(BLOCK) void k_rank_permute(View v) {
     v.rho_s_w[k] = v.rho_s[i];
     v.nu_l_w[k] = v.nu_l[i];
   }
-  int32_t pc = GHOST_CELL;
   int ci[3] = {0, 0, 0};
-  if (c < v.ncell) {
-    ci[0] = c % v.nx;
-    ci[1] = (c / v.nx) % v.ny;
-    ci[2] = c / (v.nx * v.ny);
-    pc = pack_cell(ci[0], ci[1], ci[2]);
+  if (pc != GHOST_CELL) {
+    ci[0] = ucx(pc);
+    ci[1] = ucy(pc);
+    ci[2] = ucz(pc);
   }
   v.pcell[k] = pc;
+  if (build && v.r_build) store_vec<DIM>(v.r_build, k, x);
   if constexpr (MIXED) {
     float r[3] = {0.f, 0.f, 0.f};
 #pragma unroll
@@ -239,6 +255,7 @@ __global__ __launch_bounds__(BLOCK) void k_rank_permute(View v) {
 // appends hits in candidate order with a ballot, so the list order is fixed.
 template <int DIM>
 __global__ __launch_bounds__(BLOCK) void k_neighbors(View v) {
+  if (skip_build(v)) return;
   constexpr int NR = DIM == 3 ? 9 : 3;  // cell rows of the 3^DIM block
   const int64_t row = (int64_t)xcd_block() * ROWS_PER_BLOCK + threadIdx.x / TEAM;
   const int t = team_lane();
@@ -292,7 +309,124 @@ __global__ __launch_bounds__(BLOCK) void k_neighbors(View v) {
   if (t == 0) v.nb_count[row] = count;
 }
 
-// Export: lists in original order with original ids, ascending.
+// Lists kept over steps, start of a step: the largest squared
+// displacement of a particle since the build (positions are in the build's
+// order until the next build), and a forced build if a particle has left
+// the grid or is not finite.  One atomic per wavefront.
+template <int DIM>
+__global__ __launch_bounds__(BLOCK) void k_list_check(View v) {
+  const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  double d2 = 0.0;
+  bool force = false;
+  if (i < v.n && v.type[i] != MPS_GHOST) {
+    double x[DIM], xb[DIM];
+    load_vec<DIM>(v.pos, i, x);
+    load_vec<DIM>(v.r_build, i, xb);
+    const int nn[3] = {v.nx, v.ny, v.nz};
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+      const double f = floor((x[a] - v.lo[a]) * v.inv_cs);
+      if (!(f >= 0.0 && f < (double)nn[a])) force = true;  // also NaN
+      const double d = x[a] - xb[a];
+      d2 += d * d;
+    }
+    if (!(d2 < 1e300)) force = true;
+  }
+  for (int o = WAVE / 2; o > 0; o >>= 1) d2 = fmax(d2, __shfl_xor(d2, o, WAVE));
+  const bool anyf = __ballot(force) != 0;
+  if ((threadIdx.x & (WAVE - 1)) == 0) {
+    if (d2 > 0.0) atomicMax(&v.ls->disp2, (unsigned long long)__double_as_longlong(d2));
+    if (anyf) atomicOr(&v.ls->force, 1);
+  }
+}
+
+// The decision of the step (one thread): build when forced or when a
+// particle has moved skin/2 or more since the build (then no pair that is
+// closer than re_lap now was farther than re_lap + skin then).
+__global__ void k_list_decide(View v) {
+  if (threadIdx.x != 0) return;
+  ListState* ls = v.ls;
+  const double d2 = __longlong_as_double((long long)ls->disp2);
+  const int rb = ls->force || !(d2 < v.half_skin2);
+  ls->rebuild = rb;
+  ls->since = rb ? 0 : ls->since + 1;
+  ls->builds += rb;
+  ls->disp2 = 0ull;
+  ls->force = 0;
+}
+
+// The exact list of every particle from its superset row: the members with
+// d2 < re_lap^2 at the step's positions, d2 by the same term-by-term FP64
+// expression as the cell search, in the superset's order (one team per
+// particle, ballot compaction).  FILT_U entries per lane and step: their
+// position gathers are in flight together while the next step's superset
+// entries load (slot indices past the row clamped to its first slot).
+#ifndef FILT_U
+#define FILT_U 4
+#endif
+template <int DIM>
+__global__ __launch_bounds__(BLOCK) void k_list_filter(View v) {
+  constexpr int U = FILT_U;
+  const int64_t row = (int64_t)xcd_block() * ROWS_PER_BLOCK + threadIdx.x / TEAM;
+  const int t = team_lane();
+  if (row >= v.n) return;
+  const int cs = v.sk_count[row];
+  double xi[DIM];
+  load_vec<DIM>(v.pos, row, xi);
+  const int64_t s0 = sl_index(row, t, v.kpad_s), e0 = sl_index(row, 0, v.kpad);
+  const int ng = v.kpad_s / TEAM;
+  int32_t jn[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) jn[u] = v.sk_list[s0 + (int64_t)(u < ng ? u : 0) * WAVE];
+  int count = 0;
+  bool coinc = false;
+  for (int k0 = 0; t + k0 * TEAM < cs; k0 += U) {
+    int32_t j[U];
+    bool in[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      in[u] = t + (k0 + u) * TEAM < cs;
+      j[u] = in[u] ? jn[u] : (int32_t)row;
+    }
+    double xj[U][DIM];
+#pragma unroll
+    for (int u = 0; u < U; ++u) load_vec<DIM>(v.pos, j[u], xj[u]);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = k0 + U + u;
+      jn[u] = v.sk_list[s0 + (int64_t)(k < ng ? k : 0) * WAVE];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const double d2 = dist2_exact<DIM>(xi, xj[u]);
+      const bool hit = in[u] && d2 < v.re_lap2;
+      coinc = coinc || (hit && d2 == 0.0);
+      const uint32_t m = team_ballot(hit);
+      if (hit) {
+        const unsigned q = (unsigned)(count + __popc(m & ((1u << t) - 1u)));
+        if (q < (unsigned)v.max_neigh)
+          v.nb_list[e0 + (int64_t)(q / TEAM) * WAVE + (q % TEAM)] = j[u];
+      }
+      count += __popc(m);
+    }
+  }
+  if (coinc) atomicOr(v.status, ST_COINCIDENT);
+  if (count > v.max_neigh) {
+    if (t == 0) atomicOr(v.status, ST_OVERFLOW);
+    count = v.max_neigh;
+  }
+  if (t == 0) v.nb_count[row] = count;
+}
+
+__global__ void k_list_force(ListState* ls) {
+  if (threadIdx.x == 0) ls->force = 1;
+}
+
+// Export: lists in original order with original ids, ascending; the cell
+// of every particle at its current position (as the binning computes it:
+// with lists kept over steps the particles keep the cells of the last
+// build between builds).
+template <int DIM>
 __global__ __launch_bounds__(BLOCK) void k_export_lists(View v, int32_t* cell_out,
                                                         int32_t* count_out,
                                                         int32_t* list_out) {
@@ -302,8 +436,22 @@ __global__ __launch_bounds__(BLOCK) void k_export_lists(View v, int32_t* cell_ou
   const int c = v.nb_count[k];
   if (count_out) count_out[o] = c;
   if (cell_out) {
-    const int32_t pc = v.pcell[k];
-    cell_out[o] = pc == GHOST_CELL ? -1 : ucx(pc) + v.nx * (ucy(pc) + v.ny * ucz(pc));
+    int cell = -1;
+    if (v.type[k] != MPS_GHOST) {
+      double x[DIM];
+      load_vec<DIM>(v.pos, k, x);
+      const int nn[3] = {v.nx, v.ny, v.nz};
+      int ci[3] = {0, 0, 0};
+      bool in = true;
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) {
+        const double f = floor((x[a] - v.lo[a]) * v.inv_cs);
+        if (!(f >= 0.0 && f < (double)nn[a])) in = false;
+        else ci[a] = (int)f;
+      }
+      if (in) cell = ci[0] + v.nx * (ci[1] + v.ny * ci[2]);
+    }
+    cell_out[o] = cell;
   }
   if (!list_out) return;
   int32_t* row = list_out + o * v.max_neigh;
@@ -351,10 +499,29 @@ int launch_neighbors(const View& v, int dim, int precision, hipStream_t s) {
   return 0;
 }
 
+int launch_list_check(const View& v, int dim, hipStream_t s) {
+  if (dim == 2) k_list_check<2><<<nblk(v.n, BLOCK), BLOCK, 0, s>>>(v);
+  else k_list_check<3><<<nblk(v.n, BLOCK), BLOCK, 0, s>>>(v);
+  k_list_decide<<<1, 64, 0, s>>>(v);
+  return 0;
+}
+
+int launch_list_filter(const View& v, int dim, hipStream_t s) {
+  const unsigned nb = nblk(v.n, ROWS_PER_BLOCK);
+  if (dim == 2) k_list_filter<2><<<nb, BLOCK, 0, s>>>(v);
+  else k_list_filter<3><<<nb, BLOCK, 0, s>>>(v);
+  return 0;
+}
+
+int launch_list_force(const View& v, hipStream_t s) {
+  k_list_force<<<1, 64, 0, s>>>(v.ls);
+  return 0;
+}
+
 int launch_export_lists(const View& v, int32_t* cell_out, int32_t* count_out,
                         int32_t* list_out, int dim, hipStream_t s) {
-  (void)dim;
-  k_export_lists<<<nblk(v.n, BLOCK), BLOCK, 0, s>>>(v, cell_out, count_out, list_out);
+  if (dim == 2) k_export_lists<2><<<nblk(v.n, BLOCK), BLOCK, 0, s>>>(v, cell_out, count_out, list_out);
+  else k_export_lists<3><<<nblk(v.n, BLOCK), BLOCK, 0, s>>>(v, cell_out, count_out, list_out);
   return 0;
 }
 

@@ -40,6 +40,7 @@ class Params(C.Structure):
         ("gamma", C.c_double), ("alpha", C.c_double), ("cg_tol", C.c_double),
         ("grid_lo", C.c_double * 3), ("cell_size", C.c_double),
         ("smagorinsky_cs", C.c_double), ("source", C.c_int32), ("laplacian", C.c_int32),
+        ("skin", C.c_double),
     ]
 
 
@@ -48,7 +49,7 @@ class StepStats(C.Structure):
                 ("cg_iters_total", C.c_int64), ("cg_relres_last", C.c_double),
                 ("n_surface", C.c_int64), ("n_ghost", C.c_int64),
                 ("list_entries", C.c_int64), ("ppe_nnz", C.c_int64),
-                ("cg_redone", C.c_int32)]
+                ("cg_redone", C.c_int32), ("list_builds", C.c_int32)]
 
 
 _lib = None
@@ -119,6 +120,7 @@ def make_params(p: dict) -> Params:
     o.smagorinsky_cs = float(p.get("smag_cs", 0.0))
     o.source = int(p.get("source", 0))
     o.laplacian = int(p.get("laplacian", 0))
+    o.skin = float(p.get("skin", 0.0))
     for a in range(3):
         o.g[a] = float(p["g"][a])
         o.grid_lo[a] = float(p["grid_lo"][a])
@@ -233,7 +235,7 @@ class MPS:
                     "cg_iters_total": s.cg_iters_total, "cg_relres_last": s.cg_relres_last,
                     "n_surface": s.n_surface, "n_ghost": s.n_ghost,
                     "list_entries": s.list_entries, "ppe_nnz": s.ppe_nnz,
-                    "cg_redone": s.cg_redone}
+                    "cg_redone": s.cg_redone, "list_builds": s.list_builds}
 
     def step(self, nsteps: int = 1, *, allow_noconv=False) -> dict:
         st, stats = self.step_status(nsteps)

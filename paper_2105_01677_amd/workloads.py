@@ -55,7 +55,7 @@ def default_params(dim: int, l0: float, *, re_n_over_l0: float = 2.1,
         rho=rho, nu=nu, g=gvec, dt=dt, beta=0.97, c0=c0, gamma=7.0,
         alpha=1e-7, cg_tol=1e-9, cg_maxit=10000, max_neigh=300,
         pmode=pmode, kernel=kernel, precision=precision, grad=GRAD_STD,
-        clamp=1, smag_cs=0.0, cg_pipelined=1, source=SRC_STD, laplacian=LAP_STD,
+        clamp=1, smag_cs=0.0, cg_pipelined=1, source=SRC_STD, laplacian=LAP_STD, skin=0.0,
         grid_lo=[0.0, 0.0, 0.0], grid_n=[1, 1, 1], cell_size=0.0,
     )
 
@@ -136,6 +136,21 @@ def _set_grid(params, pos, l0, ni, nl, headroom_cells):
         lo[a] = lo_a
         n[a] = int(math.ceil((hi_a - lo_a) / cs))
     params["grid_lo"], params["grid_n"], params["cell_size"] = lo, n, cs
+
+
+def with_skin(w: Workload, skin_over_l0: float) -> Workload:
+    """The same workload with neighbour lists kept over steps: a skin of
+    skin_over_l0 * l0 and grid cells enlarged to re_lap + skin (same lower
+    corner, at least the same extent)."""
+    prm = dict(w.params)
+    skin = skin_over_l0 * prm["l0"]
+    cs = (prm["re_lap"] + skin) * (1.0 + 2.0 ** -20)
+    ext = [prm["grid_n"][a] * prm["cell_size"] for a in range(3)]
+    prm["grid_n"] = [max(1, int(math.ceil(ext[a] / cs))) if a < prm["dim"] else 1
+                     for a in range(3)]
+    prm["cell_size"] = cs
+    prm["skin"] = skin
+    return dataclasses.replace(w, params=prm)
 
 
 def wc_dt(l0: float, c0: float, dt: float) -> float:

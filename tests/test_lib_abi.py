@@ -37,10 +37,13 @@ def test_params_layout():
     from paper_2105_01677_amd import mps
     P = mps.Params
     assert P.l0.offset == 48          # 12 int32 before the doubles
-    assert ctypes.sizeof(P) == 48 + 8 * 19 + 8   # + int32 source, padded
-    assert P.source.offset == 48 + 8 * 19
+    assert P.source.offset == 48 + 8 * 19      # then int32 laplacian, double skin
+    assert P.laplacian.offset == P.source.offset + 4
+    assert P.skin.offset == 48 + 8 * 20
+    assert ctypes.sizeof(P) == 48 + 8 * 21
     assert ctypes.sizeof(mps.StepStats) == 64
     assert mps.StepStats.cg_redone.offset == 56
+    assert mps.StepStats.list_builds.offset == 60
 
 
 def test_struct_layouts_match_the_c_header(tmp_path):
