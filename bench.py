@@ -38,7 +38,8 @@ def log(*a):
 
 
 def algorithmic_bytes(cls: str, n: int, list_entries: int, nnz: int, dim: int,
-                      mixed: bool, wc: bool, pipelined: bool = True) -> float:
+                      mixed: bool, wc: bool, pipelined: bool = True,
+                      two_level: bool = False) -> float:
     """HBM bytes one launch of a kernel class must move: each particle's own
     state once, its list entries (4 B) and matrix row (column 4 B + value
     4/8 B).  Gathers of neighbour data are cache hits after the cell sort
@@ -46,15 +47,19 @@ def algorithmic_bytes(cls: str, n: int, list_entries: int, nnz: int, dim: int,
     (row length, 7 FP64 vectors read, 6 written) or, with pipelined=False,
     the SpMV kernel of the two-kernel CG; cg_update is the partial-sum
     reduction of the split pipelined schedule or, with pipelined=False, the
-    vector update of the two-kernel CG."""
+    vector update of the two-kernel CG.  With the two-level preconditioner
+    the iteration also reads and writes u, q and w; its cell-level kernels
+    (the cg_update class then) are not given a byte count."""
     vec = 8 * (2 if dim == 2 else 4)       # stored FP64 vector
     f4 = 16 if mixed else 0                # FP32 relative position copy
     val = 4 if mixed else 8
     if cls == "cg_spmv":
         if pipelined:
-            return n * (4 + 13 * 8) + nnz * (4 + val)
+            return n * (4 + (19 if two_level else 13) * 8) + nnz * (4 + val)
         return n * (4 + 5 * 8) + nnz * (4 + val)
     if cls == "cg_update":
+        if two_level:
+            return float("nan")
         if pipelined:
             # k_pcg_reduce of the split schedule: reads the per-workgroup
             # partials of the iteration (one double4 per 32-row workgroup)
@@ -231,9 +236,12 @@ def kernel_bandwidth(w, r, mixed, wc):
             continue
         avg = ms / nl
         b = algorithmic_bytes(k, w.n, s["list_entries"], s["ppe_nnz"], w.params["dim"], mixed, wc,
-                              bool(w.params.get("cg_pipelined", 1)))
-        out[k] = {"avg_launch_us": 1e3 * avg, "launches": nl, "algorithmic_GBps": b / (avg * 1e-3) / 1e9,
-                  "hbm_frac": b / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS}
+                              bool(w.params.get("cg_pipelined", 1)),
+                              w.params.get("precond", 0) == 1)
+        gbs = b / (avg * 1e-3) / 1e9
+        out[k] = {"avg_launch_us": 1e3 * avg, "launches": nl,
+                  "algorithmic_GBps": None if gbs != gbs else gbs,
+                  "hbm_frac": None if gbs != gbs else gbs / HBM_PEAK_GBS}
     return out
 
 
@@ -252,7 +260,8 @@ def run_3d(name, w, steps, warmup):
            "kernels": kernel_bandwidth(w, br, mixed, w.params["pmode"] == 1)}
     log(name, {k: v for k, v in res.items() if k != "kernels"})
     for k, v in res["kernels"].items():
-        log(f"   {k:10s} {v['avg_launch_us']:9.2f} us  {v['algorithmic_GBps']:8.1f} GB/s")
+        gb = v["algorithmic_GBps"]
+        log(f"   {k:10s} {v['avg_launch_us']:9.2f} us  " + (f"{gb:8.1f} GB/s" if gb else "   -"))
     return res
 
 
@@ -493,6 +502,13 @@ def main():
         runs_3d["dam_break_3d_l0=0.007_fp64_plain"] = f64
         runs_3d["dam_break_3d_l0=0.007"]["mixed_vs_fp64_plain"] = (
             runs_3d["dam_break_3d_l0=0.007"]["value"] / f64["value"])
+        # the two-level preconditioner (cell aggregates, Chebyshev steps on
+        # the cell operator) against Jacobi on the same case
+        w3p = W.config("dam_break_3d_441282", precision=W.MIXED)
+        w3p.params.update(cg_pipelined=1, precond=W.PC_TWO_LEVEL)
+        t3 = run_3d("dam_break_3d_two_level", w3p, args.steps_3d, 2)
+        t3["vs_jacobi"] = t3["value"] / runs_3d["dam_break_3d_l0=0.007"]["value"]
+        runs_3d["dam_break_3d_l0=0.007_two_level"] = t3
         # lists kept over steps with a skin of 0.2 l0 (rebuilt when a
         # particle has moved 0.1 l0 since the build)
         w3k = W.with_skin(W.config("dam_break_3d_441282", precision=W.MIXED), 0.2)
@@ -501,6 +517,11 @@ def main():
         w5 = W.config("two_phase_3d_2314616", precision=W.MIXED)
         w5.params["cg_pipelined"] = 1
         runs_3d["two_phase_3d_l0=0.005"] = run_3d("two_phase_3d", w5, max(args.steps_3d // 2, 2), 1)
+        w5p = W.config("two_phase_3d_2314616", precision=W.MIXED)
+        w5p.params.update(cg_pipelined=1, precond=W.PC_TWO_LEVEL)
+        t5 = run_3d("two_phase_3d_two_level", w5p, max(args.steps_3d // 2, 2), 1)
+        t5["vs_jacobi"] = t5["value"] / runs_3d["two_phase_3d_l0=0.005"]["value"]
+        runs_3d["two_phase_3d_l0=0.005_two_level"] = t5
         if not args.no_adjoint:
             wa = W.config("two_phase_3d_2314616", precision=W.MIXED)
             runs_3d["two_phase_3d_l0=0.005"]["adjoint"] = run_adjoint(wa, 50, 50)

@@ -83,6 +83,12 @@ enum { MPS_SRC_STD = 0, MPS_SRC_HS = 1, MPS_SRC_HS_ECS = 2 };
  * tends to the exact Laplacian of a quadratic field in two and three
  * dimensions as re_lap/l0 grows) */
 enum { MPS_LAP_STD = 0, MPS_LAP_HL = 1 };
+/* Preconditioner of the pipelined CG: the diagonal of A (Jacobi); or an
+ * additive two-level preconditioner D^-1 + P C P^T, P the aggregation of
+ * the pressure unknowns by background grid cell, C three Chebyshev steps on
+ * the cell-level operator P^T A P (for the large systems the paper solves
+ * by ICCG: same solution, fewer iterations) */
+enum { MPS_PC_JACOBI = 0, MPS_PC_TWO_LEVEL = 1 };
 
 typedef struct {
   int32_t dim;              /* 2 or 3 */
@@ -135,6 +141,8 @@ typedef struct {
                                superset row beyond 1.2 max_neigh ((re_lap +
                                skin)/re_lap)^dim entries is reported as
                                MPS_E_NEIGH_OVERFLOW.  The adjoint needs 0. */
+  int32_t precond;          /* MPS_PC_*: preconditioner of the CG (the
+                               two-level one needs cg_pipelined = 1) */
 } mps_params;
 
 typedef struct {

@@ -61,6 +61,7 @@ struct mps_ctx {
   int32_t *sk_count = nullptr, *sk_list = nullptr;
   double* r_build = nullptr;
   ListState* ls = nullptr;
+  double* red_blk = nullptr;   // per-workgroup maxima (list check, coarse bound)
   int kpad_s = 0, cap_s = 0;
   int64_t slots_s = 0;
   int32_t *a_nnz = nullptr, *a_col = nullptr;
@@ -78,6 +79,10 @@ struct mps_ctx {
   double* mu = nullptr;
   double* partA = nullptr;
   double* partB = nullptr;
+  // two-level preconditioner: cell operator and cell vectors, u, q, w
+  double *ac = nullptr, *rc = nullptr, *xc = nullptr, *dc[2] = {nullptr, nullptr};
+  double* cwork = nullptr;
+  double *pl_u = nullptr, *pl_q = nullptr, *pl_w = nullptr;
   double *pl_z = nullptr, *pl_s = nullptr, *pl_m[2] = {nullptr, nullptr},
          *pl_part[2] = {nullptr, nullptr}, *pl_part2[2] = {nullptr, nullptr};
   int nspmv = 0, nupd = 0, nasmb = 0, npcg = 0, pcg_fused = 0, pcg_pred = 0;
@@ -268,6 +273,7 @@ View make_view(const mps_ctx* c) {
     v.sk_count = c->sk_count;
     v.r_build = c->r_build;
   }
+  v.red_blk = c->red_blk;
   v.flags = c->flags;
   v.cellid = c->cellid;
   v.slot = c->slot;
@@ -301,6 +307,15 @@ View make_view(const mps_ctx* c) {
   v.pl_part2[0] = c->pl_part2[0];
   v.pl_part2[1] = c->pl_part2[1];
   v.npcg2 = std::min(c->npcg, PCG_SPLIT_G);
+  v.ac = c->ac;
+  v.cwork = c->cwork;
+  v.rc = c->rc;
+  v.xc = c->xc;
+  v.dc[0] = c->dc[0];
+  v.dc[1] = c->dc[1];
+  v.pl_u = c->pl_u;
+  v.pl_q = c->pl_q;
+  v.pl_w = c->pl_w;
   v.nspmv = c->nspmv;
   v.nasmb = c->nasmb;
   v.nupd = c->nupd;
@@ -352,6 +367,9 @@ mps_status check_params(const mps_params* P, int64_t n) {
   if (P->laplacian != MPS_LAP_STD && P->laplacian != MPS_LAP_HL) return MPS_E_ARG;
   if (P->laplacian != MPS_LAP_STD && P->pmode != MPS_PPE_CG) return MPS_E_ARG;
   if (!(P->skin >= 0.0) || !(P->skin < P->re_lap)) return MPS_E_ARG;
+  if (P->precond != MPS_PC_JACOBI && P->precond != MPS_PC_TWO_LEVEL) return MPS_E_ARG;
+  if (P->precond == MPS_PC_TWO_LEVEL && (P->cg_pipelined != 1 || P->pmode != MPS_PPE_CG))
+    return MPS_E_ARG;
   if (P->skin > 0.0 && !(P->cell_size >= P->re_lap + P->skin)) return MPS_E_ARG;
   int64_t nc = 1;
   for (int a = 0; a < P->dim; ++a) {
@@ -553,9 +571,12 @@ void enqueue_assemble(mps_ctx* c, const View& v, const double* rhs, bool zero_x0
     launch_assemble(v, c->dim, c->P.precision, rhs, zero_x0, c->s);
   }
   if (c->P.cg_pipelined) {
-    // the CG start (w0 = A u0 and its dot products) is timed with the assembly
+    // the CG start (w0 = A u0 and its dot products; two-level: the cell
+    // operator and the coarse corrections of r0 and w0) is timed with the
+    // assembly
     Prof pr(c, MPS_KC_ASSEMBLE);
-    launch_pcg_setup(v, c->P.precision, c->s);
+    if (c->ac) launch_coarse_assemble(v, c->dim, c->P.precision, c->s);
+    launch_pcg_setup(v, c->P.precision, c->dim, c->s);
   }
 }
 
@@ -590,8 +611,15 @@ void enqueue_cg(mps_ctx* c, int iters) {
         Prof pr(c, MPS_KC_CG_UPDATE, true);
         launch_pcg_reduce(v, it & 1, c->s);
       }
-      Prof pr(c, MPS_KC_CG_SPMV, true);
-      launch_pcg_iter(v, c->P.precision, it & 1, c->s);
+      {
+        Prof pr(c, MPS_KC_CG_SPMV, true);
+        launch_pcg_iter(v, c->P.precision, it & 1, c->s);
+      }
+      if (c->ac) {
+        // two-level: the coarse part of m = M^-1 w for the next iteration
+        Prof pr(c, MPS_KC_CG_UPDATE);
+        launch_coarse_correct(v, c->dim, c->pl_w, c->pl_m[(it & 1) ^ 1], c->s);
+      }
     }
     return;
   }
@@ -1048,8 +1076,24 @@ mps_status mps_init(const mps_params* params, int64_t n, const double* pos, cons
   c->nupd = cg_update_blocks(n);
   A(dalloc(&c->partA, (size_t)std::max({c->nspmv, c->nupd, c->nasmb}) * 4));
   A(dalloc(&c->partB, (size_t)c->nspmv));
-  c->pcg_fused = pcg_blocks(n, true) <= pcg_fused_capacity() ? 1 : 0;
+  c->pcg_fused =
+      pcg_blocks(n, true) <= pcg_fused_capacity(params->precond == MPS_PC_TWO_LEVEL) ? 1 : 0;
   c->npcg = pcg_blocks(n, c->pcg_fused != 0);
+  if (params->skin > 0.0 || params->precond == MPS_PC_TWO_LEVEL)
+    A(dalloc(&c->red_blk, std::max<int64_t>((n + BLOCK - 1) / BLOCK,
+                                            (c->ncell + BLOCK - 1) / BLOCK)));
+  if (params->precond == MPS_PC_TWO_LEVEL) {
+    const int ns = c->dim == 3 ? 27 : 9;
+    A(dalloc(&c->ac, (size_t)c->ncell * ns));
+    A(dalloc(&c->cwork, (size_t)2 * ((n + ROWS_PER_BLOCK - 1) / ROWS_PER_BLOCK) * ns));
+    A(dalloc(&c->rc, c->ncell));
+    A(dalloc(&c->xc, c->ncell));
+    A(dalloc(&c->dc[0], c->ncell));
+    A(dalloc(&c->dc[1], c->ncell));
+    A(dalloc(&c->pl_u, n));
+    A(dalloc(&c->pl_q, n));
+    A(dalloc(&c->pl_w, n));
+  }
   if (params->cg_pipelined) {
     A(dalloc(&c->pl_z, n));
     A(dalloc(&c->pl_s, n));
@@ -1164,7 +1208,9 @@ mps_status mps_free(mps_ctx* c) {
                   c->nb_count,
                   c->nb_list, c->a_nnz, c->a_col, c->a_val, c->diag, c->b, c->r, c->z,
                   c->q, c->p_save, c->partA, c->partB, c->sc, c->status, c->step_count,
-                  c->sk_count, c->sk_list, c->r_build, c->ls,
+                  c->sk_count, c->sk_list, c->r_build, c->ls, c->red_blk,
+                  c->ac, c->cwork, c->rc, c->xc, c->dc[0], c->dc[1], c->pl_u, c->pl_q,
+                  c->pl_w,
                   c->counts,
                   c->nut, c->mu,
                   c->rho_o, c->nu_o,

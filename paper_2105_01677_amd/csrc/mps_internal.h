@@ -73,6 +73,9 @@ struct CGScalars {
   // by workgroup 0 of iteration k and read by iteration k + 1 only
   double gam[2];
   double alp[2];
+  // two-level preconditioner: Gershgorin bound of D_c^-1 A_c (bits of a
+  // non-negative double; written after the coarse assembly)
+  unsigned long long cg_bits;
 };
 
 // Neighbour lists kept over several steps (skin > 0): the cell search
@@ -82,8 +85,6 @@ struct CGScalars {
 // build, or left the grid; in between the particle order stays fixed.  One
 // record on the device, written by the check and decision kernels of a step.
 struct ListState {
-  unsigned long long disp2;  // largest squared displacement since the build
-                             // this step (bits of a non-negative double)
   int32_t force;             // rebuild at the next decision
   int32_t rebuild;           // decision of the running step
   int32_t since;             // steps since the last build
@@ -146,6 +147,18 @@ struct View {
   int32_t* sk_list;   // superset lists (sliced, kpad_s slots per row)
   int32_t* sk_count;
   double* r_build;    // sorted positions at the last build
+  double* red_blk;    // per-workgroup maxima of a step's order-free reductions
+                      // (list displacement, coarse Gershgorin bound)
+  // two-level preconditioner of the pipelined CG (null ac: Jacobi)
+  double* ac;         // cell-level operator P^T A P, 3^DIM stencil slots,
+                      // slot-major: ac[slot * ncell + cell]
+  double* cwork;      // partial cell rows of workgroups (2 x rows/32 x 3^DIM)
+  double* rc;         // cell residual of the Chebyshev steps
+  double* xc;         // cell correction
+  double* dc[2];      // Chebyshev directions (double buffered)
+  double* pl_u;       // u = M^-1 r, q, w (stored: M is not diagonal)
+  double* pl_q;
+  double* pl_w;
   // sorted state, current buffers
   const double* pos;  double* pos_w;
   const double* vel;  double* vel_w;
@@ -453,10 +466,16 @@ int launch_assemble(const View& v, int dim, int precision, const double* rhs_sor
 int launch_cg_spmv(const View& v, int precision, hipStream_t s);
 int launch_cg_update(const View& v, hipStream_t s);
 int pcg_blocks(int64_t n, bool fused);
-int pcg_fused_capacity();
-int launch_pcg_setup(const View& v, int precision, hipStream_t s);
+int pcg_fused_capacity(bool two);
+int launch_pcg_setup(const View& v, int precision, int dim, hipStream_t s);
 int launch_pcg_iter(const View& v, int precision, int parity, hipStream_t s);
 int launch_pcg_reduce(const View& v, int parity, hipStream_t s);
+// two-level preconditioner: the cell operator after the assembly, and
+// target += P C P^T src on the pressure unknowns (restriction, Chebyshev
+// steps, prolongation)
+int launch_coarse_assemble(const View& v, int dim, int precision, hipStream_t s);
+int launch_coarse_correct(const View& v, int dim, const double* src, double* target,
+                          hipStream_t s);
 int launch_gradient(const View& v, int dim, int precision, hipStream_t s);
 int launch_scatter_orig(const View& v, const double* src, double* dst, int comps,
                         int stride, hipStream_t s);

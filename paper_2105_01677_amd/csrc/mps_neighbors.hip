@@ -311,18 +311,19 @@ __global__ __launch_bounds__(BLOCK) void k_neighbors(View v) {
 
 // Lists kept over steps, start of a step: the largest squared
 // displacement of a particle since the build (positions are in the build's
-// order until the next build), and a forced build if a particle has left
-// the grid or is not finite.  One atomic per wavefront.
+// order until the next build), infinite if a particle has left the grid or
+// is not finite; one maximum per workgroup (no atomics: device-scope
+// atomics on one address serialise across the chip).
 template <int DIM>
 __global__ __launch_bounds__(BLOCK) void k_list_check(View v) {
   const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   double d2 = 0.0;
-  bool force = false;
   if (i < v.n && v.type[i] != MPS_GHOST) {
     double x[DIM], xb[DIM];
     load_vec<DIM>(v.pos, i, x);
     load_vec<DIM>(v.r_build, i, xb);
     const int nn[3] = {v.nx, v.ny, v.nz};
+    bool force = false;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
       const double f = floor((x[a] - v.lo[a]) * v.inv_cs);
@@ -330,28 +331,38 @@ __global__ __launch_bounds__(BLOCK) void k_list_check(View v) {
       const double d = x[a] - xb[a];
       d2 += d * d;
     }
-    if (!(d2 < 1e300)) force = true;
+    if (force || !(d2 < 1e300)) d2 = __builtin_inf();
   }
   for (int o = WAVE / 2; o > 0; o >>= 1) d2 = fmax(d2, __shfl_xor(d2, o, WAVE));
-  const bool anyf = __ballot(force) != 0;
-  if ((threadIdx.x & (WAVE - 1)) == 0) {
-    if (d2 > 0.0) atomicMax(&v.ls->disp2, (unsigned long long)__double_as_longlong(d2));
-    if (anyf) atomicOr(&v.ls->force, 1);
+  __shared__ double sh[BLOCK / WAVE];
+  if ((threadIdx.x & (WAVE - 1)) == 0) sh[threadIdx.x / WAVE] = d2;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = sh[0];
+    for (int k = 1; k < BLOCK / WAVE; ++k) m = fmax(m, sh[k]);
+    v.red_blk[blockIdx.x] = m;
   }
 }
 
-// The decision of the step (one thread): build when forced or when a
-// particle has moved skin/2 or more since the build (then no pair that is
-// closer than re_lap now was farther than re_lap + skin then).
-__global__ void k_list_decide(View v) {
+// The decision of the step (one workgroup over the workgroup maxima):
+// build when forced or when a particle has moved skin/2 or more since the
+// build (then no pair that is closer than re_lap now was farther than
+// re_lap + skin then).
+constexpr int DECIDE_NT = 1024;
+__global__ __launch_bounds__(DECIDE_NT) void k_list_decide(View v, int nblk) {
+  double m = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += DECIDE_NT) m = fmax(m, v.red_blk[b]);
+  for (int o = WAVE / 2; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, WAVE));
+  __shared__ double sh[DECIDE_NT / WAVE];
+  if ((threadIdx.x & (WAVE - 1)) == 0) sh[threadIdx.x / WAVE] = m;
+  __syncthreads();
   if (threadIdx.x != 0) return;
+  for (int k = 0; k < DECIDE_NT / WAVE; ++k) m = fmax(m, sh[k]);
   ListState* ls = v.ls;
-  const double d2 = __longlong_as_double((long long)ls->disp2);
-  const int rb = ls->force || !(d2 < v.half_skin2);
+  const int rb = ls->force || !(m < v.half_skin2);
   ls->rebuild = rb;
   ls->since = rb ? 0 : ls->since + 1;
   ls->builds += rb;
-  ls->disp2 = 0ull;
   ls->force = 0;
 }
 
@@ -500,9 +511,10 @@ int launch_neighbors(const View& v, int dim, int precision, hipStream_t s) {
 }
 
 int launch_list_check(const View& v, int dim, hipStream_t s) {
-  if (dim == 2) k_list_check<2><<<nblk(v.n, BLOCK), BLOCK, 0, s>>>(v);
-  else k_list_check<3><<<nblk(v.n, BLOCK), BLOCK, 0, s>>>(v);
-  k_list_decide<<<1, 64, 0, s>>>(v);
+  const unsigned nb = nblk(v.n, BLOCK);
+  if (dim == 2) k_list_check<2><<<nb, BLOCK, 0, s>>>(v);
+  else k_list_check<3><<<nb, BLOCK, 0, s>>>(v);
+  k_list_decide<<<1, DECIDE_NT, 0, s>>>(v, (int)nb);
   return 0;
 }
 

@@ -289,6 +289,7 @@ __global__ __launch_bounds__(BLOCK) void k_assemble(View v, const double* rhs, i
       sc->converged = 0;
       sc->iter = 0;
       sc->nasm = gridDim.x;
+      sc->cg_bits = 0ull;
     }
   }
 }
@@ -508,7 +509,7 @@ __global__ __launch_bounds__(RED_BLOCK) void k_pcg_start(View v) {
   pcg_start_scalars(v, tot, true);
 }
 
-template <class VT, bool FUSED>
+template <class VT, bool FUSED, bool TWO>
 __global__ __launch_bounds__(pcg_nt<FUSED>()) void k_pcg_setup(View v) {
   constexpr int NT = pcg_nt<FUSED>();
   CGScalars* sc = v.sc;
@@ -530,7 +531,9 @@ __global__ __launch_bounds__(pcg_nt<FUSED>()) void k_pcg_setup(View v) {
     return;
   }
   const VT* __restrict__ aval = reinterpret_cast<const VT*>(v.a_val);
-  const double* __restrict__ u0 = v.z;  // D^-1 r0, written by the assembly
+  // u0 = M^-1 r0: D^-1 r0 written by the assembly (plus, two-level, the
+  // coarse correction added before this kernel)
+  const double* __restrict__ u0 = v.z;
   double gam = 0.0, del = 0.0, rr2 = 0.0;
   if (row < v.n) {
     double s = row_dot<4>(v.a_col, aval, row, v.a_nnz[row], v.kpad, t,
@@ -539,10 +542,16 @@ __global__ __launch_bounds__(pcg_nt<FUSED>()) void k_pcg_setup(View v) {
     if (t == 0) {
       const double dg = v.diag[row], u = u0[row], r = v.r[row];
       const double w = dg * u + s;
+      // m0 = D^-1 w0 (two-level: its coarse part is added after this kernel)
       v.pl_m[0][row] = w / dg;
       v.pl_z[row] = 0.0;
       v.pl_s[row] = 0.0;
       v.pd[0][row] = 0.0;
+      if constexpr (TWO) {
+        v.pl_u[row] = u;
+        v.pl_q[row] = 0.0;
+        v.pl_w[row] = w;
+      }
       gam = r * u;
       del = w * u;
       rr2 = r * r;
@@ -602,7 +611,7 @@ __global__ __launch_bounds__(RED2_BLOCK) void k_pcg_reduce(View v) {
 // loads then wait for the row length).  Without it every lane loads its
 // first U slots whatever the row length, which keeps the load chain short
 // but reads padding for rows with few or no entries (dummy particles).
-template <class VT, int PAR, bool FUSED, bool PRED>
+template <class VT, int PAR, bool FUSED, bool PRED, bool TWO>
 __global__ __launch_bounds__(pcg_nt<FUSED>()) void k_pcg_iter(View v) {
   constexpr int U = CG_UNROLL;
   constexpr int NT = pcg_nt<FUSED>();
@@ -654,6 +663,13 @@ __global__ __launch_bounds__(pcg_nt<FUSED>()) void k_pcg_iter(View v) {
   const double* optr = t == 0 ? v.diag : t == 1 ? M : t == 2 ? v.pl_z : t == 3 ? v.pl_s
                        : t == 4 ? v.pd[0] : t == 5 ? v.r : v.p;
   const double ov = optr[rc];
+  // two-level: u = M^-1 r, q = M^-1 s and w are recurrences of their own
+  double o_u = 0.0, o_q = 0.0, o_w = 0.0;
+  if constexpr (TWO) {
+    o_u = v.pl_u[rc];
+    o_q = v.pl_q[rc];
+    o_w = v.pl_w[rc];
+  }
   // a launch after convergence ends here, without waiting for the loads
   if (conv) return;
   // every load above is issued before any of them is waited for: without
@@ -695,23 +711,47 @@ __global__ __launch_bounds__(pcg_nt<FUSED>()) void k_pcg_iter(View v) {
   s += row_dot<4>(v.a_col, aval, rc, nnz, v.kpad, t + U * TEAM,
                   [&](int32_t j) { return M[j]; });
   s = team_sum(s);
-  const double w = o_d * o_m;
-  const double z = (w + s) + beta * o_z;
-  const double sv = w + beta * o_s;
-  const double pv = o_r / o_d + beta * o_p;
-  const double r = o_r - alpha * sv;
-  const double wn = w - alpha * z;
-  const double un = r / o_d;
   const bool lead = live && t == 0;
-  // the stores go out before the reduction (its barrier waits for LDS
-  // only), so their latency overlaps it
-  if (lead) {
-    v.p[row] = o_x + alpha * pv;
-    v.pl_z[row] = z;
-    v.pl_s[row] = sv;
-    v.pd[0][row] = pv;
-    v.r[row] = r;
-    Mn[row] = wn / o_d;
+  double r, wn, un;
+  if constexpr (TWO) {
+    // n = A m, z = n + beta z, q = m + beta q, s = w + beta s,
+    // p = u + beta p; x += alpha p, r -= alpha s, u -= alpha q, w -= alpha z
+    const double z = (o_d * o_m + s) + beta * o_z;
+    const double qv = o_m + beta * o_q;
+    const double sv = o_w + beta * o_s;
+    const double pv = o_u + beta * o_p;
+    r = o_r - alpha * sv;
+    un = o_u - alpha * qv;
+    wn = o_w - alpha * z;
+    if (lead) {
+      v.p[row] = o_x + alpha * pv;
+      v.pl_z[row] = z;
+      v.pl_s[row] = sv;
+      v.pd[0][row] = pv;
+      v.r[row] = r;
+      v.pl_u[row] = un;
+      v.pl_q[row] = qv;
+      v.pl_w[row] = wn;
+      Mn[row] = wn / o_d;  // the coarse part is added after this kernel
+    }
+  } else {
+    const double w = o_d * o_m;
+    const double z = (w + s) + beta * o_z;
+    const double sv = w + beta * o_s;
+    const double pv = o_r / o_d + beta * o_p;
+    r = o_r - alpha * sv;
+    wn = w - alpha * z;
+    un = r / o_d;
+    // the stores go out before the reduction (its barrier waits for LDS
+    // only), so their latency overlaps it
+    if (lead) {
+      v.p[row] = o_x + alpha * pv;
+      v.pl_z[row] = z;
+      v.pl_s[row] = sv;
+      v.pd[0][row] = pv;
+      v.r[row] = r;
+      Mn[row] = wn / o_d;
+    }
   }
   double x[3] = {lead ? r * un : 0.0, lead ? wn * un : 0.0, lead ? r * r : 0.0};
   block_sum_all<3, NT>(x, sh_out);
@@ -720,6 +760,285 @@ __global__ __launch_bounds__(pcg_nt<FUSED>()) void k_pcg_iter(View v) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) v.pl_part[PAR ^ 1][(int64_t)lb * 4 + k] = x[k];
   }
+}
+
+// ------------------------------------------------- two-level preconditioner
+// M^-1 = D^-1 + P C P^T.  Aggregates: the cells of the background grid (side
+// >= re_lap); P sums the pressure unknowns (flags inner) of a cell, whose
+// rows are contiguous in the sorted order ([cell_start[a], cell_start[a+1]);
+// with lists kept over steps, the cells of the last build, which the order
+// follows).  Every matrix entry couples cells at most one apart, so the cell
+// operator A_c = P^T A P is a 3^DIM-point stencil on the grid.  C: CHEB_K
+// steps of the Chebyshev iteration for A_c, preconditioned by its diagonal,
+// on [G/10, G], G the largest Gershgorin bound of D_c^-1 A_c (so the
+// polynomial is positive on the spectrum and M is symmetric positive
+// definite).  All sums in a fixed order.
+#ifndef CHEB_K
+#define CHEB_K 3
+#endif
+template <int DIM>
+constexpr int nsten() { return DIM == 3 ? 27 : 9; }
+
+__device__ inline int cell_lin(const View& v, int32_t pc) {
+  return ucx(pc) + v.nx * (ucy(pc) + v.ny * ucz(pc));
+}
+
+// Stencil slot of cell b seen from cell a (both packed, at most one apart).
+template <int DIM>
+__device__ inline int sten_slot(int32_t pa, int32_t pb) {
+  const int dx = ucx(pb) - ucx(pa) + 1, dy = ucy(pb) - ucy(pa) + 1;
+  if constexpr (DIM == 3) return dx + 3 * dy + 9 * (ucz(pb) - ucz(pa) + 1);
+  return dx + 3 * dy;
+}
+
+// A_c, stored slot-major (ac[o * ncell + cell]), in three kernels:
+// k_coarse_rows: one team per row (32 rows per workgroup, like the
+//   assembly): each lane adds every 8th matrix entry of its row into the
+//   bin of the neighbour cell's stencil slot (COARSE_U entries per step,
+//   their loads issued together; bins in registers, selected without
+//   indexing), the team sums its bins; the workgroup then sums its rows by
+//   runs of equal cell (rows are sorted by cell) in row order.  A run whose
+//   cell lies wholly in the workgroup's rows is written to A_c; a cell that
+//   crosses the workgroup's first or last row leaves its partial in head /
+//   tail slots of the workgroup.
+// k_coarse_join: every cell that spans workgroups b0 < b1 sums tail[b0],
+//   head[b] of the workgroups between and head[b1], in that order.
+// k_coarse_bound: the Gershgorin bound of every cell row, one maximum per
+//   workgroup, and k_coarse_gmax the largest of those.
+#ifndef COARSE_U
+#define COARSE_U 4
+#endif
+constexpr int CROWS = ROWS_PER_BLOCK;   // rows per workgroup of k_coarse_rows
+
+template <int DIM, class VT>
+__global__ __launch_bounds__(BLOCK) void k_coarse_rows(View v, double* head, double* tail) {
+  constexpr int NS = nsten<DIM>();
+  constexpr int CEN = NS / 2;
+  constexpr int U = COARSE_U;
+  __shared__ double rows[CROWS][NS];
+  __shared__ int32_t rcell[CROWS];
+  const int lr = threadIdx.x / TEAM;
+  const int64_t row = (int64_t)blockIdx.x * CROWS + lr;
+  const int t = team_lane();
+  const VT* __restrict__ aval = reinterpret_cast<const VT*>(v.a_val);
+  double bin[NS];
+#pragma unroll
+  for (int o = 0; o < NS; ++o) bin[o] = 0.0;
+  int32_t pi = GHOST_CELL;
+  bool inner = false;
+  if (row < v.n) {
+    inner = v.flags[row] == MPS_FLAG_INNER;
+    pi = v.pcell[row];
+  }
+  if (inner) {
+    if (t == 0) bin[CEN] = v.diag[row];
+    const int nnz = v.a_nnz[row];
+    for (int l0 = t; l0 < nnz; l0 += U * TEAM) {
+      int32_t jj[U];
+      double aa[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int l = l0 + u * TEAM;
+        // past the row: slot l0 again (an entry of the row), weight 0
+        const int64_t e = sl_index(row, l < nnz ? l : l0, v.kpad);
+        jj[u] = v.a_col[e];
+        aa[u] = l < nnz ? (double)aval[e] : 0.0;
+      }
+      int32_t pj[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) pj[u] = v.pcell[jj[u]];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int slot = sten_slot<DIM>(pi, pj[u]);
+#pragma unroll
+        for (int o = 0; o < NS; ++o) bin[o] += slot == o ? aa[u] : 0.0;
+      }
+    }
+  }
+#pragma unroll
+  for (int o = 0; o < NS; ++o) {
+    const double x = team_sum(bin[o]);
+    if (t == 0) rows[lr][o] = x;
+  }
+  if (t == 0) rcell[lr] = (row < v.n && pi != GHOST_CELL) ? cell_lin(v, pi) : -1;
+  __syncthreads();
+  // runs of equal cell among the workgroup's rows: thread k < NS sums slot
+  // k of every run in row order
+  const int64_t r0 = (int64_t)blockIdx.x * CROWS;
+  const int nr = (int)min<int64_t>(CROWS, v.n - r0);
+  if (threadIdx.x < NS) {
+    const int o = threadIdx.x;
+    int k = 0;
+    while (k < nr) {
+      const int c = rcell[k];
+      int e = k;
+      double sum = 0.0;
+      while (e < nr && rcell[e] == c) sum += rows[e++][o];
+      if (c >= 0) {
+        const bool starts = v.cell_start[c] >= r0, ends = v.cell_start[c + 1] <= r0 + nr;
+        if (starts && ends) v.ac[(int64_t)o * v.ncell + c] = sum;
+        else {
+          if (k == 0) head[(int64_t)blockIdx.x * NS + o] = sum;
+          if (e == nr) tail[(int64_t)blockIdx.x * NS + o] = sum;
+        }
+      }
+      k = e;
+    }
+  }
+}
+
+// Cells whose rows span workgroups: the partials in workgroup order.
+// Cells without rows get a zero centre slot.
+template <int DIM>
+__global__ __launch_bounds__(BLOCK) void k_coarse_join(View v, const double* head,
+                                                       const double* tail) {
+  constexpr int NS = nsten<DIM>();
+  const int64_t c = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (c >= v.ncell) return;
+  const int cs = v.cell_start[c], ce = v.cell_start[c + 1];
+  if (cs == ce) {
+    // only the cell's own row reads its slots, and a zero centre marks it
+    // empty (the other slots keep stale values nobody uses)
+    v.ac[(int64_t)(NS / 2) * v.ncell + c] = 0.0;
+    return;
+  }
+  const int64_t b0 = cs / CROWS, b1 = (ce - 1) / CROWS;
+  if (b0 == b1) return;  // written whole by its workgroup
+  for (int o = 0; o < NS; ++o) {
+    double sum = tail[b0 * NS + o];
+    for (int64_t b = b0 + 1; b <= b1; ++b) sum += head[b * NS + o];
+    v.ac[(int64_t)o * v.ncell + c] = sum;
+  }
+}
+
+// Gershgorin bound of D_c^-1 A_c per cell row; one maximum per workgroup.
+template <int DIM>
+__global__ __launch_bounds__(BLOCK) void k_coarse_bound(View v) {
+  constexpr int NS = nsten<DIM>();
+  const int64_t c = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  double g = 0.0;
+  if (c < v.ncell) {
+    double row[NS];
+#pragma unroll
+    for (int o = 0; o < NS; ++o) row[o] = v.ac[(int64_t)o * v.ncell + c];
+    double sum_abs = 0.0;
+#pragma unroll
+    for (int o = 0; o < NS; ++o) sum_abs += fabs(row[o]);
+    if (row[NS / 2] > 0.0) g = sum_abs / row[NS / 2];
+  }
+  for (int o = WAVE / 2; o > 0; o >>= 1) g = fmax(g, __shfl_xor(g, o, WAVE));
+  __shared__ double shg[BLOCK / WAVE];
+  if ((threadIdx.x & (WAVE - 1)) == 0) shg[threadIdx.x / WAVE] = g;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = shg[0];
+    for (int k = 1; k < BLOCK / WAVE; ++k) m = fmax(m, shg[k]);
+    v.red_blk[blockIdx.x] = m;
+  }
+}
+
+// G = the largest of the workgroup maxima (one workgroup).
+constexpr int GMAX_NT = 1024;
+__global__ __launch_bounds__(GMAX_NT) void k_coarse_gmax(View v, int nblk) {
+  double m = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += GMAX_NT) m = fmax(m, v.red_blk[b]);
+  for (int o = WAVE / 2; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, WAVE));
+  __shared__ double sh[GMAX_NT / WAVE];
+  if ((threadIdx.x & (WAVE - 1)) == 0) sh[threadIdx.x / WAVE] = m;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int k = 0; k < GMAX_NT / WAVE; ++k) m = fmax(m, sh[k]);
+  v.sc->cg_bits = (unsigned long long)__double_as_longlong(m);
+}
+
+// Chebyshev constants of [G/10, G]: theta, delta and rho_k.
+__device__ inline void cheb_consts(const View& v, double& th, double& de) {
+  const double G = __longlong_as_double((long long)v.sc->cg_bits);
+  th = 0.55 * G;
+  de = 0.45 * G;
+}
+__device__ inline double cheb_rho(double sig, int k) {
+  double rho = 1.0 / sig;
+  for (int q = 1; q <= k; ++q) rho = 1.0 / (2.0 * sig - rho);
+  return rho;
+}
+
+// Restriction and the first Chebyshev step, one team per cell:
+// r_c = sum of src over the cell's unknowns, d = D_c^-1 r_c / theta, x = d.
+__global__ __launch_bounds__(BLOCK) void k_coarse_start(View v, const double* src, int ns) {
+  if (v.sc->converged) return;
+  const int64_t cell = (int64_t)xcd_block() * ROWS_PER_BLOCK + threadIdx.x / TEAM;
+  const int t = team_lane();
+  if (cell >= v.ncell) return;
+  const int b0 = v.cell_start[cell], b1 = v.cell_start[cell + 1];
+  double sum = 0.0;
+  for (int i = b0 + t; i < b1; i += TEAM)
+    sum += v.flags[i] == MPS_FLAG_INNER ? src[i] : 0.0;
+  sum = team_sum(sum);
+  if (t == 0) {
+    double th, de;
+    cheb_consts(v, th, de);
+    const double cen = v.ac[(int64_t)(ns / 2) * v.ncell + cell];
+    const double d = cen > 0.0 && th > 0.0 ? sum / (cen * th) : 0.0;
+    v.rc[cell] = sum;
+    v.dc[0][cell] = d;
+    v.xc[cell] = d;
+  }
+}
+
+// Chebyshev step k >= 1, one thread per cell: r_c -= A_c d_(k-1),
+// d_k = rho_k rho_(k-1) d_(k-1) + 2 rho_k / delta D_c^-1 r_c, x += d_k.
+template <int DIM>
+__global__ __launch_bounds__(BLOCK) void k_coarse_step(View v, int k) {
+  constexpr int NS = nsten<DIM>();
+  if (v.sc->converged) return;
+  const int64_t cell = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (cell >= v.ncell) return;
+  const double* __restrict__ dold = v.dc[(k - 1) & 1];
+  const double* a = v.ac + cell;  // slot o at a[o * ncell]
+  const double cen = a[(int64_t)(NS / 2) * v.ncell];
+  if (!(cen > 0.0)) {
+    // a cell without unknowns: its direction stays 0
+    v.dc[k & 1][cell] = 0.0;
+    return;
+  }
+  const int cx = (int)(cell % v.nx), cy = (int)((cell / v.nx) % v.ny),
+            cz = (int)(cell / ((int64_t)v.nx * v.ny));
+  // every load first (indices of neighbours outside the grid clamped to the
+  // cell itself, their products dropped), then the sum
+  double av[NS], dv[NS];
+  bool in[NS];
+#pragma unroll
+  for (int o = 0; o < NS; ++o) {
+    const int x = cx + o % 3 - 1, y = cy + (o / 3) % 3 - 1, z = DIM == 3 ? cz + o / 9 - 1 : 0;
+    in[o] = x >= 0 && x < v.nx && y >= 0 && y < v.ny && z >= 0 && z < v.nz;
+    const int64_t nb = in[o] ? x + (int64_t)v.nx * (y + (int64_t)v.ny * z) : cell;
+    av[o] = a[(int64_t)o * v.ncell];
+    dv[o] = dold[nb];
+  }
+  double q = 0.0;
+#pragma unroll
+  for (int o = 0; o < NS; ++o) q += in[o] ? av[o] * dv[o] : 0.0;
+  double th, de;
+  cheb_consts(v, th, de);
+  const double r = v.rc[cell] - q;
+  double d = 0.0;
+  if (de > 0.0) {
+    const double sig = th / de;
+    const double rk = cheb_rho(sig, k), rk1 = cheb_rho(sig, k - 1);
+    d = rk * rk1 * dv[NS / 2] + 2.0 * rk / de * (r / cen);
+  }
+  v.rc[cell] = r;
+  v.dc[k & 1][cell] = d;
+  v.xc[cell] += d;
+}
+
+// Prolongation: target_i += x_c(cell of i) for the unknowns.
+__global__ __launch_bounds__(BLOCK) void k_coarse_prolong(View v, double* target) {
+  if (v.sc->converged) return;
+  const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= v.n || v.flags[i] != MPS_FLAG_INNER) return;
+  target[i] += v.xc[cell_lin(v, v.pcell[i])];
 }
 
 // Export of the assembled system in original order.
@@ -826,14 +1145,16 @@ int pcg_blocks(int64_t n, bool fused) {
 // resident at once (a second wave of workgroups would double the latency of
 // an iteration), and at most PCG_MAX_BLOCKS partials per reduction.  The
 // workgroups never wait for each other, so this is a matter of speed only.
-int pcg_fused_capacity() {
+int pcg_fused_capacity(bool two) {
   int dev = 0, cus = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return 0;
   int worst = 1 << 30;
-  const void* ks[] = {(const void*)k_pcg_iter<float, 0, true, false>,
-                      (const void*)k_pcg_iter<double, 0, true, false>};
+  const void* ks[] = {two ? (const void*)k_pcg_iter<float, 0, true, false, true>
+                          : (const void*)k_pcg_iter<float, 0, true, false, false>,
+                      two ? (const void*)k_pcg_iter<double, 0, true, false, true>
+                          : (const void*)k_pcg_iter<double, 0, true, false, false>};
   for (const void* k : ks) {
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, PCG_BLOCK, 0) != hipSuccess) return 0;
     worst = per < worst ? per : worst;
@@ -842,17 +1163,26 @@ int pcg_fused_capacity() {
   return cap < PCG_MAX_BLOCKS ? cap : PCG_MAX_BLOCKS;
 }
 
-int launch_pcg_setup(const View& v, int precision, hipStream_t s) {
+template <bool TWO>
+static void pcg_setup_t(const View& v, bool mx, int dim, hipStream_t s) {
   const unsigned nb = (unsigned)v.npcg;
-  const bool mx = precision == MPS_MIXED;
   if (v.pcg_fused) {
-    if (mx) k_pcg_setup<float, true><<<nb, PCG_BLOCK, 0, s>>>(v);
-    else k_pcg_setup<double, true><<<nb, PCG_BLOCK, 0, s>>>(v);
+    if constexpr (TWO) launch_coarse_correct(v, dim, v.r, v.z, s);
+    if (mx) k_pcg_setup<float, true, TWO><<<nb, PCG_BLOCK, 0, s>>>(v);
+    else k_pcg_setup<double, true, TWO><<<nb, PCG_BLOCK, 0, s>>>(v);
   } else {
     k_pcg_start<<<1, RED_BLOCK, 0, s>>>(v);
-    if (mx) k_pcg_setup<float, false><<<nb, PCG_SPLIT_BLOCK, 0, s>>>(v);
-    else k_pcg_setup<double, false><<<nb, PCG_SPLIT_BLOCK, 0, s>>>(v);
+    if constexpr (TWO) launch_coarse_correct(v, dim, v.r, v.z, s);
+    if (mx) k_pcg_setup<float, false, TWO><<<nb, PCG_SPLIT_BLOCK, 0, s>>>(v);
+    else k_pcg_setup<double, false, TWO><<<nb, PCG_SPLIT_BLOCK, 0, s>>>(v);
   }
+  if constexpr (TWO) launch_coarse_correct(v, dim, v.pl_w, v.pl_m[0], s);
+}
+
+int launch_pcg_setup(const View& v, int precision, int dim, hipStream_t s) {
+  const bool mx = precision == MPS_MIXED;
+  if (v.ac) pcg_setup_t<true>(v, mx, dim, s);
+  else pcg_setup_t<false>(v, mx, dim, s);
   return 0;
 }
 
@@ -863,36 +1193,66 @@ int launch_pcg_reduce(const View& v, int parity, hipStream_t s) {
   return 0;
 }
 
-int launch_pcg_iter(const View& v, int precision, int parity, hipStream_t s) {
+template <class VT, bool FUSED, bool PRED, bool TWO>
+static void pcg_iter_t(const View& v, int parity, hipStream_t s) {
   const unsigned nb = (unsigned)v.npcg;
+  const unsigned nt = FUSED ? PCG_BLOCK : PCG_SPLIT_BLOCK;
+  launch_k(parity ? k_pcg_iter<VT, 1, FUSED, PRED, TWO> : k_pcg_iter<VT, 0, FUSED, PRED, TWO>,
+           nb, nt, s, v);
+}
+
+template <class VT, bool TWO>
+static void pcg_iter_s(const View& v, int parity, hipStream_t s) {
+  if (v.pcg_fused) pcg_iter_t<VT, true, false, TWO>(v, parity, s);
+  else if (v.pcg_pred) pcg_iter_t<VT, false, true, TWO>(v, parity, s);
+  else pcg_iter_t<VT, false, false, TWO>(v, parity, s);
+}
+
+int launch_pcg_iter(const View& v, int precision, int parity, hipStream_t s) {
   const bool mx = precision == MPS_MIXED;
-  if (v.pcg_fused) {
-    const unsigned nt = PCG_BLOCK;
-    if (mx)
-      launch_k(parity ? k_pcg_iter<float, 1, true, false> : k_pcg_iter<float, 0, true, false>,
-               nb, nt, s, v);
-    else
-      launch_k(parity ? k_pcg_iter<double, 1, true, false> : k_pcg_iter<double, 0, true, false>,
-               nb, nt, s, v);
-    return 0;
-  }
-  const unsigned nt = PCG_SPLIT_BLOCK;
-  if (v.pcg_pred) {
-    if (mx)
-      launch_k(parity ? k_pcg_iter<float, 1, false, true> : k_pcg_iter<float, 0, false, true>,
-               nb, nt, s, v);
-    else
-      launch_k(parity ? k_pcg_iter<double, 1, false, true> : k_pcg_iter<double, 0, false, true>,
-               nb, nt, s, v);
+  if (v.ac) {
+    if (mx) pcg_iter_s<float, true>(v, parity, s);
+    else pcg_iter_s<double, true>(v, parity, s);
   } else {
-    if (mx)
-      launch_k(parity ? k_pcg_iter<float, 1, false, false> : k_pcg_iter<float, 0, false, false>,
-               nb, nt, s, v);
-    else
-      launch_k(parity ? k_pcg_iter<double, 1, false, false>
-                      : k_pcg_iter<double, 0, false, false>,
-               nb, nt, s, v);
+    if (mx) pcg_iter_s<float, false>(v, parity, s);
+    else pcg_iter_s<double, false>(v, parity, s);
   }
+  return 0;
+}
+
+int launch_coarse_assemble(const View& v, int dim, int precision, hipStream_t s) {
+  const unsigned nr = (unsigned)((v.n + CROWS - 1) / CROWS);
+  const unsigned nc = (unsigned)((v.ncell + BLOCK - 1) / BLOCK);
+  const int ns = dim == 3 ? 27 : 9;
+  double* head = v.cwork;
+  double* tail = v.cwork + (int64_t)nr * ns;
+  const bool mx = precision == MPS_MIXED;
+  if (dim == 2) {
+    if (mx) k_coarse_rows<2, float><<<nr, BLOCK, 0, s>>>(v, head, tail);
+    else k_coarse_rows<2, double><<<nr, BLOCK, 0, s>>>(v, head, tail);
+    k_coarse_join<2><<<nc, BLOCK, 0, s>>>(v, head, tail);
+    k_coarse_bound<2><<<nc, BLOCK, 0, s>>>(v);
+  } else {
+    if (mx) k_coarse_rows<3, float><<<nr, BLOCK, 0, s>>>(v, head, tail);
+    else k_coarse_rows<3, double><<<nr, BLOCK, 0, s>>>(v, head, tail);
+    k_coarse_join<3><<<nc, BLOCK, 0, s>>>(v, head, tail);
+    k_coarse_bound<3><<<nc, BLOCK, 0, s>>>(v);
+  }
+  k_coarse_gmax<<<1, GMAX_NT, 0, s>>>(v, (int)nc);
+  return 0;
+}
+
+int launch_coarse_correct(const View& v, int dim, const double* src, double* target,
+                          hipStream_t s) {
+  const int ns = dim == 3 ? 27 : 9;
+  k_coarse_start<<<(unsigned)((v.ncell + ROWS_PER_BLOCK - 1) / ROWS_PER_BLOCK), BLOCK, 0, s>>>(
+      v, src, ns);
+  const unsigned nc = (unsigned)((v.ncell + BLOCK - 1) / BLOCK);
+  for (int k = 1; k < CHEB_K; ++k) {
+    if (dim == 2) k_coarse_step<2><<<nc, BLOCK, 0, s>>>(v, k);
+    else k_coarse_step<3><<<nc, BLOCK, 0, s>>>(v, k);
+  }
+  k_coarse_prolong<<<nb_flat(v.n), BLOCK, 0, s>>>(v, target);
   return 0;
 }
 

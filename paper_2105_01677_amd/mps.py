@@ -40,7 +40,7 @@ class Params(C.Structure):
         ("gamma", C.c_double), ("alpha", C.c_double), ("cg_tol", C.c_double),
         ("grid_lo", C.c_double * 3), ("cell_size", C.c_double),
         ("smagorinsky_cs", C.c_double), ("source", C.c_int32), ("laplacian", C.c_int32),
-        ("skin", C.c_double),
+        ("skin", C.c_double), ("precond", C.c_int32),
     ]
 
 
@@ -121,6 +121,7 @@ def make_params(p: dict) -> Params:
     o.source = int(p.get("source", 0))
     o.laplacian = int(p.get("laplacian", 0))
     o.skin = float(p.get("skin", 0.0))
+    o.precond = int(p.get("precond", 0))
     for a in range(3):
         o.g[a] = float(p["g"][a])
         o.grid_lo[a] = float(p["grid_lo"][a])

@@ -28,6 +28,7 @@ FP64, MIXED = 0, 1
 GRAD_STD, GRAD_CMPS = 0, 1
 SRC_STD, SRC_HS, SRC_HS_ECS = 0, 1, 2
 LAP_STD, LAP_HL = 0, 1
+PC_JACOBI, PC_TWO_LEVEL = 0, 1
 
 SEED = 2105
 
@@ -56,6 +57,7 @@ def default_params(dim: int, l0: float, *, re_n_over_l0: float = 2.1,
         alpha=1e-7, cg_tol=1e-9, cg_maxit=10000, max_neigh=300,
         pmode=pmode, kernel=kernel, precision=precision, grad=GRAD_STD,
         clamp=1, smag_cs=0.0, cg_pipelined=1, source=SRC_STD, laplacian=LAP_STD, skin=0.0,
+        precond=PC_JACOBI,
         grid_lo=[0.0, 0.0, 0.0], grid_n=[1, 1, 1], cell_size=0.0,
     )
 

@@ -1,0 +1,109 @@
+"""The two-level preconditioner of the pipelined CG (params precond =
+PC_TWO_LEVEL: D^-1 + P C P^T with cell aggregates and Chebyshev steps on the
+cell operator).  The PPE solution is unique, so the bars are the one-step
+parity bars against the oracle (the oracle solves with plain CG); the
+preconditioner must also take fewer iterations than Jacobi's."""
+import numpy as np
+import pytest
+
+from paper_2105_01677_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+PRECISIONS = [(W.FP64, 1e-12, 1e-8), (W.MIXED, 1e-9, 1e-4)]
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2105_01677_amd import mps
+    return mps
+
+
+def rel_err(a, b):
+    den = np.abs(b).max()
+    return float(np.abs(a - b).max() / den) if den else float(np.abs(a).max())
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _step_vs_oracle(gpu, orc, w, tol, rho_i=None, nu_i=None):
+    rs = None
+    if rho_i is not None:
+        st, rs = orc.smoothed_density(w.params, w.pos, w.ptype, rho_i)
+        assert st == 0
+    m = gpu.MPS(w.params, w.pos, w.vel, w.ptype, rho_i=rho_i, nu_i=nu_i)
+    s = m.step(1)
+    g = {k: _np(v) for k, v in m.state().items()}
+    m.close()
+    st, o = orc.step(w.params, w.pos, w.vel, w.ptype, want_lists=False, rho_s=rs, nu_i=nu_i)
+    assert st == 0
+    fw = (w.ptype == W.FLUID) | (w.ptype == W.WALL)
+    mism = (g["flags"] != o["flags"]) & fw
+    if mism.any():
+        n0 = orc.lattice_constants(w.params["dim"], w.params["l0"], w.params["re_n"],
+                                   w.params["kernel"])[0]
+        assert np.abs(o["nstar"][mism] / (w.params["beta"] * n0) - 1).max() < 2e-5
+        st, o = orc.step(w.params, w.pos, w.vel, w.ptype, flags_override=g["flags"],
+                         want_lists=False, rho_s=rs, nu_i=nu_i)
+    errs = {"disp": rel_err(g["pos"] - w.pos, o["pos"] - w.pos),
+            "vel": rel_err(g["vel"], o["vel"]), "p": rel_err(g["p"], o["p"])}
+    print(w.name, "two-level cg", s["cg_iters_last"], "errors", errs, flush=True)
+    for k, e in errs.items():
+        assert e < tol, (w.name, k, e)
+    return s["cg_iters_last"]
+
+
+def _iters(gpu, w, precond, steps):
+    prm = dict(w.params, precond=precond)
+    m = gpu.MPS(prm, w.pos, w.vel, w.ptype, rho_i=w.rho_i, nu_i=w.nu_i)
+    s = m.step(steps)
+    m.close()
+    return s["cg_iters_total"] / steps
+
+
+@pytest.mark.parametrize("precision,cg_tol,tol", PRECISIONS)
+def test_two_level_small_systems(gpu, orc, precision, cg_tol, tol):
+    """2-D 1,432 (jittered) and 44,832 (one fused kernel per iteration), and
+    a 3-D block with walls, against the oracle."""
+    for w in (W.jitter(W.config("dam_break_2d_1432", precision=precision)),
+              W.jitter(W.config("dam_break_2d_44832", precision=precision)),
+              W.jitter(W.lattice_block(3, [16, 12, 10], walls_below=True, dt=2e-4))):
+        w.params.update(precision=precision, cg_tol=cg_tol, precond=W.PC_TWO_LEVEL)
+        _step_vs_oracle(gpu, orc, w, tol)
+
+
+@pytest.mark.parametrize("precision,cg_tol,tol", PRECISIONS)
+def test_two_level_dam_break_3d_441282(gpu, orc, precision, cg_tol, tol):
+    """The 441,282-particle dam break (split schedule), every particle
+    against the oracle, and fewer iterations than Jacobi over 10 steps."""
+    w = W.config("dam_break_3d_441282", precision=precision)
+    w.params.update(cg_tol=cg_tol, precond=W.PC_TWO_LEVEL)
+    _step_vs_oracle(gpu, orc, w, tol)
+    if precision == W.MIXED:
+        w = W.config("dam_break_3d_441282", precision=precision)
+        jac, two = _iters(gpu, w, W.PC_JACOBI, 10), _iters(gpu, w, W.PC_TWO_LEVEL, 10)
+        print("441,282: CG iterations per step, Jacobi", jac, "two-level", two, flush=True)
+        assert two < 0.75 * jac
+
+
+def test_two_level_two_phase_3d_2314616(gpu, orc):
+    """The 2,314,616-particle two-phase box (mixed), every particle against
+    the oracle, and fewer iterations than Jacobi over 5 steps."""
+    w = W.config("two_phase_3d_2314616", precision=W.MIXED)
+    w.params.update(precond=W.PC_TWO_LEVEL)
+    _step_vs_oracle(gpu, orc, w, 1e-4, rho_i=w.rho_i, nu_i=w.nu_i)
+    w = W.config("two_phase_3d_2314616", precision=W.MIXED)
+    jac, two = _iters(gpu, w, W.PC_JACOBI, 5), _iters(gpu, w, W.PC_TWO_LEVEL, 5)
+    print("2,314,616: CG iterations per step, Jacobi", jac, "two-level", two, flush=True)
+    assert two < 0.75 * jac
+
+
+def test_two_level_needs_the_pipelined_solver(gpu):
+    w = W.config("dam_break_2d_1432")
+    with pytest.raises(gpu.MPSError):
+        gpu.MPS(dict(w.params, precond=W.PC_TWO_LEVEL, cg_pipelined=0), w.pos, w.vel, w.ptype)

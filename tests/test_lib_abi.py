@@ -40,7 +40,8 @@ def test_params_layout():
     assert P.source.offset == 48 + 8 * 19      # then int32 laplacian, double skin
     assert P.laplacian.offset == P.source.offset + 4
     assert P.skin.offset == 48 + 8 * 20
-    assert ctypes.sizeof(P) == 48 + 8 * 21
+    assert P.precond.offset == 48 + 8 * 21
+    assert ctypes.sizeof(P) == 48 + 8 * 22
     assert ctypes.sizeof(mps.StepStats) == 64
     assert mps.StepStats.cg_redone.offset == 56
     assert mps.StepStats.list_builds.offset == 60
