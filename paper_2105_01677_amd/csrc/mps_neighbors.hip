@@ -248,65 +248,142 @@ __global__ __launch_bounds__(BLOCK) void k_rank_permute(View v) {
   }
 }
 
-// a2: neighbour list of each particle, one team of TEAM lanes per
-// particle.  The candidate cells of one grid row (x-1 .. x+1) are contiguous
-// in the sorted order, so each of the 3 (2-D) or 9 (3-D) rows is one
-// contiguous index range; the team scans it TEAM candidates at a time and
-// appends hits in candidate order with a ballot, so the list order is fixed.
+// Wavefront-uniform loads through the constant address space: the arrays
+// read this way are not written while the search runs, so the compiler may
+// (and does) use scalar loads for them.
+template <class T>
+__device__ inline T ld_uniform(const T* a, int64_t i) {
+  typedef const __attribute__((address_space(4))) T cT;
+  return ((const cT*)a)[i];
+}
+template <int DIM>
+__device__ inline void load_vec_uniform(const double* a, int64_t i, double (&x)[DIM]) {
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) x[k] = ld_uniform(a, PS<DIM>::v * i + k);
+}
+
+// a2: neighbour lists, one wavefront per group of SLICE consecutive sorted
+// particles (the rows of one slice of the list layout).  The particles of a
+// cell share their candidates: the 3 (2-D) or 9 (3-D) grid rows x-1 .. x+1
+// of the 3^DIM block around the cell, each one contiguous index range of
+// the sorted order.  The group is taken one cell at a time (a group spans
+// one or two cells, rarely more); the wavefront lays that cell's ranges end
+// to end, loads WAVE candidates at a time (one per lane) and tests each of
+// the group's particles in the cell against them.  A particle's position is
+// uniform (scalar loads), its hits are compacted with a wavefront ballot and
+// appended in candidate order, so a list comes out in the same order as a
+// per-particle scan of the ranges, and its list length is a uniform
+// register.  Each candidate position is loaded once per group and cell
+// instead of once per particle; the groups follow the particle order, so
+// the XCD-aware block mapping splits the work evenly.  The particles are
+// tested NBU at a time (their distance chains are independent) before their
+// hits are appended.
 template <int DIM>
 __global__ __launch_bounds__(BLOCK) void k_neighbors(View v) {
   if (skip_build(v)) return;
   constexpr int NR = DIM == 3 ? 9 : 3;  // cell rows of the 3^DIM block
-  const int64_t row = (int64_t)xcd_block() * ROWS_PER_BLOCK + threadIdx.x / TEAM;
-  const int t = team_lane();
-  if (row >= v.n) return;
-  const int32_t pc = v.pcell[row];
-  int count = 0;
-  if (pc != GHOST_CELL) {
-    double xi[DIM];
-    load_vec<DIM>(v.pos, row, xi);
+  constexpr int G = SLICE;
+  constexpr int NBU = 2;  // particles tested per pass (independent chains)
+  static_assert(G == 8 && TEAM == 8 && WAVE == 64, "slot arithmetic below");
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int64_t g0 = ((int64_t)xcd_block() * (BLOCK / WAVE) +
+                      __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE))) * G;
+  if (g0 >= v.n) return;
+  const int ng = (int)min((int64_t)G, v.n - g0);
+  // row u of the group starts at slot u * TEAM of its slice
+  int32_t* const gb = v.nb_list + (g0 / SLICE) * ((int64_t)v.kpad * SLICE);
+  const double re2 = v.re_lap2;
+  const unsigned maxn = (unsigned)v.max_neigh;
+  int cnt[G];
+#pragma unroll
+  for (int u = 0; u < G; ++u) cnt[u] = 0;
+  uint64_t coinc = 0;
+  int s = 0;  // first row of the group not yet done
+  while (s < ng) {
+    const int32_t pc = ld_uniform(v.pcell, g0 + s);
+    if (pc == GHOST_CELL) break;  // ghosts are sorted last: no neighbours
     const int cx = ucx(pc), cy = ucy(pc), cz = ucz(pc);
+    const int c = cx + v.nx * (cy + v.ny * cz);
+    const int se = (int)min((int64_t)ng, (int64_t)ld_uniform(v.cell_start, c + 1) - g0);
     const int x0 = max(cx - 1, 0), x1 = min(cx + 1, v.nx - 1);
-    // every row range first (no dependent wait per range); rows outside
-    // the grid get an empty range
-    int jb[NR], je[NR];
+    // the ranges end to end: candidate k of range q is particle k + dlt[q]
+    int pre[NR], dlt[NR], total = 0;
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
       const int y = cy - 1 + q % 3, z = DIM == 3 ? cz - 1 + q / 3 : 0;
       const bool in = y >= 0 && y < v.ny && z >= 0 && z < v.nz;
       const int base = v.nx * ((in ? y : cy) + v.ny * (in ? z : cz));
-      jb[q] = v.cell_start[base + x0];
-      je[q] = in ? v.cell_start[base + x1 + 1] : 0;
+      const int jb = ld_uniform(v.cell_start, base + x0);
+      const int je = in ? ld_uniform(v.cell_start, base + x1 + 1) : jb;
+      pre[q] = total;
+      dlt[q] = jb - total;
+      total += je - jb;
     }
-    bool coinc = false;
-    const int64_t slot0 = sl_index(row, 0, v.kpad);
+    for (int k0 = 0; k0 < total; k0 += WAVE) {
+      const int k = k0 + lane;
+      int d = dlt[0];
 #pragma unroll
-    for (int q = 0; q < NR; ++q) {
-      const int b = jb[q], e = je[q];
-      for (int jj = b; jj < e; jj += TEAM) {
-        const int j = jj + t;
-        // branch-free: a lane past the range tests its own particle
-        double xj[DIM];
-        load_vec<DIM>(v.pos, j < e ? j : row, xj);
-        const double d2 = dist2_exact<DIM>(xi, xj);
-        const bool hit = j < e && j != row && d2 < v.re_lap2;
-        coinc = coinc || (hit && d2 == 0.0);
-        const uint32_t m = team_ballot(hit);
-        if (hit) {
-          const unsigned l = (unsigned)(count + __popc(m & ((1u << t) - 1u)));
-          if (l < (unsigned)v.max_neigh)
-            v.nb_list[slot0 + (int64_t)(l / TEAM) * WAVE + (l % TEAM)] = j;
+      for (int q = 1; q < NR; ++q) d = k >= pre[q] ? dlt[q] : d;
+      const bool valid = k < total;
+      const int j = valid ? k + d : (int)g0;
+      double xj[DIM];
+      load_vec<DIM>(v.pos, j, xj);
+      // a lane past the ranges sits at infinity and never hits
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) xj[a] = valid ? xj[a] : __builtin_inf();
+#pragma unroll
+      for (int u0 = 0; u0 < G; u0 += NBU) {
+        bool in[NBU];
+        bool any = false;
+#pragma unroll
+        for (int w = 0; w < NBU; ++w) {
+          in[w] = u0 + w >= s && u0 + w < se;
+          any = any || in[w];
         }
-        count += __popc(m);
+        if (!any) continue;
+        double d2[NBU];
+        bool hit[NBU];
+        uint64_t m[NBU];
+#pragma unroll
+        for (int w = 0; w < NBU; ++w) {
+          // a particle outside the cell's run tests a clamped one, no hit
+          const int i = (int)g0 + min(max(u0 + w, s), se - 1);
+          double xi[DIM];
+          load_vec_uniform<DIM>(v.pos, i, xi);
+          d2[w] = dist2_exact<DIM>(xi, xj);
+          hit[w] = in[w] && j != (int)g0 + u0 + w && d2[w] < re2;
+          m[w] = __builtin_amdgcn_ballot_w64(hit[w]);
+        }
+#pragma unroll
+        for (int w = 0; w < NBU; ++w) {
+          const int u = u0 + w;
+          if (m[w]) {
+            coinc |= __builtin_amdgcn_ballot_w64(hit[w] && d2[w] == 0.0);
+            if (hit[w]) {
+              const unsigned l = (unsigned)cnt[u] + __builtin_amdgcn_mbcnt_hi(
+                                     (uint32_t)(m[w] >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m[w], 0u));
+              // slot l of row u: (l / TEAM) * WAVE + u * TEAM + l % TEAM
+              if (l < maxn) gb[(((l << 3) & ~63u) | (l & 7u)) + u * TEAM] = j;
+            }
+            cnt[u] += __popcll(m[w]);
+          }
+        }
       }
     }
-    if (coinc) atomicOr(v.status, ST_COINCIDENT);
-    if (count > v.max_neigh) {
-      if (t == 0) atomicOr(v.status, ST_OVERFLOW);
-      count = v.max_neigh;
-    }
+    s = se;
   }
-  if (t == 0) v.nb_count[row] = count;
+  int my = 0;
+#pragma unroll
+  for (int u = 0; u < G; ++u) my = lane == u ? cnt[u] : my;
+  if (lane < ng) {
+    if (my > (int)maxn) {
+      atomicOr(v.status, ST_OVERFLOW);
+      my = (int)maxn;
+    }
+    v.nb_count[g0 + lane] = my;
+  }
+  if (coinc && lane == 0) atomicOr(v.status, ST_COINCIDENT);
 }
 
 // Lists kept over steps, start of a step: the largest squared
@@ -504,7 +581,7 @@ int launch_permute(const View& v, int dim, int precision, hipStream_t s) {
 
 int launch_neighbors(const View& v, int dim, int precision, hipStream_t s) {
   (void)precision;
-  const unsigned nb = nblk(v.n, ROWS_PER_BLOCK);
+  const unsigned nb = nblk(v.n, BLOCK / WAVE * SLICE);
   if (dim == 2) k_neighbors<2><<<nb, BLOCK, 0, s>>>(v);
   else k_neighbors<3><<<nb, BLOCK, 0, s>>>(v);
   return 0;

@@ -66,13 +66,29 @@ def _list_inputs():
     pos = np.concatenate([w.pos, far])
     cases["big_grid_3d"] = W.Workload("big_grid", pos, np.zeros_like(pos),
                                       np.zeros(len(pos), np.int8), prm)
+    # cells several times wider than re_lap: about 140 (2-D) and 220 (3-D)
+    # particles per cell, so a cell's particles are taken in several groups
+    # of one wavefront each, with a ragged last group
+    cases["big_cells_2d"] = _wide_cells(W.random_box(3000, 2, seed=15), 3.0)
+    cases["big_cells_3d"] = _wide_cells(W.random_box(6000, 3, seed=16), 2.6)
     return cases
+
+
+def _wide_cells(w, factor):
+    prm = dict(w.params)
+    dim, cs0, lo = prm["dim"], prm["cell_size"], prm["grid_lo"]
+    cs = cs0 * factor
+    prm["grid_n"] = [int(np.ceil(prm["grid_n"][a] * cs0 / cs)) if a < dim else 1
+                     for a in range(3)]
+    prm["cell_size"] = cs
+    assert all(lo[a] + prm["grid_n"][a] * cs > w.pos[:, a].max() for a in range(dim))
+    return W.Workload(w.name + "_wide_cells", w.pos, w.vel, w.ptype, prm)
 
 
 @pytest.mark.parametrize("precision", [W.FP64, W.MIXED])
 @pytest.mark.parametrize("name", ["random2d", "random3d", "db2d_1432_jitter", "block3d_jitter",
                                   "cell_faces", "db2d_1432_lattice", "block3d_lattice",
-                                  "big_grid_3d"])
+                                  "big_grid_3d", "big_cells_2d", "big_cells_3d"])
 def test_neighbor_lists_bit_exact(gpu, orc, name, precision):
     """Lists against the oracle's cell-linked list, bit for bit.  Both
     paths decide d^2 < re_lap^2 on the same FP64 expression; the unjittered
