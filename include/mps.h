@@ -201,7 +201,8 @@ const char* mps_last_error(const mps_ctx* ctx);
  * ascending original ids, padded with -1.  The set is exactly
  * { j != i : d2 < re_lap^2 } with d2 = (dx*dx + dy*dy) + dz*dz rounded term
  * by term in FP64 (dx = x_j - x_i), over particles that are not ghosts.
- * Errors: MPS_E_NEIGH_OVERFLOW, MPS_E_COINCIDENT, MPS_E_POISONED. */
+ * Errors: MPS_E_NEIGH_OVERFLOW, MPS_E_COINCIDENT, MPS_E_POISONED; after an
+ * error the outputs are unspecified. */
 mps_status mps_neighbors(mps_ctx* ctx, int32_t* cell_id, int32_t* count,
                          int32_t* list);
 
@@ -228,8 +229,9 @@ mps_status mps_neighbors(mps_ctx* ctx, int32_t* cell_id, int32_t* count,
  * Errors: MPS_E_ARG (parameters, NULL pos/type, a type outside
  * MPS_FLUID..MPS_GHOST), MPS_E_SCRATCH (n, max_neigh and the grid need more
  * than the fixed array; nothing is launched), MPS_E_NEIGH_OVERFLOW,
- * MPS_E_COINCIDENT, MPS_E_NONFINITE, MPS_E_DEVICE.  mps_last_error(NULL)
- * gives the text of this thread's last such error. */
+ * MPS_E_COINCIDENT, MPS_E_NONFINITE, MPS_E_DEVICE; after an error the
+ * outputs are unspecified.  mps_last_error(NULL) gives the text of this
+ * thread's last such error. */
 #define MPS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
 mps_status mps_neighbors_noalloc(const mps_params* params, int64_t n, const double* pos,
                                  const int8_t* type, int32_t* cell_id, int32_t* count,

@@ -56,6 +56,7 @@ struct mps_ctx {
   int32_t *cellid = nullptr, *slot = nullptr, *cell_count = nullptr, *cell_start = nullptr,
           *cell_local = nullptr, *tile_sum = nullptr, *perm = nullptr;
   int32_t *nb_count = nullptr, *nb_list = nullptr;
+  int32_t *nbn_count = nullptr, *nbn_list = nullptr;  // short lists (re_n at r*)
   // lists kept over steps (skin > 0): superset lists, positions at the
   // build, the device record of the decisions
   int32_t *sk_count = nullptr, *sk_list = nullptr;
@@ -285,6 +286,9 @@ View make_view(const mps_ctx* c) {
   v.perm = c->perm;
   v.nb_count = c->nb_count;
   v.nb_list = c->nb_list;
+  v.nbn_count = c->nbn_count;
+  v.nbn_list = c->nbn_list;
+  v.re_n2_keep = v.re_n2 * (1.0 + 1e-4);
   v.a_nnz = c->a_nnz;
   v.a_col = c->a_col;
   v.a_val = c->a_val;
@@ -1036,6 +1040,8 @@ mps_status mps_init(const mps_params* params, int64_t n, const double* pos, cons
   A(dalloc(&c->tile_sum, scan_tiles(c->ncell)));
   A(dalloc(&c->nb_count, n));
   A(dalloc(&c->nb_list, c->slots));
+  A(dalloc(&c->nbn_count, n));
+  A(dalloc(&c->nbn_list, c->slots));
   if (params->skin > 0.0) {
     // superset capacity: the cap scaled by the volume of the larger ball,
     // with a fifth more for density fluctuations
@@ -1129,6 +1135,7 @@ mps_status mps_init(const mps_params* params, int64_t n, const double* pos, cons
   A(hipMemsetAsync(c->step_count, 0, sizeof(int32_t), s));
   A(hipMemsetAsync(c->sc, 0, sizeof(CGScalars), s));
   A(hipMemsetAsync(c->nb_count, 0, n * sizeof(int32_t), s));
+  A(hipMemsetAsync(c->nbn_count, 0, n * sizeof(int32_t), s));
   if (c->ls) {
     A(hipMemsetAsync(c->ls, 0, sizeof(ListState), s));
     A(hipMemsetAsync(c->sk_count, 0, n * sizeof(int32_t), s));
@@ -1206,7 +1213,7 @@ mps_status mps_free(mps_ctx* c) {
                   c->cellid, c->slot, c->perm, c->cell_count, c->cell_start,
                   c->cell_local, c->tile_sum,
                   c->nb_count,
-                  c->nb_list, c->a_nnz, c->a_col, c->a_val, c->diag, c->b, c->r, c->z,
+                  c->nb_list, c->nbn_count, c->nbn_list, c->a_nnz, c->a_col, c->a_val, c->diag, c->b, c->r, c->z,
                   c->q, c->p_save, c->partA, c->partB, c->sc, c->status, c->step_count,
                   c->sk_count, c->sk_list, c->r_build, c->ls, c->red_blk,
                   c->ac, c->cwork, c->rc, c->xc, c->dc[0], c->dc[1], c->pl_u, c->pl_q,

@@ -187,6 +187,15 @@ struct View {
   // lists
   int32_t* nb_count;
   int32_t* nb_list;
+  // short lists: the entries of each list within re_n at r*, in list
+  // order, written by the density kernel for the p-hat and gradient kernels
+  // (same layout and slot capacity as nb_list).  re_n2_keep: re_n^2 widened
+  // by a relative 1e-4, so that the FP32 distance tests of the mixed path,
+  // which round differently from the FP64 test of the density kernel, never
+  // meet an entry it dropped.
+  int32_t* nbn_count;
+  int32_t* nbn_list;
+  double re_n2_keep;
 
   // PPE
   int32_t* a_nnz;
@@ -409,6 +418,38 @@ __device__ inline R dweight(int kernel, R r, R re) {
   if (!(r < re)) return R(0);
   if (kernel == MPS_K_KOSHIZUKA) return -re / (r * r);
   R q = R(1) - r / re;
+  return R(-3) * q * q / re;
+}
+
+// 1/sqrt(x) for the kernel sums (x > 0): the hardware reciprocal square
+// root, in FP64 refined by RSQ_NEWTON Newton-Raphson steps
+// y <- y + y (1 - x y^2) / 2, which square the relative error, so that the
+// result is within a few ulp (no correctly rounded sqrt and division).
+#ifndef RSQ_NEWTON
+#define RSQ_NEWTON 2
+#endif
+__device__ inline float rsqrt_k(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ inline double rsqrt_k(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int k = 0; k < RSQ_NEWTON; ++k) y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+  return y;
+}
+
+// The kernel weight (Eq. 4, or the cubic kernel) and its derivative from
+// r^2 and ir = 1/r, zero at and beyond re (re2 = re^2).
+template <class R>
+__device__ inline R weight_r2(int kernel, R r2, R ir, R re, R re2) {
+  if (!(r2 < re2)) return R(0);
+  if (kernel == MPS_K_KOSHIZUKA) return re * ir - R(1);
+  const R q = R(1) - r2 * ir / re;
+  return q * q * q;
+}
+template <class R>
+__device__ inline R dweight_r2(int kernel, R r2, R ir, R re, R re2) {
+  if (!(r2 < re2)) return R(0);
+  if (kernel == MPS_K_KOSHIZUKA) return -re * ir * ir;
+  const R q = R(1) - r2 * ir / re;
   return R(-3) * q * q / re;
 }
 

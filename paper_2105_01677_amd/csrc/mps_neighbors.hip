@@ -280,7 +280,9 @@ __device__ inline void load_vec_uniform(const double* a, int64_t i, double (&x)[
 // hits are appended.
 template <int DIM>
 __global__ __launch_bounds__(BLOCK) void k_neighbors(View v) {
-  if (skip_build(v)) return;
+  // after an error raised earlier in the call the permutation wrote nothing,
+  // so the packed cells need not match this step's cell starts: no search
+  if (skip_build(v) || *v.status) return;
   constexpr int NR = DIM == 3 ? 9 : 3;  // cell rows of the 3^DIM block
   constexpr int G = SLICE;
   constexpr int NBU = 2;  // particles tested per pass (independent chains)
@@ -304,7 +306,9 @@ __global__ __launch_bounds__(BLOCK) void k_neighbors(View v) {
     if (pc == GHOST_CELL) break;  // ghosts are sorted last: no neighbours
     const int cx = ucx(pc), cy = ucy(pc), cz = ucz(pc);
     const int c = cx + v.nx * (cy + v.ny * cz);
-    const int se = (int)min((int64_t)ng, (int64_t)ld_uniform(v.cell_start, c + 1) - g0);
+    // the run of the group in cell c (at least one row: progress even if
+    // the cells were inconsistent)
+    const int se = max(s + 1, (int)min((int64_t)ng, (int64_t)ld_uniform(v.cell_start, c + 1) - g0));
     const int x0 = max(cx - 1, 0), x1 = min(cx + 1, v.nx - 1);
     // the ranges end to end: candidate k of range q is particle k + dlt[q]
     int pre[NR], dlt[NR], total = 0;
@@ -519,7 +523,8 @@ __global__ __launch_bounds__(BLOCK) void k_export_lists(View v, int32_t* cell_ou
                                                         int32_t* count_out,
                                                         int32_t* list_out) {
   const int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (k >= v.n) return;
+  // nothing is exported after an error (the lists may not have been built)
+  if (k >= v.n || *v.status) return;
   const int64_t o = v.id[k];
   const int c = v.nb_count[k];
   if (count_out) count_out[o] = c;

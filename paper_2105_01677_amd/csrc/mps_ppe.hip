@@ -230,8 +230,8 @@ __global__ __launch_bounds__(BLOCK) void k_assemble(View v, const double* rhs, i
               in = s2 < v.re_lap2;
             }
           }
-          const R r = sqrt(r2);
-          R cr = hl ? chl / (r2 * r) : cpp * weight<R>(v.kernel, r, re);
+          const R ir = rsqrt_k(r2);
+          R cr = hl ? chl * (ir * ir * ir) : cpp * weight_r2<R>(v.kernel, r2, ir, re, re2);
           // two-phase: 1/rho -> 2/(<rho>_i + <rho>_j), symmetric
           if constexpr (MULTI) cr *= (R)(v.rho * 2.0 / (rho_i + rhoj[u]));
           c[u] = in ? cr : R(0);

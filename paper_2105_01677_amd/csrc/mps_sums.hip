@@ -4,9 +4,10 @@
 //               explicit prediction u* = u + dt a, r* = r + dt u* (fluid)
 //   k_density   number density n* at r* (Eq. 5, radius re_n), free-surface
 //               flag n* < beta n0 (Eq. 15); in the weakly-compressible model
-//               also the equation of state (Eq. 16)
+//               also the equation of state (Eq. 16); writes the short lists
+//               (the entries within re_n at r*)
 //   k_gradient  p-hat, pressure gradient (standard MPS form or Eq. 18) and
-//               the first-order Euler update
+//               the first-order Euler update, over the short lists
 // Each particle is handled by a team of TEAM lanes that split its neighbour
 // list (see mps_internal.h).  The precision template: FP64 throughout, or
 // MIXED = FP32 distances and sums on positions stored relative to the lower
@@ -194,7 +195,7 @@ __global__ __launch_bounds__(BLOCK) void k_predict(View v) {
 #pragma unroll
   for (int a = 0; a < DIM; ++a) { us[a] = ui[a]; rs[a] = xi[a]; }
   {
-    const R re = (R)v.re_lap;
+    const R re = (R)v.re_lap, re2 = (R)v.re_lap2;
     R acc[DIM];
 #pragma unroll
     for (int a = 0; a < DIM; ++a) acc[a] = R(0);
@@ -213,7 +214,8 @@ __global__ __launch_bounds__(BLOCK) void k_predict(View v) {
         [&](int32_t, const Rec& rj, bool ok) {
           R d[DIM];
           ri.p.diff(rj.k.p, v.cs32, d);
-          const R wr = weight<R>(v.kernel, sqrt(norm2<DIM, R>(d)), re);
+          const R r2 = norm2<DIM, R>(d);
+          const R wr = weight_r2<R>(v.kernel, r2, rsqrt_k(r2), re, re2);
           R w = ok ? wr : R(0);
           if constexpr (MULTI) {
             // two-phase: harmonic mean of the pair's dynamic viscosities
@@ -280,6 +282,10 @@ __global__ __launch_bounds__(BLOCK) void k_density(View v, int wc) {
   //   Dn_i/Dt = sum_j w'(r_ij) ((r_j - r_i) . (u_j - u_i)) / r_ij
   R s = R(0);
   double dns = 0.0, nk = 0.0, dnk = 0.0;
+  // the short list: entries within re_n at r* (widened by re_n2_keep),
+  // appended in list order by a team ballot; nq is the same in every lane
+  int nq = 0;
+  const int64_t q0 = sl_index(row, 0, v.kpad);
   {
     const R re = (R)v.re_n, re2 = (R)v.re_n2;
     struct Rec {
@@ -298,19 +304,26 @@ __global__ __launch_bounds__(BLOCK) void k_density(View v, int wc) {
           }
           return r;
         },
-        [&](int32_t, const Rec& rj, bool ok) {
+        [&](int32_t j, const Rec& rj, bool ok) {
           R d[DIM];
           pi.diff(rj.p, v.cs32, d);
           const R r2 = norm2<DIM, R>(d);
-          const R rr = sqrt(r2);
+          const R ir = rsqrt_k(r2);
           const bool in = ok && r2 < re2;
-          const R w = weight<R>(v.kernel, rr, re);
+          const bool keep = ok && r2 < v.re_n2_keep;
+          const uint32_t km = team_ballot(keep);
+          if (keep) {
+            const unsigned q = (unsigned)(nq + __popc(km & ((1u << t) - 1u)));
+            v.nbn_list[q0 + (int64_t)(q / TEAM) * WAVE + (q % TEAM)] = j;
+          }
+          nq += __popc(km);
+          const R w = weight_r2<R>(v.kernel, r2, ir, re, re2);
           s += in ? w : R(0);
           if constexpr (SRC >= MPS_SRC_HS) {
             double dud = 0.0;
 #pragma unroll
             for (int a = 0; a < DIM; ++a) dud += d[a] * (rj.u[a] - ui[a]);
-            const double f = dweight<double>(v.kernel, rr, re) * dud / rr;
+            const double f = dweight_r2<double>(v.kernel, r2, ir, re, re2) * dud * ir;
             dns += in ? f : 0.0;
           }
           if constexpr (SRC == MPS_SRC_HS_ECS) {
@@ -321,10 +334,10 @@ __global__ __launch_bounds__(BLOCK) void k_density(View v, int wc) {
               dud += dk[a] * (rj.w[a] - uk[a]);
             }
             const double rk2 = norm2<DIM, double>(dk);
-            const double rk = sqrt(rk2);
+            const double irk = rsqrt_k(rk2);
             const bool ink = ok && rk2 < v.re_n2;
-            const double wk = weight<double>(v.kernel, rk, v.re_n);
-            const double fk = dweight<double>(v.kernel, rk, v.re_n) * dud / rk;
+            const double wk = weight_r2<double>(v.kernel, rk2, irk, v.re_n, v.re_n2);
+            const double fk = dweight_r2<double>(v.kernel, rk2, irk, v.re_n, v.re_n2) * dud * irk;
             nk += ink ? wk : 0.0;
             dnk += ink ? fk : 0.0;
           }
@@ -349,6 +362,7 @@ __global__ __launch_bounds__(BLOCK) void k_density(View v, int wc) {
     }
   }
   if (t != 0) return;
+  v.nbn_count[row] = nq;
   const double ns = (double)s;
   int8_t fl;
   if (ty == MPS_GHOST) fl = MPS_FLAG_GHOST;
@@ -397,7 +411,8 @@ __global__ __launch_bounds__(BLOCK) void k_viscosity(View v) {
       R d[DIM];
       ri.p.diff(rj.p, v.cs32, d);
       const R r2 = norm2<DIM, R>(d);
-      const R fr = weight<R>(v.kernel, sqrt(r2), re) / r2;
+      const R ir = rsqrt_k(r2);
+      const R fr = weight_r2<R>(v.kernel, r2, ir, re, re2) * ir * ir;
       const R f = (ok && r2 < re2) ? fr : R(0);
 #pragma unroll
       for (int a = 0; a < DIM; ++a)
@@ -553,7 +568,8 @@ __global__ __launch_bounds__(BLOCK) void k_gradient(View v, const double* phat) 
     const double pj = rj.pj;
     // flags mark exactly the dummy particles MPS_FLAG_DUMMY
     const bool in = ok && rj.fj != MPS_FLAG_DUMMY && r2 < re2;
-    const R wr = weight<R>(v.kernel, sqrt(r2), re) / r2;
+    const R ir = rsqrt_k(r2);
+    const R wr = weight_r2<R>(v.kernel, r2, ir, re, re2) * ir * ir;
     const R f = in ? wr : R(0);
     if constexpr (CMPS) {
       const double num = (p_i + pj) - (ph_i + rj.phj);
@@ -670,8 +686,13 @@ static void gradient_dim(const View& v, hipStream_t s) {
   }
 }
 
-int launch_gradient(const View& v, int dim, int precision, hipStream_t s) {
+int launch_gradient(const View& v0, int dim, int precision, hipStream_t s) {
   const bool mx = precision == MPS_MIXED;
+  // p-hat and the gradient walk the short lists (within re_n at r*) that
+  // the density kernel of the step wrote
+  View v = v0;
+  v.nb_list = v0.nbn_list;
+  v.nb_count = v0.nbn_count;
   if (dim == 2) {
     if (mx) gradient_dim<2, true>(v, s);
     else gradient_dim<2, false>(v, s);
