@@ -39,10 +39,12 @@ def log(*a):
 
 def algorithmic_bytes(cls: str, n: int, list_entries: int, nnz: int, dim: int,
                       mixed: bool, wc: bool, pipelined: bool = True,
-                      two_level: bool = False) -> float:
+                      two_level: bool = False, short_entries: int = 0) -> float:
     """HBM bytes one launch of a kernel class must move: each particle's own
     state once, its list entries (4 B) and matrix row (column 4 B + value
-    4/8 B).  Gathers of neighbour data are cache hits after the cell sort
+    4/8 B).  The density kernel also writes the short lists (entries within
+    re_n at r*, 4 B each, and a 4-B count per particle) that the gradient
+    kernel reads instead of the full lists.  Gathers of neighbour data are cache hits after the cell sort
     and are not counted.  cg_spmv is the one-kernel pipelined CG iteration
     (row length, 7 FP64 vectors read, 6 written) or, with pipelined=False,
     the SpMV kernel of the two-kernel CG; cg_update is the partial-sum
@@ -71,11 +73,12 @@ def algorithmic_bytes(cls: str, n: int, list_entries: int, nnz: int, dim: int,
     if cls == "predict":
         return n * (4 + 1 + 4 + 2 * vec + f4 + 2 * vec + f4) + list_entries * 4
     if cls == "density":
-        return n * (4 + 1 + (f4 or vec) + 8 + 1 + (8 if wc else 0)) + list_entries * 4
+        return (n * (4 + 1 + (f4 or vec) + 8 + 1 + (8 if wc else 0) + 4) + list_entries * 4
+                + short_entries * 4)
     if cls == "assemble":
         return n * (4 + 1 + 1 + (f4 or vec) + 8 + 8 + 4 + 8 * 6) + list_entries * 4 + nnz * (4 + val)
     if cls == "gradient":
-        return n * (4 + 1 + (f4 or vec) + 8 + 2 * vec + 2 * vec) + list_entries * 4
+        return n * (4 + 1 + (f4 or vec) + 8 + 2 * vec + 2 * vec) + short_entries * 4
     if cls == "sort":
         return n * (2 * (2 * vec + 1 + 4 + 8) + 4 * 4 + 4 + f4)
     raise KeyError(cls)
@@ -237,7 +240,7 @@ def kernel_bandwidth(w, r, mixed, wc):
         avg = ms / nl
         b = algorithmic_bytes(k, w.n, s["list_entries"], s["ppe_nnz"], w.params["dim"], mixed, wc,
                               bool(w.params.get("cg_pipelined", 1)),
-                              w.params.get("precond", 0) == 1)
+                              w.params.get("precond", 0) == 1, s["short_entries"])
         gbs = b / (avg * 1e-3) / 1e9
         out[k] = {"avg_launch_us": 1e3 * avg, "launches": nl,
                   "algorithmic_GBps": None if gbs != gbs else gbs,
@@ -443,7 +446,7 @@ def main():
     ms_dom, n_dom = br["profile"][dom]
     avg_ms = ms_dom / max(n_dom, 1)
     nbytes = algorithmic_bytes(dom, w.n, s["list_entries"], s["ppe_nnz"], 2, True, False,
-                               bool(w.params["cg_pipelined"]))
+                               bool(w.params["cg_pipelined"]), False, s["short_entries"])
     achieved = nbytes / (avg_ms * 1e-3) / 1e9
     log(f"headline {hd['particle_steps_per_s']:.4g} particle-steps/s, "
         f"{hd['ms_per_step']:.4f} ms/step, cg iters last {s['cg_iters_last']}")

@@ -158,6 +158,9 @@ typedef struct {
                               did not converge and that were redone */
   int32_t list_builds;     /* steps that built their neighbour lists with a
                               cell sort (all of them when skin = 0) */
+  int64_t short_entries;   /* entries within re_n at the predicted positions
+                              r* (Eq. 5), the lists that p-hat and the
+                              pressure gradient walk, of the last step */
 } mps_step_stats;
 
 /* Kernel classes for mps_profile: cell binning + sort + permutation (a1),

@@ -90,7 +90,8 @@ struct mps_ctx {
   CGScalars* sc = nullptr;
   int32_t* status = nullptr;
   int32_t* step_count = nullptr;   // steps of a call begun with a clean status
-  int64_t* counts = nullptr;   // [4]: surface, ghost, list entries, matrix nnz
+  int64_t* counts = nullptr;   // surface, ghost, list entries, matrix nnz,
+                                // short-list entries
   // pinned host mirrors
   CGScalars* h_sc = nullptr;
   int32_t* h_status = nullptr;
@@ -409,28 +410,31 @@ __global__ void k_check_types(int64_t n, const int8_t* t, int32_t* status) {
   const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (k < n && (t[k] < MPS_FLUID || t[k] > MPS_GHOST)) atomicOr(status, ST_BADTYPE);
 }
+constexpr int NCOUNTS = 5;
 __global__ __launch_bounds__(256) void k_count_flags(int64_t n, const int8_t* flags,
                                                      const int32_t* nb_count,
+                                                     const int32_t* nbn_count,
                                                      const int32_t* a_nnz, int ppe,
                                                      int64_t* counts) {
   const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  unsigned long long c[4] = {0, 0, 0, 0};
+  unsigned long long c[NCOUNTS] = {0, 0, 0, 0, 0};
   if (k < n) {
     const int8_t f = flags[k];
     c[0] = f == MPS_FLAG_SURFACE;
     c[1] = f == MPS_FLAG_GHOST;
     c[2] = (unsigned long long)nb_count[k];
     c[3] = ppe ? (unsigned long long)a_nnz[k] : 0ull;
+    c[4] = (unsigned long long)nbn_count[k];
   }
-  __shared__ unsigned long long sh[4][4];
+  __shared__ unsigned long long sh[NCOUNTS][4];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < NCOUNTS; ++q) {
     for (int o = 32; o > 0; o >>= 1) c[q] += __shfl_down(c[q], o, 64);
     if ((threadIdx.x & 63) == 0) sh[q][threadIdx.x / 64] = c[q];
   }
   __syncthreads();
   // integer atomics, one per workgroup: the totals do not depend on the order
-  if (threadIdx.x < 4) {
+  if (threadIdx.x < NCOUNTS) {
     const unsigned long long t = sh[threadIdx.x][0] + sh[threadIdx.x][1] + sh[threadIdx.x][2] +
                                  sh[threadIdx.x][3];
     if (t) atomicAdd((unsigned long long*)&counts[threadIdx.x], t);
@@ -1113,7 +1117,7 @@ mps_status mps_init(const mps_params* params, int64_t n, const double* pos, cons
   // [1 + b]: copy taken before a whole-step graph from buffer b
   A(dalloc(&c->status, 1 + mps_ctx::NBUF));
   A(dalloc(&c->step_count, 1));
-  A(dalloc(&c->counts, 4));
+  A(dalloc(&c->counts, NCOUNTS));
   g_bytes = nullptr;
   // [0]: polled solves; [1 + b]: the whole-step graph from buffer b
   if (e == hipSuccess)
@@ -1123,7 +1127,7 @@ mps_status mps_init(const mps_params* params, int64_t n, const double* pos, cons
   if (e == hipSuccess)
     e = hipHostMalloc((void**)&c->h_step_status, (mps_ctx::NBUF + 2) * sizeof(int32_t),
                       hipHostMallocDefault);
-  if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_counts, 4 * sizeof(int64_t), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_counts, NCOUNTS * sizeof(int64_t), hipHostMallocDefault);
   if (e != hipSuccess) {
     mps_free(c);
     return e == hipErrorOutOfMemory ? MPS_E_NOMEM : MPS_E_DEVICE;
@@ -1316,15 +1320,18 @@ mps_status mps_step(mps_ctx* c, int32_t nsteps, mps_step_stats* stats) {
   if (st != MPS_OK) return st;
   if (stats) {
     stats->steps = c->steps_ok;
-    HIPCHK(c, hipMemsetAsync(c->counts, 0, 4 * sizeof(int64_t), c->s));
-    k_count_flags<<<flat_blocks(c->n), 256, 0, c->s>>>(c->n, c->flags, c->nb_count, c->a_nnz,
+    HIPCHK(c, hipMemsetAsync(c->counts, 0, NCOUNTS * sizeof(int64_t), c->s));
+    k_count_flags<<<flat_blocks(c->n), 256, 0, c->s>>>(c->n, c->flags, c->nb_count,
+                                                       c->nbn_count, c->a_nnz,
                                                        c->P.pmode == MPS_PPE_CG, c->counts);
-    HIPCHK(c, hipMemcpyAsync(c->h_counts, c->counts, 4 * sizeof(int64_t), hipMemcpyDeviceToHost, c->s));
+    HIPCHK(c, hipMemcpyAsync(c->h_counts, c->counts, NCOUNTS * sizeof(int64_t),
+                             hipMemcpyDeviceToHost, c->s));
     HIPCHK(c, hipStreamSynchronize(c->s));
     stats->n_surface = c->h_counts[0];
     stats->n_ghost = c->h_counts[1];
     stats->list_entries = c->h_counts[2];
     stats->ppe_nnz = c->h_counts[3];
+    stats->short_entries = c->h_counts[4];
     stats->list_builds = nsteps;
     if (c->ls) {
       int32_t* hb = c->h_step_status + mps_ctx::NBUF + 1;

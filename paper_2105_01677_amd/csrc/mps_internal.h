@@ -436,6 +436,15 @@ __device__ inline double rsqrt_k(double x) {
   return y;
 }
 
+// 1/x for the per-pair means of the two-phase sums (x > 0): the hardware
+// reciprocal refined by two Newton-Raphson steps y <- y + y (1 - x y).
+__device__ inline double rcp_k(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+#pragma unroll
+  for (int k = 0; k < 2; ++k) y = fma(y, fma(-x, y, 1.0), y);
+  return y;
+}
+
 // The kernel weight (Eq. 4, or the cubic kernel) and its derivative from
 // r^2 and ir = 1/r, zero at and beyond re (re2 = re^2).
 template <class R>

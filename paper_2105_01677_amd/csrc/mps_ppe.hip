@@ -233,7 +233,7 @@ __global__ __launch_bounds__(BLOCK) void k_assemble(View v, const double* rhs, i
           const R ir = rsqrt_k(r2);
           R cr = hl ? chl * (ir * ir * ir) : cpp * weight_r2<R>(v.kernel, r2, ir, re, re2);
           // two-phase: 1/rho -> 2/(<rho>_i + <rho>_j), symmetric
-          if constexpr (MULTI) cr *= (R)(v.rho * 2.0 / (rho_i + rhoj[u]));
+          if constexpr (MULTI) cr *= (R)(v.rho * 2.0 * rcp_k(rho_i + rhoj[u]));
           c[u] = in ? cr : R(0);
           dsum += (double)c[u];
           keep[u] = in && fj[u] == MPS_FLAG_INNER;

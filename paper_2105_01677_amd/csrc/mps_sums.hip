@@ -220,7 +220,7 @@ __global__ __launch_bounds__(BLOCK) void k_predict(View v) {
           if constexpr (MULTI) {
             // two-phase: harmonic mean of the pair's dynamic viscosities
             const double ms = mi + rj.mj;
-            w *= (R)(ms > 0.0 ? 2.0 * mi * rj.mj / ms : 0.0);
+            w *= (R)(ms > 0.0 ? 2.0 * mi * rj.mj * rcp_k(ms) : 0.0);
           }
 #pragma unroll
           for (int a = 0; a < DIM; ++a) acc[a] += (R)(rj.k.u[a] - ri.u[a]) * w;

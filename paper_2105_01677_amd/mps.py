@@ -49,7 +49,8 @@ class StepStats(C.Structure):
                 ("cg_iters_total", C.c_int64), ("cg_relres_last", C.c_double),
                 ("n_surface", C.c_int64), ("n_ghost", C.c_int64),
                 ("list_entries", C.c_int64), ("ppe_nnz", C.c_int64),
-                ("cg_redone", C.c_int32), ("list_builds", C.c_int32)]
+                ("cg_redone", C.c_int32), ("list_builds", C.c_int32),
+                ("short_entries", C.c_int64)]
 
 
 _lib = None
@@ -236,7 +237,8 @@ class MPS:
                     "cg_iters_total": s.cg_iters_total, "cg_relres_last": s.cg_relres_last,
                     "n_surface": s.n_surface, "n_ghost": s.n_ghost,
                     "list_entries": s.list_entries, "ppe_nnz": s.ppe_nnz,
-                    "cg_redone": s.cg_redone, "list_builds": s.list_builds}
+                    "cg_redone": s.cg_redone, "list_builds": s.list_builds,
+                    "short_entries": s.short_entries}
 
     def step(self, nsteps: int = 1, *, allow_noconv=False) -> dict:
         st, stats = self.step_status(nsteps)

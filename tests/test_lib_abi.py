@@ -42,9 +42,10 @@ def test_params_layout():
     assert P.skin.offset == 48 + 8 * 20
     assert P.precond.offset == 48 + 8 * 21
     assert ctypes.sizeof(P) == 48 + 8 * 22
-    assert ctypes.sizeof(mps.StepStats) == 64
+    assert ctypes.sizeof(mps.StepStats) == 72
     assert mps.StepStats.cg_redone.offset == 56
     assert mps.StepStats.list_builds.offset == 60
+    assert mps.StepStats.short_entries.offset == 64
 
 
 def test_struct_layouts_match_the_c_header(tmp_path):
