@@ -412,15 +412,6 @@ __device__ inline double row_dot(const int32_t* __restrict__ col, const VT* __re
   return s;
 }
 
-// d w / d r of the two kernels, zero at and beyond re.
-template <class R>
-__device__ inline R dweight(int kernel, R r, R re) {
-  if (!(r < re)) return R(0);
-  if (kernel == MPS_K_KOSHIZUKA) return -re / (r * r);
-  R q = R(1) - r / re;
-  return R(-3) * q * q / re;
-}
-
 // 1/sqrt(x) for the kernel sums (x > 0): the hardware reciprocal square
 // root, in FP64 refined by RSQ_NEWTON Newton-Raphson steps
 // y <- y + y (1 - x y^2) / 2, which square the relative error, so that the

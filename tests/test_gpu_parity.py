@@ -164,6 +164,26 @@ def test_one_step_dam_break_2d_1432_jittered(gpu, orc, precision, cg_tol, pmode,
     _compare_step(gpu, orc, w, tol)
 
 
+@pytest.mark.parametrize("precision,cg_tol,tol", PRECISIONS)
+@pytest.mark.parametrize("dim", [2, 3])
+def test_one_step_pairs_at_re_n(gpu, orc, dim, precision, cg_tol, tol):
+    """Pairs within rounding of re_n at r*: a lattice block with re_n = 2 l0
+    (lattice pairs at exactly 2 l0) and velocities that move a particle by
+    about 1e-7 l0 in the step, so that the density kernel's FP64 test, which
+    writes the short lists, and the gradient's own distance test (FP32 on
+    the mixed path) both meet pairs inside the band by which the short lists
+    are widened."""
+    m = [16, 12] if dim == 2 else [10, 8, 7]
+    w = W.lattice_block(dim, m, walls_below=True)
+    l0, dt = w.params["l0"], w.params["dt"]
+    w.params.update(re_n=2.0 * l0, precision=precision, cg_tol=cg_tol)
+    rng = np.random.default_rng(31)
+    vel = rng.normal(0.0, 1e-7 * l0 / dt, size=w.pos.shape)
+    vel[w.ptype != W.FLUID] = 0.0
+    w = W.Workload(w.name + "_re_n_band", w.pos, vel, w.ptype, w.params)
+    _compare_step(gpu, orc, w, tol)
+
+
 def test_one_step_fp64_production_tolerance(gpu, orc):
     """FP64 path at the production CG tolerance 1e-9: within the bound the
     stopping criterion allows."""
