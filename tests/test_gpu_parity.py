@@ -119,6 +119,20 @@ def test_neighbor_lists_bit_exact_dam_break_2d_44832(gpu, orc):
     m.close()
 
 
+def test_neighbor_lists_bit_exact_dam_break_3d_441282(gpu, orc):
+    """The full 441,282-particle 3-D dam break (bench size), jittered: cell
+    ids, counts and lists against the oracle's cell-linked list."""
+    w = W.jitter(W.config("dam_break_3d_441282", precision=W.MIXED))
+    st, cell_o, cnt_o, lst_o = orc.neighbors_cells(w.params, w.pos, w.ptype)
+    assert st == 0
+    m = gpu.MPS(w.params, w.pos, w.vel, w.ptype)
+    cell, cnt, lst = m.neighbors()
+    np.testing.assert_array_equal(_np(cell), cell_o)
+    np.testing.assert_array_equal(_np(cnt), cnt_o)
+    np.testing.assert_array_equal(_np(lst), lst_o)
+    m.close()
+
+
 def _compare_step(gpu, orc, w, tol, *, steps=1):
     m = gpu.MPS(w.params, w.pos, w.vel, w.ptype)
     s = m.step(steps)
