@@ -255,9 +255,11 @@ __global__ __launch_bounds__(BLOCK) void k_adj_route(View v, AdjView a, int wc) 
 }
 
 // (3b, PPE) after A lambda = x-bar: n*-bar from b_i = (n*_i - n0)/(n0 dt^2)
-// and r*-bar from the couplings c_ij = cpp w_lap(r*_ij), whose cotangent
+// and r*-bar from the couplings c_ij = cpp w_lap(r*_ij) (Eq. 7) or
+// chl / r*_ij^3 (Eq. 23, HL), times the two-phase factor, whose cotangent
 // over both rows of the pair is -(lambda_i - lambda_j)(x_i - x_j) (x and
-// lambda vanish on rows that are not unknowns).
+// lambda vanish on rows that are not unknowns).  The pairs are those of the
+// forward step (the cut-off at re_lap is a frozen decision).
 template <int DIM>
 __global__ __launch_bounds__(BLOCK) void k_adj_ppe(View v, AdjView a) {
   const int64_t k = arow();
@@ -274,6 +276,8 @@ __global__ __launch_bounds__(BLOCK) void k_adj_ppe(View v, AdjView a) {
     double pk[DIM];
     load_vec<DIM>(v.rs, k, pk);
     const double cpp = 2.0 * DIM / (v.lam_lap * v.n0_lap * v.rho);
+    const double chl = 2.0 * v.re_lap / (v.n0_lap * v.rho);
+    const bool hl = v.laplacian == MPS_LAP_HL;
     const int cnt = v.nb_count[k];
     for (int l = t; l < cnt; l += TEAM) {
       const int32_t j = v.nb_list[sl_index(k, l, v.kpad)];
@@ -291,9 +295,10 @@ __global__ __launch_bounds__(BLOCK) void k_adj_ppe(View v, AdjView a) {
       const double lj = ij ? a.lam[j] : 0.0;
       const double xj = ij ? v.p[j] : 0.0;
       const double cbar = -(lk - lj) * (xk - xj);
-      // two-phase: 1/rho -> 2/(<rho>_k + <rho>_j) (constant per pair)
-      const double cp = v.rho_s ? cpp * v.rho * 2.0 / (v.rho_s[k] + v.rho_s[j]) : cpp;
-      const double f = cbar * cp * dw / r;
+      // dc/dr; two-phase: 1/rho -> 2/(<rho>_k + <rho>_j) (constant per pair)
+      const double dcdr = hl ? -3.0 * chl / ((r * r) * (r * r)) : cpp * dw;
+      const double fac = v.rho_s ? v.rho * 2.0 / (v.rho_s[k] + v.rho_s[j]) : 1.0;
+      const double f = cbar * fac * dcdr / r;
 #pragma unroll
       for (int q = 0; q < DIM; ++q) rb[q] -= f * d[q];  // r*_k is the "i" end
     }

@@ -1570,8 +1570,6 @@ mps_status mps_step_adjoint(mps_ctx* c, const double* pos_bar, const double* vel
   if (!c->tape) return fail(c, MPS_E_ARG, "call mps_tape_alloc first");
   if (c->P.grad != MPS_GRAD_STD) return fail(c, MPS_E_ARG, "adjoint needs the standard gradient");
   if (c->P.source != MPS_SRC_STD) return fail(c, MPS_E_ARG, "adjoint needs the source of Eq. 13");
-  if (c->P.laplacian != MPS_LAP_STD)
-    return fail(c, MPS_E_ARG, "adjoint needs the Laplacian of Eq. 7");
   if (c->P.skin > 0.0) return fail(c, MPS_E_ARG, "adjoint needs lists built every step (skin 0)");
   if (c->poisoned) return fail(c, MPS_E_POISONED, "context poisoned; call mps_set_state");
   const bool wc = c->P.pmode == MPS_WC_EOS;

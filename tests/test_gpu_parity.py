@@ -629,21 +629,6 @@ def test_one_step_textbook_cg(gpu, orc, precision, cg_tol, tol):
         _compare_step(gpu, orc, w, tol)
 
 
-def test_hl_refused_by_the_adjoint(gpu):
-    w = W.config("dam_break_2d_1432")
-    w.params.update(laplacian=W.LAP_HL)
-    m = gpu.MPS(w.params, w.pos, w.vel, w.ptype)
-    m.tape_alloc(2)
-    m.tape_save(0)
-    m.step(1)
-    m.tape_load(0)
-    import torch
-    z = torch.zeros((w.n, 2), dtype=torch.float64, device="cuda")
-    with pytest.raises(gpu.MPSError):
-        m.step_adjoint(z, z)
-    m.close()
-
-
 def test_dn_dt_source_refused_by_the_adjoint(gpu):
     w = W.config("dam_break_2d_1432")
     w.params.update(source=W.SRC_HS)
