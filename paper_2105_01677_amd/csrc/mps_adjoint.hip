@@ -57,6 +57,19 @@ __device__ inline void wdw(int kernel, double r, double re, double* w, double* d
   }
 }
 
+// w, dw/dr and d2w/dr2 (0 beyond re).
+__device__ inline void wdw2(int kernel, double r, double re, double* w, double* dw,
+                            double* d2w) {
+  wdw(kernel, r, re, w, dw);
+  if (!(r < re)) {
+    *d2w = 0.0;
+  } else if (kernel == MPS_K_KOSHIZUKA) {
+    *d2w = 2.0 * re / (r * r * r);
+  } else {
+    *d2w = 6.0 * (1.0 - r / re) / (re * re);
+  }
+}
+
 // Effective (clamped) pressure of the forward step.
 __device__ inline double peff(const View& v, int64_t j) {
   const double x = v.p[j];
@@ -254,12 +267,18 @@ __global__ __launch_bounds__(BLOCK) void k_adj_route(View v, AdjView a, int wc) 
   }
 }
 
-// (3b, PPE) after A lambda = x-bar: n*-bar from b_i = (n*_i - n0)/(n0 dt^2)
-// and r*-bar from the couplings c_ij = cpp w_lap(r*_ij) (Eq. 7) or
-// chl / r*_ij^3 (Eq. 23, HL), times the two-phase factor, whose cotangent
-// over both rows of the pair is -(lambda_i - lambda_j)(x_i - x_j) (x and
-// lambda vanish on rows that are not unknowns).  The pairs are those of the
-// forward step (the cut-off at re_lap is a frozen decision).
+// (3b, PPE) after A lambda = x-bar: b-bar = lambda.  Source of Eq. 13,
+// b_i = (n*_i - n0)/(n0 dt^2): n*-bar.  Source of Eq. 21 (HS),
+// b_i = (Dn/Dt)*_i / (n0 dt) with Dn_i/Dt = sum_j g(r) (d . du), g = w_n'/r,
+// d = r*_j - r*_i, du = u*_j - u*_i over the list within re_n: per pair
+// (gathered from both ends, beta = lambda/(n0 dt) on the unknowns)
+//   r*-bar_k -= (beta_k + beta_j) (g du + (d . du) g'/r d),
+//   u*-bar_k -= (beta_k + beta_j) g d.
+// r*-bar from the couplings c_ij = cpp w_lap(r*_ij) (Eq. 7) or chl /
+// r*_ij^3 (Eq. 23, HL), times the two-phase factor, whose cotangent over
+// both rows of the pair is -(lambda_i - lambda_j)(x_i - x_j) (x and lambda
+// vanish on rows that are not unknowns).  The pairs are those of the
+// forward step (the cut-offs are frozen decisions).
 template <int DIM>
 __global__ __launch_bounds__(BLOCK) void k_adj_ppe(View v, AdjView a) {
   const int64_t k = arow();
@@ -269,49 +288,81 @@ __global__ __launch_bounds__(BLOCK) void k_adj_ppe(View v, AdjView a) {
   const bool ik = v.flags[k] == MPS_FLAG_INNER;
   const double lk = ik ? a.lam[k] : 0.0;
   const double xk = ik ? v.p[k] : 0.0;
-  double rb[DIM];
+  const bool hs = v.source == MPS_SRC_HS;
+  const double cb = 1.0 / (v.n0_n * v.dt);
+  const double bk = lk * cb;
+  double rb[DIM], ub[DIM];
 #pragma unroll
-  for (int q = 0; q < DIM; ++q) rb[q] = 0.0;
-  if (tk != MPS_DUMMY && tk != MPS_GHOST) {
-    double pk[DIM];
+  for (int q = 0; q < DIM; ++q) rb[q] = ub[q] = 0.0;
+  if (tk != MPS_GHOST) {
+    double pk[DIM], uk[DIM];
     load_vec<DIM>(v.rs, k, pk);
+    if (hs) load_vec<DIM>(v.us, k, uk);
     const double cpp = 2.0 * DIM / (v.lam_lap * v.n0_lap * v.rho);
     const double chl = 2.0 * v.re_lap / (v.n0_lap * v.rho);
     const bool hl = v.laplacian == MPS_LAP_HL;
     const int cnt = v.nb_count[k];
     for (int l = t; l < cnt; l += TEAM) {
       const int32_t j = v.nb_list[sl_index(k, l, v.kpad)];
-      if (v.type[j] == MPS_DUMMY) continue;
+      const int8_t tj = v.type[j];
       const bool ij = v.flags[j] == MPS_FLAG_INNER;
-      if (!ik && !ij) continue;
+      const bool cpl = tk != MPS_DUMMY && tj != MPS_DUMMY && (ik || ij);
+      const bool src = hs && (ik || ij);
+      if (!cpl && !src) continue;
       double pj[DIM], d[DIM];
       load_vec<DIM>(v.rs, j, pj);
 #pragma unroll
       for (int q = 0; q < DIM; ++q) d[q] = pj[q] - pk[q];
       const double r = sqrt(dot3<DIM>(d, d));
-      if (!(r < v.re_lap)) continue;
-      double w, dw;
-      wdw(v.kernel, r, v.re_lap, &w, &dw);
       const double lj = ij ? a.lam[j] : 0.0;
-      const double xj = ij ? v.p[j] : 0.0;
-      const double cbar = -(lk - lj) * (xk - xj);
-      // dc/dr; two-phase: 1/rho -> 2/(<rho>_k + <rho>_j) (constant per pair)
-      const double dcdr = hl ? -3.0 * chl / ((r * r) * (r * r)) : cpp * dw;
-      const double fac = v.rho_s ? v.rho * 2.0 / (v.rho_s[k] + v.rho_s[j]) : 1.0;
-      const double f = cbar * fac * dcdr / r;
+      if (cpl && r < v.re_lap) {
+        double w, dw;
+        wdw(v.kernel, r, v.re_lap, &w, &dw);
+        const double xj = ij ? v.p[j] : 0.0;
+        const double cbar = -(lk - lj) * (xk - xj);
+        // dc/dr; two-phase: 1/rho -> 2/(<rho>_k + <rho>_j) (constant per pair)
+        const double dcdr = hl ? -3.0 * chl / ((r * r) * (r * r)) : cpp * dw;
+        const double fac = v.rho_s ? v.rho * 2.0 / (v.rho_s[k] + v.rho_s[j]) : 1.0;
+        const double f = cbar * fac * dcdr / r;
 #pragma unroll
-      for (int q = 0; q < DIM; ++q) rb[q] -= f * d[q];  // r*_k is the "i" end
+        for (int q = 0; q < DIM; ++q) rb[q] -= f * d[q];  // r*_k is the "i" end
+      }
+      if (src && r < v.re_n) {
+        double uj[DIM], du[DIM];
+        load_vec<DIM>(v.us, j, uj);
+#pragma unroll
+        for (int q = 0; q < DIM; ++q) du[q] = uj[q] - uk[q];
+        double w, dw, d2w;
+        wdw2(v.kernel, r, v.re_n, &w, &dw, &d2w);
+        const double g = dw / r, gpr = (d2w - dw / r) / (r * r);  // g'(r)/r
+        const double sb = bk + lj * cb, dd = dot3<DIM>(d, du);
+#pragma unroll
+        for (int q = 0; q < DIM; ++q) {
+          rb[q] -= sb * (g * du[q] + dd * gpr * d[q]);
+          ub[q] -= sb * g * d[q];
+        }
+      }
     }
 #pragma unroll
-    for (int q = 0; q < DIM; ++q) rb[q] = team_sum(rb[q]);
+    for (int q = 0; q < DIM; ++q) {
+      rb[q] = team_sum(rb[q]);
+      if (hs) ub[q] = team_sum(ub[q]);
+    }
   }
   if (t == 0) {
-    a.nbar[k] = ik ? lk / (v.n0_n * v.dt * v.dt) : 0.0;
+    a.nbar[k] = ik && !hs ? lk / (v.n0_n * v.dt * v.dt) : 0.0;
     double r0[DIM];
     load_vec<DIM>(a.rs_bar, k, r0);
 #pragma unroll
     for (int q = 0; q < DIM; ++q) r0[q] += rb[q];
     store_vec<DIM>(a.rs_bar, k, r0);
+    if (hs) {
+      double u0[DIM];
+      load_vec<DIM>(a.ut, k, u0);
+#pragma unroll
+      for (int q = 0; q < DIM; ++q) u0[q] += ub[q];
+      store_vec<DIM>(a.ut, k, u0);
+    }
   }
 }
 
