@@ -338,9 +338,10 @@ mps_status mps_tape_load(mps_ctx* ctx, int32_t slot);
  * contributions to dL/dnu (*nu_bar, host) and dL/dg (g_bar[dim], host);
  * either may be NULL.  Recomputes the step's forward stages first; the
  * state is not advanced.  The PPE may use either Laplacian (Eq. 7 or the
- * HL form of Eq. 23) and the source of Eq. 13 or the HS source of Eq. 21.
- * Errors: MPS_E_ARG (no tape; CMPS gradient, the ECS source, or lists kept
- * with a skin, which have no adjoint), the errors of mps_step. */
+ * HL form of Eq. 23), the source of Eq. 13 or the HS source of Eq. 21, and
+ * either gradient (standard or Eq. 18).  Errors: MPS_E_ARG (no tape; the
+ * ECS source or lists kept with a skin, which have no adjoint), the errors
+ * of mps_step. */
 mps_status mps_step_adjoint(mps_ctx* ctx, const double* pos_bar, const double* vel_bar,
                             double* pos_bar_prev, double* vel_bar_prev, double* nu_bar,
                             double* g_bar);

@@ -78,8 +78,10 @@ __device__ inline double peff(const View& v, int64_t j) {
 
 }  // namespace
 
-// p-hat argmin of every fluid particle, with the same cut-off precision as
-// the forward gradient kernel.  Ties go to the smaller sorted index.
+// p-hat argmin of every fluid particle (and, with the gradient of Eq. 18,
+// every wall particle: both ends of a pair carry p-hat there), with the
+// same cut-off precision as the forward kernels.  Ties go to the smaller
+// sorted index.
 template <int DIM, bool MIXED>
 __global__ __launch_bounds__(BLOCK) void k_phat_arg(View v, AdjView a) {
   const int64_t row = arow();
@@ -87,7 +89,8 @@ __global__ __launch_bounds__(BLOCK) void k_phat_arg(View v, AdjView a) {
   if (row >= v.n) return;
   double m = peff(v, row);
   int32_t am = (int32_t)row;
-  if (v.type[row] == MPS_FLUID) {
+  const int8_t ty = v.type[row];
+  if (ty == MPS_FLUID || (v.grad == MPS_GRAD_CMPS && ty == MPS_WALL)) {
     const int cnt = v.nb_count[row];
     for (int l = t; l < cnt; l += TEAM) {
       const int32_t j = v.nb_list[sl_index(row, l, v.kpad)];
@@ -163,7 +166,10 @@ __device__ inline void hdh(int kernel, double r, double re, double* h, double* d
 // (2) Reverse of the pressure gradient.  For particle k:
 //   as owner (k fluid):       phat-bar_k, and r*-bar_k -= d-bar_kj
 //   as neighbour (k non-dummy) of fluid i: p-bar_k, r*-bar_k += d-bar_ik
-// with d-bar_ij = d/n0 (p_j - phat_i) (h G-bar_i + h'/r (d_ij . G-bar_i) d_ij).
+// with d-bar_ij = d/n0 num_ij (h G-bar_i + h'/r (d_ij . G-bar_i) d_ij),
+// num_ij = p_j - phat_i (standard form) or (p_i + p_j) - (phat_i + phat_j)
+// (Eq. 18, which also gives the owner a p-bar and the neighbour a
+// phat-bar for every pair).
 template <int DIM>
 __global__ __launch_bounds__(BLOCK) void k_adj_gradient(View v, AdjView a) {
   const int64_t k = arow();
@@ -181,8 +187,9 @@ __global__ __launch_bounds__(BLOCK) void k_adj_gradient(View v, AdjView a) {
   double xk[DIM], gk[DIM];
   load_vec<DIM>(v.rs, k, xk);
   load_vec<DIM>(a.gbar, k, gk);
+  const bool cmps = v.grad == MPS_GRAD_CMPS;
   const double pk = peff(v, k);
-  const double phk = tk == MPS_FLUID ? peff(v, a.arg[k]) : 0.0;
+  const double phk = tk == MPS_FLUID || (cmps && tk == MPS_WALL) ? peff(v, a.arg[k]) : 0.0;
   double phb = 0.0, pb = 0.0, rb[DIM];
 #pragma unroll
   for (int q = 0; q < DIM; ++q) rb[q] = 0.0;
@@ -202,7 +209,12 @@ __global__ __launch_bounds__(BLOCK) void k_adj_gradient(View v, AdjView a) {
       // k is the owner of pair (k, j)
       const double gd = dot3<DIM>(gk, d);
       phb -= cgd * h * gd;
-      const double c = cgd * (peff(v, j) - phk);
+      double num = peff(v, j) - phk;
+      if (cmps) {
+        pb += cgd * h * gd;
+        num += pk - peff(v, a.arg[j]);
+      }
+      const double c = cgd * num;
 #pragma unroll
       for (int q = 0; q < DIM; ++q) rb[q] -= c * (h * gk[q] + dh / r * gd * d[q]);
     }
@@ -212,7 +224,12 @@ __global__ __launch_bounds__(BLOCK) void k_adj_gradient(View v, AdjView a) {
       load_vec<DIM>(a.gbar, j, gj);
       const double gd = -dot3<DIM>(gj, d);
       pb += cgd * h * gd;
-      const double c = cgd * (pk - peff(v, a.arg[j]));
+      double num = pk - peff(v, a.arg[j]);
+      if (cmps) {
+        phb -= cgd * h * gd;
+        num += peff(v, j) - phk;
+      }
+      const double c = cgd * num;
 #pragma unroll
       for (int q = 0; q < DIM; ++q) rb[q] += c * (h * gj[q] - dh / r * gd * d[q]);
     }
@@ -222,7 +239,7 @@ __global__ __launch_bounds__(BLOCK) void k_adj_gradient(View v, AdjView a) {
 #pragma unroll
   for (int q = 0; q < DIM; ++q) rb[q] = team_sum(rb[q]);
   if (t == 0) {
-    a.phat_bar[k] = tk == MPS_FLUID ? phb : 0.0;
+    a.phat_bar[k] = tk == MPS_FLUID || (cmps && tk == MPS_WALL) ? phb : 0.0;
     a.pbar[k] = pb;
     double r0[DIM];
     load_vec<DIM>(a.rs_bar, k, r0);
@@ -243,11 +260,14 @@ __global__ __launch_bounds__(BLOCK) void k_adj_route(View v, AdjView a, int wc) 
   const int cnt = v.nb_count[m];
   for (int l = t; l < cnt; l += TEAM) {
     const int32_t i = v.nb_list[sl_index(m, l, v.kpad)];
-    if (v.type[i] == MPS_FLUID && a.arg[i] == (int32_t)m) s += a.phat_bar[i];
+    // (phat-bar is 0 on particles without a p-hat)
+    const int8_t ti = v.type[i];
+    if ((ti == MPS_FLUID || ti == MPS_WALL) && a.arg[i] == (int32_t)m) s += a.phat_bar[i];
   }
   s = team_sum(s);
   if (t != 0) return;
-  if (v.type[m] == MPS_FLUID && a.arg[m] == (int32_t)m) s += a.phat_bar[m];
+  const int8_t tm = v.type[m];
+  if ((tm == MPS_FLUID || tm == MPS_WALL) && a.arg[m] == (int32_t)m) s += a.phat_bar[m];
   double pb = a.pbar[m] + s;
   const double x = v.p[m];
   if (v.clamp && !(x > 0.0)) pb = 0.0;

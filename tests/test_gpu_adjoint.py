@@ -81,23 +81,27 @@ def test_adjoint_matches_oracle_dual(torch_gpu, orc, pmode):
     assert rel(g_u, o_u) < 1e-3
 
 
-@pytest.mark.parametrize("source,laplacian", [(W.SRC_STD, W.LAP_HL), (W.SRC_HS, W.LAP_STD),
-                                              (W.SRC_HS, W.LAP_HL)])
-def test_adjoint_improved_pressure_matches_oracle_dual(torch_gpu, orc, source, laplacian):
-    """The PPE with the HL Laplacian (Eq. 23, couplings 2 r_e/(n0 rho r^3);
-    the adjoint's coupling derivative -3 c/r) and/or the HS source (Eq. 21,
-    b = (Dn/Dt)*/(n0 dt); its reverse carries the second derivative of the
-    kernel) against the oracle's dual numbers through the same rollout
-    (FP64)."""
+@pytest.mark.parametrize("source,laplacian,grad", [
+    (W.SRC_STD, W.LAP_HL, W.GRAD_STD), (W.SRC_HS, W.LAP_STD, W.GRAD_STD),
+    (W.SRC_HS, W.LAP_HL, W.GRAD_STD), (W.SRC_STD, W.LAP_STD, W.GRAD_CMPS),
+    (W.SRC_HS, W.LAP_HL, W.GRAD_CMPS)])
+def test_adjoint_improved_pressure_matches_oracle_dual(torch_gpu, orc, source, laplacian,
+                                                       grad):
+    """The improved pressure pipeline: the HL Laplacian (Eq. 23, couplings
+    2 r_e/(n0 rho r^3); the adjoint's coupling derivative -3 c/r), the HS
+    source (Eq. 21, b = (Dn/Dt)*/(n0 dt); its reverse carries the second
+    derivative of the kernel) and the gradient of Eq. 18 (p-hat at both ends
+    of a pair, fluid and wall), alone and together, against the oracle's
+    dual numbers through the same rollout (FP64)."""
     w = W.jitter(W.config("dam_break_2d_1432"), vel_sigma=0.02)
-    w.params.update(cg_tol=1e-12, dt=2e-4, source=source, laplacian=laplacian)
+    w.params.update(cg_tol=1e-12, dt=2e-4, source=source, laplacian=laplacian, grad=grad)
     nsteps, K = 8, 3
     d = _direction(w)
     L, g_nu, g_gx, g_u = gpu_grads(torch_gpu, w, nsteps, K, d)
     st, Lo, o_nu, o_gx, o_u = orc.rollout_grad(w.params, w.pos, w.vel, w.ptype, nsteps, d)
     assert st == 0
-    print("source", source, "laplacian", laplacian, "loss", L, Lo, "nu", g_nu, o_nu, "gx", g_gx,
-          o_gx, "u0", g_u, o_u, flush=True)
+    print("source", source, "laplacian", laplacian, "grad", grad, "loss", L, Lo, "nu", g_nu, o_nu,
+          "gx", g_gx, o_gx, "u0", g_u, o_u, flush=True)
     assert rel(L, Lo) < 1e-8
     assert rel(g_nu, o_nu) < 1e-3
     assert rel(g_gx, o_gx) < 1e-3
