@@ -337,11 +337,11 @@ mps_status mps_tape_load(mps_ctx* ctx, int32_t slot);
  * original order, [n][dim] FP64; may not alias the inputs) and this step's
  * contributions to dL/dnu (*nu_bar, host) and dL/dg (g_bar[dim], host);
  * either may be NULL.  Recomputes the step's forward stages first; the
- * state is not advanced.  The PPE may use either Laplacian (Eq. 7 or the
- * HL form of Eq. 23), the source of Eq. 13 or the HS source of Eq. 21, and
- * either gradient (standard or Eq. 18).  Errors: MPS_E_ARG (no tape; the
- * ECS source or lists kept with a skin, which have no adjoint), the errors
- * of mps_step. */
+ * state is not advanced.  Every pressure option has an adjoint: either
+ * Laplacian (Eq. 7 or the HL form of Eq. 23), each source (Eq. 13, HS of
+ * Eq. 21, HS + ECS of Eq. 24-25) and either gradient (standard or Eq. 18).
+ * Errors: MPS_E_ARG (no tape; lists kept with a skin, which have no
+ * adjoint), the errors of mps_step. */
 mps_status mps_step_adjoint(mps_ctx* ctx, const double* pos_bar, const double* vel_bar,
                             double* pos_bar_prev, double* vel_bar_prev, double* nu_bar,
                             double* g_bar);

@@ -308,7 +308,8 @@ __global__ __launch_bounds__(BLOCK) void k_adj_ppe(View v, AdjView a) {
   const bool ik = v.flags[k] == MPS_FLAG_INNER;
   const double lk = ik ? a.lam[k] : 0.0;
   const double xk = ik ? v.p[k] : 0.0;
-  const bool hs = v.source == MPS_SRC_HS;
+  // the HS term (Dn/Dt)*/(n0 dt) is part of both Dn/Dt sources
+  const bool hs = v.source == MPS_SRC_HS || v.source == MPS_SRC_HS_ECS;
   const double cb = 1.0 / (v.n0_n * v.dt);
   const double bk = lk * cb;
   double rb[DIM], ub[DIM];
@@ -383,6 +384,116 @@ __global__ __launch_bounds__(BLOCK) void k_adj_ppe(View v, AdjView a) {
       for (int q = 0; q < DIM; ++q) u0[q] += ub[q];
       store_vec<DIM>(a.ut, k, u0);
     }
+  }
+}
+
+// (3c, ECS) The terms of Eq. 24-25 at r^k, u^k (the step input):
+//   b_i += (|e_i| g_i + |g_i dt| e_i / dt) / dt,  e = (n - n0)/n0,
+//   g = (Dn/Dt)/n0, both summed over the list within re_n at r^k.
+// (a) per particle: n and Dn/Dt at r^k again, then n-bar = e-bar/n0 and
+// (Dn/Dt)-bar = g-bar/n0 with e-bar = q-bar (s_e g + |g|), g-bar = q-bar
+// (|e| + s_g e), q-bar = lambda/dt and s the sign (+1 at 0) -- into the
+// phat-bar and p-bar arrays, free once the transposed solve is done;
+// (b) the gather of both into the input cotangents, pairs from both ends
+// (the Dn/Dt reverse as for HS, at r^k, u^k):
+//   r-bar_k -= (nbar_k + nbar_j) w'/r d + (beta_k + beta_j) (g du + (d.du) g'/r d),
+//   u-bar_k -= (beta_k + beta_j) g d,     d = r_j - r_k, du = u_j - u_k.
+template <int DIM>
+__global__ __launch_bounds__(BLOCK) void k_adj_ecs_a(View v, AdjView a) {
+  const int64_t k = arow();
+  const int t = team_lane();
+  if (k >= v.n) return;
+  const bool ik = v.flags[k] == MPS_FLAG_INNER;
+  const double lk = ik ? a.lam[k] : 0.0;
+  double n = 0.0, dn = 0.0;
+  if (ik) {
+    double xk[DIM], uk[DIM];
+    load_vec<DIM>(v.pos, k, xk);
+    load_vec<DIM>(v.vel, k, uk);
+    const int cnt = v.nb_count[k];
+    for (int l = t; l < cnt; l += TEAM) {
+      const int32_t j = v.nb_list[sl_index(k, l, v.kpad)];
+      double xj[DIM], uj[DIM], d[DIM], du[DIM];
+      load_vec<DIM>(v.pos, j, xj);
+      load_vec<DIM>(v.vel, j, uj);
+#pragma unroll
+      for (int q = 0; q < DIM; ++q) {
+        d[q] = xj[q] - xk[q];
+        du[q] = uj[q] - uk[q];
+      }
+      const double r2 = dot3<DIM>(d, d);
+      if (!(r2 < v.re_n2)) continue;
+      const double r = sqrt(r2);
+      double w, dw;
+      wdw(v.kernel, r, v.re_n, &w, &dw);
+      n += w;
+      dn += dw * dot3<DIM>(d, du) / r;
+    }
+    n = team_sum(n);
+    dn = team_sum(dn);
+  }
+  if (t == 0) {
+    const double qb = lk / v.dt;
+    const double e = (n - v.n0_n) / v.n0_n, g = dn / v.n0_n;
+    const double se = e < 0.0 ? -1.0 : 1.0, sg = g < 0.0 ? -1.0 : 1.0;
+    a.phat_bar[k] = ik ? qb * (se * g + fabs(g)) / v.n0_n : 0.0;
+    a.pbar[k] = ik ? qb * (fabs(e) + sg * e) / v.n0_n : 0.0;
+  }
+}
+
+template <int DIM>
+__global__ __launch_bounds__(BLOCK) void k_adj_ecs_b(View v, AdjView a) {
+  const int64_t k = arow();
+  const int t = team_lane();
+  if (k >= v.n) return;
+  if (v.type[k] == MPS_GHOST) return;
+  double xk[DIM], uk[DIM], rb[DIM], ub[DIM];
+  load_vec<DIM>(v.pos, k, xk);
+  load_vec<DIM>(v.vel, k, uk);
+#pragma unroll
+  for (int q = 0; q < DIM; ++q) rb[q] = ub[q] = 0.0;
+  const double nk = a.phat_bar[k], bk = a.pbar[k];
+  const int cnt = v.nb_count[k];
+  for (int l = t; l < cnt; l += TEAM) {
+    const int32_t j = v.nb_list[sl_index(k, l, v.kpad)];
+    const double ns = nk + a.phat_bar[j], bs = bk + a.pbar[j];
+    if (ns == 0.0 && bs == 0.0) continue;
+    double xj[DIM], uj[DIM], d[DIM], du[DIM];
+    load_vec<DIM>(v.pos, j, xj);
+    load_vec<DIM>(v.vel, j, uj);
+#pragma unroll
+    for (int q = 0; q < DIM; ++q) {
+      d[q] = xj[q] - xk[q];
+      du[q] = uj[q] - uk[q];
+    }
+    const double r2 = dot3<DIM>(d, d);
+    if (!(r2 < v.re_n2)) continue;
+    const double r = sqrt(r2);
+    double w, dw, d2w;
+    wdw2(v.kernel, r, v.re_n, &w, &dw, &d2w);
+    const double g = dw / r, gpr = (d2w - dw / r) / (r * r), dd = dot3<DIM>(d, du);
+#pragma unroll
+    for (int q = 0; q < DIM; ++q) {
+      rb[q] -= ns * g * d[q] + bs * (g * du[q] + dd * gpr * d[q]);
+      ub[q] -= bs * g * d[q];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < DIM; ++q) {
+    rb[q] = team_sum(rb[q]);
+    ub[q] = team_sum(ub[q]);
+  }
+  if (t == 0) {
+    double r0[DIM], u0[DIM];
+    load_vec<DIM>(a.pos_bar_in, k, r0);
+    load_vec<DIM>(a.vel_bar_in, k, u0);
+#pragma unroll
+    for (int q = 0; q < DIM; ++q) {
+      r0[q] += rb[q];
+      u0[q] += ub[q];
+    }
+    store_vec<DIM>(a.pos_bar_in, k, r0);
+    store_vec<DIM>(a.vel_bar_in, k, u0);
   }
 }
 
@@ -796,8 +907,14 @@ int launch_adjoint_head(const View& v, const AdjView& a, int dim, int precision,
 }
 
 int launch_adjoint_ppe(const View& v, const AdjView& a, int dim, hipStream_t s) {
-  if (dim == 2) k_adj_ppe<2><<<tb(v.n), BLOCK, 0, s>>>(v, a);
-  else k_adj_ppe<3><<<tb(v.n), BLOCK, 0, s>>>(v, a);
+  const bool ecs = v.source == MPS_SRC_HS_ECS;
+  if (dim == 2) {
+    k_adj_ppe<2><<<tb(v.n), BLOCK, 0, s>>>(v, a);
+    if (ecs) k_adj_ecs_a<2><<<tb(v.n), BLOCK, 0, s>>>(v, a);
+  } else {
+    k_adj_ppe<3><<<tb(v.n), BLOCK, 0, s>>>(v, a);
+    if (ecs) k_adj_ecs_a<3><<<tb(v.n), BLOCK, 0, s>>>(v, a);
+  }
   return 0;
 }
 
@@ -820,6 +937,12 @@ int launch_adjoint_tail(const View& v, const AdjView& a, int dim, hipStream_t s)
       k_adj_smag_a<3><<<nt, BLOCK, 0, s>>>(v, a);
       k_adj_smag_b<3><<<nt, BLOCK, 0, s>>>(v, a);
     }
+  }
+  // the ECS terms at r^k, u^k go straight to the input cotangents (the
+  // Dn/Dt sources exist only with the pressure equation)
+  if (v.source == MPS_SRC_HS_ECS) {
+    if (dim == 2) k_adj_ecs_b<2><<<nt, BLOCK, 0, s>>>(v, a);
+    else k_adj_ecs_b<3><<<nt, BLOCK, 0, s>>>(v, a);
   }
   return 0;
 }

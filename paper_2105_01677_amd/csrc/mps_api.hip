@@ -1568,8 +1568,6 @@ mps_status mps_step_adjoint(mps_ctx* c, const double* pos_bar, const double* vel
                             double* g_bar) {
   if (!c || !pos_bar || !vel_bar || !pos_bar_prev || !vel_bar_prev) return MPS_E_ARG;
   if (!c->tape) return fail(c, MPS_E_ARG, "call mps_tape_alloc first");
-  if (c->P.source == MPS_SRC_HS_ECS)
-    return fail(c, MPS_E_ARG, "adjoint needs the source of Eq. 13 or Eq. 21 (no ECS)");
   if (c->P.skin > 0.0) return fail(c, MPS_E_ARG, "adjoint needs lists built every step (skin 0)");
   if (c->poisoned) return fail(c, MPS_E_POISONED, "context poisoned; call mps_set_state");
   const bool wc = c->P.pmode == MPS_WC_EOS;

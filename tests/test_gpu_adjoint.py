@@ -84,15 +84,17 @@ def test_adjoint_matches_oracle_dual(torch_gpu, orc, pmode):
 @pytest.mark.parametrize("source,laplacian,grad", [
     (W.SRC_STD, W.LAP_HL, W.GRAD_STD), (W.SRC_HS, W.LAP_STD, W.GRAD_STD),
     (W.SRC_HS, W.LAP_HL, W.GRAD_STD), (W.SRC_STD, W.LAP_STD, W.GRAD_CMPS),
-    (W.SRC_HS, W.LAP_HL, W.GRAD_CMPS)])
+    (W.SRC_HS, W.LAP_HL, W.GRAD_CMPS), (W.SRC_HS_ECS, W.LAP_STD, W.GRAD_STD),
+    (W.SRC_HS_ECS, W.LAP_HL, W.GRAD_CMPS)])
 def test_adjoint_improved_pressure_matches_oracle_dual(torch_gpu, orc, source, laplacian,
                                                        grad):
     """The improved pressure pipeline: the HL Laplacian (Eq. 23, couplings
     2 r_e/(n0 rho r^3); the adjoint's coupling derivative -3 c/r), the HS
     source (Eq. 21, b = (Dn/Dt)*/(n0 dt); its reverse carries the second
-    derivative of the kernel) and the gradient of Eq. 18 (p-hat at both ends
-    of a pair, fluid and wall), alone and together, against the oracle's
-    dual numbers through the same rollout (FP64)."""
+    derivative of the kernel), the ECS terms (Eq. 24-25, n and Dn/Dt at the
+    step input with their absolute values) and the gradient of Eq. 18
+    (p-hat at both ends of a pair, fluid and wall), alone and together,
+    against the oracle's dual numbers through the same rollout (FP64)."""
     w = W.jitter(W.config("dam_break_2d_1432"), vel_sigma=0.02)
     w.params.update(cg_tol=1e-12, dt=2e-4, source=source, laplacian=laplacian, grad=grad)
     nsteps, K = 8, 3

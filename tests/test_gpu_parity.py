@@ -629,10 +629,9 @@ def test_one_step_textbook_cg(gpu, orc, precision, cg_tol, tol):
         _compare_step(gpu, orc, w, tol)
 
 
-def test_ecs_source_refused_by_the_adjoint(gpu):
-    """The ECS terms (Eq. 24-25) have no adjoint kernels: refused."""
-    w = W.config("dam_break_2d_1432")
-    w.params.update(source=W.SRC_HS_ECS)
+def test_kept_lists_refused_by_the_adjoint(gpu):
+    """Lists kept over steps (skin > 0) have no adjoint: refused."""
+    w = W.with_skin(W.config("dam_break_2d_1432"), 0.2)
     m = gpu.MPS(w.params, w.pos, w.vel, w.ptype)
     m.tape_alloc(2)
     m.tape_save(0)
