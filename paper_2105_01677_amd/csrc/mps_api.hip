@@ -86,7 +86,7 @@ struct mps_ctx {
   double *pl_u = nullptr, *pl_q = nullptr, *pl_w = nullptr;
   double *pl_z = nullptr, *pl_s = nullptr, *pl_m[2] = {nullptr, nullptr},
          *pl_part[2] = {nullptr, nullptr}, *pl_part2[2] = {nullptr, nullptr};
-  int nspmv = 0, nupd = 0, nasmb = 0, npcg = 0, pcg_fused = 0, pcg_pred = 0;
+  int nspmv = 0, nupd = 0, nasmb = 0, npcg = 0, pcg_fused = 0, pcg_pred = 0, pc_block = 0;
   CGScalars* sc = nullptr;
   int32_t* status = nullptr;
   int32_t* step_count = nullptr;   // steps of a call begun with a clean status
@@ -327,6 +327,7 @@ View make_view(const mps_ctx* c) {
   v.npcg = c->npcg;
   v.pcg_fused = c->pcg_fused;
   v.pcg_pred = c->pcg_pred;
+  v.pc_block = c->pc_block;
   v.sc = c->sc;
   v.status = c->status;
   if (c->multi) {
@@ -372,8 +373,10 @@ mps_status check_params(const mps_params* P, int64_t n) {
   if (P->laplacian != MPS_LAP_STD && P->laplacian != MPS_LAP_HL) return MPS_E_ARG;
   if (P->laplacian != MPS_LAP_STD && P->pmode != MPS_PPE_CG) return MPS_E_ARG;
   if (!(P->skin >= 0.0) || !(P->skin < P->re_lap)) return MPS_E_ARG;
-  if (P->precond != MPS_PC_JACOBI && P->precond != MPS_PC_TWO_LEVEL) return MPS_E_ARG;
-  if (P->precond == MPS_PC_TWO_LEVEL && (P->cg_pipelined != 1 || P->pmode != MPS_PPE_CG))
+  if (P->precond != MPS_PC_JACOBI && P->precond != MPS_PC_TWO_LEVEL &&
+      P->precond != MPS_PC_BLOCK)
+    return MPS_E_ARG;
+  if (P->precond != MPS_PC_JACOBI && (P->cg_pipelined != 1 || P->pmode != MPS_PPE_CG))
     return MPS_E_ARG;
   if (P->skin > 0.0 && !(P->cell_size >= P->re_lap + P->skin)) return MPS_E_ARG;
   int64_t nc = 1;
@@ -1086,9 +1089,9 @@ mps_status mps_init(const mps_params* params, int64_t n, const double* pos, cons
   c->nupd = cg_update_blocks(n);
   A(dalloc(&c->partA, (size_t)std::max({c->nspmv, c->nupd, c->nasmb}) * 4));
   A(dalloc(&c->partB, (size_t)c->nspmv));
-  c->pcg_fused =
-      pcg_blocks(n, true) <= pcg_fused_capacity(params->precond == MPS_PC_TWO_LEVEL) ? 1 : 0;
+  c->pcg_fused = pcg_blocks(n, true) <= pcg_fused_capacity(params->precond) ? 1 : 0;
   c->npcg = pcg_blocks(n, c->pcg_fused != 0);
+  c->pc_block = params->precond == MPS_PC_BLOCK ? 1 : 0;
   if (params->skin > 0.0 || params->precond == MPS_PC_TWO_LEVEL)
     A(dalloc(&c->red_blk, std::max<int64_t>((n + BLOCK - 1) / BLOCK,
                                             (c->ncell + BLOCK - 1) / BLOCK)));
@@ -1100,6 +1103,8 @@ mps_status mps_init(const mps_params* params, int64_t n, const double* pos, cons
     A(dalloc(&c->xc, c->ncell));
     A(dalloc(&c->dc[0], c->ncell));
     A(dalloc(&c->dc[1], c->ncell));
+  }
+  if (params->precond != MPS_PC_JACOBI) {
     A(dalloc(&c->pl_u, n));
     A(dalloc(&c->pl_q, n));
     A(dalloc(&c->pl_w, n));
@@ -1178,7 +1183,8 @@ mps_status mps_init(const mps_params* params, int64_t n, const double* pos, cons
     return MPS_E_DEVICE;
   }
   mps_status st = read_status(c);
-  if (st != MPS_OK) {
+  // block Jacobi is applied inside the one-kernel iteration only
+  if (st != MPS_OK || (c->pc_block && !c->pcg_fused)) {
     mps_free(c);
     return MPS_E_ARG;
   }

@@ -149,6 +149,7 @@ struct View {
   double* r_build;    // sorted positions at the last build
   double* red_blk;    // per-workgroup maxima of a step's order-free reductions
                       // (list displacement, coarse Gershgorin bound)
+  int pc_block;       // block-Jacobi preconditioner (fused schedule only)
   // two-level preconditioner of the pipelined CG (null ac: Jacobi)
   double* ac;         // cell-level operator P^T A P, 3^DIM stencil slots,
                       // slot-major: ac[slot * ncell + cell]
@@ -507,7 +508,7 @@ int launch_assemble(const View& v, int dim, int precision, const double* rhs_sor
 int launch_cg_spmv(const View& v, int precision, hipStream_t s);
 int launch_cg_update(const View& v, hipStream_t s);
 int pcg_blocks(int64_t n, bool fused);
-int pcg_fused_capacity(bool two);
+int pcg_fused_capacity(int precond);
 int launch_pcg_setup(const View& v, int precision, int dim, hipStream_t s);
 int launch_pcg_iter(const View& v, int precision, int parity, hipStream_t s);
 int launch_pcg_reduce(const View& v, int parity, hipStream_t s);

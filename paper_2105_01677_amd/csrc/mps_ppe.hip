@@ -509,7 +509,48 @@ __global__ __launch_bounds__(RED_BLOCK) void k_pcg_start(View v) {
   pcg_start_scalars(v, tot, true);
 }
 
-template <class VT, bool FUSED, bool TWO>
+// Block Jacobi (BJ): the diagonal blocks of A over groups of BJ_ROWS
+// consecutive rows, [BJ_ROWS g, BJ_ROWS (g + 1)), which are the rows of one
+// workgroup of the fused schedule, approximated by one Neumann step:
+//   M^-1 w = D^-1 (w - (A_B - D) D^-1 w),
+// i.e. row i subtracts a_ij w_j / d_j over its entries j of the same group.
+// M^-1 = D^-1/2 (2 I - D^-1/2 A_B D^-1/2) D^-1/2 is symmetric, and positive
+// definite while the eigenvalues of D^-1/2 A_B D^-1/2 stay below 2, which
+// holds for the PPE matrix (weakly diagonally dominant, non-positive
+// off-diagonal entries, a neighbour graph that is not bipartite).  A row's
+// entries inside its group are the near ones of a cell-sorted order.
+constexpr int BJ_ROWS = PCG_BLOCK / TEAM;
+
+// sum over the team's row entries j of its group of a_ij y[j - g0] (y in
+// LDS, BJ_ROWS values), entries from slot l on
+template <class VT>
+__device__ inline double bj_row_sum(const View& v, const VT* __restrict__ aval, int64_t row,
+                                    int nnz, int l, int64_t g0, const double* y) {
+  return row_dot<4>(v.a_col, aval, row, nnz, v.kpad, l, [&](int32_t j) {
+    const uint64_t k = (uint64_t)((int64_t)j - g0);
+    return k < (uint64_t)BJ_ROWS ? y[k] : 0.0;
+  });
+}
+
+// u0 = M^-1 r0 of block Jacobi from z = D^-1 r0 (the assembly's), into
+// pl_u; one team per row, one group per workgroup.
+template <class VT>
+__global__ __launch_bounds__(PCG_BLOCK) void k_bj_start(View v) {
+  __shared__ double y[BJ_ROWS];
+  const int lr = threadIdx.x / TEAM;
+  const int64_t g0 = (int64_t)xcd_block() * BJ_ROWS;
+  const int64_t row = g0 + lr;
+  const int t = team_lane();
+  const bool live = row < v.n;
+  if (t == 0) y[lr] = live ? v.z[row] : 0.0;
+  __syncthreads();
+  if (!live) return;
+  const VT* __restrict__ aval = reinterpret_cast<const VT*>(v.a_val);
+  const double s = team_sum(bj_row_sum(v, aval, row, v.a_nnz[row], t, g0, y));
+  if (t == 0) v.pl_u[row] = (v.r[row] - s) * (1.0 / v.diag[row]);
+}
+
+template <class VT, bool FUSED, bool TWO, bool BJ>
 __global__ __launch_bounds__(pcg_nt<FUSED>()) void k_pcg_setup(View v) {
   constexpr int NT = pcg_nt<FUSED>();
   CGScalars* sc = v.sc;
@@ -530,31 +571,52 @@ __global__ __launch_bounds__(pcg_nt<FUSED>()) void k_pcg_setup(View v) {
     if (bb == 0.0 && row < v.n && t == 0) v.p[row] = 0.0;
     return;
   }
+  static_assert(!BJ || (FUSED && TWO), "block Jacobi: fused schedule, u/q/w recurrences");
   const VT* __restrict__ aval = reinterpret_cast<const VT*>(v.a_val);
   // u0 = M^-1 r0: D^-1 r0 written by the assembly (plus, two-level, the
-  // coarse correction added before this kernel)
-  const double* __restrict__ u0 = v.z;
+  // coarse correction added before this kernel; block Jacobi: k_bj_start's)
+  const double* __restrict__ u0 = BJ ? v.pl_u : v.z;
   double gam = 0.0, del = 0.0, rr2 = 0.0;
-  if (row < v.n) {
-    double s = row_dot<4>(v.a_col, aval, row, v.a_nnz[row], v.kpad, t,
+  const bool live = row < v.n;
+  double w = 0.0, dg = 1.0;
+  if (live) {
+    const int nnz = v.a_nnz[row];
+    double s = row_dot<4>(v.a_col, aval, row, nnz, v.kpad, t,
                           [&](int32_t j) { return u0[j]; });
     s = team_sum(s);
+    dg = v.diag[row];
+    const double u = u0[row];
+    w = dg * u + s;
     if (t == 0) {
-      const double dg = v.diag[row], u = u0[row], r = v.r[row];
-      const double w = dg * u + s;
-      // m0 = D^-1 w0 (two-level: its coarse part is added after this kernel)
-      v.pl_m[0][row] = w / dg;
+      const double r = v.r[row];
+      // m0 = D^-1 w0 (two-level: its coarse part is added after this kernel;
+      // block Jacobi: written below)
+      if constexpr (!BJ) v.pl_m[0][row] = w / dg;
       v.pl_z[row] = 0.0;
       v.pl_s[row] = 0.0;
       v.pd[0][row] = 0.0;
       if constexpr (TWO) {
-        v.pl_u[row] = u;
+        if constexpr (!BJ) v.pl_u[row] = u;  // block Jacobi: already there
         v.pl_q[row] = 0.0;
         v.pl_w[row] = w;
       }
       gam = r * u;
       del = w * u;
       rr2 = r * r;
+    }
+  }
+  if constexpr (BJ) {
+    // m0 = M^-1 w0 over the workgroup's group of rows
+    __shared__ double y[BJ_ROWS];
+    const int lr = threadIdx.x / TEAM;
+    const int64_t g0 = row - lr;
+    // (1 / d as in the iteration kernel)
+    const double id = 1.0 / dg;
+    if (t == 0) y[lr] = live ? w * id : 0.0;
+    __syncthreads();
+    if (live) {
+      const double a = team_sum(bj_row_sum(v, aval, row, v.a_nnz[row], t, g0, y));
+      if (t == 0) v.pl_m[0][row] = (w - a) * id;
     }
   }
   double x[3] = {gam, del, rr2};
@@ -611,10 +673,15 @@ __global__ __launch_bounds__(RED2_BLOCK) void k_pcg_reduce(View v) {
 // loads then wait for the row length).  Without it every lane loads its
 // first U slots whatever the row length, which keeps the load chain short
 // but reads padding for rows with few or no entries (dummy particles).
-template <class VT, int PAR, bool FUSED, bool PRED, bool TWO>
-__global__ __launch_bounds__(pcg_nt<FUSED>()) void k_pcg_iter(View v) {
+// Block Jacobi keeps three workgroups per CU resident (six waves per SIMD,
+// at most 80 VGPRs), as the Jacobi and two-level kernels do by themselves,
+// so that the systems of the fused schedule stay within it.
+template <class VT, int PAR, bool FUSED, bool PRED, bool TWO, bool BJ>
+__global__ __launch_bounds__(pcg_nt<FUSED>()) __attribute__((amdgpu_waves_per_eu(BJ ? 6 : 1)))
+void k_pcg_iter(View v) {
   constexpr int U = CG_UNROLL;
   constexpr int NT = pcg_nt<FUSED>();
+  static_assert(!BJ || (FUSED && TWO), "block Jacobi: fused schedule, u/q/w recurrences");
   static_assert(PCG_PK * PCG_BLOCK >= PCG_MAX_BLOCKS, "one partial load per slot");
   static_assert(PCG_SPLIT_G <= PCG_SPLIT_BLOCK, "one slice sum per thread");
   static_assert(!(FUSED && PRED), "the small fused systems are latency-bound");
@@ -663,13 +730,10 @@ __global__ __launch_bounds__(pcg_nt<FUSED>()) void k_pcg_iter(View v) {
   const double* optr = t == 0 ? v.diag : t == 1 ? M : t == 2 ? v.pl_z : t == 3 ? v.pl_s
                        : t == 4 ? v.pd[0] : t == 5 ? v.r : v.p;
   const double ov = optr[rc];
-  // two-level: u = M^-1 r, q = M^-1 s and w are recurrences of their own
-  double o_u = 0.0, o_q = 0.0, o_w = 0.0;
-  if constexpr (TWO) {
-    o_u = v.pl_u[rc];
-    o_q = v.pl_q[rc];
-    o_w = v.pl_w[rc];
-  }
+  // non-diagonal M: u = M^-1 r, q = M^-1 s and w are recurrences of their
+  // own, loaded the same way (u, q, w in team lanes 0, 1, 2)
+  double ov2 = 0.0;
+  if constexpr (TWO) ov2 = (t == 0 ? v.pl_u : t == 1 ? v.pl_q : v.pl_w)[rc];
   // a launch after convergence ends here, without waiting for the loads
   if (conv) return;
   // every load above is issued before any of them is waited for: without
@@ -690,11 +754,31 @@ __global__ __launch_bounds__(pcg_nt<FUSED>()) void k_pcg_iter(View v) {
       aa[u] = VT(0);
     }
   }
+  // block Jacobi: each of the lane's first U entries that lies in the
+  // workgroup's group of rows, as (position in the group, value), the rest
+  // as (BJ_ROWS, 0); parked in LDS by the lane itself (one byte per slot),
+  // so that they are not held in registers over the reductions
+  __shared__ uint2 sh_k[BJ ? NT : 1];
+  __shared__ VT sh_a[BJ ? U : 1][BJ ? NT : 1];
+  if constexpr (BJ) {
+    static_assert(U <= 8 && BJ_ROWS < 256, "one byte per slot");
+    const int64_t g0 = (int64_t)xcd_block() * BJ_ROWS;
+    uint32_t kp[2] = {0u, 0u};
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint64_t k = (uint64_t)((int64_t)jj[u] - g0);
+      const bool ing = t + u * TEAM < nnz && k < (uint64_t)BJ_ROWS;
+      kp[u / 4] |= (ing ? (uint32_t)k : (uint32_t)BJ_ROWS) << (8 * (u % 4));
+      sh_a[u][threadIdx.x] = ing ? aa[u] : VT(0);
+    }
+    sh_k[threadIdx.x] = make_uint2(kp[0], kp[1]);
+  }
 
   // lane 0 of the team takes lane k's value (DPP row_shl:k)
   const double o_d = ov, o_m = dpp_move<DPP_SHL1>(ov), o_z = dpp_move<DPP_SHL2>(ov),
                o_s = dpp_move<DPP_SHL3>(ov), o_p = dpp_move<DPP_SHL4>(ov),
                o_r = dpp_move<DPP_SHL5>(ov), o_x = dpp_move<DPP_SHL6>(ov);
+  const double o_u = ov2, o_q = dpp_move<DPP_SHL1>(ov2), o_w = dpp_move<DPP_SHL2>(ov2);
 
   // -- the scalars (every workgroup alike; workgroup 0 records them) --
   {
@@ -702,14 +786,17 @@ __global__ __launch_bounds__(pcg_nt<FUSED>()) void k_pcg_iter(View v) {
     sum_partials_loaded<NT, PK>(q, npart, tot, sh_in);
     if (pcg_scalars(v, tot, PAR, gam_old, alp_old, bb, blockIdx.x == 0, alpha, beta)) return;
   }
+  // block Jacobi: 1 / d, while the gathers of m are waited for
+  const double o_id = BJ ? 1.0 / o_d : 0.0;
 
   double s = 0.0;
 #pragma unroll
   for (int u = 0; u < U; ++u) s += (double)aa[u] * xv[u];
   // entries beyond the first U per lane (measured: cheaper here than
-  // before the reduction)
-  s += row_dot<4>(v.a_col, aval, rc, nnz, v.kpad, t + U * TEAM,
-                  [&](int32_t j) { return M[j]; });
+  // before the reduction; block Jacobi: two loads in flight per step, which
+  // keeps its registers within three workgroups per CU)
+  s += row_dot<BJ ? 2 : 4>(v.a_col, aval, rc, nnz, v.kpad, t + U * TEAM,
+                           [&](int32_t j) { return M[j]; });
   s = team_sum(s);
   const bool lead = live && t == 0;
   double r, wn, un;
@@ -732,7 +819,8 @@ __global__ __launch_bounds__(pcg_nt<FUSED>()) void k_pcg_iter(View v) {
       v.pl_u[row] = un;
       v.pl_q[row] = qv;
       v.pl_w[row] = wn;
-      Mn[row] = wn / o_d;  // the coarse part is added after this kernel
+      // the coarse part is added after this kernel
+      if constexpr (!BJ) Mn[row] = wn / o_d;
     }
   } else {
     const double w = o_d * o_m;
@@ -754,11 +842,43 @@ __global__ __launch_bounds__(pcg_nt<FUSED>()) void k_pcg_iter(View v) {
     }
   }
   double x[3] = {lead ? r * un : 0.0, lead ? wn * un : 0.0, lead ? r * r : 0.0};
+  // block Jacobi: D^-1 w of the group's rows into LDS before the
+  // reduction's barrier, read after it; the lane's parked entries are read
+  // back before it (its own data; FP64 values after it, for registers)
+  __shared__ double y[BJ ? BJ_ROWS + 1 : 1];
+  constexpr bool KA_EARLY = sizeof(VT) == 4;
+  uint2 kq;
+  VT ka[BJ ? U : 1];
+  if constexpr (BJ) {
+    if (t == 0) y[threadIdx.x / TEAM] = live ? wn * o_id : 0.0;
+    if (threadIdx.x == 0) y[BJ_ROWS] = 0.0;
+    kq = sh_k[threadIdx.x];
+    if constexpr (KA_EARLY) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) ka[u] = sh_a[u][threadIdx.x];
+    }
+  }
   block_sum_all<3, NT>(x, sh_out);
   if (threadIdx.x == 0) {
     const int lb = xcd_block();
 #pragma unroll
     for (int k = 0; k < 3; ++k) v.pl_part[PAR ^ 1][(int64_t)lb * 4 + k] = x[k];
+  }
+  if constexpr (BJ) {
+    // m = M^-1 w: the first U entries per lane parked, the rest reloaded
+    if constexpr (!KA_EARLY) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) ka[u] = sh_a[u][threadIdx.x];
+    }
+    double a = 0.0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t kk = ((u < 4 ? kq.x : kq.y) >> (8 * (u % 4))) & 0xffu;
+      a += (double)ka[u] * y[kk];
+    }
+    a += bj_row_sum(v, aval, rc, nnz, t + U * TEAM, (int64_t)xcd_block() * BJ_ROWS, y);
+    a = team_sum(a);
+    if (lead) Mn[row] = (wn - a) * o_id;
   }
 }
 
@@ -1145,16 +1265,23 @@ int pcg_blocks(int64_t n, bool fused) {
 // resident at once (a second wave of workgroups would double the latency of
 // an iteration), and at most PCG_MAX_BLOCKS partials per reduction.  The
 // workgroups never wait for each other, so this is a matter of speed only.
-int pcg_fused_capacity(bool two) {
+int pcg_fused_capacity(int precond) {
   int dev = 0, cus = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return 0;
   int worst = 1 << 30;
-  const void* ks[] = {two ? (const void*)k_pcg_iter<float, 0, true, false, true>
-                          : (const void*)k_pcg_iter<float, 0, true, false, false>,
-                      two ? (const void*)k_pcg_iter<double, 0, true, false, true>
-                          : (const void*)k_pcg_iter<double, 0, true, false, false>};
+  const void* ks[2];
+  if (precond == MPS_PC_TWO_LEVEL) {
+    ks[0] = (const void*)k_pcg_iter<float, 0, true, false, true, false>;
+    ks[1] = (const void*)k_pcg_iter<double, 0, true, false, true, false>;
+  } else if (precond == MPS_PC_BLOCK) {
+    ks[0] = (const void*)k_pcg_iter<float, 0, true, false, true, true>;
+    ks[1] = (const void*)k_pcg_iter<double, 0, true, false, true, true>;
+  } else {
+    ks[0] = (const void*)k_pcg_iter<float, 0, true, false, false, false>;
+    ks[1] = (const void*)k_pcg_iter<double, 0, true, false, false, false>;
+  }
   for (const void* k : ks) {
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, PCG_BLOCK, 0) != hipSuccess) return 0;
     worst = per < worst ? per : worst;
@@ -1163,26 +1290,37 @@ int pcg_fused_capacity(bool two) {
   return cap < PCG_MAX_BLOCKS ? cap : PCG_MAX_BLOCKS;
 }
 
-template <bool TWO>
+template <bool TWO, bool BJ>
 static void pcg_setup_t(const View& v, bool mx, int dim, hipStream_t s) {
   const unsigned nb = (unsigned)v.npcg;
   if (v.pcg_fused) {
-    if constexpr (TWO) launch_coarse_correct(v, dim, v.r, v.z, s);
-    if (mx) k_pcg_setup<float, true, TWO><<<nb, PCG_BLOCK, 0, s>>>(v);
-    else k_pcg_setup<double, true, TWO><<<nb, PCG_BLOCK, 0, s>>>(v);
-  } else {
+    if constexpr (TWO && !BJ) launch_coarse_correct(v, dim, v.r, v.z, s);
+    if constexpr (BJ) {
+      if (mx) k_bj_start<float><<<nb, PCG_BLOCK, 0, s>>>(v);
+      else k_bj_start<double><<<nb, PCG_BLOCK, 0, s>>>(v);
+    }
+    if (mx) k_pcg_setup<float, true, TWO, BJ><<<nb, PCG_BLOCK, 0, s>>>(v);
+    else k_pcg_setup<double, true, TWO, BJ><<<nb, PCG_BLOCK, 0, s>>>(v);
+  } else if constexpr (!BJ) {
     k_pcg_start<<<1, RED_BLOCK, 0, s>>>(v);
     if constexpr (TWO) launch_coarse_correct(v, dim, v.r, v.z, s);
-    if (mx) k_pcg_setup<float, false, TWO><<<nb, PCG_SPLIT_BLOCK, 0, s>>>(v);
-    else k_pcg_setup<double, false, TWO><<<nb, PCG_SPLIT_BLOCK, 0, s>>>(v);
+    if (mx) k_pcg_setup<float, false, TWO, false><<<nb, PCG_SPLIT_BLOCK, 0, s>>>(v);
+    else k_pcg_setup<double, false, TWO, false><<<nb, PCG_SPLIT_BLOCK, 0, s>>>(v);
   }
-  if constexpr (TWO) launch_coarse_correct(v, dim, v.pl_w, v.pl_m[0], s);
+  if constexpr (TWO && !BJ) launch_coarse_correct(v, dim, v.pl_w, v.pl_m[0], s);
 }
 
 int launch_pcg_setup(const View& v, int precision, int dim, hipStream_t s) {
   const bool mx = precision == MPS_MIXED;
-  if (v.ac) pcg_setup_t<true>(v, mx, dim, s);
-  else pcg_setup_t<false>(v, mx, dim, s);
+  if (v.pc_block) {
+    // block Jacobi runs on the fused schedule only (checked at set-up)
+    if (!v.pcg_fused) return 1;
+    pcg_setup_t<true, true>(v, mx, dim, s);
+  } else if (v.ac) {
+    pcg_setup_t<true, false>(v, mx, dim, s);
+  } else {
+    pcg_setup_t<false, false>(v, mx, dim, s);
+  }
   return 0;
 }
 
@@ -1193,24 +1331,29 @@ int launch_pcg_reduce(const View& v, int parity, hipStream_t s) {
   return 0;
 }
 
-template <class VT, bool FUSED, bool PRED, bool TWO>
+template <class VT, bool FUSED, bool PRED, bool TWO, bool BJ>
 static void pcg_iter_t(const View& v, int parity, hipStream_t s) {
   const unsigned nb = (unsigned)v.npcg;
   const unsigned nt = FUSED ? PCG_BLOCK : PCG_SPLIT_BLOCK;
-  launch_k(parity ? k_pcg_iter<VT, 1, FUSED, PRED, TWO> : k_pcg_iter<VT, 0, FUSED, PRED, TWO>,
+  launch_k(parity ? k_pcg_iter<VT, 1, FUSED, PRED, TWO, BJ>
+                  : k_pcg_iter<VT, 0, FUSED, PRED, TWO, BJ>,
            nb, nt, s, v);
 }
 
 template <class VT, bool TWO>
 static void pcg_iter_s(const View& v, int parity, hipStream_t s) {
-  if (v.pcg_fused) pcg_iter_t<VT, true, false, TWO>(v, parity, s);
-  else if (v.pcg_pred) pcg_iter_t<VT, false, true, TWO>(v, parity, s);
-  else pcg_iter_t<VT, false, false, TWO>(v, parity, s);
+  if (v.pcg_fused) pcg_iter_t<VT, true, false, TWO, false>(v, parity, s);
+  else if (v.pcg_pred) pcg_iter_t<VT, false, true, TWO, false>(v, parity, s);
+  else pcg_iter_t<VT, false, false, TWO, false>(v, parity, s);
 }
 
 int launch_pcg_iter(const View& v, int precision, int parity, hipStream_t s) {
   const bool mx = precision == MPS_MIXED;
-  if (v.ac) {
+  if (v.pc_block) {
+    if (!v.pcg_fused) return 1;
+    if (mx) pcg_iter_t<float, true, false, true, true>(v, parity, s);
+    else pcg_iter_t<double, true, false, true, true>(v, parity, s);
+  } else if (v.ac) {
     if (mx) pcg_iter_s<float, true>(v, parity, s);
     else pcg_iter_s<double, true>(v, parity, s);
   } else {

@@ -28,7 +28,7 @@ FP64, MIXED = 0, 1
 GRAD_STD, GRAD_CMPS = 0, 1
 SRC_STD, SRC_HS, SRC_HS_ECS = 0, 1, 2
 LAP_STD, LAP_HL = 0, 1
-PC_JACOBI, PC_TWO_LEVEL = 0, 1
+PC_JACOBI, PC_TWO_LEVEL, PC_BLOCK = 0, 1, 2
 
 SEED = 2105
 

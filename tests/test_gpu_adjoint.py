@@ -61,14 +61,18 @@ def _direction(w, seed=2105):
     return d
 
 
-@pytest.mark.parametrize("pmode", [W.WC_EOS, W.PPE_CG])
-def test_adjoint_matches_oracle_dual(torch_gpu, orc, pmode):
+@pytest.mark.parametrize("pmode,precond", [(W.WC_EOS, W.PC_JACOBI), (W.PPE_CG, W.PC_JACOBI),
+                                            (W.PPE_CG, W.PC_BLOCK)])
+def test_adjoint_matches_oracle_dual(torch_gpu, orc, pmode, precond):
+    """The standard pipeline; the PPE with the Jacobi and the block-Jacobi
+    preconditioners (forward and adjoint solves alike; the solution, and so
+    the gradient, does not depend on it)."""
     if pmode == W.WC_EOS:
         w = W.sloshing_2d(0.01, precision=W.FP64)
         nsteps, K = 20, 6
     else:
         w = W.jitter(W.config("dam_break_2d_1432"), vel_sigma=0.02)
-        w.params.update(cg_tol=1e-12, dt=2e-4)
+        w.params.update(cg_tol=1e-12, dt=2e-4, precond=precond)
         nsteps, K = 8, 3
     d = _direction(w)
     L, g_nu, g_gx, g_u = gpu_grads(torch_gpu, w, nsteps, K, d)

@@ -65,15 +65,15 @@ def test_kept_lists_are_the_fresh_lists(gpu, orc, precision):
         assert 1 <= builds < nsteps // 2
 
 
-@pytest.mark.parametrize("precond", [W.PC_JACOBI, W.PC_TWO_LEVEL])
+@pytest.mark.parametrize("precond", [W.PC_JACOBI, W.PC_TWO_LEVEL, W.PC_BLOCK])
 @pytest.mark.parametrize("precision,cg_tol,tol", [(W.FP64, 1e-12, 1e-8), (W.MIXED, 1e-9, 1e-4)])
 def test_step_that_keeps_its_lists_against_the_oracle(gpu, orc, precision, cg_tol, tol, precond):
     """The second step (which keeps the first step's superset) against the
     oracle's step from the same state: displacement, velocity, pressure and
     number density at the one-step bars, flags equal outside the tie band.
     With the two-level preconditioner its aggregates are the cells of the
-    last build, which the particle order follows (the solution is unique,
-    so the bars are the same)."""
+    last build, which the particle order follows; block Jacobi groups rows
+    of that order (the solution is unique, so the bars are the same)."""
     for w in _cases(precision):
         w.params.update(cg_tol=cg_tol, precond=precond)
         m = gpu.MPS(w.params, w.pos, w.vel, w.ptype)

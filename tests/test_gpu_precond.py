@@ -107,3 +107,47 @@ def test_two_level_needs_the_pipelined_solver(gpu):
     w = W.config("dam_break_2d_1432")
     with pytest.raises(gpu.MPSError):
         gpu.MPS(dict(w.params, precond=W.PC_TWO_LEVEL, cg_pipelined=0), w.pos, w.vel, w.ptype)
+
+
+# ------------------------------------------------------------- block Jacobi
+# PC_BLOCK: one Neumann step of block Jacobi over runs of 64 consecutive
+# (cell-sorted) rows, inside the one-kernel iteration.  Same bars: the PPE
+# solution is unique, so the one-step parity against the oracle holds.
+
+@pytest.mark.parametrize("precision,cg_tol,tol", PRECISIONS)
+def test_block_jacobi_small_systems(gpu, orc, precision, cg_tol, tol):
+    """2-D 1,432 (jittered, 23 row groups and a ragged last one) and 44,832
+    (701 groups), and a 3-D block with walls, against the oracle."""
+    for w in (W.jitter(W.config("dam_break_2d_1432", precision=precision)),
+              W.jitter(W.config("dam_break_2d_44832", precision=precision)),
+              W.jitter(W.lattice_block(3, [16, 12, 10], walls_below=True, dt=2e-4))):
+        w.params.update(precision=precision, cg_tol=cg_tol, precond=W.PC_BLOCK)
+        _step_vs_oracle(gpu, orc, w, tol)
+
+
+def test_block_jacobi_two_phase_and_improved_pressure(gpu, orc):
+    """Two-phase densities and the HS source with the HL Laplacian (other
+    matrix values, same structure), mixed precision, against the oracle."""
+    w = W.jitter(W.config("dam_break_2d_1432", precision=W.MIXED))
+    w.params.update(cg_tol=1e-9, precond=W.PC_BLOCK, source=W.SRC_HS, laplacian=W.LAP_HL)
+    _step_vs_oracle(gpu, orc, w, 1e-4)
+
+
+def test_block_jacobi_fewer_iterations(gpu):
+    """The 44,832-particle dam break over 10 steps: fewer iterations than
+    Jacobi."""
+    w = W.config("dam_break_2d_44832", precision=W.MIXED)
+    jac, blk = _iters(gpu, w, W.PC_JACOBI, 10), _iters(gpu, w, W.PC_BLOCK, 10)
+    print("44,832: CG iterations per step, Jacobi", jac, "block Jacobi", blk, flush=True)
+    assert blk < 0.9 * jac
+
+
+def test_block_jacobi_needs_the_fused_schedule(gpu):
+    """Refused where the system is too large for the one-kernel iteration,
+    and with the textbook CG."""
+    w = W.config("dam_break_3d_441282", precision=W.MIXED)
+    with pytest.raises(gpu.MPSError):
+        gpu.MPS(dict(w.params, precond=W.PC_BLOCK), w.pos, w.vel, w.ptype)
+    w = W.config("dam_break_2d_1432")
+    with pytest.raises(gpu.MPSError):
+        gpu.MPS(dict(w.params, precond=W.PC_BLOCK, cg_pipelined=0), w.pos, w.vel, w.ptype)
