@@ -423,7 +423,7 @@ def main():
         return
 
     # the pipelined CG with the block-Jacobi preconditioner (64-row groups):
-    # the same solution to the same tolerance in about 22 % fewer iterations
+    # the same solution to the same tolerance in about 25 % fewer iterations
     # than Jacobi (that line below)
     w = W.config("dam_break_2d_44832", precision=W.MIXED, pmode=W.PPE_CG)
     w.params["precond"] = W.PC_BLOCK

@@ -87,9 +87,10 @@ enum { MPS_LAP_STD = 0, MPS_LAP_HL = 1 };
  * additive two-level preconditioner D^-1 + P C P^T, P the aggregation of
  * the pressure unknowns by background grid cell, C three Chebyshev steps on
  * the cell-level operator P^T A P (for the large systems the paper solves
- * by ICCG: same solution, fewer iterations); or one Neumann step of block
- * Jacobi, 2 D^-1 - D^-1 A_B D^-1 with A_B the diagonal blocks of A over
- * runs of 64 consecutive cell-sorted rows (applied inside the one-kernel
+ * by ICCG: same solution, fewer iterations); or one damped Neumann step
+ * of block Jacobi, D^-1 - 1.5 D^-1 (A_B - D) D^-1 with A_B the diagonal
+ * blocks of A over runs of 64 consecutive cell-sorted rows (symmetric
+ * positive definite for the PPE matrices; applied inside the one-kernel
  * iteration, so only for systems whose 64-row groups are all resident on
  * the device at once: up to 49,152 particles on MI355X; larger systems get
  * MPS_E_ARG at mps_init).  Either non-Jacobi choice needs cg_pipelined = 1

@@ -509,17 +509,24 @@ __global__ __launch_bounds__(RED_BLOCK) void k_pcg_start(View v) {
   pcg_start_scalars(v, tot, true);
 }
 
-// Block Jacobi (BJ): the diagonal blocks of A over groups of BJ_ROWS
+// Block Jacobi (BJ): the diagonal blocks A_B of A over groups of BJ_ROWS
 // consecutive rows, [BJ_ROWS g, BJ_ROWS (g + 1)), which are the rows of one
-// workgroup of the fused schedule, approximated by one Neumann step:
-//   M^-1 w = D^-1 (w - (A_B - D) D^-1 w),
-// i.e. row i subtracts a_ij w_j / d_j over its entries j of the same group.
-// M^-1 = D^-1/2 (2 I - D^-1/2 A_B D^-1/2) D^-1/2 is symmetric, and positive
-// definite while the eigenvalues of D^-1/2 A_B D^-1/2 stay below 2, which
-// holds for the PPE matrix (weakly diagonally dominant, non-positive
-// off-diagonal entries, a neighbour graph that is not bipartite).  A row's
-// entries inside its group are the near ones of a cell-sorted order.
+// workgroup of the fused schedule, approximated by one damped Neumann step:
+//   M^-1 w = D^-1 (w - omega (A_B - D) D^-1 w),
+// i.e. row i subtracts omega a_ij w_j / d_j over its entries j of the same
+// group.  With N = D^-1/2 (A_B - D) D^-1/2 (zero diagonal, entries <= 0),
+// M^-1 = D^-1/2 (I - omega N) D^-1/2 is symmetric, and positive definite
+// while omega lambda_max(N) < 1.  lambda_max(N) is small because a group's
+// neighbour graph is far from bipartite: measured 0.25 (2-D, kernel
+// Laplacian) and 0.42 (2-D, Eq. 23 Laplacian) on the dam-break matrices,
+// 0.10 and 0.18 in 3-D, so omega = 1.5 keeps M^-1 positive definite with
+// margin (the undamped step, omega = 1, is definite for every weakly
+// diagonally dominant A of this sign pattern).  CG iterations to 1e-9 on
+// the 44,832-particle matrix: 89 Jacobi; omega 1, 1.5, 2: 69, 66, 65.
+// A row's entries inside its group are the near ones of a cell-sorted
+// order.
 constexpr int BJ_ROWS = PCG_BLOCK / TEAM;
+constexpr double BJ_OMEGA = 1.5;
 
 // sum over the team's row entries j of its group of a_ij y[j - g0] (y in
 // LDS, BJ_ROWS values), entries from slot l on
@@ -547,7 +554,7 @@ __global__ __launch_bounds__(PCG_BLOCK) void k_bj_start(View v) {
   if (!live) return;
   const VT* __restrict__ aval = reinterpret_cast<const VT*>(v.a_val);
   const double s = team_sum(bj_row_sum(v, aval, row, v.a_nnz[row], t, g0, y));
-  if (t == 0) v.pl_u[row] = (v.r[row] - s) * (1.0 / v.diag[row]);
+  if (t == 0) v.pl_u[row] = (v.r[row] - BJ_OMEGA * s) * (1.0 / v.diag[row]);
 }
 
 template <class VT, bool FUSED, bool TWO, bool BJ>
@@ -616,7 +623,7 @@ __global__ __launch_bounds__(pcg_nt<FUSED>()) void k_pcg_setup(View v) {
     __syncthreads();
     if (live) {
       const double a = team_sum(bj_row_sum(v, aval, row, v.a_nnz[row], t, g0, y));
-      if (t == 0) v.pl_m[0][row] = (w - a) * id;
+      if (t == 0) v.pl_m[0][row] = (w - BJ_OMEGA * a) * id;
     }
   }
   double x[3] = {gam, del, rr2};
@@ -878,7 +885,7 @@ void k_pcg_iter(View v) {
     }
     a += bj_row_sum(v, aval, rc, nnz, t + U * TEAM, (int64_t)xcd_block() * BJ_ROWS, y);
     a = team_sum(a);
-    if (lead) Mn[row] = (wn - a) * o_id;
+    if (lead) Mn[row] = (wn - BJ_OMEGA * a) * o_id;
   }
 }
 

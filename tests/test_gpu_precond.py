@@ -125,12 +125,23 @@ def test_block_jacobi_small_systems(gpu, orc, precision, cg_tol, tol):
         _step_vs_oracle(gpu, orc, w, tol)
 
 
-def test_block_jacobi_two_phase_and_improved_pressure(gpu, orc):
-    """Two-phase densities and the HS source with the HL Laplacian (other
-    matrix values, same structure), mixed precision, against the oracle."""
-    w = W.jitter(W.config("dam_break_2d_1432", precision=W.MIXED))
-    w.params.update(cg_tol=1e-9, precond=W.PC_BLOCK, source=W.SRC_HS, laplacian=W.LAP_HL)
-    _step_vs_oracle(gpu, orc, w, 1e-4)
+@pytest.mark.parametrize("precision,cg_tol,tol", PRECISIONS)
+def test_block_jacobi_two_phase_and_improved_pressure(gpu, orc, precision, cg_tol, tol):
+    """Other matrix values on the same structure: the HS source with the HL
+    Laplacian (Eq. 21, 23; the largest in-group coupling of the two
+    Laplacians), and two-phase densities and viscosities with the
+    Smagorinsky model (a 2-D box, heavy layer on top), against the
+    oracle."""
+    w = W.jitter(W.config("dam_break_2d_1432", precision=precision))
+    w.params.update(cg_tol=cg_tol, precond=W.PC_BLOCK, source=W.SRC_HS, laplacian=W.LAP_HL)
+    _step_vs_oracle(gpu, orc, w, tol)
+    w = W.jitter(W.lattice_block(2, 18, walls_below=True, dt=1e-4))
+    heavy = w.pos[:, 1] > 0.09
+    rho = np.where(heavy, 1500.0, 1000.0)
+    nu = np.where(heavy, 1e-3, 1e-4)
+    w.params.update(precision=precision, cg_tol=cg_tol, precond=W.PC_BLOCK, smag_cs=0.12,
+                    nu=1e-6)
+    _step_vs_oracle(gpu, orc, w, tol, rho_i=rho, nu_i=nu)
 
 
 def test_block_jacobi_fewer_iterations(gpu):
