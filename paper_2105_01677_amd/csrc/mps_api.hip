@@ -468,9 +468,27 @@ mps_status read_status(mps_ctx* c) {
   return status_error(c, st);
 }
 
-// Counts a step begun with a clean status word (one thread).
-__global__ void k_step_begin(const int32_t* status, int32_t* count) {
-  if (threadIdx.x == 0 && *status == 0) *count += 1;
+// Counts a step begun with a clean status word and, for a whole-step graph,
+// keeps a copy of that word from before the step (one thread).
+__global__ void k_step_begin(const int32_t* status, int32_t* count, int32_t* snap) {
+  if (threadIdx.x == 0) {
+    const int32_t st = *status;
+    if (snap) *snap = st;
+    if (st == 0) *count += 1;
+  }
+}
+
+// End of a whole-step graph: the CG scalars and the status word into their
+// pinned host copies, which the host reads once the step's event has
+// completed (one wavefront, a word per lane; one kernel instead of two
+// copies in the graph).
+__global__ void k_step_end(const CGScalars* sc, const int32_t* status, CGScalars* h_sc,
+                           int32_t* h_status) {
+  constexpr int NW = (int)(sizeof(CGScalars) / sizeof(int32_t));
+  static_assert(sizeof(CGScalars) % sizeof(int32_t) == 0 && NW <= 64, "a word per lane");
+  const int i = threadIdx.x;
+  if (i < NW) reinterpret_cast<int32_t*>(h_sc)[i] = reinterpret_cast<const int32_t*>(sc)[i];
+  if (i == 0) *h_status = *status;
 }
 
 // Accumulate the recorded event pairs (the stream must be synchronised).
@@ -593,8 +611,8 @@ void enqueue_assemble(mps_ctx* c, const View& v, const double* rhs, bool zero_x0
 
 // Stages before the pressure solve: a1-a5 (PPE) or a1-a4 + a7 (EOS).
 // Leaves the context in the new sorted order (flips cur).
-void enqueue_pre(mps_ctx* c) {
-  k_step_begin<<<1, 64, 0, c->s>>>(c->status, c->step_count);
+void enqueue_pre(mps_ctx* c, int32_t* status_snap = nullptr) {
+  k_step_begin<<<1, 64, 0, c->s>>>(c->status, c->step_count, status_snap);
   search(c);
   View v = make_view(c);
   if (c->multi) {
@@ -782,15 +800,10 @@ mps_status step_graph(mps_ctx* c, int par, int ncg, hipGraphExec_t* out) {
   const int cur0 = c->cur;
   c->cur = par;
   mps_status st = capture(c, &slot->g, [&] {
-    (void)hipMemcpyAsync(c->status + 1 + par, c->status, sizeof(int32_t),
-                         hipMemcpyDeviceToDevice, c->s);
-    enqueue_pre(c);
+    enqueue_pre(c, c->status + 1 + par);
     enqueue_cg(c, ncg);
-    (void)hipMemcpyAsync(c->h_sc + 1 + par, c->sc, sizeof(CGScalars), hipMemcpyDeviceToHost,
-                         c->s);
     enqueue_post(c);
-    (void)hipMemcpyAsync(c->h_step_status + par, c->status, sizeof(int32_t),
-                         hipMemcpyDeviceToHost, c->s);
+    k_step_end<<<1, 64, 0, c->s>>>(c->sc, c->status, c->h_sc + 1 + par, c->h_step_status + par);
   });
   c->cur = cur0;
   if (st != MPS_OK) {
