@@ -123,7 +123,7 @@ struct mps_ctx {
     uint64_t used = 0;
     hipGraphExec_t g = nullptr;
   };
-  static constexpr int kStepGraphs = 6;
+  static constexpr int kStepGraphs = 12;
   StepGraph g_step[NBUF][kStepGraphs];
   hipEvent_t ev_step[NBUF] = {};  // end of the whole-step graph from buffer b
   bool ev_step_created = false;
@@ -146,6 +146,10 @@ struct mps_ctx {
   bool poisoned = false;
   bool ppe_valid = false;
   int last_iters = 0;
+  // margin of the speculative CG count (spec_ncg)
+  static constexpr int CG_MARGIN_MIN = 3, CG_MARGIN_MAX = 9;
+  int cg_margin = CG_MARGIN_MIN;
+  int cg_quiet = 0;    // accepted speculative steps since the last change
   int32_t steps_ok = 0;    // steps of the running mps_step call completed
   char err[256] = {0};
 };
@@ -864,11 +868,29 @@ mps_status one_step_polled(mps_ctx* c, mps_step_stats* st) {
   return res;
 }
 
-// CG iterations of a speculative whole step: the previous step's count
-// plus a margin (launches after convergence return at once).
+// CG iterations of a speculative whole step: the last accepted step's
+// count plus a margin, rounded up to even (launches after convergence
+// return at once; a step that needs more is redone, which costs about two
+// steps).  The margin starts at 3, grows by 3 (to at most 9) at every redo
+// and shrinks by 1 after 50 accepted steps without one.  With two steps in
+// flight the count comes from two steps back; on the 2-D dam break it
+// rises by at most 3 over two steps with the kernel Laplacian, by more
+// with the Eq. 23 Laplacian (one redo in 240 steps under this rule,
+// against 5 with a fixed margin of 3).
 int spec_ncg(const mps_ctx* c) {
-  const int B = mps_ctx::CG_BATCH;
-  return std::min(((c->last_iters + B + B - 1) / B) * B, ((c->P.cg_maxit + B - 1) / B) * B);
+  const int B = 2;
+  return std::min(((c->last_iters + c->cg_margin + B - 1) / B) * B,
+                  ((c->P.cg_maxit + B - 1) / B) * B);
+}
+
+void margin_after(mps_ctx* c, bool redone) {
+  if (redone) {
+    c->cg_margin = std::min(mps_ctx::CG_MARGIN_MAX, c->cg_margin + 3);
+    c->cg_quiet = 0;
+  } else if (++c->cg_quiet >= 50 && c->cg_margin > mps_ctx::CG_MARGIN_MIN) {
+    c->cg_margin -= 1;
+    c->cg_quiet = 0;
+  }
 }
 
 // Spin on an event (the host's next decision waits for it: a blocking
@@ -906,6 +928,7 @@ mps_status redo_step(mps_ctx* c, int b, mps_step_stats* st) {
   c->cur = b;
   // the discarded steps may have rebuilt the lists in another order
   force_build(c);
+  margin_after(c, true);
   if (st) st->cg_redone += 1;
   return one_step_polled(c, st);
 }
@@ -920,6 +943,7 @@ int accept_step(mps_ctx* c, int b, mps_step_stats* st) {
   c->cur = (b + 1) % mps_ctx::NBUF;
   c->ppe_valid = true;
   record_cg(c, st, h.iter, h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0);
+  margin_after(c, false);
   return 1;
 }
 
