@@ -162,3 +162,41 @@ def test_block_jacobi_needs_the_fused_schedule(gpu):
     w = W.config("dam_break_2d_1432")
     with pytest.raises(gpu.MPSError):
         gpu.MPS(dict(w.params, precond=W.PC_BLOCK, cg_pipelined=0), w.pos, w.vel, w.ptype)
+
+
+@pytest.mark.parametrize("precision", [W.FP64, W.MIXED])
+def test_block_jacobi_pressure_solve(gpu, orc, precision):
+    """mps_pressure_solve with block Jacobi against the dense solution of the
+    assembled system (mps_get_ppe) for a seeded right-hand side, and the
+    same solve with Jacobi; then the state's own right-hand side, twice in a
+    row (the preconditioner's start is rebuilt for every solve)."""
+    w = W.jitter(W.config("dam_break_2d_1432", precision=precision))
+    rng = np.random.default_rng(11)
+    b2 = rng.normal(size=w.n)
+    sols = {}
+    for pc in (W.PC_BLOCK, W.PC_JACOBI):
+        m = gpu.MPS(dict(w.params, precond=pc, cg_tol=1e-12), w.pos, w.vel, w.ptype)
+        p, it, rr = m.pressure_solve()
+        p_again, it_again, _ = m.pressure_solve()
+        assert it_again == it and np.array_equal(_np(p_again), _np(p))
+        p2, it2, rr2 = m.pressure_solve(b2)
+        A = {k: _np(v) for k, v in m.get_ppe().items()}
+        m.close()
+        sols[pc] = (_np(p), _np(p2), it2)
+    # the pressure unknowns: the oracle's inner particles of the same state
+    st, o = orc.step(dict(w.params, clamp=0), w.pos, w.vel, w.ptype, want_lists=False)
+    assert st == 0
+    inner = np.nonzero(o["flags"] == 0)[0]
+    n = w.n
+    Ad = np.zeros((n, n))
+    for i in inner:
+        k = A["nnz"][i]
+        Ad[i, A["cols"][i, :k]] = A["vals"][i, :k]
+        Ad[i, i] = A["diag"][i]
+    ref = np.zeros(n)
+    ref[inner] = np.linalg.solve(Ad[np.ix_(inner, inner)], b2[inner])
+    print("iterations: block Jacobi", sols[W.PC_BLOCK][2], "Jacobi", sols[W.PC_JACOBI][2],
+          flush=True)
+    assert rel_err(sols[W.PC_BLOCK][1], ref) < 1e-8
+    assert rel_err(sols[W.PC_BLOCK][0], sols[W.PC_JACOBI][0]) < 1e-8
+    assert sols[W.PC_BLOCK][2] < sols[W.PC_JACOBI][2]
