@@ -397,17 +397,18 @@ __global__ __launch_bounds__(BLOCK) void k_cg_update(View v) {
 
 // ------------------------------------------------------- pipelined variant
 // Preconditioned CG with one global reduction per iteration (Ghysels and
-// Vanroose's pipelined CG) and the Jacobi preconditioner D = diag(A):
-//   gamma = (r, u), delta = (w, u), m = D^-1 w, n = A m,
+// Vanroose's pipelined CG), preconditioner M:
+//   gamma = (r, u), delta = (w, u), m = M^-1 w, n = A m,
 //   beta = gamma/gamma_old, alpha = gamma/(delta - beta gamma/alpha_old),
-//   z = n + beta z, s = w + beta s, p = u + beta p,
-//   x += alpha p, r -= alpha s, w -= alpha z.
-// With a diagonal preconditioner the recurrences u = D^-1 r and
-// q = D^-1 s reduce to one division each, so u and q are not stored, and
-// w = D m is not stored either: m is the one vector the SpMV gathers,
+//   z = n + beta z, q = m + beta q, s = w + beta s, p = u + beta p,
+//   x += alpha p, r -= alpha s, u -= alpha q, w -= alpha z.
+// With the Jacobi preconditioner M = D = diag(A) the recurrences u = D^-1 r
+// and q = D^-1 s reduce to one division each, so u and q are not stored,
+// and w = D m is not stored either: m is the one vector the SpMV gathers,
 // double buffered because the neighbours' m of this iteration are read
 // while the new m is written.  Per row an iteration loads D, m, z, s, p, r,
-// x and stores m, z, s, p, r, x.
+// x and stores m, z, s, p, r, x.  With block Jacobi (BJ, below) or the
+// two-level M (TWO) u, q and w are stored as well.
 // Every workgroup handles one group of PCG_ROWS rows and leaves one partial
 // of the next iteration's dot products.  Two schedules:
 //   fused  (grid <= pcg_fused_capacity(), all workgroups resident): one
@@ -419,8 +420,10 @@ __global__ __launch_bounds__(BLOCK) void k_cg_update(View v) {
 // In both, every load that does not depend on the scalars (the row length,
 // its first matrix entries, the gathers of m, the row's own vectors) is
 // issued first, so their latencies overlap.
-// Setup: w0 = A u0 with u0 = D^-1 r0 from the assembly; gamma_old = inf and
-// alpha_old = 1 make the first iteration beta = 0, alpha = gamma/delta.
+// Setup: w0 = A u0 with u0 = M^-1 r0 (Jacobi: D^-1 r0 from the assembly;
+// block Jacobi: k_bj_start; two-level: plus the coarse correction), and
+// m0 = M^-1 w0; gamma_old = inf and alpha_old = 1 make the first iteration
+// beta = 0, alpha = gamma/delta.
 // workgroup size of the two schedules (measured on MI355X: 512 fused, 256
 // split)
 template <bool FUSED>
