@@ -36,9 +36,11 @@ def _run(mps, w, steps, graphs, maxit=None, per_call=1):
     return out, stats
 
 
+@pytest.mark.parametrize("precond", [W.PC_JACOBI, W.PC_BLOCK])
 @pytest.mark.parametrize("precision", [W.MIXED, W.FP64])
-def test_speculative_steps_match_polled(gpu, precision):
+def test_speculative_steps_match_polled(gpu, precision, precond):
     w = W.jitter(W.config("dam_break_2d_1432", precision=precision))
+    w.params["precond"] = precond
     a, sa = _run(gpu, w, 30, True)
     b, sb = _run(gpu, w, 30, False)
     assert [s["cg_iters_last"] for s in sa] == [s["cg_iters_last"] for s in sb]
@@ -47,11 +49,13 @@ def test_speculative_steps_match_polled(gpu, precision):
         assert np.array_equal(a[k], b[k]), k
 
 
+@pytest.mark.parametrize("precond", [W.PC_JACOBI, W.PC_BLOCK])
 @pytest.mark.parametrize("precision", [W.MIXED, W.FP64])
-def test_pipelined_steps_match_polled(gpu, precision):
+def test_pipelined_steps_match_polled(gpu, precision, precond):
     """30 steps in one call (two step graphs in flight) against 30 polled
     single steps, and against 3 calls of 10."""
     w = W.jitter(W.config("dam_break_2d_1432", precision=precision))
+    w.params["precond"] = precond
     a, sa = _run(gpu, w, 30, True, per_call=30)
     b, _ = _run(gpu, w, 30, False)
     c, _ = _run(gpu, w, 30, True, per_call=10)
@@ -61,11 +65,13 @@ def test_pipelined_steps_match_polled(gpu, precision):
         assert np.array_equal(c[k], b[k]), k
 
 
-def test_speculative_step_redone_when_solve_needs_more(gpu):
+@pytest.mark.parametrize("precond", [W.PC_JACOBI, W.PC_BLOCK])
+def test_speculative_step_redone_when_solve_needs_more(gpu, precond):
     # the solve is capped below what it needs: every speculative step after
     # the first fails to converge, is discarded and redone, and ends with
     # the capped iterate like the polled path
     w = W.jitter(W.config("dam_break_2d_1432"))
+    w.params["precond"] = precond
     a, sa = _run(gpu, w, 5, True, maxit=12)
     b, sb = _run(gpu, w, 5, False, maxit=12)
     assert all(s["status"] == gpu.E_CG_NOCONV for s in sa + sb)
