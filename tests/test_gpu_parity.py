@@ -339,8 +339,10 @@ def test_ppe_matrix_and_solve(gpu, orc, precision):
     m.close()
 
 
-def test_bitwise_determinism(gpu):
+@pytest.mark.parametrize("precond", [W.PC_JACOBI, W.PC_BLOCK])
+def test_bitwise_determinism(gpu, precond):
     w = W.jitter(W.config("dam_break_2d_44832", precision=W.MIXED))
+    w.params["precond"] = precond
     outs = []
     for _ in range(2):
         m = gpu.MPS(w.params, w.pos, w.vel, w.ptype)
