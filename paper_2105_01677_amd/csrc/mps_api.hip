@@ -557,7 +557,9 @@ struct Prof {
 // the cell sort and a search at radius re_lap + skin write the superset
 // lists, if not the state is copied in its order; then the superset is
 // filtered to the exact lists at the step's positions.
-mps_status search(mps_ctx* c) {
+// fold: the caller's prediction filters kept lists (single phase), so the
+// separate filter is not launched.
+mps_status search(mps_ctx* c, bool fold = false) {
   c->ppe_valid = false;
   const bool keep = c->P.skin > 0.0;
   View v = make_view(c);
@@ -582,7 +584,7 @@ mps_status search(mps_ctx* c) {
       vs.max_neigh = c->cap_s;
       vs.re_lap2 = vs.re_s2;
       launch_neighbors(vs, c->dim, c->P.precision, c->s);
-      launch_list_filter(v, c->dim, c->s);
+      if (!fold) launch_list_filter(v, c->dim, c->s);
     } else {
       launch_neighbors(v, c->dim, c->P.precision, c->s);
     }
@@ -617,7 +619,9 @@ void enqueue_assemble(mps_ctx* c, const View& v, const double* rhs, bool zero_x0
 // Leaves the context in the new sorted order (flips cur).
 void enqueue_pre(mps_ctx* c, int32_t* status_snap = nullptr) {
   k_step_begin<<<1, 64, 0, c->s>>>(c->status, c->step_count, status_snap);
-  search(c);
+  // kept lists, single phase: the prediction filters the superset
+  const bool fold = c->P.skin > 0.0 && !c->multi;
+  search(c, fold);
   View v = make_view(c);
   if (c->multi) {
     Prof pr(c, MPS_KC_PREDICT);
@@ -625,7 +629,7 @@ void enqueue_pre(mps_ctx* c, int32_t* status_snap = nullptr) {
   }
   {
     Prof pr(c, MPS_KC_PREDICT);
-    launch_predict(v, c->dim, c->P.precision, c->s);
+    launch_predict(v, c->dim, c->P.precision, fold, c->s);
   }
   {
     Prof pr(c, MPS_KC_DENSITY);
@@ -1390,11 +1394,12 @@ mps_status mps_pressure_solve(mps_ctx* c, const double* rhs, double* p, int32_t*
                               double* relres) {
   if (!c || !p) return MPS_E_ARG;
   if (c->poisoned) return fail(c, MPS_E_POISONED, "context poisoned; call mps_set_state");
-  search(c);
+  const bool fold = c->P.skin > 0.0 && !c->multi;
+  search(c, fold);
   View v = make_view(c);
   HIPCHK(c, hipMemcpyAsync(c->p_save, c->pres[c->cur], c->n * sizeof(double),
                            hipMemcpyDeviceToDevice, c->s));
-  launch_predict(v, c->dim, c->P.precision, c->s);
+  launch_predict(v, c->dim, c->P.precision, fold, c->s);
   launch_density(v, c->dim, c->P.precision, MPS_PPE_CG, c->s);
   const double* rhs_sorted = nullptr;
   if (rhs) {

@@ -305,6 +305,22 @@ __device__ inline int xcd_block() {
   return xcd < r ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
 }
 
+// Squared FP64 distance term by term, without contraction: the neighbour
+// decision of the lists (search, superset filter, the prediction that
+// filters kept lists), so that every path decides a pair the same way.
+template <int DIM>
+__device__ inline double dist2_exact(const double (&a)[DIM], const double (&b)[DIM]) {
+#pragma clang fp contract(off)
+  double dx = b[0] - a[0];
+  double dy = b[1] - a[1];
+  double s = dx * dx + dy * dy;
+  if constexpr (DIM == 3) {
+    double dz = b[2] - a[2];
+    s = s + dz * dz;
+  }
+  return s;
+}
+
 // Team helpers: lanes of one team are contiguous (lane = row * TEAM + t).
 __device__ inline int team_lane() { return threadIdx.x & (TEAM - 1); }
 
@@ -498,7 +514,10 @@ int launch_list_filter(const View& v, int dim, hipStream_t s);
 int launch_list_force(const View& v, hipStream_t s);
 int launch_export_lists(const View& v, int32_t* cell_out, int32_t* count_out,
                         int32_t* list_out, int dim, hipStream_t s);
-int launch_predict(const View& v, int dim, int precision, hipStream_t s);
+// filter_kept: lists kept over steps, single phase -- the kernel also
+// filters the superset into this step's exact lists (k_predict_keep), in
+// place of launch_list_filter
+int launch_predict(const View& v, int dim, int precision, bool filter_kept, hipStream_t s);
 int launch_density(const View& v, int dim, int precision, int pmode, hipStream_t s);
 int launch_viscosity(const View& v, int dim, int precision, hipStream_t s);
 int launch_smooth_density(const View& v, const double* rho_raw, double* rho_out, int dim,

@@ -19,21 +19,9 @@ namespace mps {
 // only in the steps whose decision kernel asked for a build.
 __device__ inline bool skip_build(const View& v) { return v.ls && !v.ls->rebuild; }
 
-// Squared distance rounded term by term: (dx*dx + dy*dy) + dz*dz.  The
-// neighbour criterion d2 < re_lap^2 is evaluated on exactly this expression,
-// so the lists are reproducible bit for bit on any IEEE machine.
-template <int DIM>
-__device__ inline double dist2_exact(const double (&a)[DIM], const double (&b)[DIM]) {
-#pragma clang fp contract(off)
-  double dx = b[0] - a[0];
-  double dy = b[1] - a[1];
-  double s = dx * dx + dy * dy;
-  if constexpr (DIM == 3) {
-    double dz = b[2] - a[2];
-    s = s + dz * dz;
-  }
-  return s;
-}
+// The neighbour criterion d2 < re_lap^2 is evaluated on dist2_exact
+// (mps_internal.h: rounded term by term, (dx*dx + dy*dy) + dz*dz), so the
+// lists are reproducible bit for bit on any IEEE machine.
 
 // a1: cell of every particle (current sorted order), rank inside its cell.
 // A particle outside the grid becomes a ghost and goes to cell ncell.

@@ -243,6 +243,111 @@ __global__ __launch_bounds__(BLOCK) void k_predict(View v) {
   }
 }
 
+// a2 + a3 with lists kept over steps (single phase): the prediction walks
+// the superset list (radius re_lap + skin at the last build) and writes the
+// exact list of this step -- the entries within re_lap at r, decided on
+// dist2_exact of the FP64 positions in list order, with the same
+// compaction, cap and flags as k_list_filter -- while it sums the viscous
+// term over those entries.  On the mixed path the decision is taken on the
+// FP32 cell-relative records the sum gathers anyway, except inside a band
+// of +-KEEP_BAND re_lap^2 around the cut-off and for separations below
+// KEEP_BAND re_lap^2 (coincidence), where the FP64 positions decide: the
+// FP32 squared separation is within ~3e-6 re_lap^2 of the FP64 one (cell-
+// relative coordinates of at most a cell side plus the skin, rounded once,
+// subtracted, offset by whole FP32 cell sides), so outside the band both
+// give the same answer.
+#ifndef KEEP_BAND
+#define KEEP_BAND 4e-5
+#endif
+template <int DIM, bool MIXED>
+__global__ __launch_bounds__(BLOCK) void k_predict_keep(View v) {
+  using P = PosRef<DIM, MIXED>;
+  using R = typename P::R;
+  using K = KRec<DIM, MIXED>;
+  const int64_t row = team_row();
+  const int t = team_lane();
+  if (row >= v.n) return;
+  double ui[DIM], xi[DIM];
+  load_vec<DIM>(v.vel, row, ui);
+  load_vec<DIM>(v.pos, row, xi);
+  const bool fluid = v.type[row] == MPS_FLUID;
+  const int cs = v.sk_count[row];
+  const K ri = K::load(v, row);
+  // the superset is walked; the exact list is written
+  View vs = v;
+  vs.nb_list = v.sk_list;
+  vs.kpad = v.kpad_s;
+  const int64_t e0 = sl_index(row, 0, v.kpad);
+  const float lo = (float)(v.re_lap2 * (1.0 - KEEP_BAND)), hi = (float)(v.re_lap2 * (1.0 + KEEP_BAND)),
+              tiny = (float)(v.re_lap2 * KEEP_BAND);
+  int count = 0;
+  bool coinc = false;
+  double us[DIM], rs[DIM];
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) { us[a] = ui[a]; rs[a] = xi[a]; }
+  {
+    const R re = (R)v.re_lap, re2 = (R)v.re_lap2;
+    R acc[DIM];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) acc[a] = R(0);
+    for_list<SUM_U_PREDICT>(
+        vs, row, cs, t, [&](int32_t j) { return K::load(v, j); },
+        [&](int32_t j, const K& rj, bool ok) {
+          R d[DIM];
+          ri.p.diff(rj.p, v.cs32, d);
+          const R r2 = norm2<DIM, R>(d);
+          bool hit;
+          double d2 = 1.0;   // the FP64 separation, where it was computed
+          if constexpr (MIXED) {
+            if (r2 < tiny || (r2 >= lo && r2 < hi)) {
+              double xj[DIM];
+              load_vec<DIM>(v.pos, j, xj);
+              d2 = dist2_exact<DIM>(xi, xj);
+              hit = ok && d2 < v.re_lap2;
+            } else {
+              hit = ok && r2 < lo;
+            }
+          } else {
+            d2 = dist2_exact<DIM>(xi, rj.p.x);
+            hit = ok && d2 < v.re_lap2;
+          }
+          coinc = coinc || (hit && d2 == 0.0);
+          const uint32_t m = team_ballot(hit);
+          if (hit) {
+            const unsigned q = (unsigned)(count + __popc(m & ((1u << t) - 1u)));
+            if (q < (unsigned)v.max_neigh)
+              v.nb_list[e0 + (int64_t)(q / TEAM) * WAVE + (q % TEAM)] = j;
+          }
+          count += __popc(m);
+          const R wr = weight_r2<R>(v.kernel, r2, rsqrt_k(r2), re, re2);
+          const R w = (fluid && hit) ? wr : R(0);
+#pragma unroll
+          for (int a = 0; a < DIM; ++a) acc[a] += (R)(rj.u[a] - ri.u[a]) * w;
+        });
+    if (fluid) {
+      const double clap = 2.0 * DIM / (v.lam_lap * v.n0_lap);
+      const double visc = v.nu * clap;
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) {
+        const double lap = (double)team_sum(acc[a]);
+        us[a] = ui[a] + v.dt * (visc * lap + v.g[a]);
+        rs[a] = xi[a] + v.dt * us[a];
+      }
+    }
+  }
+  if (coinc) atomicOr(v.status, ST_COINCIDENT);
+  if (count > v.max_neigh) {
+    if (t == 0) atomicOr(v.status, ST_OVERFLOW);
+    count = v.max_neigh;
+  }
+  if (t == 0) {
+    v.nb_count[row] = count;
+    store_vec<DIM>(v.us, row, us);
+    store_vec<DIM>(v.rs, row, rs);
+    if constexpr (MIXED) v.rsf[row] = to_rel<DIM>(v, rs, v.pcell[row]);
+  }
+}
+
 // Integer power by multiplication (Eq. 16 uses gamma = 7).
 __device__ inline double ipow(double x, int e) {
   double r = 1.0;
@@ -613,9 +718,14 @@ static inline unsigned team_blocks(int64_t n) {
 }
 
 template <int DIM>
-static void predict_t(const View& v, bool mx, hipStream_t s) {
+static void predict_t(const View& v, bool mx, bool keep, hipStream_t s) {
   const unsigned nb = team_blocks(v.n);
   const bool multi = v.rho_s != nullptr;
+  if (keep && !multi) {
+    if (mx) k_predict_keep<DIM, true><<<nb, BLOCK, 0, s>>>(v);
+    else k_predict_keep<DIM, false><<<nb, BLOCK, 0, s>>>(v);
+    return;
+  }
   if (mx) {
     if (multi) k_predict<DIM, true, true><<<nb, BLOCK, 0, s>>>(v);
     else k_predict<DIM, true, false><<<nb, BLOCK, 0, s>>>(v);
@@ -625,12 +735,12 @@ static void predict_t(const View& v, bool mx, hipStream_t s) {
   }
 }
 
-int launch_predict(const View& v, int dim, int precision, hipStream_t s) {
+int launch_predict(const View& v, int dim, int precision, bool filter_kept, hipStream_t s) {
   const bool mx = precision == MPS_MIXED;
   if (dim == 2) {
-    predict_t<2>(v, mx, s);
+    predict_t<2>(v, mx, filter_kept, s);
   } else {
-    predict_t<3>(v, mx, s);
+    predict_t<3>(v, mx, filter_kept, s);
   }
   return 0;
 }

@@ -2,7 +2,7 @@
 "Computational performance analysis": lists refreshed every few steps).
 The cell search writes a superset at radius re_lap + skin, rebuilt when a
 particle has moved skin/2 since the build; every step filters it to the
-exact list.  Bars: the exported list of every step is exactly the
+exact list (with one phase, inside the prediction kernel).  Bars: the exported list of every step is exactly the
 definition's (all pairs, bit for bit); one step, including a step that
 keeps its lists, against the oracle at the one-step bars; 20 FP64 steps at
 the multi-step bar."""
@@ -148,3 +148,28 @@ def test_dam_break_3d_kept_lists_stay_physical(gpu):
     print("3-D kept lists: builds", s["list_builds"], "of 100, vmax", vmax, flush=True)
     assert (typ == W.GHOST).sum() == 0 and vmax < 5.0
     assert s["list_builds"] < 100
+
+
+@pytest.mark.parametrize("precision", [W.FP64, W.MIXED])
+def test_lists_filtered_by_the_prediction(gpu, orc, precision):
+    """With kept lists and one phase the prediction kernel filters the
+    superset into the step's exact lists (on the mixed path deciding on the
+    FP32 records outside a band around the cut-off, on the FP64 positions
+    inside it).  The entries of the lists a step used (the step's
+    list_entries) equal the all-pairs count at the step's input positions,
+    for a build step and for a step that keeps its lists; the plain lattice
+    puts many pairs exactly at r = re_lap, inside the band."""
+    w0 = W.with_skin(W.config("dam_break_2d_1432", precision=precision), 0.5)
+    for w in [w0] + _cases(precision):
+        m = gpu.MPS(w.params, w.pos, w.vel, w.ptype)
+        s1 = m.step(1)
+        st, cnt, _ = orc.neighbors_brute(w.params, w.pos, w.ptype)
+        assert st == 0
+        assert s1["list_entries"] == int(cnt.sum()), (w.name, s1["list_entries"], int(cnt.sum()))
+        g = {k: _np(v) for k, v in m.state().items()}
+        s2 = m.step(1)
+        assert s2["list_builds"] == 0
+        st, cnt, _ = orc.neighbors_brute(w.params, g["pos"], g["type"])
+        assert st == 0
+        assert s2["list_entries"] == int(cnt.sum()), (w.name, s2["list_entries"], int(cnt.sum()))
+        m.close()
