@@ -200,3 +200,23 @@ def test_block_jacobi_pressure_solve(gpu, orc, precision):
     assert rel_err(sols[W.PC_BLOCK][1], ref) < 1e-8
     assert rel_err(sols[W.PC_BLOCK][0], sols[W.PC_JACOBI][0]) < 1e-8
     assert sols[W.PC_BLOCK][2] < sols[W.PC_JACOBI][2]
+
+
+def test_block_jacobi_ten_steps_at_bench_size_fp64(gpu, orc):
+    """The 44,832-particle dam break for 10 steps in one call (whole-step
+    graphs, two in flight, speculative CG counts) with block Jacobi, FP64
+    and a 1e-12 solve, against 10 oracle steps: the multi-step bar."""
+    w = W.config("dam_break_2d_44832", precision=W.FP64)
+    w.params.update(cg_tol=1e-12, precond=W.PC_BLOCK)
+    m = gpu.MPS(w.params, w.pos, w.vel, w.ptype)
+    s = m.step(10)
+    g = {k: _np(v) for k, v in m.state().items()}
+    m.close()
+    assert s["status"] == gpu.OK and s["steps"] == 10
+    st, pos, vel, t, p, fl = orc.run(w.params, w.pos, w.vel, w.ptype, 10)
+    assert st == 0
+    errs = {"disp": rel_err(g["pos"] - w.pos, pos - w.pos), "vel": rel_err(g["vel"], vel),
+            "p": rel_err(g["p"], p)}
+    print("44,832 FP64 block Jacobi, 10 steps:", errs, "cg", s["cg_iters_total"], flush=True)
+    for k, e in errs.items():
+        assert e < 1e-6, (k, e)
