@@ -220,3 +220,23 @@ def test_block_jacobi_ten_steps_at_bench_size_fp64(gpu, orc):
     print("44,832 FP64 block Jacobi, 10 steps:", errs, "cg", s["cg_iters_total"], flush=True)
     for k, e in errs.items():
         assert e < 1e-6, (k, e)
+
+
+def test_block_jacobi_ten_steps_at_bench_size_mixed(gpu, orc):
+    """The same ten steps on the mixed path (the bench's), against the FP64
+    oracle.  Bar: the one-step mixed bar (1e-4) times the number of steps,
+    errors of a stable integration adding at most linearly."""
+    w = W.config("dam_break_2d_44832", precision=W.MIXED)
+    w.params.update(precond=W.PC_BLOCK)
+    m = gpu.MPS(w.params, w.pos, w.vel, w.ptype)
+    s = m.step(10)
+    g = {k: _np(v) for k, v in m.state().items()}
+    m.close()
+    assert s["status"] == gpu.OK and s["steps"] == 10
+    st, pos, vel, t, p, fl = orc.run(w.params, w.pos, w.vel, w.ptype, 10)
+    assert st == 0
+    errs = {"disp": rel_err(g["pos"] - w.pos, pos - w.pos), "vel": rel_err(g["vel"], vel),
+            "p": rel_err(g["p"], p)}
+    print("44,832 mixed block Jacobi, 10 steps:", errs, "cg", s["cg_iters_total"], flush=True)
+    for k, e in errs.items():
+        assert e < 10 * 1e-4, (k, e)
