@@ -52,7 +52,8 @@ def _step_vs_oracle(gpu, orc, w, tol, rho_i=None, nu_i=None):
                          want_lists=False, rho_s=rs, nu_i=nu_i)
     errs = {"disp": rel_err(g["pos"] - w.pos, o["pos"] - w.pos),
             "vel": rel_err(g["vel"], o["vel"]), "p": rel_err(g["p"], o["p"])}
-    print(w.name, "two-level cg", s["cg_iters_last"], "errors", errs, flush=True)
+    print(w.name, "precond", w.params.get("precond"), "cg", s["cg_iters_last"], "errors", errs,
+          flush=True)
     for k, e in errs.items():
         assert e < tol, (w.name, k, e)
     return s["cg_iters_last"]
@@ -240,3 +241,14 @@ def test_block_jacobi_ten_steps_at_bench_size_mixed(gpu, orc):
     print("44,832 mixed block Jacobi, 10 steps:", errs, "cg", s["cg_iters_total"], flush=True)
     for k, e in errs.items():
         assert e < 10 * 1e-4, (k, e)
+
+
+@pytest.mark.parametrize("precision,cg_tol,tol", PRECISIONS)
+def test_block_jacobi_edge_sizes(gpu, orc, precision, cg_tol, tol):
+    """Small systems: 60 particles (12 fluid on walls: one partial group of
+    rows), 86 (30 fluid: a full group and a ragged one) and 2 x 2 fluid
+    particles on walls."""
+    for m in ([4, 3], [6, 5], [2, 2]):
+        w = W.jitter(W.lattice_block(2, m, walls_below=True, dt=1e-4, g=9.81))
+        w.params.update(precision=precision, cg_tol=cg_tol, precond=W.PC_BLOCK)
+        _step_vs_oracle(gpu, orc, w, tol)
