@@ -169,8 +169,8 @@ def test_block_jacobi_needs_the_fused_schedule(gpu):
 def test_block_jacobi_pressure_solve(gpu, orc, precision):
     """mps_pressure_solve with block Jacobi against the dense solution of the
     assembled system (mps_get_ppe) for a seeded right-hand side, and the
-    same solve with Jacobi; then the state's own right-hand side, twice in a
-    row (the preconditioner's start is rebuilt for every solve)."""
+    same solve with Jacobi; the state's own right-hand side, twice in a row
+    (the preconditioner's start is rebuilt for every solve); and b = 0."""
     w = W.jitter(W.config("dam_break_2d_1432", precision=precision))
     rng = np.random.default_rng(11)
     b2 = rng.normal(size=w.n)
@@ -181,6 +181,9 @@ def test_block_jacobi_pressure_solve(gpu, orc, precision):
         p_again, it_again, _ = m.pressure_solve()
         assert it_again == it and np.array_equal(_np(p_again), _np(p))
         p2, it2, rr2 = m.pressure_solve(b2)
+        # b = 0: p = 0 without an iteration
+        p0, it0, _ = m.pressure_solve(np.zeros(w.n))
+        assert it0 == 0 and not np.any(_np(p0))
         A = {k: _np(v) for k, v in m.get_ppe().items()}
         m.close()
         sols[pc] = (_np(p), _np(p2), it2)
