@@ -1050,7 +1050,9 @@ mps_status mps_init(const mps_params* params, int64_t n, const double* pos, cons
   c->n = n;
   c->dim = params->dim;
   c->ps = c->dim == 2 ? 2 : 4;
-  c->kpad = (params->max_neigh + TEAM - 1) / TEAM * TEAM;
+  // row capacity: max_neigh in whole team steps, and at least the CG
+  // iteration's first-pass slots (CG_UNROLL per lane, loaded unchecked)
+  c->kpad = std::max((params->max_neigh + TEAM - 1) / TEAM * TEAM, CG_UNROLL * TEAM);
   c->slots = ((n + SLICE - 1) / SLICE) * (int64_t)c->kpad * SLICE;
   c->ncell = params->grid_n[0] * params->grid_n[1] * (c->dim == 3 ? params->grid_n[2] : 1);
   c->s = (hipStream_t)hip_stream;

@@ -329,15 +329,32 @@ __device__ inline int team_lane() { return threadIdx.x & (TEAM - 1); }
 // encoding used here: quad_perm [1,0,3,2] (lane ^ 1) = 0xB1, quad_perm
 // [2,3,0,1] (lane ^ 2) = 0x4E, row_half_mirror (lane l <-> 7 - l within
 // each 8 lanes) = 0x141, row_mirror (l <-> 15 - l within each 16) = 0x140.
-// row_shl:k (lane l takes lane l + k within each 16) = 0x100 + k.  The
-// source lanes of these patterns must be active.
+// row_shl:k (lane l takes lane l + k within each 16) = 0x100 + k;
+// row_bcast:15 (each row takes the last lane of the row before it) = 0x142,
+// row_bcast:31 (rows 2 and 3 take lane 31) = 0x143.  The source lanes of
+// these patterns must be active; a lane with no source reads 0 (bound_ctrl),
+// so the destination needs no initial value (no extra move).
 constexpr int DPP_XOR1 = 0xB1, DPP_XOR2 = 0x4E, DPP_HALF_MIRROR = 0x141, DPP_MIRROR = 0x140;
+constexpr int DPP_BCAST15 = 0x142, DPP_BCAST31 = 0x143;
 constexpr int DPP_SHL1 = 0x101, DPP_SHL2 = 0x102, DPP_SHL3 = 0x103, DPP_SHL4 = 0x104,
               DPP_SHL5 = 0x105, DPP_SHL6 = 0x106;
 
 template <int CTRL>
 __device__ inline uint32_t dpp_u32(uint32_t v) {
-  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, true);
+}
+// The same restricted to the 16-lane rows in the mask ROWS; the other rows'
+// results are undefined.
+template <int CTRL, int ROWS>
+__device__ inline uint32_t dpp_u32_rows(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, ROWS, 0xF, true);
+}
+template <int CTRL, int ROWS>
+__device__ inline double dpp_move_rows(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint64_t lo = dpp_u32_rows<CTRL, ROWS>((uint32_t)b),
+                 hi = dpp_u32_rows<CTRL, ROWS>((uint32_t)(b >> 32));
+  return __builtin_bit_cast(double, lo | (hi << 32));
 }
 template <int CTRL, class T>
 __device__ inline T dpp_move(T v) {
@@ -390,6 +407,17 @@ __device__ inline T wave_sum(T v) {
   v = team_sum(v);
   v += dpp_move<DPP_MIRROR>(v);
   return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
+}
+// The same sum valid in the last lane only (the bits of wave_sum): rows
+// 1 and 3 add the last lane of the row before them (row_bcast:15), then row
+// 3 adds the last lane of row 1 (row_bcast:31).  Rows 0 and 2 hold
+// meaningless values afterwards.
+__device__ inline double wave_sum_last(double v) {
+  v = team_sum(v);
+  v += dpp_move<DPP_MIRROR>(v);
+  v += dpp_move_rows<DPP_BCAST15, 0xA>(v);
+  v += dpp_move_rows<DPP_BCAST31, 0xC>(v);
+  return v;
 }
 // Bit mask of the team's lanes for which pred holds (bit t = lane t).
 __device__ inline uint32_t team_ballot(bool pred) {

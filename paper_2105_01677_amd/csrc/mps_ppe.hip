@@ -86,17 +86,17 @@ __device__ inline void block_sum_all(double (&x)[NV], double* sh) {
   constexpr int NW = NT / WAVE;
   const int w = threadIdx.x / WAVE;
 #pragma unroll
-  for (int k = 0; k < NV; ++k) x[k] = wave_sum(x[k]);
-  if ((threadIdx.x & (WAVE - 1)) == 0) {
+  for (int k = 0; k < NV; ++k) x[k] = wave_sum_last(x[k]);
+  if ((threadIdx.x & (WAVE - 1)) == WAVE - 1) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) sh[k * NW + w] = x[k];
   }
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
-    double s = 0.0;
+    double s = sh[k * NW];
 #pragma unroll
-    for (int q = 0; q < NW; ++q) s += sh[k * NW + q];
+    for (int q = 1; q < NW; ++q) s += sh[k * NW + q];
     x[k] = s;
   }
 }
@@ -473,9 +473,10 @@ __device__ inline void load_partials(const double* part, int np, double4 (&q)[K]
 template <int NT, int K>
 __device__ inline void sum_partials_loaded(const double4 (&q)[K], int np, double (&tot)[3],
                                            double* sh) {
-  double s[3] = {0.0, 0.0, 0.0};
+  const bool in0 = threadIdx.x < np;
+  double s[3] = {in0 ? q[0].x : 0.0, in0 ? q[0].y : 0.0, in0 ? q[0].z : 0.0};
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
+  for (int k = 1; k < K; ++k) {
     if (threadIdx.x + k * NT < np) {
       s[0] += q[k].x;
       s[1] += q[k].y;
@@ -535,10 +536,10 @@ constexpr double BJ_OMEGA = 1.5;
 // LDS, BJ_ROWS values), entries from slot l on
 template <class VT>
 __device__ inline double bj_row_sum(const View& v, const VT* __restrict__ aval, int64_t row,
-                                    int nnz, int l, int64_t g0, const double* y) {
+                                    int nnz, int l, int32_t g0, const double* y) {
   return row_dot<4>(v.a_col, aval, row, nnz, v.kpad, l, [&](int32_t j) {
-    const uint64_t k = (uint64_t)((int64_t)j - g0);
-    return k < (uint64_t)BJ_ROWS ? y[k] : 0.0;
+    const uint32_t k = (uint32_t)(j - g0);
+    return k < (uint32_t)BJ_ROWS ? y[k] : 0.0;
   });
 }
 
@@ -556,7 +557,7 @@ __global__ __launch_bounds__(PCG_BLOCK) void k_bj_start(View v) {
   __syncthreads();
   if (!live) return;
   const VT* __restrict__ aval = reinterpret_cast<const VT*>(v.a_val);
-  const double s = team_sum(bj_row_sum(v, aval, row, v.a_nnz[row], t, g0, y));
+  const double s = team_sum(bj_row_sum(v, aval, row, v.a_nnz[row], t, (int32_t)g0, y));
   if (t == 0) v.pl_u[row] = (v.r[row] - BJ_OMEGA * s) * (1.0 / v.diag[row]);
 }
 
@@ -625,7 +626,7 @@ __global__ __launch_bounds__(pcg_nt<FUSED>()) void k_pcg_setup(View v) {
     if (t == 0) y[lr] = live ? w * id : 0.0;
     __syncthreads();
     if (live) {
-      const double a = team_sum(bj_row_sum(v, aval, row, v.a_nnz[row], t, g0, y));
+      const double a = team_sum(bj_row_sum(v, aval, row, v.a_nnz[row], t, (int32_t)g0, y));
       if (t == 0) v.pl_m[0][row] = (w - BJ_OMEGA * a) * id;
     }
   }
@@ -647,8 +648,9 @@ __device__ inline bool pcg_scalars(const View& v, const double (&tot)[3], int pa
   CGScalars* sc = v.sc;
   const double gam = tot[0], del = tot[1], rr = tot[2];
   const bool done = rr <= v.cg_tol2 * bb;
+  // alpha = gam / (del - beta gam / alpha_old), with one division
   beta = gam / gam_old;
-  alpha = gam / (del - beta * gam / alp_old);
+  alpha = gam * alp_old / (del * alp_old - beta * gam);
   if (write && threadIdx.x == 0) {
     sc->rr = rr;
     if (done) {
@@ -695,7 +697,7 @@ void k_pcg_iter(View v) {
   static_assert(PCG_PK * PCG_BLOCK >= PCG_MAX_BLOCKS, "one partial load per slot");
   static_assert(PCG_SPLIT_G <= PCG_SPLIT_BLOCK, "one slice sum per thread");
   static_assert(!(FUSED && PRED), "the small fused systems are latency-bound");
-  __shared__ double sh_in[3 * (NT / WAVE)], sh_out[3 * (NT / WAVE)];
+  __shared__ double sh_in[3 * (NT / WAVE)], sh_lead[3][NT / TEAM];
   CGScalars* sc = v.sc;
   const int t = team_lane();
 
@@ -723,9 +725,9 @@ void k_pcg_iter(View v) {
   VT aa[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    // slot u of the row exists (kpad is uniform); stale slots past the row
-    // length are masked below
-    const int64_t e = u * TEAM < v.kpad ? e0 + u * WAVE : e0;
+    // slot u of the row exists (the context's row capacity kpad is at least
+    // U * TEAM); stale slots past the row length are masked below
+    const int64_t e = e0 + u * WAVE;
     if constexpr (PRED) {
       const bool in = t + u * TEAM < nnz;
       jj[u] = in ? v.a_col[e] : 0;
@@ -772,13 +774,13 @@ void k_pcg_iter(View v) {
   __shared__ VT sh_a[BJ ? U : 1][BJ ? NT : 1];
   if constexpr (BJ) {
     static_assert(U <= 8 && BJ_ROWS < 256, "one byte per slot");
-    const int64_t g0 = (int64_t)xcd_block() * BJ_ROWS;
+    const int32_t g0 = xcd_block() * BJ_ROWS;
     uint32_t kp[2] = {0u, 0u};
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const uint64_t k = (uint64_t)((int64_t)jj[u] - g0);
-      const bool ing = t + u * TEAM < nnz && k < (uint64_t)BJ_ROWS;
-      kp[u / 4] |= (ing ? (uint32_t)k : (uint32_t)BJ_ROWS) << (8 * (u % 4));
+      const uint32_t k = (uint32_t)(jj[u] - g0);
+      const bool ing = t + u * TEAM < nnz && k < (uint32_t)BJ_ROWS;
+      kp[u / 4] |= (ing ? k : (uint32_t)BJ_ROWS) << (8 * (u % 4));
       sh_a[u][threadIdx.x] = ing ? aa[u] : VT(0);
     }
     sh_k[threadIdx.x] = make_uint2(kp[0], kp[1]);
@@ -851,9 +853,15 @@ void k_pcg_iter(View v) {
       Mn[row] = wn / o_d;
     }
   }
-  double x[3] = {lead ? r * un : 0.0, lead ? wn * un : 0.0, lead ? r * r : 0.0};
+  // the workgroup's partial: one value per row, from the team leads
+  if (t == 0) {
+    const int i = threadIdx.x / TEAM;
+    sh_lead[0][i] = live ? r * un : 0.0;
+    sh_lead[1][i] = live ? wn * un : 0.0;
+    sh_lead[2][i] = live ? r * r : 0.0;
+  }
   // block Jacobi: D^-1 w of the group's rows into LDS before the
-  // reduction's barrier, read after it; the lane's parked entries are read
+  // barrier below, read after it; the lane's parked entries are read
   // back before it (its own data; FP64 values after it, for registers)
   __shared__ double y[BJ ? BJ_ROWS + 1 : 1];
   constexpr bool KA_EARLY = sizeof(VT) == 4;
@@ -868,11 +876,21 @@ void k_pcg_iter(View v) {
       for (int u = 0; u < U; ++u) ka[u] = sh_a[u][threadIdx.x];
     }
   }
-  block_sum_all<3, NT>(x, sh_out);
-  if (threadIdx.x == 0) {
-    const int lb = xcd_block();
+  __syncthreads();
+  // wavefront 0 alone sums the row values (one per lane) into the partial
+  if (threadIdx.x < WAVE) {
+    static_assert(NT / TEAM <= WAVE, "one row per lane of wavefront 0");
+    double x[3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) v.pl_part[PAR ^ 1][(int64_t)lb * 4 + k] = x[k];
+    for (int k = 0; k < 3; ++k) {
+      x[k] = threadIdx.x < NT / TEAM ? sh_lead[k][threadIdx.x] : 0.0;
+      x[k] = wave_sum_last(x[k]);
+    }
+    if (threadIdx.x == WAVE - 1) {
+      const int lb = xcd_block();
+#pragma unroll
+      for (int k = 0; k < 3; ++k) v.pl_part[PAR ^ 1][(int64_t)lb * 4 + k] = x[k];
+    }
   }
   if constexpr (BJ) {
     // m = M^-1 w: the first U entries per lane parked, the rest reloaded
@@ -886,7 +904,7 @@ void k_pcg_iter(View v) {
       const uint32_t kk = ((u < 4 ? kq.x : kq.y) >> (8 * (u % 4))) & 0xffu;
       a += (double)ka[u] * y[kk];
     }
-    a += bj_row_sum(v, aval, rc, nnz, t + U * TEAM, (int64_t)xcd_block() * BJ_ROWS, y);
+    a += bj_row_sum(v, aval, rc, nnz, t + U * TEAM, xcd_block() * BJ_ROWS, y);
     a = team_sum(a);
     if (lead) Mn[row] = (wn - BJ_OMEGA * a) * o_id;
   }
