@@ -208,6 +208,12 @@ hipError_t dalloc(T** p, size_t count) {
   return e;
 }
 
+// Doubles in each partial buffer of the pipelined CG: four per workgroup
+// (split schedule) or three arrays of PCG_PSTRIDE (fused).
+inline size_t pl_part_len(const mps_ctx* c) {
+  return std::max((size_t)c->npcg * 4, (size_t)3 * PCG_PSTRIDE);
+}
+
 // The buffer a step from buffer cur writes.
 inline int nxt(const mps_ctx* c) { return (c->cur + 1) % mps_ctx::NBUF; }
 
@@ -1157,7 +1163,7 @@ mps_status mps_init(const mps_params* params, int64_t n, const double* pos, cons
     A(dalloc(&c->pl_s, n));
     for (int k = 0; k < 2; ++k) {
       A(dalloc(&c->pl_m[k], n));
-      A(dalloc(&c->pl_part[k], (size_t)c->npcg * 4));
+      A(dalloc(&c->pl_part[k], pl_part_len(c)));
       A(dalloc(&c->pl_part2[k], (size_t)PCG_SPLIT_G * 4));
     }
   }
@@ -1186,6 +1192,10 @@ mps_status mps_init(const mps_params* params, int64_t n, const double* pos, cons
   A(hipMemsetAsync(c->status, 0, sizeof(int32_t), s));
   A(hipMemsetAsync(c->step_count, 0, sizeof(int32_t), s));
   A(hipMemsetAsync(c->sc, 0, sizeof(CGScalars), s));
+  // the fused iteration sums every slot of its partial arrays: zeros past
+  // npcg, which no kernel writes
+  for (int k = 0; k < 2; ++k)
+    if (c->pl_part[k]) A(hipMemsetAsync(c->pl_part[k], 0, pl_part_len(c) * sizeof(double), s));
   A(hipMemsetAsync(c->nb_count, 0, n * sizeof(int32_t), s));
   A(hipMemsetAsync(c->nbn_count, 0, n * sizeof(int32_t), s));
   if (c->ls) {

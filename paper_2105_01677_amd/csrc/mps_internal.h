@@ -97,8 +97,8 @@ constexpr int CG_SPMV_BLOCKS = 2048;
 constexpr int CG_UPD_BLOCKS = 1024;
 // Pipelined CG: workgroup size (one group of PCG_BLOCK / TEAM rows per
 // workgroup) and the largest grid of the fused one-kernel iteration, whose
-// workgroups all load every partial of the previous iteration (one double4
-// per workgroup); it is also kept within what runs in one wave of
+// workgroups all load every partial of the previous iteration (three
+// doubles per workgroup); it is also kept within what runs in one wave of
 // workgroups on the device.
 #ifndef PCG_BLOCK
 #define PCG_BLOCK 512
@@ -106,6 +106,9 @@ constexpr int CG_UPD_BLOCKS = 1024;
 #ifndef PCG_MAX_BLOCKS
 #define PCG_MAX_BLOCKS 1024
 #endif
+// fused schedule: each quantity of the per-workgroup partials in an array
+// of its own, this long
+constexpr int PCG_PSTRIDE = PCG_MAX_BLOCKS;
 #ifndef PCG_SPLIT_BLOCK
 #define PCG_SPLIT_BLOCK 256
 #endif

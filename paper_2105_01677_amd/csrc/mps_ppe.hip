@@ -430,6 +430,18 @@ template <bool FUSED>
 constexpr int pcg_nt() { return FUSED ? PCG_BLOCK : PCG_SPLIT_BLOCK; }
 constexpr int PCG_PK = (PCG_MAX_BLOCKS + PCG_BLOCK - 1) / PCG_BLOCK;
 
+// Quantity k of workgroup b's partial of the pipelined iteration: the fused
+// schedule keeps one array per quantity (PCG_PSTRIDE doubles each, zeros
+// past npcg), the split schedule four doubles per workgroup.
+template <bool FUSED>
+__device__ inline int64_t part_at(int64_t b, int k) {
+  return FUSED ? (int64_t)k * PCG_PSTRIDE + b : b * 4 + k;
+}
+// fused: each of six wavefronts loads PCG_FQ double2 per lane, one half of
+// one quantity's array
+constexpr int PCG_FQ = PCG_PSTRIDE / (2 * 2 * WAVE);
+static_assert(PCG_FQ * 2 * 2 * WAVE == PCG_PSTRIDE, "whole double2 loads per lane");
+
 // Fixed-order sum of np partials (double4 .x/.y/.z) by one workgroup of NT
 // threads: thread i adds partials i, i + NT, ... in order (K loads in
 // flight), then the workgroup tree.  Result valid in every thread.
@@ -635,7 +647,7 @@ __global__ __launch_bounds__(pcg_nt<FUSED>()) void k_pcg_setup(View v) {
   if (threadIdx.x == 0) {
     const int lb = xcd_block();
 #pragma unroll
-    for (int k = 0; k < 3; ++k) v.pl_part[0][(int64_t)lb * 4 + k] = x[k];
+    for (int k = 0; k < 3; ++k) v.pl_part[0][part_at<FUSED>(lb, k)] = x[k];
   }
 }
 
@@ -704,12 +716,25 @@ void k_pcg_iter(View v) {
   // -- loads that do not need this iteration's scalars, all issued before
   //    the first wait: the previous partials, the row length, the first U
   //    entries per lane, the row's own vectors (every lane: clamped row) --
-  // fused: every partial of the previous iteration; split: the slice sums
-  constexpr int PK = FUSED ? PCG_PK : 1;
-  const double* part = FUSED ? v.pl_part[PAR] : v.pl_part2[PAR];
-  const int npart = FUSED ? v.npcg : v.npcg2;
-  double4 q[PK];
-  load_partials<NT, PK>(part, npart, q);
+  // fused: every partial of the previous iteration, one quantity per
+  // wavefront: wavefronts k and 4 + k (k < 3) load the first and the second
+  // half of quantity k's array, wavefronts 3 and 7 none; split: the slice
+  // sums (every thread all three)
+  const int wv = threadIdx.x / WAVE, wk = wv & 3;
+  double2 qf[FUSED ? PCG_FQ : 1];
+  double4 q[1];
+  if constexpr (FUSED) {
+    static_assert(NT == 8 * WAVE, "two wavefronts per quantity");
+    if (wk < 3) {
+      const double2* p2 = reinterpret_cast<const double2*>(
+                              v.pl_part[PAR] + part_at<true>((wv >> 2) * (PCG_PSTRIDE / 2), wk)) +
+                          (threadIdx.x & (WAVE - 1));
+#pragma unroll
+      for (int j = 0; j < PCG_FQ; ++j) qf[j] = p2[j * WAVE];
+    }
+  } else {
+    load_partials<NT, 1>(v.pl_part2[PAR], v.npcg2, q);
+  }
   const double* __restrict__ M = v.pl_m[PAR];
   double* __restrict__ Mn = v.pl_m[PAR ^ 1];
   const VT* __restrict__ aval = reinterpret_cast<const VT*>(v.a_val);
@@ -795,7 +820,20 @@ void k_pcg_iter(View v) {
   // -- the scalars (every workgroup alike; workgroup 0 records them) --
   {
     double tot[3];
-    sum_partials_loaded<NT, PK>(q, npart, tot, sh_in);
+    if constexpr (FUSED) {
+      if (wk < 3) {
+        double ps = qf[0].x + qf[0].y;
+#pragma unroll
+        for (int j = 1; j < PCG_FQ; ++j) ps += qf[j].x + qf[j].y;
+        ps = wave_sum_last(ps);
+        if ((threadIdx.x & (WAVE - 1)) == WAVE - 1) sh_in[2 * wk + (wv >> 2)] = ps;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < 3; ++k) tot[k] = sh_in[2 * k] + sh_in[2 * k + 1];
+    } else {
+      sum_partials_loaded<NT, 1>(q, v.npcg2, tot, sh_in);
+    }
     if (pcg_scalars(v, tot, PAR, gam_old, alp_old, bb, blockIdx.x == 0, alpha, beta)) return;
   }
   // block Jacobi: 1 / d, while the gathers of m are waited for
@@ -889,7 +927,7 @@ void k_pcg_iter(View v) {
     if (threadIdx.x == WAVE - 1) {
       const int lb = xcd_block();
 #pragma unroll
-      for (int k = 0; k < 3; ++k) v.pl_part[PAR ^ 1][(int64_t)lb * 4 + k] = x[k];
+      for (int k = 0; k < 3; ++k) v.pl_part[PAR ^ 1][part_at<FUSED>(lb, k)] = x[k];
     }
   }
   if constexpr (BJ) {
