@@ -720,7 +720,8 @@ void k_pcg_iter(View v) {
   // wavefront: wavefronts k and 4 + k (k < 3) load the first and the second
   // half of quantity k's array, wavefronts 3 and 7 none; split: the slice
   // sums (every thread all three)
-  const int wv = threadIdx.x / WAVE, wk = wv & 3;
+  // the wavefront index, uniform (a scalar register)
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE), wk = wv & 3;
   double2 qf[FUSED ? PCG_FQ : 1];
   double4 q[1];
   if constexpr (FUSED) {
@@ -915,19 +916,15 @@ void k_pcg_iter(View v) {
     }
   }
   __syncthreads();
-  // wavefront 0 alone sums the row values (one per lane) into the partial
-  if (threadIdx.x < WAVE) {
-    static_assert(NT / TEAM <= WAVE, "one row per lane of wavefront 0");
-    double x[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      x[k] = threadIdx.x < NT / TEAM ? sh_lead[k][threadIdx.x] : 0.0;
-      x[k] = wave_sum_last(x[k]);
-    }
-    if (threadIdx.x == WAVE - 1) {
-      const int lb = xcd_block();
-#pragma unroll
-      for (int k = 0; k < 3; ++k) v.pl_part[PAR ^ 1][part_at<FUSED>(lb, k)] = x[k];
+  // the last three wavefronts each sum one quantity's row values (one per
+  // lane) into the partial
+  {
+    static_assert(NT / TEAM <= WAVE && NT / WAVE >= 3, "one row per lane");
+    const int k = NT / WAVE - 1 - wv, l = threadIdx.x & (WAVE - 1);
+    if (k < 3) {
+      double x = l < NT / TEAM ? sh_lead[k][l] : 0.0;
+      x = wave_sum_last(x);
+      if (l == WAVE - 1) v.pl_part[PAR ^ 1][part_at<FUSED>(xcd_block(), k)] = x;
     }
   }
   if constexpr (BJ) {
