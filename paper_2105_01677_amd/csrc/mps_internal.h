@@ -69,8 +69,9 @@ struct CGScalars {
   int32_t iter;      // iterations completed
   int32_t nasm;      // number of assembly partials (written by assembly)
   int32_t pad;
-  // pipelined variant: (r,u) and alpha of iteration k in slot k & 1, written
-  // by workgroup 0 of iteration k and read by iteration k + 1 only
+  // pipelined variant: 1 / (r,u) and alpha of iteration k in slot k & 1,
+  // written by workgroup 0 of iteration k and read by iteration k + 1 only
+  // (which then needs no division for beta)
   double gam[2];
   double alp[2];
   // two-level preconditioner: Gershgorin bound of D_c^-1 A_c (bits of a

@@ -512,7 +512,7 @@ __device__ inline bool pcg_start_scalars(const View& v, const double (&tot)[3], 
     sc->rr = rr;
     sc->iter = 0;
     sc->converged = done ? 1 : 0;
-    sc->gam[1] = __builtin_inf();
+    sc->gam[1] = 0.0;  // 1 / (r,u) of a previous iteration: beta = 0
     sc->alp[1] = 1.0;
   }
   return done;
@@ -655,20 +655,21 @@ __global__ __launch_bounds__(pcg_nt<FUSED>()) void k_pcg_setup(View v) {
 // convergence test, beta and alpha; workgroup 0 of the iteration kernel
 // records them.
 __device__ inline bool pcg_scalars(const View& v, const double (&tot)[3], int par,
-                                   double gam_old, double alp_old, double bb, bool write,
+                                   double igam_old, double alp_old, double bb, bool write,
                                    double& alpha, double& beta) {
   CGScalars* sc = v.sc;
   const double gam = tot[0], del = tot[1], rr = tot[2];
   const bool done = rr <= v.cg_tol2 * bb;
-  // alpha = gam / (del - beta gam / alpha_old), with one division
-  beta = gam / gam_old;
+  // beta = gam / gam_old from the stored 1 / gam_old; alpha = gam / (del -
+  // beta gam / alpha_old), with one division
+  beta = gam * igam_old;
   alpha = gam * alp_old / (del * alp_old - beta * gam);
   if (write && threadIdx.x == 0) {
     sc->rr = rr;
     if (done) {
       sc->converged = 1;
     } else {
-      sc->gam[par] = gam;
+      sc->gam[par] = 1.0 / gam;
       sc->alp[par] = alpha;
       sc->iter += 1;
     }
@@ -740,7 +741,7 @@ void k_pcg_iter(View v) {
   double* __restrict__ Mn = v.pl_m[PAR ^ 1];
   const VT* __restrict__ aval = reinterpret_cast<const VT*>(v.a_val);
   const int conv = sc->converged;
-  const double gam_old = sc->gam[PAR ^ 1], alp_old = sc->alp[PAR ^ 1], bb = sc->bb;
+  const double igam_old = sc->gam[PAR ^ 1], alp_old = sc->alp[PAR ^ 1], bb = sc->bb;
   double alpha = 0.0, beta = 0.0;
   const int64_t row = (int64_t)xcd_block() * (NT / TEAM) + threadIdx.x / TEAM;
   const bool live = row < v.n;
@@ -835,7 +836,7 @@ void k_pcg_iter(View v) {
     } else {
       sum_partials_loaded<NT, 1>(q, v.npcg2, tot, sh_in);
     }
-    if (pcg_scalars(v, tot, PAR, gam_old, alp_old, bb, blockIdx.x == 0, alpha, beta)) return;
+    if (pcg_scalars(v, tot, PAR, igam_old, alp_old, bb, blockIdx.x == 0, alpha, beta)) return;
   }
   // block Jacobi: 1 / d, while the gathers of m are waited for
   const double o_id = BJ ? 1.0 / o_d : 0.0;
