@@ -470,37 +470,6 @@ __device__ inline void reduce_partials(const double* part, int np, double (&tot)
   tot[2] = s[2];
 }
 
-// The same for np <= K * NT in two phases, so that the loads can be issued
-// before other work: load_partials (clamped index, no branch), then
-// sum_partials_loaded.
-template <int NT, int K>
-__device__ inline void load_partials(const double* part, int np, double4 (&q)[K]) {
-  const double4* p4 = reinterpret_cast<const double4*>(part);
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int b = threadIdx.x + k * NT;
-    q[k] = p4[b < np ? b : 0];
-  }
-}
-template <int NT, int K>
-__device__ inline void sum_partials_loaded(const double4 (&q)[K], int np, double (&tot)[3],
-                                           double* sh) {
-  const bool in0 = threadIdx.x < np;
-  double s[3] = {in0 ? q[0].x : 0.0, in0 ? q[0].y : 0.0, in0 ? q[0].z : 0.0};
-#pragma unroll
-  for (int k = 1; k < K; ++k) {
-    if (threadIdx.x + k * NT < np) {
-      s[0] += q[k].x;
-      s[1] += q[k].y;
-      s[2] += q[k].z;
-    }
-  }
-  block_sum_all<3, NT>(s, sh);
-  tot[0] = s[0];
-  tot[1] = s[1];
-  tot[2] = s[2];
-}
-
 // Start of the solve from the assembly partials: (r0, r0), (b, b), the
 // convergence test, and the scalars that make iteration 0 take beta = 0.
 __device__ inline bool pcg_start_scalars(const View& v, const double (&tot)[3], bool write) {
@@ -719,12 +688,12 @@ void k_pcg_iter(View v) {
   //    entries per lane, the row's own vectors (every lane: clamped row) --
   // fused: every partial of the previous iteration, one quantity per
   // wavefront: wavefronts k and 4 + k (k < 3) load the first and the second
-  // half of quantity k's array, wavefronts 3 and 7 none; split: the slice
-  // sums (every thread all three)
+  // half of quantity k's array, wavefronts 3 and 7 none; split: wavefront k
+  // (k < 3) loads quantity k of the slice sums, one per lane
   // the wavefront index, uniform (a scalar register)
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE), wk = wv & 3;
   double2 qf[FUSED ? PCG_FQ : 1];
-  double4 q[1];
+  double qs = 0.0;
   if constexpr (FUSED) {
     static_assert(NT == 8 * WAVE, "two wavefronts per quantity");
     if (wk < 3) {
@@ -735,7 +704,9 @@ void k_pcg_iter(View v) {
       for (int j = 0; j < PCG_FQ; ++j) qf[j] = p2[j * WAVE];
     }
   } else {
-    load_partials<NT, 1>(v.pl_part2[PAR], v.npcg2, q);
+    static_assert(PCG_SPLIT_G <= WAVE && NT / WAVE >= 3, "one slice sum per lane");
+    const int l = threadIdx.x & (WAVE - 1);
+    if (wk < 3) qs = l < v.npcg2 ? v.pl_part2[PAR][l * 4 + wk] : 0.0;
   }
   const double* __restrict__ M = v.pl_m[PAR];
   double* __restrict__ Mn = v.pl_m[PAR ^ 1];
@@ -834,7 +805,13 @@ void k_pcg_iter(View v) {
 #pragma unroll
       for (int k = 0; k < 3; ++k) tot[k] = sh_in[2 * k] + sh_in[2 * k + 1];
     } else {
-      sum_partials_loaded<NT, 1>(q, v.npcg2, tot, sh_in);
+      if (wk < 3) {
+        const double ps = wave_sum_last(qs);
+        if ((threadIdx.x & (WAVE - 1)) == WAVE - 1) sh_in[wk] = ps;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < 3; ++k) tot[k] = sh_in[k];
     }
     if (pcg_scalars(v, tot, PAR, igam_old, alp_old, bb, blockIdx.x == 0, alpha, beta)) return;
   }
